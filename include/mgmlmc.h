@@ -1,0 +1,321 @@
+/*
+ * mgmlmc.h -- C ABI of a single-GPU (MI355X, gfx950) library for multigrid
+ * multilevel Monte Carlo trace estimation with orthogonal projectors
+ * (Frommer, Jimenez-Merchan, Knechtli, Korzec, Ramirez-Hidalgo,
+ * arXiv:2509.11424).
+ *
+ * The calls follow the paper's statement of the problem: build the level
+ * hierarchy (Sec. 2.2: aggregation-based unitary P_l, Galerkin
+ * D_{l+1} = P_l^H D_l P_l), draw Z4 probes (Sec. 1, eq. z4), and estimate a
+ * trace, a connected correlator or disconnected loops per level with the
+ * variance of every term (Sec. 3 decomposition; Sec. 4 variance estimator;
+ * Sec. 4.1 correlator split; Sec. 4.3 loops).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status codes are returned, never thrown; mgm_last_error() gives a
+ *   thread-local message for the last failing call.
+ * - Complex numbers are interleaved (re, im).
+ * - Device pointers ("_dev") are plain device addresses (for example from
+ *   torch tensors); host pointers ("_host") are ordinary host memory.  The
+ *   library never frees memory it did not allocate.
+ * - Device memory: the caller owns every device buffer, including the
+ *   workspace handed to mgm_operator_create and mgm_hierarchy_create, whose
+ *   size comes from the matching *_workspace_size call.  The workspace must
+ *   stay valid and untouched until the object is destroyed.  The library
+ *   itself allocates only small pinned host staging buffers.
+ * - Lattice: dims = {X, Y, Z, T}; site s = x + X*(y + Y*(z + Z*t)).
+ *   Fine dof per site d = 12, dof = 3*spin + colour, chiral gamma basis with
+ *   gamma5 = diag(1, 1, -1, -1).  Level l >= 1 has d = 2*N_tv(l-1) dof per
+ *   site, dof = N_tv*chi + k.
+ * - Vector layout on every level ("dof-major"): a batch of nrhs vectors of a
+ *   level with V_l sites and d_l dof per site is one array with element
+ *   (dof, site, rhs) at index (dof*V_l + site)*nrhs + rhs.
+ * - Gauge field input (host, FP64): [T][Z][Y][X][mu][3][3] complex,
+ *   mu = 0..3 for x, y, z, t; U_mu(x) connects x + mu to x.
+ * - All work is enqueued on the HIP stream given to mgm_context_create.
+ *   Calls that return host results synchronise that stream.
+ * - Handles are not thread safe; distinct contexts are independent.
+ */
+#ifndef MGMLMC_H
+#define MGMLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MGM_OK = 0,
+  MGM_ERR_INVALID_ARG = -1,
+  MGM_ERR_SHAPE = -2,
+  MGM_ERR_WORKSPACE = -3,
+  MGM_ERR_NOT_CONVERGED = -4,
+  MGM_ERR_RANK_DEFICIENT = -5,
+  MGM_ERR_NUMERIC = -6,
+  MGM_ERR_HIP = -7
+} mgm_status;
+
+/* Storage precision of an operator application or a vector.
+ * F64: double complex; F32: float complex; F16: IEEE half complex
+ * (arithmetic in FP32); BF16 is used only for coarse-stencil MFMA operands. */
+typedef enum { MGM_PREC_F64 = 0, MGM_PREC_F32 = 1, MGM_PREC_F16 = 2, MGM_PREC_BF16 = 3 } mgm_prec;
+
+typedef struct mgm_context_s* mgm_context;
+typedef struct mgm_operator_s* mgm_operator;
+typedef struct mgm_hierarchy_s* mgm_hierarchy;
+
+/* Human-readable name of a status code (static string). */
+const char* mgm_status_string(mgm_status s);
+/* Message describing the last error on this thread ("" if none). */
+const char* mgm_last_error(void);
+/* Library version string. */
+const char* mgm_version(void);
+
+/* ------------------------------------------------------------- context */
+
+/* Binds the library to HIP device `device` and to `hip_stream` (a
+ * hipStream_t, NULL for the default stream).  Errors: INVALID_ARG, HIP. */
+mgm_status mgm_context_create(int device, void* hip_stream, mgm_context* out);
+/* Switches the stream used by later calls on this context. */
+mgm_status mgm_context_set_stream(mgm_context ctx, void* hip_stream);
+void mgm_context_destroy(mgm_context ctx);
+
+/* --------------------------------------------------------- fine operator */
+
+/* The Wilson-clover Dirac operator (the paper requires only a discretised,
+ * Gamma5-hermitian Dirac operator with 12 dof per site, Sec. 1 and Sec. 2.1):
+ *   (D psi)(x) = (4 + m0) psi(x)
+ *     - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^H psi(x-mu)]
+ *     + csw (i/4) sum_{mu != nu} sigma_mu_nu F_mu_nu(x) psi(x)
+ * with clover-leaf F_mu_nu = (Q - Q^H)/8 and, if t_antiperiodic != 0, a
+ * factor -1 on hops across the time boundary. */
+typedef struct {
+  int32_t dims[4];        /* X, Y, Z, T; each >= 2 */
+  double m0;              /* bare mass */
+  double csw;             /* clover coefficient (0: plain Wilson) */
+  int32_t t_antiperiodic; /* 1: antiperiodic in time, 0: periodic */
+} mgm_lattice_desc;
+
+/* Workspace (bytes) needed by mgm_operator_create: links and clover blocks
+ * in FP64, FP32 and FP16.  Errors: INVALID_ARG, SHAPE. */
+mgm_status mgm_operator_workspace_size(const mgm_lattice_desc* desc, size_t* bytes);
+
+/* Copies the FP64 gauge field from host memory (layout above), builds the
+ * clover term on the GPU and keeps FP32/FP16 copies.  `ws_dev` must hold
+ * mgm_operator_workspace_size bytes, 256-byte aligned.
+ * Errors: INVALID_ARG, SHAPE, WORKSPACE, HIP. */
+mgm_status mgm_operator_create(mgm_context ctx, const mgm_lattice_desc* desc,
+                               const double* gauge_host, void* ws_dev, size_t ws_bytes,
+                               mgm_operator* out);
+
+/* y = D x for nrhs vectors in dof-major layout, in precision `prec`
+ * (F64, F32 or F16; x and y hold elements of that precision).  x and y must
+ * not overlap.  Errors: INVALID_ARG, HIP. */
+mgm_status mgm_operator_apply(mgm_operator op, mgm_prec prec, const void* x_dev, void* y_dev,
+                              int32_t nrhs);
+
+/* Number of lattice sites of the fine operator. */
+int64_t mgm_operator_sites(mgm_operator op);
+void mgm_operator_destroy(mgm_operator op);
+
+/* ----------------------------------------------------------------- probes */
+
+/* Z4 probe entries (eq. z4): entry i of probe p is
+ * (1, i, -1, -i)[w0 >> 30] with w0 the first output word of Philox4x32-10
+ * (Salmon et al., SC'11) at key (seed & 0xffffffff, seed >> 32) and counter
+ * (i & 0xffffffff, i >> 32, p, stream).  `stream` = 256*level + kind with
+ * kind 0 plain, 1 O_l, 2 F_l, 3 M_l, 4 coarsest, 5 correlator source,
+ * 6 loop source, 7 test vector.  Writes nprobe vectors of n_site*dof entries
+ * in dof-major layout (probe p = first_probe + rhs; entry index
+ * i = site*dof + dof_index) to out_dev in precision `prec` (F64 or F32).
+ * Errors: INVALID_ARG, HIP. */
+mgm_status mgm_draw_z4(mgm_context ctx, uint64_t seed, uint32_t stream, uint64_t first_probe,
+                       int32_t nprobe, int64_t n_site, int32_t dof, mgm_prec prec,
+                       void* out_dev);
+
+/* -------------------------------------------------------------- hierarchy */
+
+#define MGM_MAX_LEVELS 4
+
+/* Multigrid hierarchy (Sec. 2.2).  Level l >= 1 is the Galerkin operator of
+ * level l-1 on aggregates of block[l-1] sites, built from ntv[l-1] test
+ * vectors (Z4 starts, setup_steps rounds of setup_mr minimal-residual steps
+ * on D_{l-1}, normalised) orthonormalised per (aggregate, chirality) block by
+ * modified Gram-Schmidt with re-orthogonalisation (diag R > 0). */
+typedef struct {
+  int32_t nlevels;                    /* 2..MGM_MAX_LEVELS */
+  int32_t block[MGM_MAX_LEVELS - 1][4];
+  int32_t ntv[MGM_MAX_LEVELS - 1];    /* test vectors per transfer, <= 32 */
+  int32_t setup_steps;                /* default 20 */
+  int32_t setup_mr;                   /* default 4 */
+  uint64_t seed;                      /* test-vector probes (kind 7) */
+  int32_t max_nrhs;                   /* largest batch of right-hand sides */
+  int32_t restart;                    /* FGMRES restart length, >= 2 */
+  int32_t mixed;                      /* 0: FP64 solver workspaces only;
+                                         1: FP32 Krylov workspaces plus FP32/BF16
+                                         copies of P and D_c for the mixed solver
+                                         (FP64 keeps only defect-correction vectors);
+                                         2: both full */
+  int32_t with_corr;                  /* 1: reserve the fine-level term vectors needed
+                                         by CORR_PS and LOOPS estimates */
+} mgm_hierarchy_desc;
+
+mgm_status mgm_hierarchy_workspace_size(mgm_operator op, const mgm_hierarchy_desc* desc,
+                                        size_t* bytes);
+
+/* Builds the hierarchy on the GPU.  Errors: INVALID_ARG, SHAPE, WORKSPACE,
+ * RANK_DEFICIENT (a test-vector block lost rank), NUMERIC, HIP. */
+mgm_status mgm_hierarchy_create(mgm_operator op, const mgm_hierarchy_desc* desc, void* ws_dev,
+                                size_t ws_bytes, mgm_hierarchy* out);
+
+/* Dimension bookkeeping of level `level`: sites, dof per site, n = sites*dof. */
+mgm_status mgm_hierarchy_level_info(mgm_hierarchy h, int32_t level, int64_t* sites,
+                                    int32_t* dof, int64_t* n);
+
+/* What mgm_hierarchy_export copies to host memory. */
+typedef enum {
+  MGM_EXPORT_AGG_MAP = 0,  /* int64 [Vc][2][rows]: flat dof index (site*d + chi*d/2 + j)
+                              of block row loc*(d/2) + j of aggregate a, chirality chi */
+  MGM_EXPORT_P = 1,        /* complex FP64 [Vc][2][rows][ntv] */
+  MGM_EXPORT_COARSE = 2,   /* complex FP64 [Vc][9][dc][dc] stencil of D_{level+1};
+                              dir 0 self, 1+mu forward, 5+mu backward */
+  MGM_EXPORT_TV = 3        /* complex FP64 [ntv][n_level] test vectors (before QR) */
+} mgm_export_kind;
+
+/* Copies one object of transfer `level` (0 <= level < nlevels-1) to
+ * host_buf, which must hold `bytes` >= the object size.  Synchronises. */
+mgm_status mgm_hierarchy_export(mgm_hierarchy h, int32_t level, mgm_export_kind what,
+                                void* host_buf, size_t bytes);
+
+/* Level operators applied in FP64 (fine: the Wilson-clover stencil; coarse:
+ * the nine-point Galerkin stencil), and the transfers:
+ *   restrict: y_c = P_l^H x, prolong: y = P_l x_c, project: y = (I - P_l P_l^H) x
+ * all in dof-major FP64 layout. */
+mgm_status mgm_level_apply(mgm_hierarchy h, int32_t level, const void* x_dev, void* y_dev,
+                           int32_t nrhs);
+mgm_status mgm_restrict(mgm_hierarchy h, int32_t level, const void* x_dev, void* y_dev,
+                        int32_t nrhs);
+mgm_status mgm_prolong(mgm_hierarchy h, int32_t level, const void* x_dev, void* y_dev,
+                       int32_t nrhs);
+mgm_status mgm_project_out(mgm_hierarchy h, int32_t level, const void* x_dev, void* y_dev,
+                           int32_t nrhs);
+
+/* ------------------------------------------------------------------ solve */
+
+typedef enum {
+  MGM_SOLVE_MG = 0,        /* FP64 FGMRES preconditioned by an FP64 MG V-cycle */
+  MGM_SOLVE_MG_MIXED = 1,  /* FP64 defect correction around FP32 FGMRES with an
+                              FP16-smoother / BF16-MFMA-coarse V-cycle */
+  MGM_SOLVE_GMRES = 2,     /* unpreconditioned FP64 GMRES */
+  MGM_SOLVE_NET = 3        /* MG_MIXED with the learned smoother (mgm_net) */
+} mgm_solve_kind;
+
+typedef struct {
+  double tol;          /* stop when every |b - D x| / |b| <= tol (true FP64 residual) */
+  int32_t maxiter;     /* outer iteration cap */
+  int32_t kind;        /* mgm_solve_kind */
+  int32_t smooth;      /* minimal-residual smoothing steps (pre and post) */
+  int32_t coarse_iters;/* iterations of the coarse-level solve inside a V-cycle */
+  double inner_tol;    /* MG_MIXED: relative reduction per FP32 inner solve */
+  void* net;           /* MGM_SOLVE_NET: network handle (mgm_net), else NULL */
+} mgm_solve_desc;
+
+typedef struct {
+  int32_t iterations;  /* total outer Arnoldi steps (all right-hand sides together) */
+  int32_t restarts;    /* FGMRES cycles */
+  int32_t fallbacks;   /* NET: cycles that fell back to plain MG */
+  double max_rel_residual;  /* largest final true relative residual */
+  double seconds;      /* wall time of the call */
+} mgm_solve_stats;
+
+/* Solves D_level x = b for nrhs right-hand sides (dof-major FP64), x0 = 0.
+ * Every right-hand side is judged by its own true FP64 residual.  Returns
+ * NOT_CONVERGED (with x and stats written) if any misses tol within maxiter. */
+mgm_status mgm_solve(mgm_hierarchy h, int32_t level, const mgm_solve_desc* desc,
+                     const void* b_dev, void* x_dev, int32_t nrhs, mgm_solve_stats* stats);
+
+/* --------------------------------------------------------------- estimate */
+
+typedef enum { MGM_OBS_TRACE = 0, MGM_OBS_CORR_PS = 1, MGM_OBS_LOOPS = 2 } mgm_observable;
+typedef enum { MGM_DEC_PLAIN = 0, MGM_DEC_OBLIQUE = 1, MGM_DEC_ORTHOGONAL = 2 } mgm_decomposition;
+
+/*
+ * Term numbering (L = nlevels):
+ *  TRACE  plain:      [0] x^H D^-1 x
+ *         oblique:    [l] M_l (l < L-1), [L-1] coarsest
+ *         orthogonal: [l] O_l, [L-1+l] F_l (l < L-1), [2L-2] coarsest
+ *  CORR_PS / LOOPS: terms B_r of the paper's correlator split (Sec. 4.1),
+ *         plain [0] D^-1; oblique [l] B_l (l <= L-1); orthogonal
+ *         [l] J_l, [L-1+l] K_l, [2L-2] coarsest.  Correlator results are
+ *         per pair (r, s) in row-major order r*R + s.
+ * Probe groups: nprobe[g] probes for every term (TRACE, LOOPS) or pair
+ * (CORR_PS) whose finest level is g; plain uses nprobe[0].
+ */
+typedef struct {
+  int32_t observable;       /* mgm_observable */
+  int32_t decomposition;    /* mgm_decomposition */
+  int32_t nprobe[MGM_MAX_LEVELS];
+  uint64_t seed;
+  uint64_t first_probe;     /* probe index offset (restart / sharding) */
+  int32_t batch;            /* right-hand sides per solver launch (<= max_nrhs) */
+  mgm_solve_desc solve;
+} mgm_estimate_desc;
+
+typedef struct {
+  int32_t nterms;           /* TRACE, LOOPS: terms; CORR_PS: pairs R*R */
+  int32_t T;                /* time extent (1 for TRACE) */
+  int32_t ngamma;           /* 6 for LOOPS, else 1 */
+  int64_t nsamples;         /* entries of `samples` */
+} mgm_estimate_sizes;
+
+/* Caller-owned host arrays (sizes from mgm_estimate_sizes).  Per term (and
+ * per t, Gamma): N, mean (complex), variance sum|X - mean|^2/(N-1) (Sec. 4);
+ * cost_s = solver seconds spent per sample.  `samples` (optional, may be
+ * NULL) receives every per-probe complex value ordered
+ * [term][probe][gamma][t].  total_mean / total_var: sum over terms of the
+ * means and of var/N (independent probe sets); per t for CORR_PS / LOOPS. */
+typedef struct {
+  int64_t* n;               /* [nterms] */
+  double* mean;             /* [nterms][ngamma][T] complex */
+  double* var;              /* [nterms][ngamma][T] */
+  double* cost_s;           /* [nterms] */
+  double* samples;          /* [nsamples] complex, or NULL */
+  double* total_mean;       /* [ngamma][T] complex */
+  double* total_var;        /* [ngamma][T] */
+  mgm_solve_stats stats;    /* accumulated over all solves */
+} mgm_estimate_result;
+
+mgm_status mgm_estimate_sizes_query(mgm_hierarchy h, const mgm_estimate_desc* desc,
+                                    mgm_estimate_sizes* sizes);
+mgm_status mgm_estimate(mgm_hierarchy h, const mgm_estimate_desc* desc, mgm_estimate_result* out);
+
+/* ------------------------------------------------------------------- MLMC */
+
+/* Optimal sample sizes for target variance eps2 (Sec. 2.2, eq. MLMC-Nl):
+ * N_l = ceil(eps2^-1 sqrt(V_l/C_l) sum_i sqrt(V_i C_i)), at least 2.
+ * Pure host function.  Errors: INVALID_ARG. */
+mgm_status mgm_mlmc_allocate(int32_t nterms, const double* var, const double* cost, double eps2,
+                             int64_t* n_out);
+
+/* -------------------------------------------------------------- profiling */
+
+/* Kernel-level event timing of the library's own launches (dslash, coarse
+ * stencil, transfers), off by default.  mgm_profile_query returns the number
+ * of launches, their summed duration in ms and the summed algorithmic bytes
+ * of kernel class `kclass` (0 fine dslash F64, 1 F32, 2 F16, 3 coarse stencil
+ * F64, 4 coarse stencil F32, 5 coarse stencil BF16 MFMA, 6 restrict/prolong).
+ * Synchronises. */
+mgm_status mgm_profile_enable(mgm_context ctx, int32_t on);
+mgm_status mgm_profile_reset(mgm_context ctx);
+mgm_status mgm_profile_query(mgm_context ctx, int32_t kclass, int64_t* launches, double* ms,
+                             double* bytes);
+
+void mgm_hierarchy_destroy(mgm_hierarchy h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGMLMC_H */

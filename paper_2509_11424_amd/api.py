@@ -1,0 +1,428 @@
+"""Python binding of the mgmlmc C ABI (include/mgmlmc.h).
+
+Argument marshalling only: every computation runs in the HIP library.  torch
+provides the device memory (workspaces, vectors) and the HIP stream.  Vectors
+are complex torch tensors in the library's dof-major layout, shape
+(dof, sites, nrhs); `to_dofmajor` / `from_dofmajor` convert from the natural
+(nrhs, sites, dof) layout.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgmlmc.so")
+
+MAX_LEVELS = 4
+PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+SOLVE = {"mg": 0, "mg_mixed": 1, "gmres": 2, "net": 3}
+OBS = {"trace": 0, "corr": 1, "loops": 2}
+DEC = {"plain": 0, "oblique": 1, "orthogonal": 2}
+EXPORT = {"agg_map": 0, "P": 1, "coarse": 2, "tv": 3}
+KCLASS = {"dslash_f64": 0, "dslash_f32": 1, "dslash_f16": 2, "coarse_f64": 3, "coarse_f32": 4,
+          "coarse_bf16": 5, "transfer": 6}
+STATUS = {0: "MGM_OK", -1: "MGM_ERR_INVALID_ARG", -2: "MGM_ERR_SHAPE", -3: "MGM_ERR_WORKSPACE",
+          -4: "MGM_ERR_NOT_CONVERGED", -5: "MGM_ERR_RANK_DEFICIENT", -6: "MGM_ERR_NUMERIC",
+          -7: "MGM_ERR_HIP"}
+
+
+class MgmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class LatticeDesc(C.Structure):
+    _fields_ = [("dims", C.c_int32 * 4), ("m0", C.c_double), ("csw", C.c_double),
+                ("t_antiperiodic", C.c_int32)]
+
+
+class HierarchyDesc(C.Structure):
+    _fields_ = [("nlevels", C.c_int32), ("block", (C.c_int32 * 4) * (MAX_LEVELS - 1)),
+                ("ntv", C.c_int32 * (MAX_LEVELS - 1)), ("setup_steps", C.c_int32),
+                ("setup_mr", C.c_int32), ("seed", C.c_uint64), ("max_nrhs", C.c_int32),
+                ("restart", C.c_int32), ("mixed", C.c_int32), ("with_corr", C.c_int32)]
+
+
+class SolveDesc(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("kind", C.c_int32),
+                ("smooth", C.c_int32), ("coarse_iters", C.c_int32), ("inner_tol", C.c_double),
+                ("net", C.c_void_p)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("fallbacks", C.c_int32),
+                ("max_rel_residual", C.c_double), ("seconds", C.c_double)]
+
+
+class EstimateDesc(C.Structure):
+    _fields_ = [("observable", C.c_int32), ("decomposition", C.c_int32),
+                ("nprobe", C.c_int32 * MAX_LEVELS), ("seed", C.c_uint64),
+                ("first_probe", C.c_uint64), ("batch", C.c_int32), ("solve", SolveDesc)]
+
+
+class EstimateSizes(C.Structure):
+    _fields_ = [("nterms", C.c_int32), ("T", C.c_int32), ("ngamma", C.c_int32),
+                ("nsamples", C.c_int64)]
+
+
+class EstimateResult(C.Structure):
+    _fields_ = [("n", C.POINTER(C.c_int64)), ("mean", C.POINTER(C.c_double)),
+                ("var", C.POINTER(C.c_double)), ("cost_s", C.POINTER(C.c_double)),
+                ("samples", C.POINTER(C.c_double)), ("total_mean", C.POINTER(C.c_double)),
+                ("total_var", C.POINTER(C.c_double)), ("stats", SolveStats)]
+
+
+_lib = None
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("mgm_status_string", C.c_char_p, [C.c_int]),
+    ("mgm_last_error", C.c_char_p, []),
+    ("mgm_version", C.c_char_p, []),
+    ("mgm_context_create", C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("mgm_context_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("mgm_context_destroy", None, [C.c_void_p]),
+    ("mgm_operator_workspace_size", C.c_int, [C.POINTER(LatticeDesc), C.POINTER(C.c_size_t)]),
+    ("mgm_operator_create", C.c_int, [C.c_void_p, C.POINTER(LatticeDesc), C.c_void_p, C.c_void_p,
+                                      C.c_size_t, C.POINTER(C.c_void_p)]),
+    ("mgm_operator_apply", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("mgm_operator_sites", C.c_int64, [C.c_void_p]),
+    ("mgm_operator_destroy", None, [C.c_void_p]),
+    ("mgm_draw_z4", C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int32, C.c_int64,
+                              C.c_int32, C.c_int, C.c_void_p]),
+    ("mgm_hierarchy_workspace_size", C.c_int, [C.c_void_p, C.POINTER(HierarchyDesc),
+                                               C.POINTER(C.c_size_t)]),
+    ("mgm_hierarchy_create", C.c_int, [C.c_void_p, C.POINTER(HierarchyDesc), C.c_void_p, C.c_size_t,
+                                       C.POINTER(C.c_void_p)]),
+    ("mgm_hierarchy_level_info", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
+                                           C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    ("mgm_hierarchy_export", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_void_p, C.c_size_t]),
+    ("mgm_level_apply", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("mgm_restrict", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("mgm_prolong", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("mgm_project_out", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("mgm_solve", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(SolveDesc), C.c_void_p, C.c_void_p,
+                            C.c_int32, C.POINTER(SolveStats)]),
+    ("mgm_estimate_sizes_query", C.c_int, [C.c_void_p, C.POINTER(EstimateDesc),
+                                           C.POINTER(EstimateSizes)]),
+    ("mgm_estimate", C.c_int, [C.c_void_p, C.POINTER(EstimateDesc), C.POINTER(EstimateResult)]),
+    ("mgm_mlmc_allocate", C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.c_double, C.POINTER(C.c_int64)]),
+    ("mgm_profile_enable", C.c_int, [C.c_void_p, C.c_int32]),
+    ("mgm_profile_reset", C.c_int, [C.c_void_p]),
+    ("mgm_profile_query", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("mgm_hierarchy_destroy", None, [C.c_void_p]),
+]
+
+EXPORTED = [s[0] for s in _SIGS]
+
+
+def lib():
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmgmlmc.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_2509_11424_amd.build); there is no fallback")
+        l = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise MgmError(st, lib().mgm_last_error().decode())
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+# ------------------------------------------------------------------ layout
+
+def to_dofmajor(x: np.ndarray) -> np.ndarray:
+    """(nrhs, sites, dof) -> (dof, sites, nrhs) contiguous."""
+    return np.ascontiguousarray(np.transpose(x, (2, 1, 0)))
+
+
+def from_dofmajor(x: np.ndarray) -> np.ndarray:
+    """(dof, sites, nrhs) -> (nrhs, sites, dof) contiguous."""
+    return np.ascontiguousarray(np.transpose(x, (2, 1, 0)))
+
+
+def gauge_to_host(U: np.ndarray) -> np.ndarray:
+    """(T, Z, Y, X, 4, 3, 3) complex128 -> contiguous float64 view for the ABI."""
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    return U.view(np.float64)
+
+
+# ------------------------------------------------------------------ objects
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = C.c_void_p()
+        _check(lib().mgm_context_create(device, C.c_void_p(stream), C.byref(h)))
+        self.h = h
+
+    def set_stream(self, stream):
+        _check(lib().mgm_context_set_stream(self.h, C.c_void_p(stream)))
+
+    def profile(self, on: bool = True):
+        _check(lib().mgm_profile_enable(self.h, 1 if on else 0))
+
+    def profile_reset(self):
+        _check(lib().mgm_profile_reset(self.h))
+
+    def profile_query(self, kclass: str):
+        n = C.c_int64()
+        ms = C.c_double()
+        by = C.c_double()
+        _check(lib().mgm_profile_query(self.h, KCLASS[kclass], C.byref(n), C.byref(ms), C.byref(by)))
+        return {"launches": n.value, "ms": ms.value, "bytes": by.value}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mgm_context_destroy(self.h)
+            self.h = None
+
+
+def _empty_ws(nbytes: int, device: int):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda:%d" % device)
+
+
+class Operator:
+    """Wilson-clover operator on the GPU built from an FP64 host gauge field."""
+
+    def __init__(self, ctx: Context, gauge: np.ndarray, m0: float, csw: float,
+                 antiperiodic_t: bool = True):
+        T, Z, Y, X = gauge.shape[:4]
+        self.ctx = ctx
+        self.dims = (X, Y, Z, T)
+        self.V = X * Y * Z * T
+        d = LatticeDesc()
+        d.dims[:] = [X, Y, Z, T]
+        d.m0 = m0
+        d.csw = csw
+        d.t_antiperiodic = 1 if antiperiodic_t else 0
+        self.desc = d
+        nb = C.c_size_t()
+        _check(lib().mgm_operator_workspace_size(C.byref(d), C.byref(nb)))
+        self.ws = _empty_ws(nb.value, ctx.device)
+        g = gauge_to_host(gauge)
+        h = C.c_void_p()
+        _check(lib().mgm_operator_create(ctx.h, C.byref(d), g.ctypes.data_as(C.c_void_p),
+                                         C.c_void_p(_ptr(self.ws)), self.ws.numel(), C.byref(h)))
+        self.h = h
+
+    def apply(self, x, y=None, prec: str = "f64"):
+        """y = D x; x is a dof-major tensor (12, V, nrhs) of the precision's dtype
+        (f64: complex128, f32: complex64, f16: float16 pairs (12, V, nrhs, 2))."""
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        nrhs = x.shape[2]
+        _check(lib().mgm_operator_apply(self.h, PREC[prec], C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)),
+                                        nrhs))
+        return y
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mgm_operator_destroy(self.h)
+            self.h = None
+
+
+def draw_z4(ctx: Context, seed: int, stream: int, first_probe: int, nprobe: int, nsite: int, dof: int,
+            prec: str = "f64"):
+    import torch
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    out = torch.empty((dof, nsite, nprobe), dtype=dt, device="cuda:%d" % ctx.device)
+    _check(lib().mgm_draw_z4(ctx.h, seed, stream, first_probe, nprobe, nsite, dof, PREC[prec],
+                             C.c_void_p(_ptr(out))))
+    return out
+
+
+def solve_desc(tol=1e-12, maxiter=2000, kind="mg", smooth=2, coarse_iters=12, inner_tol=1e-5,
+               net=None) -> SolveDesc:
+    d = SolveDesc()
+    d.tol = tol
+    d.maxiter = maxiter
+    d.kind = SOLVE[kind] if isinstance(kind, str) else int(kind)
+    d.smooth = smooth
+    d.coarse_iters = coarse_iters
+    d.inner_tol = inner_tol
+    d.net = net.h if net is not None else None
+    return d
+
+
+class Hierarchy:
+    def __init__(self, op: Operator, blocks, ntv, seed: int, setup_steps: int = 20, setup_mr: int = 4,
+                 max_nrhs: int = 8, restart: int = 16, mixed: int = 0, with_corr: bool = False):
+        self.op = op
+        self.ctx = op.ctx
+        d = HierarchyDesc()
+        d.nlevels = len(blocks) + 1
+        for l, b in enumerate(blocks):
+            d.block[l][:] = list(b)
+            d.ntv[l] = ntv[l]
+        d.setup_steps = setup_steps
+        d.setup_mr = setup_mr
+        d.seed = seed
+        d.max_nrhs = max_nrhs
+        d.restart = restart
+        d.mixed = mixed
+        d.with_corr = 1 if with_corr else 0
+        self.desc = d
+        self.L = d.nlevels
+        nb = C.c_size_t()
+        _check(lib().mgm_hierarchy_workspace_size(op.h, C.byref(d), C.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = _empty_ws(nb.value, self.ctx.device)
+        h = C.c_void_p()
+        _check(lib().mgm_hierarchy_create(op.h, C.byref(d), C.c_void_p(_ptr(self.ws)), self.ws.numel(),
+                                          C.byref(h)))
+        self.h = h
+
+    def level_info(self, level: int):
+        s = C.c_int64()
+        d = C.c_int32()
+        n = C.c_int64()
+        _check(lib().mgm_hierarchy_level_info(self.h, level, C.byref(s), C.byref(d), C.byref(n)))
+        return s.value, d.value, n.value
+
+    def export(self, level: int, what: str) -> np.ndarray:
+        sites, dof, n = self.level_info(level)
+        cs, cd, cn = self.level_info(level + 1)
+        ntv = cd // 2
+        rows = (sites // cs) * (dof // 2)
+        if what == "agg_map":
+            out = np.zeros((cs, 2, rows), dtype=np.int64)
+        elif what == "P":
+            out = np.zeros((cs, 2, rows, ntv), dtype=np.complex128)
+        elif what == "coarse":
+            out = np.zeros((cs, 9, cd, cd), dtype=np.complex128)
+        elif what == "tv":
+            out = np.zeros((ntv, n), dtype=np.complex128)
+        else:
+            raise ValueError(what)
+        _check(lib().mgm_hierarchy_export(self.h, level, EXPORT[what], out.ctypes.data_as(C.c_void_p),
+                                          out.nbytes))
+        return out
+
+    def _vec(self, level: int, nrhs: int):
+        import torch
+        s, d, _ = self.level_info(level)
+        return torch.empty((d, s, nrhs), dtype=torch.complex128, device="cuda:%d" % self.ctx.device)
+
+    def apply(self, level: int, x):
+        y = self._vec(level, x.shape[2])
+        _check(lib().mgm_level_apply(self.h, level, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)), x.shape[2]))
+        return y
+
+    def restrict(self, level: int, x):
+        y = self._vec(level + 1, x.shape[2])
+        _check(lib().mgm_restrict(self.h, level, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)), x.shape[2]))
+        return y
+
+    def prolong(self, level: int, xc):
+        y = self._vec(level, xc.shape[2])
+        _check(lib().mgm_prolong(self.h, level, C.c_void_p(_ptr(xc)), C.c_void_p(_ptr(y)), xc.shape[2]))
+        return y
+
+    def project_out(self, level: int, x):
+        y = self._vec(level, x.shape[2])
+        _check(lib().mgm_project_out(self.h, level, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)), x.shape[2]))
+        return y
+
+    def solve(self, level: int, b, desc: SolveDesc | None = None, x=None, check: bool = True):
+        desc = desc or solve_desc()
+        if x is None:
+            x = self._vec(level, b.shape[2])
+        st = SolveStats()
+        rc = lib().mgm_solve(self.h, level, C.byref(desc), C.c_void_p(_ptr(b)), C.c_void_p(_ptr(x)),
+                             b.shape[2], C.byref(st))
+        stats = {"iterations": st.iterations, "restarts": st.restarts, "fallbacks": st.fallbacks,
+                 "max_rel_residual": st.max_rel_residual, "seconds": st.seconds, "status": rc}
+        if check:
+            _check(rc)
+        return x, stats
+
+    def estimate(self, observable: str, decomposition: str, nprobe, seed: int, batch: int = 8,
+                 first_probe: int = 0, solve: SolveDesc | None = None, samples: bool = True,
+                 check: bool = True):
+        d = EstimateDesc()
+        d.observable = OBS[observable]
+        d.decomposition = DEC[decomposition]
+        npr = list(nprobe) + [0] * (MAX_LEVELS - len(nprobe))
+        d.nprobe[:] = npr[:MAX_LEVELS]
+        d.seed = seed
+        d.first_probe = first_probe
+        d.batch = batch
+        d.solve = solve or solve_desc()
+        sz = EstimateSizes()
+        _check(lib().mgm_estimate_sizes_query(self.h, C.byref(d), C.byref(sz)))
+        K = sz.ngamma * sz.T
+        n = np.zeros(sz.nterms, dtype=np.int64)
+        mean = np.zeros(sz.nterms * K * 2)
+        var = np.zeros(sz.nterms * K)
+        cost = np.zeros(sz.nterms)
+        smp = np.zeros(max(1, sz.nsamples) * 2) if samples else None
+        tm = np.zeros(K * 2)
+        tv = np.zeros(K)
+        r = EstimateResult()
+        P = C.POINTER
+        r.n = n.ctypes.data_as(P(C.c_int64))
+        r.mean = mean.ctypes.data_as(P(C.c_double))
+        r.var = var.ctypes.data_as(P(C.c_double))
+        r.cost_s = cost.ctypes.data_as(P(C.c_double))
+        r.samples = smp.ctypes.data_as(P(C.c_double)) if samples else None
+        r.total_mean = tm.ctypes.data_as(P(C.c_double))
+        r.total_var = tv.ctypes.data_as(P(C.c_double))
+        rc = lib().mgm_estimate(self.h, C.byref(d), C.byref(r))
+        if check:
+            _check(rc)
+        shape = (sz.nterms, sz.ngamma, sz.T)
+        out = {"status": rc, "n": n, "mean": mean.view(np.complex128).reshape(shape),
+               "var": var.reshape(shape), "cost_s": cost,
+               "total_mean": tm.view(np.complex128).reshape(sz.ngamma, sz.T),
+               "total_var": tv.reshape(sz.ngamma, sz.T),
+               "stats": {"iterations": r.stats.iterations, "restarts": r.stats.restarts,
+                         "max_rel_residual": r.stats.max_rel_residual, "seconds": r.stats.seconds,
+                         "fallbacks": r.stats.fallbacks}}
+        if samples:
+            flat = smp[:2 * sz.nsamples].view(np.complex128)
+            per, off = [], 0
+            for q in range(sz.nterms):
+                m = int(n[q]) * K
+                per.append(flat[off:off + m].reshape(int(n[q]), sz.ngamma, sz.T))
+                off += m
+            out["samples"] = per
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mgm_hierarchy_destroy(self.h)
+            self.h = None
+
+
+def mlmc_allocate(var, cost, eps2: float) -> np.ndarray:
+    var = np.ascontiguousarray(var, dtype=np.float64)
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    out = np.zeros(len(var), dtype=np.int64)
+    _check(lib().mgm_mlmc_allocate(len(var), var.ctypes.data_as(C.POINTER(C.c_double)),
+                                   cost.ctypes.data_as(C.POINTER(C.c_double)), eps2,
+                                   out.ctypes.data_as(C.POINTER(C.c_int64))))
+    return out

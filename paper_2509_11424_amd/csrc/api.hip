@@ -1,0 +1,497 @@
+// C ABI of the library: argument checks, status codes, object lifetimes.
+#include <cmath>
+#include <cstring>
+
+#include "lib.h"
+#include "net.h"
+
+using namespace mgm;
+
+namespace mgm {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void* Context::host_stage(size_t bytes) {
+  if (bytes > pinned_bytes) {
+    if (pinned) MGM_HIP(hipHostFree(pinned));
+    pinned = nullptr;
+    MGM_HIP(hipHostMalloc(&pinned, bytes, hipHostMallocDefault));
+    pinned_bytes = bytes;
+  }
+  return pinned;
+}
+
+hipEvent_t Context::take_event() {
+  if (!prof.pool.empty()) {
+    hipEvent_t e = prof.pool.back();
+    prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  MGM_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void Context::prof_begin(int, double, hipEvent_t* a) {
+  *a = take_event();
+  MGM_HIP(hipEventRecord(*a, stream));
+}
+
+void Context::prof_end(int kclass, double bytes, hipEvent_t a) {
+  hipEvent_t b = take_event();
+  MGM_HIP(hipEventRecord(b, stream));
+  prof.pending.push_back({a, b, kclass, bytes});
+  if (prof.pending.size() > 4096) prof_flush();
+}
+
+void Context::prof_flush() {
+  if (prof.pending.empty()) return;
+  sync();
+  for (auto& r : prof.pending) {
+    float ms = 0;
+    MGM_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    prof.launches[r.kclass]++;
+    prof.ms[r.kclass] += ms;
+    prof.bytes[r.kclass] += r.bytes;
+    prof.pool.push_back(r.a);
+    prof.pool.push_back(r.b);
+  }
+  prof.pending.clear();
+}
+
+}  // namespace mgm
+
+#define API_BEGIN try {
+#define API_END                                   \
+  return MGM_OK;                                  \
+  }                                               \
+  catch (const mgm::Error& e) {                   \
+    set_last_error(e.what());                     \
+    return e.code;                                \
+  }                                               \
+  catch (const std::exception& e) {               \
+    set_last_error(e.what());                     \
+    return MGM_ERR_INVALID_ARG;                   \
+  }
+
+extern "C" {
+
+const char* mgm_status_string(mgm_status s) {
+  switch (s) {
+    case MGM_OK: return "ok";
+    case MGM_ERR_INVALID_ARG: return "invalid argument";
+    case MGM_ERR_SHAPE: return "unsupported shape";
+    case MGM_ERR_WORKSPACE: return "workspace too small";
+    case MGM_ERR_NOT_CONVERGED: return "solver did not converge";
+    case MGM_ERR_RANK_DEFICIENT: return "rank-deficient test vectors";
+    case MGM_ERR_NUMERIC: return "non-finite value";
+    case MGM_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* mgm_last_error(void) { return g_last_error.c_str(); }
+const char* mgm_version(void) { return "mgmlmc 0.1 (gfx950)"; }
+
+mgm_status mgm_context_create(int device, void* hip_stream, mgm_context* out) {
+  API_BEGIN
+  MGM_CHECK(out != nullptr, MGM_ERR_INVALID_ARG, "out is NULL");
+  int n = 0;
+  MGM_HIP(hipGetDeviceCount(&n));
+  MGM_CHECK(device >= 0 && device < n, MGM_ERR_INVALID_ARG, "no such device");
+  MGM_HIP(hipSetDevice(device));
+  auto* c = new mgm_context_s();
+  c->c.device = device;
+  c->c.stream = (hipStream_t)hip_stream;
+  hipDeviceProp_t prop;
+  MGM_HIP(hipGetDeviceProperties(&prop, device));
+  c->c.cu_count = prop.multiProcessorCount;
+  *out = c;
+  API_END
+}
+
+mgm_status mgm_context_set_stream(mgm_context ctx, void* hip_stream) {
+  API_BEGIN
+  MGM_CHECK(ctx != nullptr, MGM_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->c.stream = (hipStream_t)hip_stream;
+  API_END
+}
+
+void mgm_context_destroy(mgm_context ctx) {
+  if (!ctx) return;
+  try {
+    ctx->c.prof_flush();
+    for (auto e : ctx->c.prof.pool) (void)hipEventDestroy(e);
+    if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
+  } catch (...) {
+  }
+  delete ctx;
+}
+
+// ------------------------------------------------------------ operator
+
+static Geom geom_of(const mgm_lattice_desc* d) {
+  MGM_CHECK(d != nullptr, MGM_ERR_INVALID_ARG, "desc is NULL");
+  for (int m = 0; m < 4; m++) MGM_CHECK(d->dims[m] >= 2, MGM_ERR_SHAPE, "every lattice extent must be >= 2");
+  MGM_CHECK(std::isfinite(d->m0) && std::isfinite(d->csw), MGM_ERR_INVALID_ARG, "non-finite m0 or csw");
+  Geom g;
+  g.X = d->dims[0];
+  g.Y = d->dims[1];
+  g.Z = d->dims[2];
+  g.T = d->dims[3];
+  g.V = (int64_t)g.X * g.Y * g.Z * g.T;
+  g.antiperiodic = d->t_antiperiodic ? 1 : 0;
+  return g;
+}
+
+mgm_status mgm_operator_workspace_size(const mgm_lattice_desc* desc, size_t* bytes) {
+  API_BEGIN
+  MGM_CHECK(bytes != nullptr, MGM_ERR_INVALID_ARG, "bytes is NULL");
+  Geom g = geom_of(desc);
+  Arena a;
+  FineOp tmp;
+  FineOp::layout(a, g, &tmp);
+  *bytes = a.off;
+  API_END
+}
+
+mgm_status mgm_operator_create(mgm_context ctx, const mgm_lattice_desc* desc, const double* gauge_host,
+                               void* ws_dev, size_t ws_bytes, mgm_operator* out) {
+  API_BEGIN
+  MGM_CHECK(ctx && gauge_host && ws_dev && out, MGM_ERR_INVALID_ARG, "NULL argument");
+  MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  Geom g = geom_of(desc);
+  Arena a;
+  a.base = (char*)ws_dev;
+  a.cap = ws_bytes;
+  auto* op = new mgm_operator_s();
+  try {
+    op->ctx = &ctx->c;
+    op->desc = *desc;
+    op->op.ctx = &ctx->c;
+    op->op.m0 = desc->m0;
+    op->op.csw = desc->csw;
+    FineOp::layout(a, g, &op->op);
+    op->op.build(gauge_host);
+  } catch (...) {
+    delete op;
+    throw;
+  }
+  *out = op;
+  API_END
+}
+
+mgm_status mgm_operator_apply(mgm_operator op, mgm_prec prec, const void* x, void* y, int32_t nrhs) {
+  API_BEGIN
+  MGM_CHECK(op && x && y && nrhs >= 1, MGM_ERR_INVALID_ARG, "bad arguments");
+  MGM_CHECK(x != y, MGM_ERR_INVALID_ARG, "x and y must not overlap");
+  op->op.apply(prec, x, y, nrhs);
+  API_END
+}
+
+int64_t mgm_operator_sites(mgm_operator op) { return op ? op->op.g.V : 0; }
+void mgm_operator_destroy(mgm_operator op) { delete op; }
+
+// --------------------------------------------------------------- probes
+
+mgm_status mgm_draw_z4(mgm_context ctx, uint64_t seed, uint32_t stream, uint64_t first_probe, int32_t nprobe,
+                       int64_t n_site, int32_t dof, mgm_prec prec, void* out) {
+  API_BEGIN
+  MGM_CHECK(ctx && out && nprobe >= 1 && n_site >= 1 && dof >= 1, MGM_ERR_INVALID_ARG, "bad arguments");
+  MGM_CHECK(first_probe + (uint64_t)nprobe <= (1ull << 32), MGM_ERR_INVALID_ARG,
+            "probe indices must be below 2^32 (32-bit counter word)");
+  draw_z4(&ctx->c, seed, stream, first_probe, nprobe, n_site, dof, prec, out);
+  API_END
+}
+
+// ------------------------------------------------------------ hierarchy
+
+static void check_hdesc(mgm_operator op, const mgm_hierarchy_desc* d) {
+  MGM_CHECK(op && d, MGM_ERR_INVALID_ARG, "NULL argument");
+  MGM_CHECK(d->nlevels >= 2 && d->nlevels <= MGM_MAX_LEVELS, MGM_ERR_INVALID_ARG, "nlevels must be 2..4");
+  MGM_CHECK(d->setup_steps >= 1 && d->setup_mr >= 1, MGM_ERR_INVALID_ARG, "setup steps must be >= 1");
+  MGM_CHECK(d->max_nrhs >= 1 && d->max_nrhs <= 256, MGM_ERR_INVALID_ARG, "max_nrhs must be 1..256");
+  MGM_CHECK(d->restart >= 2 && d->restart <= 63, MGM_ERR_INVALID_ARG, "restart must be 2..63");
+  int dims[4] = {op->op.g.X, op->op.g.Y, op->op.g.Z, op->op.g.T};
+  int dof = 12;
+  for (int l = 0; l + 1 < d->nlevels; l++) {
+    MGM_CHECK(d->ntv[l] >= 1 && d->ntv[l] <= 32, MGM_ERR_INVALID_ARG, "ntv must be 1..32");
+    MGM_CHECK(2 * d->ntv[l] <= 64 && dof <= 64, MGM_ERR_SHAPE, "coarse dof must be <= 64");
+    for (int m = 0; m < 4; m++) {
+      int b = d->block[l][m];
+      MGM_CHECK(b >= 1 && dims[m] % b == 0 && dims[m] / b >= 2, MGM_ERR_SHAPE,
+                "lattice not divisible into aggregates with coarse extent >= 2");
+      dims[m] /= b;
+    }
+    int rows = d->block[l][0] * d->block[l][1] * d->block[l][2] * d->block[l][3] * (dof / 2);
+    MGM_CHECK(rows * 16 <= 64 * 1024, MGM_ERR_SHAPE, "aggregate too large");
+    MGM_CHECK(d->ntv[l] <= rows, MGM_ERR_RANK_DEFICIENT, "more test vectors than aggregate rows");
+    dof = 2 * d->ntv[l];
+  }
+}
+
+mgm_status mgm_hierarchy_workspace_size(mgm_operator op, const mgm_hierarchy_desc* desc, size_t* bytes) {
+  API_BEGIN
+  check_hdesc(op, desc);
+  MGM_CHECK(bytes, MGM_ERR_INVALID_ARG, "bytes is NULL");
+  Hier h;
+  h.ctx = op->ctx;
+  h.fine = &op->op;
+  h.desc = *desc;
+  Arena a;
+  h.layout(a);
+  *bytes = a.off;
+  API_END
+}
+
+mgm_status mgm_hierarchy_create(mgm_operator op, const mgm_hierarchy_desc* desc, void* ws_dev, size_t ws_bytes,
+                                mgm_hierarchy* out) {
+  API_BEGIN
+  check_hdesc(op, desc);
+  MGM_CHECK(ws_dev && out, MGM_ERR_INVALID_ARG, "NULL argument");
+  MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  auto* hh = new mgm_hierarchy_s();
+  try {
+    Hier& h = hh->h;
+    h.ctx = op->ctx;
+    h.fine = &op->op;
+    h.desc = *desc;
+    Arena a;
+    a.base = (char*)ws_dev;
+    a.cap = ws_bytes;
+    h.layout(a);
+    h.pinned_n = 4 * 256;
+    h.pinned = (double*)h.ctx->host_stage(h.pinned_n * sizeof(double));
+    h.build();
+    h.tv_valid = true;
+  } catch (...) {
+    delete hh;
+    throw;
+  }
+  *out = hh;
+  API_END
+}
+
+mgm_status mgm_hierarchy_level_info(mgm_hierarchy h, int32_t level, int64_t* sites, int32_t* dof, int64_t* n) {
+  API_BEGIN
+  MGM_CHECK(h && level >= 0 && level < h->h.L, MGM_ERR_INVALID_ARG, "bad level");
+  if (sites) *sites = h->h.g[level].V;
+  if (dof) *dof = h->h.g[level].dof;
+  if (n) *n = h->h.n(level);
+  API_END
+}
+
+mgm_status mgm_hierarchy_export(mgm_hierarchy hh, int32_t level, mgm_export_kind what, void* host_buf,
+                                size_t bytes) {
+  API_BEGIN
+  MGM_CHECK(hh && host_buf, MGM_ERR_INVALID_ARG, "NULL argument");
+  Hier& h = hh->h;
+  MGM_CHECK(level >= 0 && level + 1 < h.L, MGM_ERR_INVALID_ARG, "bad transfer level");
+  Context* c = h.ctx;
+  const TGeom& t = h.T[level].t;
+  if (what == MGM_EXPORT_AGG_MAP) {
+    size_t need = (size_t)t.c.V * 2 * t.rows * sizeof(int64_t);
+    MGM_CHECK(bytes >= need, MGM_ERR_INVALID_ARG, "buffer too small");
+    MGM_CHECK(h.ws64[level].prec == MGM_PREC_F64 && h.ws64[level].r, MGM_ERR_WORKSPACE, "no scratch");
+    h.tv_valid = false;
+    int64_t* tmp = (int64_t*)h.ws64[level].r;  // scratch: n_l * nmax * 16 bytes >= n_l * 8
+    mg_agg_map(c, t, tmp);
+    MGM_HIP(hipMemcpyAsync(host_buf, tmp, need, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+  } else if (what == MGM_EXPORT_P) {
+    size_t need = (size_t)t.c.V * 2 * t.rows * t.ntv * sizeof(double2);
+    MGM_CHECK(bytes >= need, MGM_ERR_INVALID_ARG, "buffer too small");
+    MGM_HIP(hipMemcpyAsync(host_buf, h.T[level].P64, need, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+  } else if (what == MGM_EXPORT_COARSE) {
+    const CoarseOp& A = h.A[level + 1];
+    const int d = A.d;
+    const int64_t V = A.g.V;
+    size_t need = (size_t)V * 9 * d * d * sizeof(double2);
+    MGM_CHECK(bytes >= need, MGM_ERR_INVALID_ARG, "buffer too small");
+    std::vector<double2> tmp((size_t)V * 9 * d * d);
+    MGM_HIP(hipMemcpyAsync(tmp.data(), A.A64, need, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    double2* o = (double2*)host_buf;
+    for (int k = 0; k < 9; k++)
+      for (int i = 0; i < d; i++)
+        for (int j = 0; j < d; j++)
+          for (int64_t s = 0; s < V; s++)
+            o[((s * 9 + k) * d + i) * d + j] = tmp[(((size_t)k * d + i) * d + j) * V + s];
+  } else if (what == MGM_EXPORT_TV) {
+    MGM_CHECK(h.tv_valid, MGM_ERR_INVALID_ARG, "test vectors are only kept until the first solve");
+    const int ntv = t.ntv;
+    const int64_t nl = h.n(level);
+    size_t need = (size_t)ntv * nl * sizeof(double2);
+    MGM_CHECK(bytes >= need, MGM_ERR_INVALID_ARG, "buffer too small");
+    std::vector<double2> tmp((size_t)ntv * nl);
+    MGM_HIP(hipMemcpyAsync(tmp.data(), h.tv[level], need, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    // dof-major [dof][site][k] -> [k][site*dof + dof]
+    const int dof = h.g[level].dof;
+    const int64_t V = h.g[level].V;
+    double2* o = (double2*)host_buf;
+    for (int dd = 0; dd < dof; dd++)
+      for (int64_t s = 0; s < V; s++)
+        for (int k = 0; k < ntv; k++) o[(size_t)k * nl + s * dof + dd] = tmp[((size_t)dd * V + s) * ntv + k];
+  } else {
+    throw Error(MGM_ERR_INVALID_ARG, "unknown export kind");
+  }
+  API_END
+}
+
+static void check_level(mgm_hierarchy h, int level, int nrhs, bool transfer) {
+  MGM_CHECK(h != nullptr, MGM_ERR_INVALID_ARG, "h is NULL");
+  MGM_CHECK(level >= 0 && level < h->h.L - (transfer ? 1 : 0), MGM_ERR_INVALID_ARG, "bad level");
+  MGM_CHECK(nrhs >= 1, MGM_ERR_INVALID_ARG, "nrhs must be >= 1");
+}
+
+mgm_status mgm_level_apply(mgm_hierarchy h, int32_t level, const void* x, void* y, int32_t nrhs) {
+  API_BEGIN
+  check_level(h, level, nrhs, false);
+  MGM_CHECK(x && y && x != y, MGM_ERR_INVALID_ARG, "bad vectors");
+  h->h.apply(level, MGM_PREC_F64, x, y, nrhs);
+  API_END
+}
+
+mgm_status mgm_restrict(mgm_hierarchy h, int32_t level, const void* x, void* y, int32_t nrhs) {
+  API_BEGIN
+  check_level(h, level, nrhs, true);
+  MGM_CHECK(x && y, MGM_ERR_INVALID_ARG, "bad vectors");
+  h->h.T[level].restrict_(MGM_PREC_F64, x, y, nrhs);
+  API_END
+}
+
+mgm_status mgm_prolong(mgm_hierarchy h, int32_t level, const void* x, void* y, int32_t nrhs) {
+  API_BEGIN
+  check_level(h, level, nrhs, true);
+  MGM_CHECK(x && y, MGM_ERR_INVALID_ARG, "bad vectors");
+  h->h.T[level].prolong(MGM_PREC_F64, x, nullptr, y, nrhs, 0);
+  API_END
+}
+
+mgm_status mgm_project_out(mgm_hierarchy h, int32_t level, const void* x, void* y, int32_t nrhs) {
+  API_BEGIN
+  check_level(h, level, nrhs, true);
+  MGM_CHECK(x && y, MGM_ERR_INVALID_ARG, "bad vectors");
+  Hier& H = h->h;
+  MGM_CHECK(nrhs <= H.est.nmax, MGM_ERR_INVALID_ARG, "nrhs exceeds max_nrhs");
+  H.T[level].restrict_(MGM_PREC_F64, x, H.est.w[level + 1], nrhs);
+  H.T[level].prolong(MGM_PREC_F64, H.est.w[level + 1], x, y, nrhs, 1);
+  API_END
+}
+
+static SolveCfg cfg_of(const mgm_solve_desc* d) {
+  MGM_CHECK(d != nullptr, MGM_ERR_INVALID_ARG, "solve desc is NULL");
+  MGM_CHECK(d->tol > 0 && d->maxiter >= 1 && d->smooth >= 0 && d->coarse_iters >= 1, MGM_ERR_INVALID_ARG,
+            "bad solve parameters");
+  SolveCfg c;
+  c.tol = d->tol;
+  c.maxiter = d->maxiter;
+  c.kind = d->kind;
+  c.smooth = d->smooth;
+  c.coarse_iters = d->coarse_iters;
+  c.inner_tol = d->inner_tol > 0 ? d->inner_tol : 1e-5;
+  c.net = (Net*)d->net;
+  MGM_CHECK(c.kind != MGM_SOLVE_NET || c.net != nullptr, MGM_ERR_INVALID_ARG, "NET solve needs a network");
+  return c;
+}
+
+mgm_status mgm_solve(mgm_hierarchy h, int32_t level, const mgm_solve_desc* desc, const void* b, void* x,
+                     int32_t nrhs, mgm_solve_stats* stats) {
+  mgm_status st = MGM_OK;
+  try {
+    check_level(h, level, nrhs, false);
+    MGM_CHECK(b && x && b != x, MGM_ERR_INVALID_ARG, "bad vectors");
+    SolveCfg cfg = cfg_of(desc);
+    SolveOut out;
+    auto t0 = std::chrono::steady_clock::now();
+    solve(h->h, level, cfg, (const double2*)b, (double2*)x, nrhs, &out);
+    double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) {
+      stats->iterations = out.iterations;
+      stats->restarts = out.restarts;
+      stats->fallbacks = out.fallbacks;
+      stats->max_rel_residual = out.max_rel;
+      stats->seconds = dt;
+    }
+    if (!out.converged) {
+      set_last_error("solve did not reach the tolerance");
+      st = MGM_ERR_NOT_CONVERGED;
+    }
+  } catch (const mgm::Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return MGM_ERR_INVALID_ARG;
+  }
+  return st;
+}
+
+mgm_status mgm_estimate_sizes_query(mgm_hierarchy h, const mgm_estimate_desc* desc, mgm_estimate_sizes* sizes) {
+  API_BEGIN
+  MGM_CHECK(h && desc && sizes, MGM_ERR_INVALID_ARG, "NULL argument");
+  *sizes = estimate_sizes(h->h, *desc);
+  API_END
+}
+
+mgm_status mgm_estimate(mgm_hierarchy h, const mgm_estimate_desc* desc, mgm_estimate_result* out) {
+  API_BEGIN
+  MGM_CHECK(h && desc && out, MGM_ERR_INVALID_ARG, "NULL argument");
+  cfg_of(&desc->solve);
+  auto t0 = std::chrono::steady_clock::now();
+  estimate(h->h, *desc, out);
+  out->stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  API_END
+}
+
+mgm_status mgm_mlmc_allocate(int32_t nterms, const double* var, const double* cost, double eps2, int64_t* n_out) {
+  API_BEGIN
+  MGM_CHECK(nterms >= 1 && var && cost && n_out && eps2 > 0, MGM_ERR_INVALID_ARG, "bad arguments");
+  double s = 0;
+  for (int i = 0; i < nterms; i++) {
+    MGM_CHECK(var[i] >= 0 && cost[i] > 0, MGM_ERR_INVALID_ARG, "variances >= 0 and costs > 0 required");
+    s += std::sqrt(var[i] * cost[i]);
+  }
+  for (int i = 0; i < nterms; i++) {
+    double n = std::sqrt(var[i] / cost[i]) * s / eps2;
+    int64_t k = (int64_t)std::ceil(n);
+    n_out[i] = k < 2 ? 2 : k;
+  }
+  API_END
+}
+
+mgm_status mgm_profile_enable(mgm_context ctx, int32_t on) {
+  API_BEGIN
+  MGM_CHECK(ctx, MGM_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->c.prof.on = on != 0;
+  API_END
+}
+
+mgm_status mgm_profile_reset(mgm_context ctx) {
+  API_BEGIN
+  MGM_CHECK(ctx, MGM_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->c.prof_flush();
+  for (int k = 0; k < KC_COUNT; k++) {
+    ctx->c.prof.launches[k] = 0;
+    ctx->c.prof.ms[k] = 0;
+    ctx->c.prof.bytes[k] = 0;
+  }
+  API_END
+}
+
+mgm_status mgm_profile_query(mgm_context ctx, int32_t kclass, int64_t* launches, double* ms, double* bytes) {
+  API_BEGIN
+  MGM_CHECK(ctx && kclass >= 0 && kclass < KC_COUNT, MGM_ERR_INVALID_ARG, "bad arguments");
+  ctx->c.prof_flush();
+  if (launches) *launches = ctx->c.prof.launches[kclass];
+  if (ms) *ms = ctx->c.prof.ms[kclass];
+  if (bytes) *bytes = ctx->c.prof.bytes[kclass];
+  API_END
+}
+
+void mgm_hierarchy_destroy(mgm_hierarchy h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,511 @@
+// BLAS-1 kernels over dof-major multi-RHS vectors and the small dense
+// kernels of device-resident (F)GMRES.  Reductions accumulate in FP64 and are
+// deterministic: fixed per-thread element sets, a fixed-order LDS tree per
+// block and a fixed-order sum over block partials in a second kernel.
+#include "blas.h"
+
+namespace mgm {
+
+#define DISPATCH_PREC(pr, TAG, ...)                                     \
+  switch (pr) {                                                         \
+    case MGM_PREC_F64: { using TAG = F64; __VA_ARGS__; } break;         \
+    case MGM_PREC_F32: { using TAG = F32; __VA_ARGS__; } break;         \
+    case MGM_PREC_F16: { using TAG = F16; __VA_ARGS__; } break;         \
+    default: throw Error(MGM_ERR_INVALID_ARG, "unsupported vector precision"); \
+  }
+
+template <class P>
+__device__ __forceinline__ cx<double> ldd(const void* p, int64_t i) {
+  cx<typename P::R> v = P::ld((const typename P::S*)p, i);
+  return {(double)v.re, (double)v.im};
+}
+template <class P>
+__device__ __forceinline__ void std_(void* p, int64_t i, cx<double> v) {
+  P::st((typename P::S*)p, i, cx<typename P::R>{(typename P::R)v.re, (typename P::R)v.im});
+}
+
+static inline unsigned ew_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 65536 * 4 ? b : 65536 * 4);
+}
+
+// ------------------------------------------------------------ elementwise
+
+__global__ void k_zero_bytes(uint4* p, int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0, 0, 0, 0);
+}
+
+void b_zero(Context* c, Vec x) {
+  size_t b = x.bytes();
+  if (b == 0) return;
+  // all vectors are carved with 256-byte granularity, so rounding up is safe
+  int64_t n16 = (int64_t)((b + 15) / 16);
+  hipLaunchKernelGGL(k_zero_bytes, dim3(ew_blocks(n16)), dim3(256), 0, c->stream, (uint4*)x.p, n16);
+  MGM_LAUNCH_CHECK();
+}
+
+template <class Pd, class Ps>
+__global__ void k_copy(void* d, const void* s, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    std_<Pd>(d, i, ldd<Ps>(s, i));
+}
+
+void b_copy(Context* c, Vec dst, Vec src) {
+  int64_t n = src.n();
+  MGM_CHECK(dst.n() == n, MGM_ERR_INVALID_ARG, "copy: shape mismatch");
+  if (n == 0) return;
+  DISPATCH_PREC(dst.prec, PD, DISPATCH_PREC(src.prec, PS,
+      hipLaunchKernelGGL((k_copy<PD, PS>), dim3(ew_blocks(n)), dim3(256), 0, c->stream, dst.p, src.p, n)));
+  MGM_LAUNCH_CHECK();
+}
+
+template <class P>
+__global__ void k_axpy(const double2* a, double sgn, const void* x, void* y, int64_t n, int nrhs) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int r = (int)(i % nrhs);
+    cx<double> al = a ? cx<double>{a[r].x, a[r].y} : cx<double>{1.0, 0.0};
+    al = sgn * al;
+    cx<double> yv = ldd<P>(y, i);
+    fma_(yv, al, ldd<P>(x, i));
+    std_<P>(y, i, yv);
+  }
+}
+void b_axpy(Context* c, const double2* a, double sgn, Vec x, Vec y) {
+  int64_t n = x.n();
+  MGM_CHECK(y.n() == n && x.prec == y.prec, MGM_ERR_INVALID_ARG, "axpy: mismatch");
+  if (n == 0) return;
+  DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_axpy<P>, dim3(ew_blocks(n)), dim3(256), 0, c->stream,
+                                              a, sgn, x.p, y.p, n, x.nrhs));
+  MGM_LAUNCH_CHECK();
+}
+
+template <class P>
+__global__ void k_xpay(const void* x, const double2* a, double sgn, void* y, int64_t n, int nrhs) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int r = (int)(i % nrhs);
+    cx<double> al = a ? cx<double>{a[r].x, a[r].y} : cx<double>{1.0, 0.0};
+    al = sgn * al;
+    cx<double> v = ldd<P>(x, i);
+    fma_(v, al, ldd<P>(y, i));
+    std_<P>(y, i, v);
+  }
+}
+void b_xpay(Context* c, Vec x, const double2* a, double sgn, Vec y) {
+  int64_t n = x.n();
+  MGM_CHECK(y.n() == n && x.prec == y.prec, MGM_ERR_INVALID_ARG, "xpay: mismatch");
+  if (n == 0) return;
+  DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_xpay<P>, dim3(ew_blocks(n)), dim3(256), 0, c->stream,
+                                              x.p, a, sgn, y.p, n, x.nrhs));
+  MGM_LAUNCH_CHECK();
+}
+
+template <class P>
+__global__ void k_scal(void* x, double s, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    std_<P>(x, i, s * ldd<P>(x, i));
+}
+void b_scal(Context* c, Vec x, double s) {
+  int64_t n = x.n();
+  if (n == 0) return;
+  DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_scal<P>, dim3(ew_blocks(n)), dim3(256), 0, c->stream, x.p, s, n));
+  MGM_LAUNCH_CHECK();
+}
+
+template <class P>
+__global__ void k_normalize(void* x, const double* n2, double* beta, int64_t n, int nrhs) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int r = (int)(i % nrhs);
+    double b = sqrt(n2[r]);
+    double s = b > 0.0 ? 1.0 / b : 0.0;
+    std_<P>(x, i, s * ldd<P>(x, i));
+    if (beta && i < nrhs) beta[r] = b;
+  }
+}
+void b_normalize(Context* c, Vec x, const double* n2, double* beta) {
+  int64_t n = x.n();
+  if (n == 0) return;
+  DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_normalize<P>, dim3(ew_blocks(n)), dim3(256), 0, c->stream,
+                                              x.p, n2, beta, n, x.nrhs));
+  MGM_LAUNCH_CHECK();
+}
+
+template <class P>
+__global__ void k_scale_rhs(void* x, const double* m, int64_t n, int nrhs) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    std_<P>(x, i, m[i % nrhs] * ldd<P>(x, i));
+}
+void b_scale_rhs(Context* c, Vec x, const double* m) {
+  int64_t n = x.n();
+  if (n == 0) return;
+  DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_scale_rhs<P>, dim3(ew_blocks(n)), dim3(256), 0, c->stream,
+                                              x.p, m, n, x.nrhs));
+  MGM_LAUNCH_CHECK();
+}
+
+template <class P>
+__global__ void k_mr_update(const double2* qr, const double* qq, void* rho, const void* q, void* y, int64_t n,
+                            int nrhs) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int r = (int)(i % nrhs);
+    double d = qq[r];
+    cx<double> al = d > 0.0 ? cx<double>{qr[r].x / d, qr[r].y / d} : cx<double>{0.0, 0.0};
+    cx<double> rv = ldd<P>(rho, i);
+    cx<double> yv = ldd<P>(y, i);
+    fma_(yv, al, rv);
+    cx<double> qv = ldd<P>(q, i);
+    rv = rv - al * qv;
+    std_<P>(y, i, yv);
+    std_<P>(rho, i, rv);
+  }
+}
+void b_mr_update(Context* c, const double2* qr, const double* qq, Vec rho, Vec q, Vec y) {
+  int64_t n = rho.n();
+  if (n == 0) return;
+  DISPATCH_PREC(rho.prec, P, hipLaunchKernelGGL(k_mr_update<P>, dim3(ew_blocks(n)), dim3(256), 0, c->stream,
+                                                qr, qq, rho.p, q.p, y.p, n, rho.nrhs));
+  MGM_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------- reductions
+
+struct RedPlan {
+  unsigned blocks;
+  int64_t J;   // threads per rhs
+  int64_t m;   // elements per rhs (n / nrhs)
+};
+static RedPlan red_plan(int64_t n, int nrhs) {
+  RedPlan p;
+  int64_t want = (n + 255) / 256;
+  if (want > kRedBlocksMax) want = kRedBlocksMax;
+  if (want < 1) want = 1;
+  // at least one full set of rhs lanes
+  while (want * 256 < nrhs) want++;
+  p.blocks = (unsigned)want;
+  p.J = (int64_t)want * 256 / nrhs;
+  p.m = n / nrhs;
+  return p;
+}
+
+// Block reduction of K complex values per thread into partial[blk][K][nrhs].
+template <int K>
+__device__ __forceinline__ void block_store(double2 (&v)[K], double2* partial, int nrhs) {
+  __shared__ double2 sh[256];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x;
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    sh[t] = v[k];
+    __syncthreads();
+    if (t < nrhs) {
+      int t0 = (int)(((t - base % nrhs) % nrhs + nrhs) % nrhs);
+      double sr = 0, si = 0;
+      for (int u = t0; u < (int)blockDim.x; u += nrhs) {
+        sr += sh[u].x;
+        si += sh[u].y;
+      }
+      partial[((int64_t)blockIdx.x * K + k) * nrhs + t] = make_double2(sr, si);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_finalize_c(const double2* partial, int nblk, int K, int nrhs, int cnt, double2* out,
+                             int64_t out_off) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  double sr = 0, si = 0;
+  for (int b = 0; b < nblk; b++) {
+    double2 v = partial[(int64_t)b * K * nrhs + i];
+    sr += v.x;
+    si += v.y;
+  }
+  out[out_off + i] = make_double2(sr, si);
+}
+__global__ void k_finalize_r(const double2* partial, int nblk, int K, int nrhs, double* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K * nrhs) return;
+  double s = 0;
+  for (int b = 0; b < nblk; b++) s += partial[(int64_t)b * K * nrhs + i].x;
+  out[i] = s;
+}
+// q^H rho and |q|^2 -> separate outputs
+__global__ void k_finalize_dn(const double2* partial, int nblk, int nrhs, double2* qr, double* qq) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrhs) return;
+  double a = 0, b = 0, d = 0;
+  for (int k = 0; k < nblk; k++) {
+    double2 v = partial[(int64_t)k * 2 * nrhs + i];
+    a += v.x;
+    b += v.y;
+    d += partial[(int64_t)k * 2 * nrhs + nrhs + i].x;
+  }
+  qr[i] = make_double2(a, b);
+  qq[i] = d;
+}
+
+static void need(Scratch& s, size_t entries) {
+  MGM_CHECK(s.partial != nullptr && entries <= s.cap, MGM_ERR_WORKSPACE, "reduction scratch too small");
+}
+
+template <class P>
+__global__ void k_dot(const void* x, const void* y, int nrhs, RedPlan pl, double2* partial) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 v[1] = {make_double2(0, 0)};
+  if (g < pl.J * nrhs) {
+    int r = (int)(g % nrhs);
+    int64_t j = g / nrhs;
+    cx<double> a = {0, 0};
+    for (int64_t m = j; m < pl.m; m += pl.J) {
+      int64_t e = m * nrhs + r;
+      fmac_(a, ldd<P>(x, e), ldd<P>(y, e));
+    }
+    v[0] = make_double2(a.re, a.im);
+  }
+  block_store<1>(v, partial, nrhs);
+}
+void b_dot(Context* c, Scratch& s, Vec x, Vec y, double2* out) {
+  RedPlan pl = red_plan(x.n(), x.nrhs);
+  need(s, (size_t)pl.blocks * x.nrhs);
+  DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_dot<P>, dim3(pl.blocks), dim3(256), 0, c->stream, x.p, y.p,
+                                              x.nrhs, pl, s.partial));
+  hipLaunchKernelGGL(k_finalize_c, dim3(nblocks_for(x.nrhs, 64)), dim3(64), 0, c->stream, s.partial,
+                     (int)pl.blocks, 1, x.nrhs, x.nrhs, out, (int64_t)0);
+  MGM_LAUNCH_CHECK();
+}
+
+template <class P>
+__global__ void k_norm2(const void* x, int nrhs, RedPlan pl, double2* partial) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 v[1] = {make_double2(0, 0)};
+  if (g < pl.J * nrhs) {
+    int r = (int)(g % nrhs);
+    int64_t j = g / nrhs;
+    double a = 0;
+    for (int64_t m = j; m < pl.m; m += pl.J) a += norm2(ldd<P>(x, m * nrhs + r));
+    v[0] = make_double2(a, 0);
+  }
+  block_store<1>(v, partial, nrhs);
+}
+void b_norm2(Context* c, Scratch& s, Vec x, double* out) {
+  RedPlan pl = red_plan(x.n(), x.nrhs);
+  need(s, (size_t)pl.blocks * x.nrhs);
+  DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_norm2<P>, dim3(pl.blocks), dim3(256), 0, c->stream, x.p,
+                                              x.nrhs, pl, s.partial));
+  hipLaunchKernelGGL(k_finalize_r, dim3(nblocks_for(x.nrhs, 64)), dim3(64), 0, c->stream, s.partial,
+                     (int)pl.blocks, 1, x.nrhs, out);
+  MGM_LAUNCH_CHECK();
+}
+
+template <class P>
+__global__ void k_dot_norm(const void* q, const void* rho, int nrhs, RedPlan pl, double2* partial) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 v[2] = {make_double2(0, 0), make_double2(0, 0)};
+  if (g < pl.J * nrhs) {
+    int r = (int)(g % nrhs);
+    int64_t j = g / nrhs;
+    cx<double> a = {0, 0};
+    double d = 0;
+    for (int64_t m = j; m < pl.m; m += pl.J) {
+      int64_t e = m * nrhs + r;
+      cx<double> qv = ldd<P>(q, e);
+      fmac_(a, qv, ldd<P>(rho, e));
+      d += norm2(qv);
+    }
+    v[0] = make_double2(a.re, a.im);
+    v[1] = make_double2(d, 0);
+  }
+  block_store<2>(v, partial, nrhs);
+}
+void b_dot_norm(Context* c, Scratch& s, Vec q, Vec rho, double2* qr, double* qq) {
+  RedPlan pl = red_plan(q.n(), q.nrhs);
+  need(s, (size_t)pl.blocks * 2 * q.nrhs);
+  DISPATCH_PREC(q.prec, P, hipLaunchKernelGGL(k_dot_norm<P>, dim3(pl.blocks), dim3(256), 0, c->stream, q.p,
+                                              rho.p, q.nrhs, pl, s.partial));
+  hipLaunchKernelGGL(k_finalize_dn, dim3(nblocks_for(q.nrhs, 64)), dim3(64), 0, c->stream, s.partial,
+                     (int)pl.blocks, q.nrhs, qr, qq);
+  MGM_LAUNCH_CHECK();
+}
+
+template <class P, int KB>
+__global__ void k_multidot(const void* base, int64_t stride, int k, const void* w, int nrhs, RedPlan pl,
+                           double2* partial) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 v[KB];
+#pragma unroll
+  for (int i = 0; i < KB; i++) v[i] = make_double2(0, 0);
+  if (g < pl.J * nrhs) {
+    int r = (int)(g % nrhs);
+    int64_t j = g / nrhs;
+    cx<double> a[KB];
+#pragma unroll
+    for (int i = 0; i < KB; i++) a[i] = {0, 0};
+    const typename P::S* B = (const typename P::S*)base;
+    for (int64_t m = j; m < pl.m; m += pl.J) {
+      int64_t e = m * nrhs + r;
+      cx<double> wv = ldd<P>(w, e);
+#pragma unroll
+      for (int i = 0; i < KB; i++)
+        if (i < k) fmac_(a[i], ldd<P>(B + i * stride, e), wv);
+    }
+#pragma unroll
+    for (int i = 0; i < KB; i++) v[i] = make_double2(a[i].re, a[i].im);
+  }
+  block_store<KB>(v, partial, nrhs);
+}
+void b_multidot(Context* c, Scratch& s, Vec base, int64_t stride, int k, Vec w, double2* out) {
+  RedPlan pl = red_plan(w.n(), w.nrhs);
+  const int KB = 8;
+  need(s, (size_t)pl.blocks * KB * w.nrhs);
+  for (int i0 = 0; i0 < k; i0 += KB) {
+    int kk = k - i0 < KB ? k - i0 : KB;
+    DISPATCH_PREC(w.prec, P, {
+      const typename P::S* b0 = (const typename P::S*)base.p + i0 * stride;
+      hipLaunchKernelGGL((k_multidot<P, 8>), dim3(pl.blocks), dim3(256), 0, c->stream, (const void*)b0, stride,
+                         kk, w.p, w.nrhs, pl, s.partial);
+    });
+    hipLaunchKernelGGL(k_finalize_c, dim3(nblocks_for(kk * w.nrhs, 64)), dim3(64), 0, c->stream, s.partial,
+                       (int)pl.blocks, KB, w.nrhs, kk * w.nrhs, out, (int64_t)i0 * w.nrhs);
+    MGM_LAUNCH_CHECK();
+  }
+}
+
+template <class P>
+__global__ void k_multiaxpy(const void* base, int64_t stride, int k, const double2* h, double sgn, void* w,
+                            int nrhs, RedPlan pl, double2* partial, int want_norm) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 v[1] = {make_double2(0, 0)};
+  if (g < pl.J * nrhs) {
+    int r = (int)(g % nrhs);
+    int64_t j = g / nrhs;
+    const typename P::S* B = (const typename P::S*)base;
+    double nn = 0;
+    for (int64_t m = j; m < pl.m; m += pl.J) {
+      int64_t e = m * nrhs + r;
+      cx<double> wv = ldd<P>(w, e);
+      for (int i = 0; i < k; i++) {
+        double2 hh = h[(int64_t)i * nrhs + r];
+        cx<double> hc = {sgn * hh.x, sgn * hh.y};
+        fma_(wv, hc, ldd<P>(B + i * stride, e));
+      }
+      std_<P>(w, e, wv);
+      if (want_norm) {
+        cx<double> st = ldd<P>(w, e);  // norm of the stored (rounded) value
+        nn += norm2(st);
+      }
+    }
+    v[0] = make_double2(nn, 0);
+  }
+  if (want_norm) block_store<1>(v, partial, nrhs);
+}
+void b_multiaxpy(Context* c, Scratch& s, Vec base, int64_t stride, int k, const double2* h, double sgn, Vec w,
+                 double* n2) {
+  RedPlan pl = red_plan(w.n(), w.nrhs);
+  need(s, (size_t)pl.blocks * w.nrhs);
+  DISPATCH_PREC(w.prec, P, hipLaunchKernelGGL(k_multiaxpy<P>, dim3(pl.blocks), dim3(256), 0, c->stream,
+                                              (const void*)base.p, stride, k, h, sgn, w.p, w.nrhs, pl,
+                                              s.partial, n2 ? 1 : 0));
+  if (n2)
+    hipLaunchKernelGGL(k_finalize_r, dim3(nblocks_for(w.nrhs, 64)), dim3(64), 0, c->stream, s.partial,
+                       (int)pl.blocks, 1, w.nrhs, n2);
+  MGM_LAUNCH_CHECK();
+}
+
+// ----------------------------------------------------------- GMRES small
+
+__global__ void kk_gmres_start(Givens G, const double* r2, int nrhs) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double b = sqrt(r2[r]);
+  G.g[r] = make_double2(b, 0.0);
+  for (int j = 1; j <= G.m; j++) G.g[(int64_t)j * nrhs + r] = make_double2(0, 0);
+  G.est[r] = b;
+}
+void k_gmres_start(Context* c, Givens& G, const double* r2, int nrhs) {
+  hipLaunchKernelGGL(kk_gmres_start, dim3(nblocks_for(nrhs, 64)), dim3(64), 0, c->stream, G, r2, nrhs);
+  MGM_LAUNCH_CHECK();
+}
+
+// Complex Givens rotation with real cosine: for the pair (x, y),
+// x' = c x + conj(s) y, y' = -s x + c y.  Chosen to zero y for (a, b):
+// c = |a| / rho, s = b conj(a) / (|a| rho), rho = sqrt(|a|^2 + |b|^2).
+__global__ void kk_gmres_column(Givens G, int j, const double* w2, int nrhs) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const int m = G.m;
+  cx<double> hcol[64];
+  for (int i = 0; i <= j; i++) {
+    double2 a = G.h[(int64_t)i * nrhs + r], b = G.h2[(int64_t)i * nrhs + r];
+    hcol[i] = {a.x + b.x, a.y + b.y};
+  }
+  double beta = sqrt(w2[r]);
+  G.beta[r] = beta;
+  for (int i = 0; i < j; i++) {
+    double cc = G.cs[(int64_t)i * nrhs + r];
+    double2 s2 = G.sn[(int64_t)i * nrhs + r];
+    cx<double> s = {s2.x, s2.y};
+    cx<double> x = hcol[i], y = hcol[i + 1];
+    hcol[i] = cc * x + cmulc(s, y);
+    hcol[i + 1] = cc * y - s * x;
+  }
+  cx<double> a = hcol[j];
+  double aa = sqrt(norm2(a));
+  double rho = sqrt(aa * aa + beta * beta);
+  double cc;
+  cx<double> s, rjj;
+  if (rho == 0.0) {
+    cc = 1.0;
+    s = {0, 0};
+    rjj = {0, 0};
+  } else if (aa == 0.0) {
+    cc = 0.0;
+    s = {1.0, 0.0};
+    rjj = {beta, 0.0};
+  } else {
+    cc = aa / rho;
+    s = (beta / (aa * rho)) * conj(a);
+    rjj = (rho / aa) * a;
+  }
+  hcol[j] = rjj;
+  G.cs[(int64_t)j * nrhs + r] = cc;
+  G.sn[(int64_t)j * nrhs + r] = make_double2(s.re, s.im);
+  for (int i = 0; i <= j; i++) G.R[((int64_t)j * m + i) * nrhs + r] = make_double2(hcol[i].re, hcol[i].im);
+  double2 gj2 = G.g[(int64_t)j * nrhs + r];
+  cx<double> gj = {gj2.x, gj2.y};
+  cx<double> g1 = (-1.0) * (s * gj);
+  gj = cc * gj;
+  G.g[(int64_t)j * nrhs + r] = make_double2(gj.re, gj.im);
+  G.g[(int64_t)(j + 1) * nrhs + r] = make_double2(g1.re, g1.im);
+  G.est[r] = sqrt(norm2(g1));
+}
+void k_gmres_column(Context* c, Givens& G, int j, const double* w2, int nrhs) {
+  MGM_CHECK(G.m <= 63, MGM_ERR_INVALID_ARG, "restart too long");
+  hipLaunchKernelGGL(kk_gmres_column, dim3(nblocks_for(nrhs, 64)), dim3(64), 0, c->stream, G, j, w2, nrhs);
+  MGM_LAUNCH_CHECK();
+}
+
+__global__ void kk_gmres_solve(Givens G, int k, int nrhs) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const int m = G.m;
+  for (int i = k - 1; i >= 0; i--) {
+    double2 gi = G.g[(int64_t)i * nrhs + r];
+    cx<double> acc = {gi.x, gi.y};
+    for (int jj = i + 1; jj < k; jj++) {
+      double2 Rij = G.R[((int64_t)jj * m + i) * nrhs + r];
+      double2 yj = G.y[(int64_t)jj * nrhs + r];
+      acc = acc - cx<double>{Rij.x, Rij.y} * cx<double>{yj.x, yj.y};
+    }
+    double2 Rii = G.R[((int64_t)i * m + i) * nrhs + r];
+    double d = Rii.x * Rii.x + Rii.y * Rii.y;
+    cx<double> yi = {0, 0};
+    if (d > 0.0) yi = (1.0 / d) * cmulc(cx<double>{Rii.x, Rii.y}, acc);  // acc / Rii
+    G.y[(int64_t)i * nrhs + r] = make_double2(yi.re, yi.im);
+  }
+}
+void k_gmres_solve(Context* c, Givens& G, int k, int nrhs) {
+  hipLaunchKernelGGL(kk_gmres_solve, dim3(nblocks_for(nrhs, 64)), dim3(64), 0, c->stream, G, k, nrhs);
+  MGM_LAUNCH_CHECK();
+}
+
+}  // namespace mgm

@@ -1,0 +1,408 @@
+// Wilson-clover operator on gfx950: clover construction and the fine dslash.
+//
+// Operator (the paper needs only a Gamma5-hermitian discretised Dirac
+// operator with 4 spin x 3 colour dof per site, Sec. 1 and Sec. 2.1):
+//   (D psi)(x) = (4 + m0) psi(x)
+//     - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^H psi(x-mu)]
+//     + csw (i/4) sum_{mu != nu} sigma_mu_nu F_mu_nu(x) psi(x)
+// Chiral basis: g_mu = [[0, A_mu], [A_mu^H, 0]] with A_x = -i s1, A_y = -i s2,
+// A_z = -i s3, A_t = 1, so (1 -/+ g_mu) psi is fixed by the half spinor
+// h = u -/+ A_mu l (u, l: upper / lower spin pairs):
+//   (1 - g) psi = (h, -A^H h),   (1 + g) psi = (h, A^H h).
+// The dslash is HBM-bound: one thread per (site, rhs), every field stored
+// component-major so each wave's loads are contiguous; the rhs index is the
+// fastest so lanes of one site share (broadcast) its links and clover.
+#include "fine.h"
+#include "fine_dev.h"
+
+namespace mgm {
+
+// ------------------------------------------------------------ sigma table
+
+// sigma_mu_nu = (i/2)[g_mu, g_nu] restricted to chirality chi (2 x 2), for
+// the six planes mu < nu.  Upper block (i/2)(A_mu A_nu^H - A_nu A_mu^H),
+// lower block (i/2)(A_mu^H A_nu - A_nu^H A_mu).
+__constant__ double2 c_sigma[6][2][2][2];
+
+static void host_sigma(double out[6][2][2][2][2]) {
+  typedef double C[2];
+  auto mul = [](const C* a, const C* b, C* o) {  // 2x2 complex a*b, row major
+    for (int i = 0; i < 2; i++)
+      for (int j = 0; j < 2; j++) {
+        double re = 0, im = 0;
+        for (int k = 0; k < 2; k++) {
+          re += a[2 * i + k][0] * b[2 * k + j][0] - a[2 * i + k][1] * b[2 * k + j][1];
+          im += a[2 * i + k][0] * b[2 * k + j][1] + a[2 * i + k][1] * b[2 * k + j][0];
+        }
+        o[2 * i + j][0] = re;
+        o[2 * i + j][1] = im;
+      }
+  };
+  auto dag = [](const C* a, C* o) {
+    for (int i = 0; i < 2; i++)
+      for (int j = 0; j < 2; j++) {
+        o[2 * i + j][0] = a[2 * j + i][0];
+        o[2 * i + j][1] = -a[2 * j + i][1];
+      }
+  };
+  C A[4][4] = {
+      {{0, 0}, {0, -1}, {0, -1}, {0, 0}},  // -i s1
+      {{0, 0}, {-1, 0}, {1, 0}, {0, 0}},   // -i s2
+      {{0, -1}, {0, 0}, {0, 0}, {0, 1}},   // -i s3
+      {{1, 0}, {0, 0}, {0, 0}, {1, 0}},    // 1
+  };
+  int p = 0;
+  for (int mu = 0; mu < 4; mu++)
+    for (int nu = mu + 1; nu < 4; nu++, p++) {
+      C Am_d[4], An_d[4], t1[4], t2[4];
+      dag(A[mu], Am_d);
+      dag(A[nu], An_d);
+      for (int chi = 0; chi < 2; chi++) {
+        if (chi == 0) {
+          mul(A[mu], An_d, t1);
+          mul(A[nu], Am_d, t2);
+        } else {
+          mul(Am_d, A[nu], t1);
+          mul(An_d, A[mu], t2);
+        }
+        for (int i = 0; i < 2; i++)
+          for (int j = 0; j < 2; j++) {
+            double dre = t1[2 * i + j][0] - t2[2 * i + j][0];
+            double dim = t1[2 * i + j][1] - t2[2 * i + j][1];
+            // (i/2) * d
+            out[p][chi][i][j][0] = -0.5 * dim;
+            out[p][chi][i][j][1] = 0.5 * dre;
+          }
+      }
+    }
+}
+
+// ------------------------------------------------------------- 3x3 helpers
+
+struct M3 {
+  cx<double> a[3][3];
+};
+
+__device__ __forceinline__ M3 ldU(const double2* U, int64_t V, int mu, int64_t s) {
+  M3 m;
+#pragma unroll
+  for (int k = 0; k < 9; k++) {
+    double2 v = U[(int64_t)(mu * 9 + k) * V + s];
+    m.a[k / 3][k % 3] = {v.x, v.y};
+  }
+  return m;
+}
+__device__ __forceinline__ M3 mm(const M3& a, const M3& b) {
+  M3 c;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      cx<double> s = {0, 0};
+#pragma unroll
+      for (int k = 0; k < 3; k++) fma_(s, a.a[i][k], b.a[k][j]);
+      c.a[i][j] = s;
+    }
+  return c;
+}
+__device__ __forceinline__ M3 dg(const M3& a) {
+  M3 c;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) c.a[i][j] = conj(a.a[j][i]);
+  return c;
+}
+
+__device__ __forceinline__ int64_t site_at(const Geom& g, int x, int y, int z, int t) {
+  x = (x + g.X) % g.X;
+  y = (y + g.Y) % g.Y;
+  z = (z + g.Z) % g.Z;
+  t = (t + g.T) % g.T;
+  return x + (int64_t)g.X * (y + (int64_t)g.Y * (z + (int64_t)g.Z * t));
+}
+
+// --------------------------------------------------------------- clover
+
+// One thread per site: F_mu_nu from the four plaquette leaves (all oriented
+// mu then nu), F = (Q - Q^H)/8; block chi = (4+m0) 1 + csw (i/2) sum_{mu<nu}
+// sigma^chi_mu_nu (x) F_mu_nu (the sum over mu != nu counts each plane twice).
+__global__ void k_clover(double* __restrict__ C, const double2* __restrict__ U, Geom g, double m0,
+                         double csw) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  int c[4];
+  {
+    int64_t q = s;
+    c[0] = q % g.X; q /= g.X;
+    c[1] = q % g.Y; q /= g.Y;
+    c[2] = q % g.Z; q /= g.Z;
+    c[3] = (int)q;
+  }
+  cx<double> blk[2][6][6];
+  for (int chi = 0; chi < 2; chi++)
+    for (int i = 0; i < 6; i++)
+      for (int j = 0; j < 6; j++) blk[chi][i][j] = {i == j ? 4.0 + m0 : 0.0, 0.0};
+  int p = 0;
+  for (int mu = 0; mu < 4; mu++)
+    for (int nu = mu + 1; nu < 4; nu++, p++) {
+      auto at = [&](int dm, int dn) {
+        int cc[4] = {c[0], c[1], c[2], c[3]};
+        cc[mu] += dm;
+        cc[nu] += dn;
+        return site_at(g, cc[0], cc[1], cc[2], cc[3]);
+      };
+      int64_t x0 = s;
+      M3 Um = ldU(U, g.V, mu, x0), Un = ldU(U, g.V, nu, x0);
+      // leaf 1: x -> x+mu -> x+mu+nu -> x+nu -> x
+      M3 l1 = mm(mm(Um, ldU(U, g.V, nu, at(1, 0))), mm(dg(ldU(U, g.V, mu, at(0, 1))), dg(Un)));
+      // leaf 2: x -> x+nu -> x+nu-mu -> x-mu -> x
+      M3 l2 = mm(mm(Un, dg(ldU(U, g.V, mu, at(-1, 1)))),
+                 mm(dg(ldU(U, g.V, nu, at(-1, 0))), ldU(U, g.V, mu, at(-1, 0))));
+      // leaf 3: x -> x-mu -> x-mu-nu -> x-nu -> x
+      M3 l3 = mm(mm(dg(ldU(U, g.V, mu, at(-1, 0))), dg(ldU(U, g.V, nu, at(-1, -1)))),
+                 mm(ldU(U, g.V, mu, at(-1, -1)), ldU(U, g.V, nu, at(0, -1))));
+      // leaf 4: x -> x-nu -> x-nu+mu -> x+mu -> x
+      M3 l4 = mm(mm(dg(ldU(U, g.V, nu, at(0, -1))), ldU(U, g.V, mu, at(0, -1))),
+                 mm(ldU(U, g.V, nu, at(1, -1)), dg(Um)));
+      M3 F;
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+          cx<double> q = l1.a[i][j] + l2.a[i][j] + l3.a[i][j] + l4.a[i][j];
+          cx<double> qd = conj(l1.a[j][i] + l2.a[j][i] + l3.a[j][i] + l4.a[j][i]);
+          F.a[i][j] = 0.125 * (q - qd);
+        }
+      for (int chi = 0; chi < 2; chi++)
+        for (int sa = 0; sa < 2; sa++)
+          for (int sb = 0; sb < 2; sb++) {
+            double2 sg = c_sigma[p][chi][sa][sb];
+            // csw * (i/2) * sigma
+            cx<double> f = {-0.5 * csw * sg.y, 0.5 * csw * sg.x};
+            for (int a = 0; a < 3; a++)
+              for (int b = 0; b < 3; b++) fma_(blk[chi][sa * 3 + a][sb * 3 + b], f, F.a[a][b]);
+          }
+    }
+  for (int chi = 0; chi < 2; chi++) {
+    double* o = C + (int64_t)(36 * chi) * g.V + s;
+    for (int i = 0; i < 6; i++) o[(int64_t)i * g.V] = blk[chi][i][i].re;
+    int q = 0;
+    for (int i = 1; i < 6; i++)
+      for (int j = 0; j < i; j++, q++) {
+        o[(int64_t)(6 + 2 * q) * g.V] = blk[chi][i][j].re;
+        o[(int64_t)(7 + 2 * q) * g.V] = blk[chi][i][j].im;
+      }
+  }
+}
+
+// ---------------------------------------------------------- conversions
+
+__global__ void k_cvt_c64_c32(float2* o, const double2* in, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+__global__ void k_cvt_c64_c16(__half2* o, const double2* in, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = __floats2half2_rn((float)in[i].x, (float)in[i].y);
+}
+__global__ void k_cvt_r64_r32(float* o, const double* in, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = (float)in[i];
+}
+__global__ void k_cvt_r64_r16(__half* o, const double* in, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = __float2half_rn((float)in[i]);
+}
+
+// ---------------------------------------------------------------- dslash
+
+template <class P>
+__global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
+                                                const typename P::S* __restrict__ in,
+                                                const typename P::S* __restrict__ U,
+                                                const typename P::RS* __restrict__ C, Geom g,
+                                                int nrhs, int64_t nblocks) {
+  using R = typename P::R;
+  const int64_t blk = xcd_block(blockIdx.x, nblocks);
+  const int64_t tid = blk * blockDim.x + threadIdx.x;
+  const int64_t V = g.V;
+  const int64_t N = V * nrhs;
+  if (tid >= N) return;
+  const int64_t s = tid / nrhs;
+  const int r = (int)(tid - s * nrhs);
+  int c[4];
+  {
+    int64_t q = s;
+    c[0] = (int)(q % g.X); q /= g.X;
+    c[1] = (int)(q % g.Y); q /= g.Y;
+    c[2] = (int)(q % g.Z); q /= g.Z;
+    c[3] = (int)q;
+  }
+  const int64_t stride[4] = {1, g.X, (int64_t)g.X * g.Y, (int64_t)g.X * g.Y * g.Z};
+  const int ext[4] = {g.X, g.Y, g.Z, g.T};
+
+  cx<R> acc[12];
+  {
+    cx<R> p[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) p[k] = P::ld(in, (int64_t)k * N + tid);
+    clover_block<P>(C, V, s, 0, p, acc);
+    clover_block<P>(C, V, s, 1, p + 6, acc + 6);
+  }
+  const R mhalf = (R)-0.5;
+#pragma unroll
+  for (int mu = 0; mu < 4; mu++) {
+    // forward hop: -1/2 (1 - g_mu) U_mu(x) psi(x + mu)
+    {
+      const bool wrap = (c[mu] == ext[mu] - 1);
+      const int64_t sn = wrap ? s - (int64_t)(ext[mu] - 1) * stride[mu] : s + stride[mu];
+      const R ph = (mu == 3 && wrap && g.antiperiodic) ? (R)-1 : (R)1;
+      const int64_t e = sn * nrhs + r;
+      cx<R> h[2][3];
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        cx<R> u0 = P::ld(in, (int64_t)(0 * 3 + a) * N + e), u1 = P::ld(in, (int64_t)(1 * 3 + a) * N + e);
+        cx<R> l0 = P::ld(in, (int64_t)(2 * 3 + a) * N + e), l1 = P::ld(in, (int64_t)(3 * 3 + a) * N + e);
+        cx<R> a0, a1;
+        A_times(mu, l0, l1, a0, a1);
+        h[0][a] = u0 - a0;
+        h[1][a] = u1 - a1;
+      }
+      cx<R> Um[3][3];
+#pragma unroll
+      for (int k = 0; k < 9; k++) Um[k / 3][k % 3] = P::ld(U, (int64_t)(mu * 9 + k) * V + s);
+      const R f = mhalf * ph;
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        cx<R> g0 = {0, 0}, g1 = {0, 0};
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+          fma_(g0, Um[a][b], h[0][b]);
+          fma_(g1, Um[a][b], h[1][b]);
+        }
+        g0 = f * g0;
+        g1 = f * g1;
+        cx<R> d0, d1;
+        Ad_times(mu, g0, g1, d0, d1);
+        acc[0 * 3 + a] = acc[0 * 3 + a] + g0;
+        acc[1 * 3 + a] = acc[1 * 3 + a] + g1;
+        acc[2 * 3 + a] = acc[2 * 3 + a] - d0;
+        acc[3 * 3 + a] = acc[3 * 3 + a] - d1;
+      }
+    }
+    // backward hop: -1/2 (1 + g_mu) U_mu(x - mu)^H psi(x - mu)
+    {
+      const bool wrap = (c[mu] == 0);
+      const int64_t sn = wrap ? s + (int64_t)(ext[mu] - 1) * stride[mu] : s - stride[mu];
+      const R ph = (mu == 3 && wrap && g.antiperiodic) ? (R)-1 : (R)1;
+      const int64_t e = sn * nrhs + r;
+      cx<R> h[2][3];
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        cx<R> u0 = P::ld(in, (int64_t)(0 * 3 + a) * N + e), u1 = P::ld(in, (int64_t)(1 * 3 + a) * N + e);
+        cx<R> l0 = P::ld(in, (int64_t)(2 * 3 + a) * N + e), l1 = P::ld(in, (int64_t)(3 * 3 + a) * N + e);
+        cx<R> a0, a1;
+        A_times(mu, l0, l1, a0, a1);
+        h[0][a] = u0 + a0;
+        h[1][a] = u1 + a1;
+      }
+      cx<R> Um[3][3];
+#pragma unroll
+      for (int k = 0; k < 9; k++) Um[k / 3][k % 3] = P::ld(U, (int64_t)(mu * 9 + k) * V + sn);
+      const R f = mhalf * ph;
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        cx<R> g0 = {0, 0}, g1 = {0, 0};
+#pragma unroll
+        for (int b = 0; b < 3; b++) {  // U^H: (U^H)_{ab} = conj(U_{ba})
+          fmac_(g0, Um[b][a], h[0][b]);
+          fmac_(g1, Um[b][a], h[1][b]);
+        }
+        g0 = f * g0;
+        g1 = f * g1;
+        cx<R> d0, d1;
+        Ad_times(mu, g0, g1, d0, d1);
+        acc[0 * 3 + a] = acc[0 * 3 + a] + g0;
+        acc[1 * 3 + a] = acc[1 * 3 + a] + g1;
+        acc[2 * 3 + a] = acc[2 * 3 + a] + d0;
+        acc[3 * 3 + a] = acc[3 * 3 + a] + d1;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 12; k++) P::st(out, (int64_t)k * N + tid, acc[k]);
+}
+
+// ------------------------------------------------------------------ host
+
+void FineOp::layout(Arena& a, const Geom& g, FineOp* op) {
+  const int64_t V = g.V;
+  op->g = g;
+  op->U64 = a.take_n<double2>(36 * V);
+  op->U32 = a.take_n<float2>(36 * V);
+  op->U16 = a.take_n<__half2>(36 * V);
+  op->C64 = a.take_n<double>(72 * V);
+  op->C32 = a.take_n<float>(72 * V);
+  op->C16 = a.take_n<__half>(72 * V);
+}
+
+void FineOp::build(const double* gauge_host) {
+  static bool sigma_ready = false;
+  if (!sigma_ready) {
+    double sig[6][2][2][2][2];
+    host_sigma(sig);
+    MGM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_sigma), sig, sizeof(sig)));
+    sigma_ready = true;
+  }
+  const int64_t V = g.V;
+  // host [V][4][3][3] complex -> device [mu][9][V]
+  std::vector<double2> tmp((size_t)36 * V);
+  for (int64_t s = 0; s < V; s++)
+    for (int k = 0; k < 36; k++) {
+      const double* p = gauge_host + 2 * (s * 36 + k);
+      tmp[(size_t)k * V + s] = make_double2(p[0], p[1]);
+    }
+  MGM_HIP(hipMemcpyAsync(U64, tmp.data(), tmp.size() * sizeof(double2), hipMemcpyHostToDevice,
+                         ctx->stream));
+  hipLaunchKernelGGL(k_clover, dim3(nblocks_for(V, 128)), dim3(128), 0, ctx->stream, C64, U64, g, m0,
+                     csw);
+  MGM_LAUNCH_CHECK();
+  const int64_t nu = 36 * V, nc = 72 * V;
+  hipLaunchKernelGGL(k_cvt_c64_c32, dim3(nblocks_for(nu, 256)), dim3(256), 0, ctx->stream, U32, U64, nu);
+  hipLaunchKernelGGL(k_cvt_c64_c16, dim3(nblocks_for(nu, 256)), dim3(256), 0, ctx->stream, U16, U64, nu);
+  hipLaunchKernelGGL(k_cvt_r64_r32, dim3(nblocks_for(nc, 256)), dim3(256), 0, ctx->stream, C32, C64, nc);
+  hipLaunchKernelGGL(k_cvt_r64_r16, dim3(nblocks_for(nc, 256)), dim3(256), 0, ctx->stream, C16, C64, nc);
+  MGM_LAUNCH_CHECK();
+  ctx->sync();  // tmp must outlive the copy
+}
+
+double FineOp::bytes(mgm_prec p, int nrhs) const {
+  double wc = (double)prec_bytes(p), wr = wc / 2;
+  return (double)g.V * (36 * wc + 72 * wr + 24.0 * wc * nrhs);
+}
+
+void FineOp::apply(mgm_prec p, const void* x, void* y, int nrhs) const {
+  const int threads = 256;
+  const int64_t n = g.V * nrhs;
+  const int64_t nb = (n + threads - 1) / threads;
+  int kc = p == MGM_PREC_F64 ? KC_DSLASH_F64 : p == MGM_PREC_F32 ? KC_DSLASH_F32 : KC_DSLASH_F16;
+  ProfScope ps(ctx, kc, bytes(p, nrhs));
+  switch (p) {
+    case MGM_PREC_F64:
+      hipLaunchKernelGGL(k_dslash<F64>, dim3((unsigned)nb), dim3(threads), 0, ctx->stream,
+                         (double2*)y, (const double2*)x, U64, C64, g, nrhs, nb);
+      break;
+    case MGM_PREC_F32:
+      hipLaunchKernelGGL(k_dslash<F32>, dim3((unsigned)nb), dim3(threads), 0, ctx->stream,
+                         (float2*)y, (const float2*)x, U32, C32, g, nrhs, nb);
+      break;
+    case MGM_PREC_F16:
+      hipLaunchKernelGGL(k_dslash<F16>, dim3((unsigned)nb), dim3(threads), 0, ctx->stream,
+                         (__half2*)y, (const __half2*)x, U16, C16, g, nrhs, nb);
+      break;
+    default:
+      throw Error(MGM_ERR_INVALID_ARG, "dslash precision must be F64, F32 or F16");
+  }
+  MGM_LAUNCH_CHECK();
+}
+
+}  // namespace mgm

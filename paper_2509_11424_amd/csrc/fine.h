@@ -1,0 +1,35 @@
+// Fine Wilson-clover operator: fields and launchers.
+#pragma once
+#include "common.h"
+
+namespace mgm {
+
+struct Geom {
+  int X, Y, Z, T;
+  int64_t V;
+  int antiperiodic;
+};
+
+struct FineOp {
+  Context* ctx = nullptr;
+  Geom g{};
+  double m0 = 0, csw = 0;
+  // links [mu][9][V] complex, clover (+ mass) [72][V] real: two 6x6 Hermitian
+  // chirality blocks per site, each 6 diagonal reals then 15 complex lower
+  // entries C[i][j] (i > j) in row order.
+  double2* U64 = nullptr;
+  float2* U32 = nullptr;
+  __half2* U16 = nullptr;
+  double* C64 = nullptr;
+  float* C32 = nullptr;
+  __half* C16 = nullptr;
+
+  static void layout(Arena& a, const Geom& g, FineOp* op);
+  void build(const double* gauge_host);
+  // y = D x, nrhs vectors in dof-major layout of precision p
+  void apply(mgm_prec p, const void* x, void* y, int nrhs) const;
+  // algorithmic bytes of one application (fields once, spinors in and out)
+  double bytes(mgm_prec p, int nrhs) const;
+};
+
+}  // namespace mgm

@@ -1,0 +1,135 @@
+// Internal objects behind the C ABI: hierarchy, solver workspaces, estimator.
+#pragma once
+#include "blas.h"
+#include "fine.h"
+#include "mg.h"
+#include "probe.h"
+
+struct mgm_context_s {
+  mgm::Context c;
+};
+
+struct mgm_operator_s {
+  mgm::Context* ctx = nullptr;
+  mgm::FineOp op;
+  mgm_lattice_desc desc{};
+};
+
+namespace mgm {
+
+struct Net;  // learned preconditioner (net.hip)
+
+// Per level and working precision: Krylov basis and V-cycle temporaries.
+struct LevelWS {
+  mgm_prec prec = MGM_PREC_F64;
+  int nmax = 0;  // right-hand sides
+  int m = 0;     // restart length
+  void* V = nullptr;  // (m+1) vectors
+  void* Z = nullptr;  // m vectors (flexible preconditioned directions)
+  void* r = nullptr;
+  void* t = nullptr;
+  void* rho = nullptr;
+  void* q = nullptr;
+  void* y = nullptr;
+  void* bc = nullptr;  // right-hand side of this level's coarse-grid solve
+  void* xc = nullptr;  // solution of this level's coarse-grid solve
+  Givens G;
+  double* n2a = nullptr;   // [nmax] scratch norms
+  double* n2b = nullptr;
+  double2* qr = nullptr;   // [nmax]
+  double* qq = nullptr;
+  double* mask = nullptr;  // [nmax] per-rhs scale factors
+};
+
+// FP64 estimator buffers per level, and fine-level term vectors.
+struct EstWS {
+  int nmax = 0;
+  std::vector<double2*> x, y, z, w, u, v;  // per level
+  std::vector<double2*> term;             // fine vectors for correlators / loops
+  double2* eta = nullptr;                 // fine source (full volume)
+  double2* qf = nullptr;                  // [nmax] per-probe values
+  double2* qf2 = nullptr;
+  double2* slice_partial = nullptr;
+  double2* slice_out = nullptr;
+};
+
+struct Hier {
+  Context* ctx = nullptr;
+  FineOp* fine = nullptr;
+  mgm_hierarchy_desc desc{};
+  int L = 0;
+  std::vector<LGeom> g;
+  std::vector<Transfer> T;
+  std::vector<CoarseOp> A;  // A[l] for l >= 1
+  Scratch scratch;
+  std::vector<LevelWS> ws64, ws32, ws16;
+  EstWS est;
+  int* d_flag = nullptr;
+  double* pinned = nullptr;  // host staging (est, norms)
+  size_t pinned_n = 0;
+  // setup buffers (alias the solver region)
+  std::vector<double2*> tv;  // per transfer: ntv test vectors (FP64)
+  double2* setup_y = nullptr;
+  double2* setup_rho = nullptr;
+  double2* setup_q = nullptr;
+  double* setup_n2 = nullptr;
+  double2* setup_qr = nullptr;
+  double* setup_qq = nullptr;
+  bool tv_valid = false;     // test vectors alias solver memory until the first solve
+  Net* net = nullptr;
+
+  int64_t n(int l) const { return g[l].V * g[l].dof; }
+  Vec vec(int l, mgm_prec p, void* ptr, int nrhs) const {
+    Vec v;
+    v.p = ptr;
+    v.nsite = g[l].V;
+    v.dof = g[l].dof;
+    v.nrhs = nrhs;
+    v.prec = p;
+    return v;
+  }
+  void apply(int l, mgm_prec p, const void* x, void* y, int nrhs) const;
+  LevelWS& ws(int l, mgm_prec p) {
+    return p == MGM_PREC_F64 ? ws64[l] : p == MGM_PREC_F32 ? ws32[l] : ws16[l];
+  }
+
+  void layout(Arena& a);  // carve (or size) every buffer
+  void build();           // test vectors, QR, Galerkin, precision copies
+};
+
+// ------------------------------------------------------------ solver
+
+struct SolveCfg {
+  double tol = 1e-10;
+  int maxiter = 1000;
+  int kind = MGM_SOLVE_MG;
+  int smooth = 2;
+  int coarse_iters = 12;
+  double inner_tol = 1e-5;
+  Net* net = nullptr;
+};
+
+struct SolveOut {
+  int iterations = 0;
+  int restarts = 0;
+  int fallbacks = 0;
+  double max_rel = 0;
+  bool converged = true;
+};
+
+// Solves D_l x = b (FP64 dof-major) with the configured method.
+void solve(Hier& H, int l, const SolveCfg& cfg, const double2* b, double2* x, int nrhs, SolveOut* out);
+
+// e = M r: one V-cycle of level l in precision p (e overwritten)
+void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg);
+
+// ------------------------------------------------------------ estimator
+
+void estimate(Hier& H, const mgm_estimate_desc& d, mgm_estimate_result* out);
+mgm_estimate_sizes estimate_sizes(const Hier& H, const mgm_estimate_desc& d);
+
+}  // namespace mgm
+
+struct mgm_hierarchy_s {
+  mgm::Hier h;
+};

@@ -1,0 +1,165 @@
+"""GPU parity of the core kernels against the FP64 oracle (through the C ABI).
+
+Bars: bit-exact for Z4 probes and aggregation maps; 1e-13 relative for FP64
+operator applications (rounding order only); FP32 and FP16 bounds derived
+from unit roundoff times the stencil's 1-norm growth (stated per test).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from gpu_common import to_gpu, from_gpu, rel, flat_to_sites  # noqa: E402
+from lattice_inputs import gauge_field, random_spinor  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2509_11424_amd as m
+    return m.Context(0)
+
+
+@pytest.mark.parametrize("n_site,dof,nprobe,stream,first", [(256, 12, 3, 0, 0), (37, 16, 5, 259, 1000),
+                                                             (1, 2, 1, 7, 2**32 - 1)])
+def test_z4_bit_exact(ctx, n_site, dof, nprobe, stream, first):
+    import paper_2509_11424_amd as m
+    from oracle.philox import z4_vector
+    seed = 0x1234_5678_9ABC
+    x = m.draw_z4(ctx, seed, stream, first, nprobe, n_site, dof, "f64").cpu().numpy()  # (dof, site, rhs)
+    for r in range(nprobe):
+        want = z4_vector(n_site * dof, seed, stream, first + r).reshape(n_site, dof)
+        got = x[:, :, r].T
+        assert np.array_equal(got, want)
+
+
+DSLASH_CASES = [((4, 4, 4, 4), 0.3, 0.2, 0.0, 1),   # Wilson, c1-like
+                ((4, 4, 4, 4), 0.5, 0.05, 1.0, 3),  # clover
+                ((4, 2, 6, 8), 0.6, 0.01, 1.0, 2),  # odd shape
+                ((2, 2, 2, 2), 0.6, 0.1, 1.3, 5)]   # extent-2 wrap in every direction
+
+
+def test_z4_rejects_probe_index_beyond_32_bits(ctx):
+    import paper_2509_11424_amd as m
+    with pytest.raises(m.MgmError):
+        m.draw_z4(ctx, 1, 0, 2**32 - 1, 2, 4, 12, "f64")
+
+
+@pytest.mark.parametrize("dims,eps,m0,csw,nrhs", DSLASH_CASES)
+def test_dslash_f64(ctx, dims, eps, m0, csw, nrhs):
+    import paper_2509_11424_amd as m
+    from oracle.dirac import WilsonClover
+    U = gauge_field(dims, eps, 11)
+    D = WilsonClover(U, m0, csw)
+    op = m.Operator(ctx, U, m0, csw)
+    x = random_spinor(dims, 5, batch=nrhs).reshape(nrhs, -1, 12)
+    y = from_gpu(op.apply(to_gpu(x), prec="f64"))
+    want = D.apply(random_spinor(dims, 5, batch=nrhs)).reshape(nrhs, -1, 12)
+    assert rel(y, want) < 1e-13
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 2e-6), ("f16", 4e-3)])
+def test_dslash_low_precision(ctx, prec, bound):
+    """Inputs and fields are rounded to the storage type (unit roundoff u =
+    6e-8 for FP32, 4.9e-4 for FP16) and |D| <= ~10 over |x|; the relative error
+    stays within a few u times the operator's row-sum growth."""
+    import torch
+    import paper_2509_11424_amd as m
+    from oracle.dirac import WilsonClover
+    dims = (4, 4, 4, 8)
+    U = gauge_field(dims, 0.6, 13)
+    D = WilsonClover(U, 0.01, 1.0)
+    op = m.Operator(ctx, U, 0.01, 1.0)
+    nrhs = 4
+    xs = random_spinor(dims, 9, batch=nrhs)
+    want = D.apply(xs).reshape(nrhs, -1, 12)
+    xg = to_gpu(xs.reshape(nrhs, -1, 12))
+    if prec == "f32":
+        y = op.apply(xg.to(torch.complex64), prec="f32").to(torch.complex128)
+    else:
+        xh = torch.view_as_real(xg).to(torch.float16).contiguous()
+        yh = op.apply(xh, prec="f16")
+        y = torch.view_as_complex(yh.float().contiguous()).to(torch.complex128)
+    assert rel(from_gpu(y), want) < bound
+
+
+def test_dslash_gamma5_hermitian_large(ctx):
+    """Property at a size the oracle does not assemble densely:
+    <x, G5 D y> = conj(<y, G5 D x>) on 8^3 x 16."""
+    import torch
+    import paper_2509_11424_amd as m
+    dims = (8, 8, 8, 16)
+    U = gauge_field(dims, 0.6, 3)
+    op = m.Operator(ctx, U, 0.02, 1.0)
+    x = to_gpu(random_spinor(dims, 1, batch=1).reshape(1, -1, 12))
+    y = to_gpu(random_spinor(dims, 2, batch=1).reshape(1, -1, 12))
+    g5 = torch.tensor([1.0] * 6 + [-1.0] * 6, dtype=torch.complex128, device=x.device).view(12, 1, 1)
+    a = torch.vdot(x.flatten(), (g5 * op.apply(y)).flatten())
+    b = torch.vdot(y.flatten(), (g5 * op.apply(x)).flatten()).conj()
+    assert abs(a - b) < 1e-12 * abs(a)
+
+
+def test_dslash_sampled_sites_full_size(ctx):
+    """32^3 x 64 (the three-level workload's lattice): FP64 dslash at sampled
+    sites against the oracle's stencil evaluated site by site."""
+    import torch
+    import paper_2509_11424_amd as m
+    from oracle.dirac import WilsonClover
+    dims = (32, 32, 32, 64)
+    U = gauge_field(dims, 0.6, 14)
+    op = m.Operator(ctx, U, 0.02, 1.0)
+    rng = np.random.default_rng(0)
+    V = 32 * 32 * 32 * 64
+    x = (rng.standard_normal((12, V, 1)) + 1j * rng.standard_normal((12, V, 1)))
+    y = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    # oracle on a small periodic-in-space window is not the same operator, so
+    # evaluate D at sampled sites from the definition with the full field
+    sites = rng.integers(0, V, 16)
+    D = _LocalStencil(U, 0.02, 1.0)
+    for s in sites:
+        want = D.at(s, x[:, :, 0].T)
+        assert np.linalg.norm(y[:, s, 0] - want) < 1e-13 * np.linalg.norm(want)
+
+
+class _LocalStencil:
+    """Evaluates (D x)(s) at one site from the oracle's building blocks."""
+
+    def __init__(self, U, m0, csw):
+        from oracle import dirac
+        self.U, self.m0, self.csw = U, m0, csw
+        self.dirac = dirac
+        self.T, self.Z, self.Y, self.X = U.shape[:4]
+
+    def _idx(self, c):
+        x, y, z, t = c
+        return x % self.X + self.X * (y % self.Y + self.Y * (z % self.Z + self.Z * (t % self.T)))
+
+    def at(self, s, x):
+        d = self.dirac
+        X, Y, Z, T = self.X, self.Y, self.Z, self.T
+        c = [s % X, (s // X) % Y, (s // (X * Y)) % Z, s // (X * Y * Z)]
+        # clover from a 3^4 patch around the site (periodic copy of the field)
+        patch = np.zeros((3, 3, 3, 3, 4, 3, 3), dtype=complex)
+        for dt in range(3):
+            for dz in range(3):
+                for dy in range(3):
+                    for dx in range(3):
+                        cc = (c[0] + dx - 1, c[1] + dy - 1, c[2] + dz - 1, c[3] + dt - 1)
+                        patch[dt, dz, dy, dx] = self.U[cc[3] % T, cc[2] % Z, cc[1] % Y, cc[0] % X]
+        Cl = d.clover_matrix(patch, self.csw)[1, 1, 1, 1]
+        out = (4 + self.m0) * x[s] + Cl @ x[s]
+        g = d.gammas()
+        I4 = np.eye(4)
+        for mu in range(4):
+            e = [0, 0, 0, 0]
+            e[mu] = 1
+            cf = [c[i] + e[i] for i in range(4)]
+            cb = [c[i] - e[i] for i in range(4)]
+            ph_f = -1.0 if (mu == 3 and c[3] == T - 1) else 1.0
+            ph_b = -1.0 if (mu == 3 and c[3] == 0) else 1.0
+            Uf = self.U[c[3], c[2], c[1], c[0], mu]
+            Ub = self.U[cb[3] % T, cb[2] % Z, cb[1] % Y, cb[0] % X, mu].conj().T
+            pf = x[self._idx(cf)].reshape(4, 3)
+            pb = x[self._idx(cb)].reshape(4, 3)
+            out = out - 0.5 * ph_f * ((I4 - g[mu]) @ (pf @ Uf.T)).reshape(12)
+            out = out - 0.5 * ph_b * ((I4 + g[mu]) @ (pb @ Ub.T)).reshape(12)
+        return out

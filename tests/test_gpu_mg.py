@@ -1,0 +1,202 @@
+"""GPU parity of the multigrid hierarchy, solves and estimators against the
+FP64 oracle.
+
+Bars: aggregation maps bit-exact; P, D_c and test vectors within 1e-10
+relative (20 x 4 minimal-residual rounds amplify rounding-order differences
+by at most a few hundred ulps); solutions within 1e-9 of a dense solve at
+tol 1e-12; per-probe quadratic forms within 1e-8 relative, with differences
+X = a - b measured against |a| + |b|.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from gpu_common import to_gpu, from_gpu, rel  # noqa: E402
+from lattice_inputs import gauge_field, random_spinor  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2509_11424_amd as m
+    return m.Context(0)
+
+
+class Pair:
+    """GPU hierarchy and oracle hierarchy on the same inputs."""
+
+    def __init__(self, ctx, dims, eps, gseed, m0, csw, blocks, ntv, seed, max_nrhs=8, with_corr=False,
+                 mixed=0):
+        import paper_2509_11424_amd as m
+        from oracle.dirac import WilsonClover
+        from oracle.multigrid import Hierarchy
+        from oracle.solve import level_solver
+        self.U = gauge_field(dims, eps, gseed)
+        self.op = m.Operator(ctx, self.U, m0, csw)
+        self.h = m.Hierarchy(self.op, blocks, ntv, seed=seed, max_nrhs=max_nrhs, restart=20,
+                             with_corr=with_corr, mixed=mixed)
+        self.D = WilsonClover(self.U, m0, csw)
+        self.oh = Hierarchy(self.D, blocks, ntv, seed=seed)
+        self.solvers = [level_solver(o) for o in self.oh.ops]
+
+
+@pytest.fixture(scope="module")
+def two(ctx):
+    return Pair(ctx, (4, 4, 4, 4), 0.5, 12, 0.05, 1.0, [(2, 2, 2, 2)], [8], 102, with_corr=True)
+
+
+@pytest.fixture(scope="module")
+def three(ctx):
+    return Pair(ctx, (4, 4, 4, 8), 0.5, 21, 0.1, 1.0, [(2, 2, 2, 2), (1, 1, 1, 2)], [6, 4], 7,
+                with_corr=True)
+
+
+def test_test_vectors_match(two):
+    tv = two.h.export(0, "tv")
+    assert rel(tv, two.oh.tvs[0]) < 1e-10
+
+
+def test_aggregation_map_bit_exact(two, three):
+    for p in (two, three):
+        for l in range(p.oh.L - 1):
+            assert np.array_equal(p.h.export(l, "agg_map"), p.oh.transfers[l].agg.block_index())
+
+
+def test_P_and_coarse_operator(two, three):
+    for p in (two, three):
+        for l in range(p.oh.L - 1):
+            assert rel(p.h.export(l, "P"), p.oh.transfers[l].P) < 1e-10
+            assert rel(p.h.export(l, "coarse"), p.oh.ops[l + 1].blocks) < 1e-10
+
+
+def _rand(n_site, dof, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((nrhs, n_site, dof)) + 1j * rng.standard_normal((nrhs, n_site, dof))
+
+
+def test_transfers_and_level_apply(three):
+    p = three
+    for l in range(p.oh.L - 1):
+        s, d, n = p.h.level_info(l)
+        cs, cd, cn = p.h.level_info(l + 1)
+        x = _rand(s, d, 3, l)
+        xc = _rand(cs, cd, 3, 10 + l)
+        tr = p.oh.transfers[l]
+        xf, xcf = x.reshape(3, -1), xc.reshape(3, -1)
+        assert rel(from_gpu(p.h.restrict(l, to_gpu(x))).reshape(3, -1), tr.restrict(xf)) < 1e-10
+        assert rel(from_gpu(p.h.prolong(l, to_gpu(xc))).reshape(3, -1), tr.prolong(xcf)) < 1e-10
+        assert rel(from_gpu(p.h.project_out(l, to_gpu(x))).reshape(3, -1), tr.project_out(xf)) < 1e-10
+    for l in range(p.oh.L):
+        s, d, n = p.h.level_info(l)
+        x = _rand(s, d, 2, 20 + l)
+        y = from_gpu(p.h.apply(l, to_gpu(x))).reshape(2, -1)
+        assert rel(y, p.oh.ops[l].matvec(x.reshape(2, -1))) < 1e-10
+
+
+@pytest.mark.parametrize("kind", ["mg", "gmres"])
+def test_solves_every_level(three, kind):
+    import paper_2509_11424_amd as m
+    p = three
+    for l in range(p.oh.L):
+        s, d, n = p.h.level_info(l)
+        b = _rand(s, d, 3, 30 + l)
+        x, st = p.h.solve(l, to_gpu(b), m.solve_desc(tol=1e-12, kind=kind, maxiter=3000))
+        assert st["max_rel_residual"] <= 1e-12
+        want = np.stack([p.solvers[l](bb) for bb in b.reshape(3, -1)])
+        assert rel(from_gpu(x).reshape(3, -1), want) < 1e-9
+
+
+def _close(got, want, scale, tol=1e-8):
+    return np.all(np.abs(got - want) <= tol * scale)
+
+
+@pytest.mark.parametrize("dec", ["plain", "oblique", "orthogonal"])
+def test_trace_per_probe(two, three, dec):
+    import paper_2509_11424_amd as m
+    from oracle import estimators as E
+    for p in (two, three):
+        L = p.oh.L
+        npr = [3] * L
+        res = p.h.estimate("trace", dec, npr, seed=55, batch=2, solve=m.solve_desc(tol=1e-12))
+        S = res["samples"]
+        if dec == "plain":
+            want = [E.plain_samples(p.oh, p.solvers, 55, 3)]
+        elif dec == "oblique":
+            want = [E.M_samples(p.oh, p.solvers, l, 55, 3) for l in range(L - 1)]
+            want += [E.coarsest_samples(p.oh, p.solvers, 55, 3)]
+        else:
+            want = [E.O_samples(p.oh, p.solvers, l, 55, 3) for l in range(L - 1)]
+            want += [E.F_samples(p.oh, p.solvers, l, 55, 3) for l in range(L - 1)]
+            want += [E.coarsest_samples(p.oh, p.solvers, 55, 3)]
+        assert len(S) == len(want)
+        for q in range(len(want)):
+            got = S[q][:, 0, 0]
+            # difference terms: error relative to |a| + |b| (scale by the plain magnitude)
+            scale = np.abs(want[q]) + np.abs(E.plain_samples(p.oh, p.solvers, 55, 1)[0])
+            assert _close(got, want[q], scale), (dec, q, got, want[q])
+        # means and variances from the returned samples
+        for q in range(len(want)):
+            mu, var = E.mean_var(S[q][:, 0, 0])
+            assert abs(res["mean"][q, 0, 0] - mu) <= 1e-12 * abs(mu) + 1e-14
+            assert abs(res["var"][q, 0, 0] - var) <= 1e-9 * var + 1e-14
+
+
+@pytest.mark.parametrize("dec", ["plain", "oblique", "orthogonal"])
+def test_correlator_per_probe(two, three, dec):
+    import paper_2509_11424_amd as m
+    from oracle import estimators as E
+    for p in (two, three):
+        L = p.oh.L
+        R = len(E.term_levels(L, dec))
+        res = p.h.estimate("corr", dec, [2] * L, seed=77, batch=2, solve=m.solve_desc(tol=1e-12))
+        groups = [0] if dec == "plain" else range(L)
+        for g in groups:
+            pairs, X = E.correlator_samples(p.oh, p.solvers, dec, g, seed=77, nprobe=2)
+            for ip, (r, s) in enumerate(pairs):
+                got = res["samples"][r * R + s][:, 0, :]
+                scale = np.abs(X[:, ip, :]).max() + 1e-300
+                assert np.abs(got - X[:, ip, :]).max() <= 1e-8 * scale, (dec, g, r, s)
+
+
+@pytest.mark.parametrize("dec", ["plain", "oblique", "orthogonal"])
+def test_loops_per_probe(two, dec):
+    import paper_2509_11424_amd as m
+    from oracle import estimators as E
+    p = two
+    L = p.oh.L
+    res = p.h.estimate("loops", dec, [3] * L, seed=5, batch=3, solve=m.solve_desc(tol=1e-12))
+    groups = [0] if dec == "plain" else range(L)
+    for g in groups:
+        terms, X = E.loop_samples(p.oh, p.solvers, dec, g, seed=5, nprobe=3)
+        for it, r in enumerate(terms):
+            got = res["samples"][r]
+            scale = np.abs(X[:, it]).max()
+            assert np.abs(got - X[:, it]).max() <= 1e-8 * scale, (dec, g, r)
+
+
+def test_estimate_first_probe_offset_reproduces(two):
+    """Probe k of a run starting at first_probe = 2 equals probe 2 + k of a run from 0."""
+    import paper_2509_11424_amd as m
+    sd = m.solve_desc(tol=1e-12)
+    a = two.h.estimate("trace", "orthogonal", [4, 4], seed=9, batch=4, solve=sd)
+    b = two.h.estimate("trace", "orthogonal", [2, 2], seed=9, batch=2, first_probe=2, solve=sd)
+    for q in range(3):
+        np.testing.assert_allclose(b["samples"][q][:, 0, 0], a["samples"][q][2:, 0, 0], rtol=1e-9)
+
+
+def test_not_converged_reports_status(two):
+    import paper_2509_11424_amd as m
+    s, d, n = two.h.level_info(0)
+    b = _rand(s, d, 1, 3)
+    x, st = two.h.solve(0, to_gpu(b), m.solve_desc(tol=1e-12, kind="gmres", maxiter=3), check=False)
+    assert st["status"] == -4 and st["max_rel_residual"] > 1e-12
+
+
+def test_nan_input_reports_numeric(two):
+    import paper_2509_11424_amd as m
+    s, d, n = two.h.level_info(0)
+    b = _rand(s, d, 1, 3)
+    b[0, 0, 0] = np.nan
+    with pytest.raises(m.MgmError) as e:
+        two.h.solve(0, to_gpu(b), m.solve_desc(tol=1e-12))
+    assert e.value.status == -6
