@@ -1,0 +1,264 @@
+"""Benchmark of the MG-MLMC hot path on one MI355X.
+
+One step = one orthogonal multigrid multilevel Monte Carlo estimate of
+tr(D^-1) (O_l, F_l and coarsest terms, Sec. 3) on the 32^3 x 64 three-level
+workload: Z4 probes, projector, transfers, level solves to a relative
+residual of 1e-10 (FGMRES + V-cycle, fine dslash, coarse MFMA stencils),
+quadratic forms and per-term statistics.  The hierarchy setup (test vectors,
+block QR, Galerkin operators) runs once before the timed region and is
+reported separately.
+
+value = right-hand sides solved to 1e-10 per second (every level's solves
+counted), whole job.  The JSON line also carries the dslash roofline (HIP
+events around every dslash launch in the timed region) and the CPU-oracle
+baseline (fine-level solve rate, extrapolated).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4|c3|c2]
+                  [--form mixed|f64] [--cpu 0|1] [--ttt]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RHS solved/s to 1e-10, dslash HBM GB/s; time-to-target-variance tr(D^-1)"
+HBM_PEAK_GBS = 8000.0
+
+CONFIGS = {
+    # 32^3 x 64, csw 1, roughness 0.6, m0 0.02; 4^4 (24 tv) then 2^4 (32 tv);
+    # probes 20 / 100 / 400 on the fine / middle / coarsest difference levels
+    "c4": dict(dims=(32, 32, 32, 64), eps=0.6, m0=0.02, csw=1.0, gseed=14, blocks=[(4, 4, 4, 4), (2, 2, 2, 2)],
+               ntv=[24, 32], nprobe=[20, 100, 400], pseed=104, batch=[8, 32, 64], restart=12,
+               name="32^3x64 Wilson-clover (csw 1, roughness 0.6, m0 0.02), 3-level orthogonal MG-MLMC "
+                    "tr(D^-1), aggregates 4^4/2^4, N_tv 24/32, probes 20/100/400"),
+    "c3": dict(dims=(16, 16, 16, 16), eps=0.6, m0=0.01, csw=1.0, gseed=13, blocks=[(2, 2, 2, 2)], ntv=[12],
+               nprobe=[64, 256], pseed=103, batch=[32, 64], restart=16,
+               name="16^4 Wilson-clover (csw 1, roughness 0.6, m0 0.01), 2-level orthogonal MG-MLMC tr(D^-1), "
+                    "2^4 aggregates, N_tv 12"),
+    "c2": dict(dims=(8, 8, 8, 8), eps=0.5, m0=0.05, csw=1.0, gseed=12, blocks=[(2, 2, 2, 2)], ntv=[8],
+               nprobe=[50, 200], pseed=102, batch=[25, 64], restart=16,
+               name="8^4 Wilson-clover (csw 1, roughness 0.5, m0 0.05), 2-level orthogonal MG-MLMC tr(D^-1), "
+                    "2^4 aggregates, N_tv 8, probes 50/200"),
+}
+
+
+def rhs_per_step(nprobe):
+    """Solves of one right-hand side per orthogonal estimate: O_l (level l),
+    F_l (levels l and l+1), coarsest."""
+    L = len(nprobe)
+    return sum(3 * nprobe[l] for l in range(L - 1)) + nprobe[L - 1]
+
+
+# ------------------------------------------------------------ CPU baseline
+
+def cpu_baseline(cfg, out_path):
+    """Oracle on the host: one fine Wilson-clover application on the
+    workload's lattice, times the number of GMRES(50) iterations the oracle
+    needs for one right-hand side to 1e-10 on the 8^4 lattice with the same
+    operator parameters (the full-size solve does not fit in a bounded
+    sample).  Writes a JSON dict to out_path."""
+    import numpy as np
+    from lattice_inputs import gauge_field
+    from oracle.dirac import WilsonClover
+    from oracle.solve import gmres
+    res = {}
+    try:
+        t0 = time.time()
+        U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])
+        D = WilsonClover(U, cfg["m0"], cfg["csw"])
+        t_build = time.time() - t0
+        x = np.random.default_rng(0).standard_normal(D.n) + 0j
+        t0 = time.time()
+        D.matvec(x)
+        t_apply = time.time() - t0
+        del D, U
+        Up = gauge_field((8, 8, 8, 8), cfg["eps"], cfg["gseed"])
+        Dp = WilsonClover(Up, cfg["m0"], cfg["csw"])
+        count = [0]
+
+        def mv(v):
+            count[0] += 1
+            return Dp.matvec(v)
+
+        b = np.random.default_rng(1).standard_normal(Dp.n) + 0j
+        gmres(mv, b, tol=1e-10, restart=50)
+        iters = count[0]
+        t_solve = t_apply * iters
+        res = {"value": 1.0 / t_solve, "unit": "RHS/s", "cores": 1, "kind": "oracle",
+               "sample": "numpy FP64 oracle, 1 thread: one Wilson-clover application on %s (%.2f s, after a "
+                         "%.0f s operator build) x %d GMRES(50) applications per RHS to 1e-10 measured by the "
+                         "oracle on the 8^4 lattice with the same parameters; fine-level RHS/s, extrapolated"
+                         % ("x".join(map(str, cfg["dims"])), t_apply, t_build, iters),
+               "t_apply_s": t_apply, "iters_proxy": iters}
+    except Exception as e:  # reported, never fatal for the GPU leg
+        res = {"error": repr(e)}
+    with open(out_path, "w") as f:
+        json.dump(res, f)
+
+
+# ------------------------------------------------------------------- GPU
+
+def run(args):
+    import numpy as np
+    cfg = CONFIGS[args.config]
+    from lattice_inputs import gauge_field
+    t0 = time.time()
+    U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])
+    t_gauge = time.time() - t0
+    cpu_pid = None
+    cpu_out = os.path.join("/tmp", "mgm_cpu_baseline_%d.json" % os.getpid())
+    if args.cpu:
+        # fork before any GPU call: the child only runs numpy
+        cpu_pid = os.fork()
+        if cpu_pid == 0:
+            try:
+                os.environ["OMP_NUM_THREADS"] = "1"
+                cpu_baseline(cfg, cpu_out)
+            finally:
+                os._exit(0)
+    import torch
+    import paper_2509_11424_amd as m
+    ctx = m.Context(0)
+    op = m.Operator(ctx, U, cfg["m0"], cfg["csw"])
+    L = len(cfg["blocks"]) + 1
+    mixed = 1 if args.form == "mixed" else 0
+    t0 = time.time()
+    h = m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=cfg["batch"][0],
+                    max_nrhs_level=cfg["batch"], restart=cfg["restart"], mixed=mixed)
+    torch.cuda.synchronize()
+    t_setup = time.time() - t0
+    kind = "mg_mixed" if mixed else "mg"
+    sd = m.solve_desc(tol=1e-10, kind=kind, smooth=2, coarse_iters=8, inner_tol=1e-5, maxiter=5000,
+                      coarse_bf16=True)
+    batch = cfg["batch"]
+
+    def step(first):
+        return h.estimate("trace", "orthogonal", cfg["nprobe"], seed=cfg["pseed"], batch=batch,
+                          first_probe=first, solve=sd, samples=False)
+
+    for w in range(args.warmup):
+        step(0)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_reset()
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for k in range(args.steps):
+        results.append(step((k + 1) * 1000))
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    prof = {c: ctx.profile_query(c) for c in ("dslash_f64", "dslash_f32", "dslash_f16", "coarse_f64",
+                                               "coarse_f32", "coarse_bf16", "transfer")}
+    ctx.profile(False)
+    nrhs_step = rhs_per_step(cfg["nprobe"])
+    value = nrhs_step * args.steps / dt
+    ds = "dslash_f32" if mixed else "dslash_f64"
+    q = prof[ds]
+    avg_ms = q["ms"] / max(q["launches"], 1)
+    bytes_launch = q["bytes"] / max(q["launches"], 1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if q["launches"] else 0.0
+    line = {
+        "metric": METRIC, "value": value, "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+bf16 (f64 defect correction)" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "lattice": "x".join(map(str, cfg["dims"])), "levels": L,
+                   "probes": cfg["nprobe"], "batch": batch, "tol": 1e-10, "form": args.form},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_dslash<%s>" % (
+                         "F32" if mixed else "F64"), "avg_launch_ms": avg_ms, "launches": q["launches"],
+                     "bytes_per_launch": bytes_launch},
+        "setup_s": t_setup, "gauge_gen_s": t_gauge, "rhs_per_step": nrhs_step,
+        "solver_iterations_per_step": results[-1]["stats"]["iterations"],
+        "estimate": {"tr_Dinv": [results[-1]["total_mean"][0, 0].real, results[-1]["total_mean"][0, 0].imag],
+                     "var_of_mean": float(results[-1]["total_var"][0, 0])},
+        "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
+                        "GBps": (v["bytes"] / v["ms"] / 1e6) if v["ms"] > 0 else 0.0} for k, v in prof.items()},
+    }
+    if args.ttt:
+        line["time_to_target"] = time_to_target(m, ctx, op, cfg, h, sd, args)
+        h = None
+    if cpu_pid:
+        os.waitpid(cpu_pid, 0)
+        try:
+            with open(cpu_out) as f:
+                line["cpu_baseline"] = json.load(f)
+            os.remove(cpu_out)
+        except Exception as e:
+            line["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(line), flush=True)
+
+
+def time_to_target(m, ctx, op, cfg, h_mixed, sd_mixed, args):
+    """Time to reach the variance of the plain FP64 orthogonal estimate at the
+    configured probe counts (target eps^2), for plain FP64 MG and for the
+    mixed form with MLMC-optimal sample sizes (Sec. 2.2, eq. MLMC-Nl)."""
+    import numpy as np
+    import torch
+    L = len(cfg["nprobe"])
+    lv = list(range(L - 1)) + list(range(L - 1)) + [L - 1]
+
+    def pilot(h, sd):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        r = h.estimate("trace", "orthogonal", cfg["nprobe"], seed=cfg["pseed"] + 7, batch=cfg["batch"],
+                       solve=sd, samples=False)
+        torch.cuda.synchronize()
+        return {"seconds": time.time() - t0, "var": r["var"][:, 0, 0], "cost": r["cost_s"],
+                "total_var": float(r["total_var"][0, 0])}
+
+    def final(h, sd, p, eps2):
+        # MLMC-optimal N per term; terms of one probe group share the largest
+        n = m.mlmc_allocate(np.maximum(p["var"], 1e-30), np.maximum(p["cost"], 1e-9), eps2)
+        npl = [int(max(n[i] for i in range(len(lv)) if lv[i] == g)) for g in range(L)]
+        torch.cuda.synchronize()
+        t0 = time.time()
+        r = h.estimate("trace", "orthogonal", npl, seed=cfg["pseed"] + 11, batch=cfg["batch"], solve=sd,
+                       samples=False)
+        torch.cuda.synchronize()
+        return {"seconds": time.time() - t0, "nprobe": npl, "achieved_var": float(r["total_var"][0, 0]),
+                "pilot_seconds": p["seconds"]}
+
+    pm = pilot(h_mixed, sd_mixed)
+    # FP64 hierarchy and pilot; eps^2 is the plain FP64 estimate's variance at
+    # the configured probe counts
+    h64 = m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=cfg["batch"][0],
+                      max_nrhs_level=cfg["batch"], restart=cfg["restart"], mixed=0)
+    sd64 = m.solve_desc(tol=1e-10, kind="mg", smooth=2, coarse_iters=8, maxiter=5000)
+    p64 = pilot(h64, sd64)
+    eps2 = p64["total_var"]
+    out = {"eps2": eps2, "f64": final(h64, sd64, p64, eps2)}
+    del h64
+    torch.cuda.empty_cache()
+    out["mixed"] = final(h_mixed, sd_mixed, pm, eps2)
+    out["ratio_f64_over_mixed"] = out["f64"]["seconds"] / out["mixed"]["seconds"]
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c4", choices=sorted(CONFIGS))
+    ap.add_argument("--form", default="mixed", choices=["mixed", "f64"])
+    ap.add_argument("--cpu", type=int, default=1)
+    ap.add_argument("--ttt", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the hot path is measured per GPU and probe sharding "
+              "across GPUs is described in DESIGN.md; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -161,6 +161,10 @@ typedef struct {
                                          2: both full */
   int32_t with_corr;                  /* 1: reserve the fine-level term vectors needed
                                          by CORR_PS and LOOPS estimates */
+  int32_t max_nrhs_level[MGM_MAX_LEVELS]; /* optional per-level batch capacity (0: max_nrhs);
+                                         level l holds max over levels <= l, so
+                                         coarse levels can batch more right-hand
+                                         sides than the fine level */
 } mgm_hierarchy_desc;
 
 mgm_status mgm_hierarchy_workspace_size(mgm_operator op, const mgm_hierarchy_desc* desc,
@@ -196,6 +200,13 @@ mgm_status mgm_hierarchy_export(mgm_hierarchy h, int32_t level, mgm_export_kind 
  * all in dof-major FP64 layout. */
 mgm_status mgm_level_apply(mgm_hierarchy h, int32_t level, const void* x_dev, void* y_dev,
                            int32_t nrhs);
+/* The same in precision `prec`: F64 (double complex vectors), F32 (float
+ * complex vectors, FP32 operator), F16 (level 0 only, half complex vectors),
+ * BF16 (level >= 1; float complex vectors, operator and vectors rounded to
+ * BF16 for the matrix cores, FP32 accumulation).  F32 and BF16 coarse
+ * operators exist only in hierarchies built with mixed != 0. */
+mgm_status mgm_level_apply_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const void* x_dev,
+                                void* y_dev, int32_t nrhs);
 mgm_status mgm_restrict(mgm_hierarchy h, int32_t level, const void* x_dev, void* y_dev,
                         int32_t nrhs);
 mgm_status mgm_prolong(mgm_hierarchy h, int32_t level, const void* x_dev, void* y_dev,
@@ -221,6 +232,9 @@ typedef struct {
   int32_t coarse_iters;/* iterations of the coarse-level solve inside a V-cycle */
   double inner_tol;    /* MG_MIXED: relative reduction per FP32 inner solve */
   void* net;           /* MGM_SOLVE_NET: network handle (mgm_net), else NULL */
+  int32_t coarse_bf16; /* MG_MIXED / NET: coarse-level operators inside the V-cycle
+                          use BF16 MFMA operands with FP32 accumulation (1) or
+                          FP32 (0); the Arnoldi operator of every solve stays FP32 */
 } mgm_solve_desc;
 
 typedef struct {
@@ -262,6 +276,8 @@ typedef struct {
   uint64_t first_probe;     /* probe index offset (restart / sharding) */
   int32_t batch;            /* right-hand sides per solver launch (<= max_nrhs) */
   mgm_solve_desc solve;
+  int32_t batch_level[MGM_MAX_LEVELS]; /* optional batch per probe group g (0: batch);
+                                          must not exceed the capacity of level g */
 } mgm_estimate_desc;
 
 typedef struct {

@@ -44,13 +44,14 @@ class HierarchyDesc(C.Structure):
     _fields_ = [("nlevels", C.c_int32), ("block", (C.c_int32 * 4) * (MAX_LEVELS - 1)),
                 ("ntv", C.c_int32 * (MAX_LEVELS - 1)), ("setup_steps", C.c_int32),
                 ("setup_mr", C.c_int32), ("seed", C.c_uint64), ("max_nrhs", C.c_int32),
-                ("restart", C.c_int32), ("mixed", C.c_int32), ("with_corr", C.c_int32)]
+                ("restart", C.c_int32), ("mixed", C.c_int32), ("with_corr", C.c_int32),
+                ("max_nrhs_level", C.c_int32 * MAX_LEVELS)]
 
 
 class SolveDesc(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("kind", C.c_int32),
                 ("smooth", C.c_int32), ("coarse_iters", C.c_int32), ("inner_tol", C.c_double),
-                ("net", C.c_void_p)]
+                ("net", C.c_void_p), ("coarse_bf16", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -61,7 +62,8 @@ class SolveStats(C.Structure):
 class EstimateDesc(C.Structure):
     _fields_ = [("observable", C.c_int32), ("decomposition", C.c_int32),
                 ("nprobe", C.c_int32 * MAX_LEVELS), ("seed", C.c_uint64),
-                ("first_probe", C.c_uint64), ("batch", C.c_int32), ("solve", SolveDesc)]
+                ("first_probe", C.c_uint64), ("batch", C.c_int32), ("solve", SolveDesc),
+                ("batch_level", C.c_int32 * MAX_LEVELS)]
 
 
 class EstimateSizes(C.Structure):
@@ -102,6 +104,8 @@ _SIGS = [
                                            C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     ("mgm_hierarchy_export", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_void_p, C.c_size_t]),
     ("mgm_level_apply", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("mgm_level_apply_prec", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_void_p, C.c_void_p,
+                                       C.c_int32]),
     ("mgm_restrict", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     ("mgm_prolong", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     ("mgm_project_out", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
@@ -255,9 +259,10 @@ def draw_z4(ctx: Context, seed: int, stream: int, first_probe: int, nprobe: int,
     return out
 
 
-def solve_desc(tol=1e-12, maxiter=2000, kind="mg", smooth=2, coarse_iters=12, inner_tol=1e-5,
-               net=None) -> SolveDesc:
+def solve_desc(tol=1e-12, maxiter=2000, kind="mg", smooth=2, coarse_iters=8, inner_tol=1e-5,
+               net=None, coarse_bf16=True) -> SolveDesc:
     d = SolveDesc()
+    d.coarse_bf16 = 1 if coarse_bf16 else 0
     d.tol = tol
     d.maxiter = maxiter
     d.kind = SOLVE[kind] if isinstance(kind, str) else int(kind)
@@ -270,7 +275,8 @@ def solve_desc(tol=1e-12, maxiter=2000, kind="mg", smooth=2, coarse_iters=12, in
 
 class Hierarchy:
     def __init__(self, op: Operator, blocks, ntv, seed: int, setup_steps: int = 20, setup_mr: int = 4,
-                 max_nrhs: int = 8, restart: int = 16, mixed: int = 0, with_corr: bool = False):
+                 max_nrhs: int = 8, restart: int = 16, mixed: int = 0, with_corr: bool = False,
+                 max_nrhs_level=None):
         self.op = op
         self.ctx = op.ctx
         d = HierarchyDesc()
@@ -285,6 +291,9 @@ class Hierarchy:
         d.restart = restart
         d.mixed = mixed
         d.with_corr = 1 if with_corr else 0
+        if max_nrhs_level is not None:
+            caps = list(max_nrhs_level) + [0] * (MAX_LEVELS - len(max_nrhs_level))
+            d.max_nrhs_level[:] = caps[:MAX_LEVELS]
         self.desc = d
         self.L = d.nlevels
         nb = C.c_size_t()
@@ -332,6 +341,15 @@ class Hierarchy:
         _check(lib().mgm_level_apply(self.h, level, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)), x.shape[2]))
         return y
 
+    def apply_prec(self, level: int, x, prec: str):
+        """Level operator in precision prec; x: complex64 (f32, bf16) or
+        complex128 (f64) dof-major tensor."""
+        import torch
+        y = torch.empty_like(x)
+        _check(lib().mgm_level_apply_prec(self.h, level, PREC[prec], C.c_void_p(_ptr(x)),
+                                          C.c_void_p(_ptr(y)), x.shape[2]))
+        return y
+
     def restrict(self, level: int, x):
         y = self._vec(level + 1, x.shape[2])
         _check(lib().mgm_restrict(self.h, level, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)), x.shape[2]))
@@ -360,10 +378,15 @@ class Hierarchy:
             _check(rc)
         return x, stats
 
-    def estimate(self, observable: str, decomposition: str, nprobe, seed: int, batch: int = 8,
+    def estimate(self, observable: str, decomposition: str, nprobe, seed: int, batch=8,
                  first_probe: int = 0, solve: SolveDesc | None = None, samples: bool = True,
                  check: bool = True):
+        """batch: an int, or a per-probe-group list (finest group first)."""
         d = EstimateDesc()
+        if not isinstance(batch, int):
+            bl = list(batch) + [0] * (MAX_LEVELS - len(batch))
+            d.batch_level[:] = bl[:MAX_LEVELS]
+            batch = int(batch[0])
         d.observable = OBS[observable]
         d.decomposition = DEC[decomposition]
         npr = list(nprobe) + [0] * (MAX_LEVELS - len(nprobe))

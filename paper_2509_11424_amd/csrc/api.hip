@@ -212,6 +212,9 @@ static void check_hdesc(mgm_operator op, const mgm_hierarchy_desc* d) {
   MGM_CHECK(d->nlevels >= 2 && d->nlevels <= MGM_MAX_LEVELS, MGM_ERR_INVALID_ARG, "nlevels must be 2..4");
   MGM_CHECK(d->setup_steps >= 1 && d->setup_mr >= 1, MGM_ERR_INVALID_ARG, "setup steps must be >= 1");
   MGM_CHECK(d->max_nrhs >= 1 && d->max_nrhs <= 256, MGM_ERR_INVALID_ARG, "max_nrhs must be 1..256");
+  for (int l = 0; l < MGM_MAX_LEVELS; l++)
+    MGM_CHECK(d->max_nrhs_level[l] >= 0 && d->max_nrhs_level[l] <= 256, MGM_ERR_INVALID_ARG,
+              "max_nrhs_level must be 0..256");
   MGM_CHECK(d->restart >= 2 && d->restart <= 63, MGM_ERR_INVALID_ARG, "restart must be 2..63");
   int dims[4] = {op->op.g.X, op->op.g.Y, op->op.g.Z, op->op.g.T};
   int dof = 12;
@@ -355,6 +358,17 @@ mgm_status mgm_level_apply(mgm_hierarchy h, int32_t level, const void* x, void* 
   API_END
 }
 
+mgm_status mgm_level_apply_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const void* x, void* y,
+                                int32_t nrhs) {
+  API_BEGIN
+  check_level(h, level, nrhs, false);
+  MGM_CHECK(x && y && x != y, MGM_ERR_INVALID_ARG, "bad vectors");
+  MGM_CHECK(!(level == 0 && prec == MGM_PREC_BF16) && !(level > 0 && prec == MGM_PREC_F16), MGM_ERR_INVALID_ARG,
+            "F16 exists on the fine level, BF16 on coarse levels");
+  h->h.apply(level, prec, x, y, nrhs);
+  API_END
+}
+
 mgm_status mgm_restrict(mgm_hierarchy h, int32_t level, const void* x, void* y, int32_t nrhs) {
   API_BEGIN
   check_level(h, level, nrhs, true);
@@ -376,7 +390,7 @@ mgm_status mgm_project_out(mgm_hierarchy h, int32_t level, const void* x, void* 
   check_level(h, level, nrhs, true);
   MGM_CHECK(x && y, MGM_ERR_INVALID_ARG, "bad vectors");
   Hier& H = h->h;
-  MGM_CHECK(nrhs <= H.est.nmax, MGM_ERR_INVALID_ARG, "nrhs exceeds max_nrhs");
+  MGM_CHECK(nrhs <= H.cap(level), MGM_ERR_INVALID_ARG, "nrhs exceeds the capacity of the level");
   H.T[level].restrict_(MGM_PREC_F64, x, H.est.w[level + 1], nrhs);
   H.T[level].prolong(MGM_PREC_F64, H.est.w[level + 1], x, y, nrhs, 1);
   API_END
@@ -393,6 +407,7 @@ static SolveCfg cfg_of(const mgm_solve_desc* d) {
   c.smooth = d->smooth;
   c.coarse_iters = d->coarse_iters;
   c.inner_tol = d->inner_tol > 0 ? d->inner_tol : 1e-5;
+  c.coarse_bf16 = d->coarse_bf16 != 0;
   c.net = (Net*)d->net;
   MGM_CHECK(c.kind != MGM_SOLVE_NET || c.net != nullptr, MGM_ERR_INVALID_ARG, "NET solve needs a network");
   return c;

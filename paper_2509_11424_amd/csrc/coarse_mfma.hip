@@ -1,11 +1,308 @@
+// Coarse stencil y(s) = sum_dir A_dir(s) x(nbr(s, dir)) on the matrix cores.
+//
+// Per coarse site the nine d x d complex blocks multiply d x nrhs neighbour
+// blocks: a dense contraction over (dir, j), done by one wave per
+// (site, 16 right-hand sides).  A is read once, from a fragment-packed copy
+// in which every MFMA A-operand of a wave is one contiguous 1 KB chunk; the
+// neighbour block is the B operand.  Complex products use real MFMAs:
+//   Re y += Re A Re x - Im A Im x,   Im y += Re A Im x + Im A Re x.
+// FP64 / FP32: v_mfma_{f64,f32}_16x16x4 (A[i][k]: lane = i%16 + 16 k;
+// B[k][n]: lane = n + 16 k; D[i][n]: lane = n + 16 q with row i = 4 q + reg
+// for FP32 and i = q + 4 reg for FP64 -- checked on the device).
+// BF16 (mixed form): v_mfma_f32_16x16x16 bf16 with FP32 accumulation
+// (A: lane holds k = 4 (lane/16) .. +3 of row lane%16; B likewise by column).
+// BF16 values are rounded to nearest even from FP32.
 #include "mg.h"
 
 namespace mgm {
 
-size_t mg_mfma_bytes(const CoarseOp& A) { return 256; }
-void mg_mfma_pack(Context*, CoarseOp&) {}
-void coarse_apply_mfma(const CoarseOp&, const float2*, float2*, int) {
-  throw Error(MGM_ERR_INVALID_ARG, "BF16 MFMA coarse stencil not available");
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void coords_c(const LGeom& g, int64_t s, int c[4]) {
+  c[0] = (int)(s % g.dims[0]); s /= g.dims[0];
+  c[1] = (int)(s % g.dims[1]); s /= g.dims[1];
+  c[2] = (int)(s % g.dims[2]); s /= g.dims[2];
+  c[3] = (int)s;
+}
+__device__ __forceinline__ int64_t nbr_c(const LGeom& g, const int c[4], int dir) {
+  int cc[4] = {c[0], c[1], c[2], c[3]};
+  if (dir > 0) {
+    int mu = (dir - 1) & 3;
+    cc[mu] += (dir <= 4) ? 1 : -1;
+    cc[mu] = (cc[mu] + g.dims[mu]) % g.dims[mu];
+  }
+  return cc[0] + (int64_t)g.dims[0] * (cc[1] + (int64_t)g.dims[1] * (cc[2] + (int64_t)g.dims[2] * cc[3]));
+}
+
+struct MGeo {
+  int d, MT, KC64, KC16;
+};
+static MGeo mgeo(int d) {
+  MGeo m;
+  m.d = d;
+  m.MT = (d + 15) / 16;
+  m.KC64 = (d + 3) / 4;
+  m.KC16 = (d + 15) / 16;
+  return m;
+}
+
+size_t mg_mfma_bytes(const CoarseOp& A) {
+  MGeo m = mgeo(A.d);
+  return (size_t)A.g.V * 9 * m.KC16 * m.MT * 2 * 64 * 4 * sizeof(uint16_t);
+}
+size_t mg_mfma64_bytes(const CoarseOp& A) {
+  MGeo m = mgeo(A.d);
+  return (size_t)A.g.V * 9 * m.KC64 * m.MT * 64 * sizeof(double2);
+}
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t b = __float_as_uint(f);
+  if ((b & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+
+// ---------------------------------------------------------------- packing
+
+__global__ void k_pack64(double2* __restrict__ out, const double2* __restrict__ A, LGeom g, MGeo m) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)9 * m.KC64 * m.MT * 64;
+  if (e >= g.V * per) return;
+  const int64_t s = e / per;
+  int64_t q = e % per;
+  const int lane = (int)(q % 64); q /= 64;
+  const int mt = (int)(q % m.MT); q /= m.MT;
+  const int kc = (int)(q % m.KC64);
+  const int dir = (int)(q / m.KC64);
+  const int i = 16 * mt + (lane & 15), k = 4 * kc + (lane >> 4);
+  double2 v = make_double2(0, 0);
+  if (i < m.d && k < m.d) v = A[((int64_t)(dir * m.d + i) * m.d + k) * g.V + s];
+  out[e] = v;
+}
+
+__global__ void k_pack_bf16(uint16_t* __restrict__ out, const double2* __restrict__ A, LGeom g, MGeo m) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)9 * m.KC16 * m.MT * 2 * 64 * 4;
+  if (e >= g.V * per) return;
+  const int64_t s = e / per;
+  int64_t q = e % per;
+  const int el = (int)(q % 4); q /= 4;
+  const int lane = (int)(q % 64); q /= 64;
+  const int part = (int)(q % 2); q /= 2;  // 0: real, 1: imaginary
+  const int mt = (int)(q % m.MT); q /= m.MT;
+  const int kc = (int)(q % m.KC16);
+  const int dir = (int)(q / m.KC16);
+  const int i = 16 * mt + (lane & 15), k = 16 * kc + 4 * (lane >> 4) + el;
+  float v = 0.0f;
+  if (i < m.d && k < m.d) {
+    double2 a = A[((int64_t)(dir * m.d + i) * m.d + k) * g.V + s];
+    v = (float)(part ? a.y : a.x);
+  }
+  out[e] = bf16_rne(v);
+}
+
+void mg_mfma_pack(Context* c, CoarseOp& A) {
+  MGeo m = mgeo(A.d);
+  if (A.Abf) {
+    int64_t n = A.g.V * 9 * m.KC16 * m.MT * 2 * 64 * 4;
+    hipLaunchKernelGGL(k_pack_bf16, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, (uint16_t*)A.Abf, A.A64,
+                       A.g, m);
+    MGM_LAUNCH_CHECK();
+  }
+}
+
+void mg_mfma64_pack(Context* c, CoarseOp& A) {
+  MGeo m = mgeo(A.d);
+  int64_t n = A.g.V * 9 * m.KC64 * m.MT * 64;
+  hipLaunchKernelGGL(k_pack64, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, A.Ap64, A.A64, A.g, m);
+  MGM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- apply
+
+// 16x16x4 MFMA in FP64 or FP32 (same lane layout, one A and one B value per lane)
+// Output row of accumulator register j in lane group q = lane/16 (column
+// lane%16): FP64 interleaves rows (4 j + q), FP32 keeps them blocked (4 q + j).
+struct M64 {
+  using R = double;
+  using C2 = double2;
+  using V4 = d4_t;
+  __device__ static V4 mfma(R a, R b, V4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int q, int j) { return 4 * j + q; }
+};
+struct M32 {
+  using R = float;
+  using C2 = float2;
+  using V4 = f4_t;
+  __device__ static V4 mfma(R a, R b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int q, int j) { return 4 * q + j; }
+};
+
+template <class M, int MT>
+__global__ __launch_bounds__(64) void k_coarse_mfma4(const typename M::C2* __restrict__ x,
+                                                     typename M::C2* __restrict__ y,
+                                                     const typename M::C2* __restrict__ Ap, LGeom g, int d, int KC,
+                                                     int nrhs, int ntr) {
+  using R = typename M::R;
+  using V4 = typename M::V4;
+  using C2 = typename M::C2;
+  const int64_t s = blockIdx.x / ntr;
+  const int nt = blockIdx.x % ntr;
+  const int lane = threadIdx.x;
+  const int n = lane & 15, kq = lane >> 4;
+  const int r = nt * 16 + n;
+  const int64_t V = g.V;
+  int c[4];
+  coords_c(g, s, c);
+  V4 yr[MT], yi[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; mt++) {
+    yr[mt] = (V4){0, 0, 0, 0};
+    yi[mt] = (V4){0, 0, 0, 0};
+  }
+  const C2* As = Ap + (int64_t)s * 9 * KC * MT * 64 + lane;
+#pragma unroll 1
+  for (int dir = 0; dir < 9; dir++) {
+    const int64_t sn = nbr_c(g, c, dir);
+    const C2* Ad = As + (int64_t)dir * KC * MT * 64;
+#pragma unroll 2
+    for (int kc = 0; kc < KC; kc++) {
+      const int k = 4 * kc + kq;
+      C2 xv = {0, 0};
+      if (k < d && r < nrhs) xv = x[((int64_t)k * V + sn) * nrhs + r];
+#pragma unroll
+      for (int mt = 0; mt < MT; mt++) {
+        const C2 a = Ad[(int64_t)(kc * MT + mt) * 64];
+        yr[mt] = M::mfma(a.x, xv.x, yr[mt]);
+        yr[mt] = M::mfma(-a.y, xv.y, yr[mt]);
+        yi[mt] = M::mfma(a.x, xv.y, yi[mt]);
+        yi[mt] = M::mfma(a.y, xv.x, yi[mt]);
+      }
+    }
+  }
+  if (r < nrhs) {
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int i = 16 * mt + M::row(kq, j);
+        if (i < d) y[((int64_t)i * V + s) * nrhs + r] = C2{(R)yr[mt][j], (R)yi[mt][j]};
+      }
+  }
+}
+
+template <int MT>
+__global__ __launch_bounds__(64) void k_coarse_mfma_bf16(const float2* __restrict__ x, float2* __restrict__ y,
+                                                         const uint16_t* __restrict__ Ap, LGeom g, int d, int KC,
+                                                         int nrhs, int ntr) {
+  const int64_t s = blockIdx.x / ntr;
+  const int nt = blockIdx.x % ntr;
+  const int lane = threadIdx.x;
+  const int n = lane & 15, kq = lane >> 4;
+  const int r = nt * 16 + n;
+  const int64_t V = g.V;
+  int c[4];
+  coords_c(g, s, c);
+  f4_t yr[MT], yi[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; mt++) {
+    yr[mt] = (f4_t){0, 0, 0, 0};
+    yi[mt] = (f4_t){0, 0, 0, 0};
+  }
+  const uint16_t* As = Ap + (int64_t)s * 9 * KC * MT * 512 + lane * 4;
+#pragma unroll 1
+  for (int dir = 0; dir < 9; dir++) {
+    const int64_t sn = nbr_c(g, c, dir);
+    const uint16_t* Ad = As + (int64_t)dir * KC * MT * 512;
+#pragma unroll 1
+    for (int kc = 0; kc < KC; kc++) {
+      s4_t br, bi;
+#pragma unroll
+      for (int el = 0; el < 4; el++) {
+        const int k = 16 * kc + 4 * kq + el;
+        float2 xv = make_float2(0.f, 0.f);
+        if (k < d && r < nrhs) xv = x[((int64_t)k * V + sn) * nrhs + r];
+        br[el] = (short)bf16_rne(xv.x);
+        bi[el] = (short)bf16_rne(xv.y);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; mt++) {
+        const uint16_t* f = Ad + (int64_t)(kc * MT + mt) * 512;
+        const s4_t ar = *(const s4_t*)f;
+        const s4_t ai = *(const s4_t*)(f + 256);
+        const s4_t nai = ai ^ (s4_t){(short)0x8000, (short)0x8000, (short)0x8000, (short)0x8000};
+        yr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, br, yr[mt], 0, 0, 0);
+        yr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nai, bi, yr[mt], 0, 0, 0);
+        yi[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bi, yi[mt], 0, 0, 0);
+        yi[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, br, yi[mt], 0, 0, 0);
+      }
+    }
+  }
+  if (r < nrhs) {
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int i = 16 * mt + 4 * kq + j;
+        if (i < d) y[((int64_t)i * V + s) * nrhs + r] = make_float2(yr[mt][j], yi[mt][j]);
+      }
+  }
+}
+
+#define MT_DISPATCH(MTV, ...)                       \
+  switch (MTV) {                                    \
+    case 1: { constexpr int MTc = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int MTc = 2; __VA_ARGS__; } break; \
+    case 3: { constexpr int MTc = 3; __VA_ARGS__; } break; \
+    case 4: { constexpr int MTc = 4; __VA_ARGS__; } break; \
+    default: throw Error(MGM_ERR_SHAPE, "coarse dof must be <= 64"); \
+  }
+
+void coarse_apply_mfma64(const CoarseOp& A, const double2* x, double2* y, int nrhs) {
+  MGeo m = mgeo(A.d);
+  const int ntr = (nrhs + 15) / 16;
+  const unsigned nb = (unsigned)(A.g.V * ntr);
+  ProfScope ps(A.ctx, KC_COARSE_F64, A.bytes(MGM_PREC_F64, nrhs));
+  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M64, MTc>), dim3(nb), dim3(64), 0, A.ctx->stream, x, y,
+                                       A.Ap64, A.g, A.d, m.KC64, nrhs, ntr));
+  MGM_LAUNCH_CHECK();
+}
+
+void coarse_apply_mfma32(const CoarseOp& A, const float2* x, float2* y, int nrhs) {
+  MGeo m = mgeo(A.d);
+  const int ntr = (nrhs + 15) / 16;
+  const unsigned nb = (unsigned)(A.g.V * ntr);
+  ProfScope ps(A.ctx, KC_COARSE_F32, A.bytes(MGM_PREC_F32, nrhs));
+  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M32, MTc>), dim3(nb), dim3(64), 0, A.ctx->stream, x, y,
+                                       A.A32, A.g, A.d, m.KC64, nrhs, ntr));
+  MGM_LAUNCH_CHECK();
+}
+
+__global__ void k_pack32(float2* __restrict__ out, const double2* __restrict__ packed64, int64_t n) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) out[e] = make_float2((float)packed64[e].x, (float)packed64[e].y);
+}
+
+size_t mg_mfma32_bytes(const CoarseOp& A) { return mg_mfma64_bytes(A) / 2; }
+
+void mg_mfma32_pack(Context* c, CoarseOp& A) {
+  MGeo m = mgeo(A.d);
+  int64_t n = A.g.V * 9 * m.KC64 * m.MT * 64;
+  hipLaunchKernelGGL(k_pack32, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, A.A32, A.Ap64, n);
+  MGM_LAUNCH_CHECK();
+}
+
+void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs) {
+  MGM_CHECK(A.Abf != nullptr, MGM_ERR_INVALID_ARG, "BF16 coarse stencil not built (mixed == 0)");
+  MGeo m = mgeo(A.d);
+  const int ntr = (nrhs + 15) / 16;
+  const unsigned nb = (unsigned)(A.g.V * ntr);
+  ProfScope ps(A.ctx, KC_COARSE_BF16, A.bytes(MGM_PREC_BF16, nrhs));
+  MT_DISPATCH(m.MT, hipLaunchKernelGGL(k_coarse_mfma_bf16<MTc>, dim3(nb), dim3(64), 0, A.ctx->stream, x, y,
+                                       (const uint16_t*)A.Abf, A.g, A.d, m.KC16, nrhs, ntr));
+  MGM_LAUNCH_CHECK();
 }
 
 }  // namespace mgm

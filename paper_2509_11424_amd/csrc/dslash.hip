@@ -215,17 +215,31 @@ __global__ void k_cvt_r64_r16(__half* o, const double* in, int64_t n) {
 
 // ---------------------------------------------------------------- dslash
 
+constexpr int kSlab = 4;  // time slices (one wave each) per 256-thread block
+
 template <class P>
 __global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
                                                 const typename P::S* __restrict__ in,
                                                 const typename P::S* __restrict__ U,
                                                 const typename P::RS* __restrict__ C, Geom g,
-                                                int nrhs, int64_t nblocks) {
+                                                int nrhs, int64_t nblocks, int slab) {
   using R = typename P::R;
   const int64_t blk = xcd_block(blockIdx.x, nblocks);
-  const int64_t tid = blk * blockDim.x + threadIdx.x;
   const int64_t V = g.V;
   const int64_t N = V * nrhs;
+  int64_t tid;
+  if (slab) {
+    // Block = kSlab waves on kSlab consecutive time slices of one 64-element
+    // chunk of a slice: the t-neighbours of the inner waves are loaded by
+    // sibling waves of the same block at about the same time.
+    const int64_t per_slice = (V / g.T) * nrhs;
+    const int64_t chunks = per_slice / 64;
+    const int64_t chunk = blk % chunks, tg = blk / chunks;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    tid = (tg * kSlab + w) * per_slice + chunk * 64 + lane;
+  } else {
+    tid = blk * blockDim.x + threadIdx.x;
+  }
   if (tid >= N) return;
   const int64_t s = tid / nrhs;
   const int r = (int)(tid - s * nrhs);
@@ -237,95 +251,80 @@ __global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
     c[2] = (int)(q % g.Z); q /= g.Z;
     c[3] = (int)q;
   }
-  const int64_t stride[4] = {1, g.X, (int64_t)g.X * g.Y, (int64_t)g.X * g.Y * g.Z};
-  const int ext[4] = {g.X, g.Y, g.Z, g.T};
+  const int64_t sy = g.X, sz = (int64_t)g.X * g.Y, st = sz * g.Z;
 
   cx<R> acc[12];
-  {
-    cx<R> p[12];
 #pragma unroll
-    for (int k = 0; k < 12; k++) p[k] = P::ld(in, (int64_t)k * N + tid);
-    clover_block<P>(C, V, s, 0, p, acc);
-    clover_block<P>(C, V, s, 1, p + 6, acc + 6);
-  }
-  const R mhalf = (R)-0.5;
+  for (int k = 0; k < 12; k++) acc[k] = {0, 0};
+  // The eight hops run as a loop that is not unrolled, so only one
+  // neighbour's spinor and link are live at a time (registers stay low and
+  // occupancy high enough to cover HBM latency).
+#pragma unroll 1
+  for (int hop = 0; hop < 8; hop++) {
+    const int mu = hop >> 1;
+    const bool fwd = (hop & 1) == 0;
+    const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
+    const int ex = mu == 0 ? g.X : mu == 1 ? g.Y : mu == 2 ? g.Z : g.T;
+    const int64_t sd = mu == 0 ? 1 : mu == 1 ? sy : mu == 2 ? sz : st;
+    const bool wrap = fwd ? (cm == ex - 1) : (cm == 0);
+    const int64_t span = (int64_t)(ex - 1) * sd;
+    const int64_t sn = fwd ? (wrap ? s - span : s + sd) : (wrap ? s + span : s - sd);
+    // -1/2 (1 -/+ g_mu), times -1 on hops across the time boundary
+    const R f = (mu == 3 && wrap && g.antiperiodic) ? (R)0.5 : (R)-0.5;
+    const R sg = fwd ? (R)-1 : (R)1;  // half spinor h = u + sg * A_mu l
+    const int64_t e = sn * nrhs + r;
+    cx<R> h[2][3];
 #pragma unroll
-  for (int mu = 0; mu < 4; mu++) {
-    // forward hop: -1/2 (1 - g_mu) U_mu(x) psi(x + mu)
-    {
-      const bool wrap = (c[mu] == ext[mu] - 1);
-      const int64_t sn = wrap ? s - (int64_t)(ext[mu] - 1) * stride[mu] : s + stride[mu];
-      const R ph = (mu == 3 && wrap && g.antiperiodic) ? (R)-1 : (R)1;
-      const int64_t e = sn * nrhs + r;
-      cx<R> h[2][3];
+    for (int a = 0; a < 3; a++) {
+      cx<R> u0 = P::ld(in, (int64_t)(0 * 3 + a) * N + e), u1 = P::ld(in, (int64_t)(1 * 3 + a) * N + e);
+      cx<R> l0 = P::ld(in, (int64_t)(2 * 3 + a) * N + e), l1 = P::ld(in, (int64_t)(3 * 3 + a) * N + e);
+      cx<R> a0, a1;
+      A_times(mu, l0, l1, a0, a1);
+      h[0][a] = u0 + sg * a0;
+      h[1][a] = u1 + sg * a1;
+    }
+    // forward: U_mu(x) h ; backward: U_mu(x - mu)^H h
+    const typename P::S* Ub = U + (int64_t)(mu * 9) * V + (fwd ? s : sn);
+    cx<R> Um[3][3];
 #pragma unroll
-      for (int a = 0; a < 3; a++) {
-        cx<R> u0 = P::ld(in, (int64_t)(0 * 3 + a) * N + e), u1 = P::ld(in, (int64_t)(1 * 3 + a) * N + e);
-        cx<R> l0 = P::ld(in, (int64_t)(2 * 3 + a) * N + e), l1 = P::ld(in, (int64_t)(3 * 3 + a) * N + e);
-        cx<R> a0, a1;
-        A_times(mu, l0, l1, a0, a1);
-        h[0][a] = u0 - a0;
-        h[1][a] = u1 - a1;
-      }
-      cx<R> Um[3][3];
+    for (int k = 0; k < 9; k++) Um[k / 3][k % 3] = P::ld(Ub, (int64_t)k * V);
 #pragma unroll
-      for (int k = 0; k < 9; k++) Um[k / 3][k % 3] = P::ld(U, (int64_t)(mu * 9 + k) * V + s);
-      const R f = mhalf * ph;
-#pragma unroll
-      for (int a = 0; a < 3; a++) {
-        cx<R> g0 = {0, 0}, g1 = {0, 0};
+    for (int a = 0; a < 3; a++) {
+      cx<R> g0 = {0, 0}, g1 = {0, 0};
+      if (fwd) {
 #pragma unroll
         for (int b = 0; b < 3; b++) {
           fma_(g0, Um[a][b], h[0][b]);
           fma_(g1, Um[a][b], h[1][b]);
         }
-        g0 = f * g0;
-        g1 = f * g1;
-        cx<R> d0, d1;
-        Ad_times(mu, g0, g1, d0, d1);
-        acc[0 * 3 + a] = acc[0 * 3 + a] + g0;
-        acc[1 * 3 + a] = acc[1 * 3 + a] + g1;
-        acc[2 * 3 + a] = acc[2 * 3 + a] - d0;
-        acc[3 * 3 + a] = acc[3 * 3 + a] - d1;
-      }
-    }
-    // backward hop: -1/2 (1 + g_mu) U_mu(x - mu)^H psi(x - mu)
-    {
-      const bool wrap = (c[mu] == 0);
-      const int64_t sn = wrap ? s + (int64_t)(ext[mu] - 1) * stride[mu] : s - stride[mu];
-      const R ph = (mu == 3 && wrap && g.antiperiodic) ? (R)-1 : (R)1;
-      const int64_t e = sn * nrhs + r;
-      cx<R> h[2][3];
+      } else {
 #pragma unroll
-      for (int a = 0; a < 3; a++) {
-        cx<R> u0 = P::ld(in, (int64_t)(0 * 3 + a) * N + e), u1 = P::ld(in, (int64_t)(1 * 3 + a) * N + e);
-        cx<R> l0 = P::ld(in, (int64_t)(2 * 3 + a) * N + e), l1 = P::ld(in, (int64_t)(3 * 3 + a) * N + e);
-        cx<R> a0, a1;
-        A_times(mu, l0, l1, a0, a1);
-        h[0][a] = u0 + a0;
-        h[1][a] = u1 + a1;
-      }
-      cx<R> Um[3][3];
-#pragma unroll
-      for (int k = 0; k < 9; k++) Um[k / 3][k % 3] = P::ld(U, (int64_t)(mu * 9 + k) * V + sn);
-      const R f = mhalf * ph;
-#pragma unroll
-      for (int a = 0; a < 3; a++) {
-        cx<R> g0 = {0, 0}, g1 = {0, 0};
-#pragma unroll
-        for (int b = 0; b < 3; b++) {  // U^H: (U^H)_{ab} = conj(U_{ba})
+        for (int b = 0; b < 3; b++) {  // (U^H)_{ab} = conj(U_{ba})
           fmac_(g0, Um[b][a], h[0][b]);
           fmac_(g1, Um[b][a], h[1][b]);
         }
-        g0 = f * g0;
-        g1 = f * g1;
-        cx<R> d0, d1;
-        Ad_times(mu, g0, g1, d0, d1);
-        acc[0 * 3 + a] = acc[0 * 3 + a] + g0;
-        acc[1 * 3 + a] = acc[1 * 3 + a] + g1;
-        acc[2 * 3 + a] = acc[2 * 3 + a] + d0;
-        acc[3 * 3 + a] = acc[3 * 3 + a] + d1;
       }
+      g0 = f * g0;
+      g1 = f * g1;
+      cx<R> d0, d1;
+      Ad_times(mu, g0, g1, d0, d1);  // lower spins: -A^H g (forward), +A^H g (backward)
+      acc[0 * 3 + a] = acc[0 * 3 + a] + g0;
+      acc[1 * 3 + a] = acc[1 * 3 + a] + g1;
+      acc[2 * 3 + a] = acc[2 * 3 + a] + sg * d0;
+      acc[3 * 3 + a] = acc[3 * 3 + a] + sg * d1;
+    }
+  }
+  // site-local term: clover blocks with the mass folded into the diagonal
+#pragma unroll 1
+  for (int chi = 0; chi < 2; chi++) {
+    cx<R> p[6], q[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) p[k] = P::ld(in, (int64_t)(6 * chi + k) * N + tid);
+    clover_block<P>(C, V, s, chi, p, q);
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      if (chi == 0) acc[k] = acc[k] + q[k];
+      else acc[6 + k] = acc[6 + k] + q[k];
     }
   }
 #pragma unroll
@@ -385,19 +384,23 @@ void FineOp::apply(mgm_prec p, const void* x, void* y, int nrhs) const {
   const int64_t n = g.V * nrhs;
   const int64_t nb = (n + threads - 1) / threads;
   int kc = p == MGM_PREC_F64 ? KC_DSLASH_F64 : p == MGM_PREC_F32 ? KC_DSLASH_F32 : KC_DSLASH_F16;
+  // slab mapping needs whole 64-element chunks per slice and kSlab | T; it
+  // then covers exactly nb * 256 = V * nrhs elements
+  const int64_t per_slice = (g.V / g.T) * nrhs;
+  const int slab = (per_slice % 64 == 0 && g.T % kSlab == 0 && threads == 64 * kSlab) ? 1 : 0;
   ProfScope ps(ctx, kc, bytes(p, nrhs));
   switch (p) {
     case MGM_PREC_F64:
       hipLaunchKernelGGL(k_dslash<F64>, dim3((unsigned)nb), dim3(threads), 0, ctx->stream,
-                         (double2*)y, (const double2*)x, U64, C64, g, nrhs, nb);
+                         (double2*)y, (const double2*)x, U64, C64, g, nrhs, nb, slab);
       break;
     case MGM_PREC_F32:
       hipLaunchKernelGGL(k_dslash<F32>, dim3((unsigned)nb), dim3(threads), 0, ctx->stream,
-                         (float2*)y, (const float2*)x, U32, C32, g, nrhs, nb);
+                         (float2*)y, (const float2*)x, U32, C32, g, nrhs, nb, slab);
       break;
     case MGM_PREC_F16:
       hipLaunchKernelGGL(k_dslash<F16>, dim3((unsigned)nb), dim3(threads), 0, ctx->stream,
-                         (__half2*)y, (const __half2*)x, U16, C16, g, nrhs, nb);
+                         (__half2*)y, (const __half2*)x, U16, C16, g, nrhs, nb, slab);
       break;
     default:
       throw Error(MGM_ERR_INVALID_ARG, "dslash precision must be F64, F32 or F16");

@@ -41,10 +41,18 @@ struct Run {
     cfg.kind = d.solve.kind;
     cfg.smooth = d.solve.smooth;
     cfg.coarse_iters = d.solve.coarse_iters;
-    cfg.inner_tol = d.solve.inner_tol;
+    cfg.inner_tol = d.solve.inner_tol > 0 ? d.solve.inner_tol : 1e-5;
+    cfg.coarse_bf16 = d.solve.coarse_bf16 != 0;
     cfg.net = (Net*)d.solve.net;
   }
   Vec v(int l, void* p, int nb) { return H.vec(l, MGM_PREC_F64, p, nb); }
+  // right-hand sides per launch for probe group g, bounded by level capacity
+  int batch(int g, int level_cap) const {
+    int b = d.batch_level[g] > 0 ? d.batch_level[g] : d.batch;
+    MGM_CHECK(b >= 1 && b <= H.cap(level_cap), MGM_ERR_INVALID_ARG,
+              "batch exceeds the right-hand-side capacity of level " + std::to_string(level_cap));
+    return b;
+  }
   void solve(int l, const double2* b, double2* x, int nb) { mgm::solve(H, l, cfg, b, x, nb, &so); }
   // Z4 probes of stream (ls, kind) on the lattice of level `lat`
   void z4(int ls, int kind, int lat, uint64_t first, int nb, double2* out, int slice = -1) {
@@ -137,11 +145,12 @@ mgm_estimate_sizes estimate_sizes(const Hier& H, const mgm_estimate_desc& d) {
 static void trace_terms(Run& R, std::vector<TermAcc>& acc) {
   Hier& H = R.H;
   EstWS& E = H.est;
-  const int L = R.L, dec = R.d.decomposition, B = R.d.batch;
+  const int L = R.L, dec = R.d.decomposition;
   const int nt = (int)acc.size();
   for (int term = 0; term < nt; term++) {
     const int lv = term_level(dec, L, term);
     const int N = R.d.nprobe[lv];
+    const int B = R.batch(lv, lv);
     TermAcc& A = acc[term];
     double t0 = now_s();
     for (int b0 = 0; b0 < N; b0 += B) {
@@ -278,7 +287,7 @@ static void term_vectors(Run& R, int g, const double2* eta, int nb, const std::v
 static void corr_terms(Run& R, std::vector<TermAcc>& acc) {
   Hier& H = R.H;
   EstWS& E = H.est;
-  const int L = R.L, dec = R.d.decomposition, B = R.d.batch;
+  const int L = R.L, dec = R.d.decomposition;
   const int Rn = nterms_for(MGM_OBS_CORR_PS, dec, L);
   const int T = H.g[0].dims[3];
   const int64_t Vs = H.g[0].V / T;
@@ -300,6 +309,7 @@ static void corr_terms(Run& R, std::vector<TermAcc>& acc) {
         if (std::min(term_level(dec, L, r), term_level(dec, L, s)) == g) pairs.push_back(r * Rn + s);
     if (pairs.empty()) continue;
     const int N = R.d.nprobe[g];
+    const int B = R.batch(g, 0);  // sources live on the fine lattice
     double t0 = now_s();
     for (int b0 = 0; b0 < N; b0 += B) {
       const int nb = std::min(B, N - b0);
@@ -358,7 +368,7 @@ static void corr_terms(Run& R, std::vector<TermAcc>& acc) {
 static void loop_terms(Run& R, std::vector<TermAcc>& acc) {
   Hier& H = R.H;
   EstWS& E = H.est;
-  const int L = R.L, dec = R.d.decomposition, B = R.d.batch;
+  const int L = R.L, dec = R.d.decomposition;
   const int Rn = nterms_for(MGM_OBS_LOOPS, dec, L);
   const int T = H.g[0].dims[3];
   const int64_t Vs = H.g[0].V / T;
@@ -372,6 +382,7 @@ static void loop_terms(Run& R, std::vector<TermAcc>& acc) {
       if (term_level(dec, L, r) == g) terms.push_back(r);
     if (terms.empty()) continue;
     const int N = R.d.nprobe[g];
+    const int B = R.batch(g, 0);  // sources live on the fine lattice
     double t0 = now_s();
     for (int b0 = 0; b0 < N; b0 += B) {
       const int nb = std::min(B, N - b0);
@@ -405,7 +416,7 @@ static void loop_terms(Run& R, std::vector<TermAcc>& acc) {
 // -------------------------------------------------------------- driver
 
 void estimate(Hier& H, const mgm_estimate_desc& d, mgm_estimate_result* out) {
-  MGM_CHECK(d.batch >= 1 && d.batch <= H.desc.max_nrhs, MGM_ERR_INVALID_ARG, "batch must be 1..max_nrhs");
+  MGM_CHECK(d.batch >= 1, MGM_ERR_INVALID_ARG, "batch must be >= 1");
   MGM_CHECK(d.decomposition >= 0 && d.decomposition <= 2 && d.observable >= 0 && d.observable <= 2,
             MGM_ERR_INVALID_ARG, "bad observable or decomposition");
   for (int l = 0; l < H.L; l++) MGM_CHECK(d.nprobe[l] >= 0, MGM_ERR_INVALID_ARG, "negative probe count");

@@ -76,15 +76,16 @@ void Hier::layout(Arena& a) {
     CoarseOp& C = A[l + 1];
     size_t na = (size_t)9 * C.d * C.d * C.g.V;
     C.A64 = a.take_n<double2>(na);
+    C.Ap64 = (double2*)a.take(mg_mfma64_bytes(C));
     if (mixed) {
-      C.A32 = a.take_n<float2>(na);
+      C.A32 = (float2*)a.take(mg_mfma32_bytes(C));
       C.Abf = a.take(mg_mfma_bytes(C));
     }
   }
   d_flag = a.take_n<int>(64);
   int ntv_max = 0;
   for (int l = 0; l + 1 < L; l++) ntv_max = std::max(ntv_max, desc.ntv[l]);
-  const int nmax = std::max(desc.max_nrhs, 1);
+  const int nmax = cap(L - 1), nfine = cap(0);
   const int red_n = std::max(nmax, ntv_max);
   const int m = desc.restart;
   scratch.cap = (size_t)kRedBlocksMax * 8 * red_n;
@@ -98,7 +99,7 @@ void Hier::layout(Arena& a) {
   est.u.assign(L, nullptr);
   est.v.assign(L, nullptr);
   for (int l = 0; l < L; l++) {
-    size_t nb = (size_t)n(l) * nmax;
+    size_t nb = (size_t)n(l) * cap(l);
     est.x[l] = a.take_n<double2>(nb);
     est.y[l] = a.take_n<double2>(nb);
     est.z[l] = a.take_n<double2>(nb);
@@ -111,13 +112,13 @@ void Hier::layout(Arena& a) {
   if (desc.with_corr) {
     int nterm = 4 * L - 3;
     est.term.assign(nterm, nullptr);
-    for (int i = 0; i < nterm; i++) est.term[i] = a.take_n<double2>((size_t)n(0) * nmax);
-    est.eta = a.take_n<double2>((size_t)n(0) * nmax);
+    for (int i = 0; i < nterm; i++) est.term[i] = a.take_n<double2>((size_t)n(0) * nfine);
+    est.eta = a.take_n<double2>((size_t)n(0) * nfine);
     const int T_ = g[0].dims[3];
-    size_t np = (size_t)kSliceChunksHost * kMaxPairs * nmax * T_;
-    size_t nl = (size_t)kSliceChunksHost * kMaxLoopVecs * 6 * nmax * T_;
+    size_t np = (size_t)kSliceChunksHost * kMaxPairs * nfine * T_;
+    size_t nl = (size_t)kSliceChunksHost * kMaxLoopVecs * 6 * nfine * T_;
     est.slice_partial = a.take_n<double2>(std::max(np, nl));
-    est.slice_out = a.take_n<double2>((size_t)std::max(kMaxPairs, kMaxLoopVecs * 6) * nmax * T_);
+    est.slice_out = a.take_n<double2>((size_t)std::max(kMaxPairs, kMaxLoopVecs * 6) * nfine * T_);
   }
   // union region: solver workspaces or setup buffers
   const size_t base = a.off;
@@ -125,8 +126,8 @@ void Hier::layout(Arena& a) {
   ws32.assign(L, LevelWS{});
   ws16.assign(L, LevelWS{});
   for (int l = 0; l < L; l++) {
-    carve_ws(a, ws64[l], MGM_PREC_F64, n(l), nmax, m, full64);
-    if (mixed) carve_ws(a, ws32[l], MGM_PREC_F32, n(l), nmax, m, true);
+    carve_ws(a, ws64[l], MGM_PREC_F64, n(l), cap(l), m, full64);
+    if (mixed) carve_ws(a, ws32[l], MGM_PREC_F32, n(l), cap(l), m, true);
   }
   const size_t solver_end = a.off;
   a.off = base;
@@ -175,6 +176,7 @@ void Hier::build() {
       mg_galerkin_fine(c, *fine, T[0], A[1]);
     else
       mg_galerkin_coarse(c, A[l], T[l], A[l + 1]);
+    mg_mfma64_pack(c, A[l + 1]);
     if (desc.mixed) {
       mg_convert_P(c, T[l]);
       mg_convert_A(c, A[l + 1]);

@@ -79,6 +79,15 @@ struct Hier {
   Net* net = nullptr;
 
   int64_t n(int l) const { return g[l].V * g[l].dof; }
+  // right-hand-side capacity of level l (non-decreasing towards coarse levels)
+  int cap(int l) const {
+    int c = 0;
+    for (int k = 0; k <= l; k++) {
+      int v = desc.max_nrhs_level[k] > 0 ? desc.max_nrhs_level[k] : desc.max_nrhs;
+      c = std::max(c, v);
+    }
+    return c;
+  }
   Vec vec(int l, mgm_prec p, void* ptr, int nrhs) const {
     Vec v;
     v.p = ptr;
@@ -106,6 +115,7 @@ struct SolveCfg {
   int smooth = 2;
   int coarse_iters = 12;
   double inner_tol = 1e-5;
+  bool coarse_bf16 = false;
   Net* net = nullptr;
 };
 

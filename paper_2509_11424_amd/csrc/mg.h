@@ -41,7 +41,8 @@ struct CoarseOp {
   int d = 0;
   double2* A64 = nullptr;
   float2* A32 = nullptr;
-  void* Abf = nullptr;  // BF16 MFMA operand layout (see coarse_mfma.hip)
+  double2* Ap64 = nullptr;  // FP64 MFMA operand layout (see coarse_mfma.hip)
+  void* Abf = nullptr;      // BF16 MFMA operand layout
   void apply(mgm_prec p, const void* x, void* y, int nrhs) const;
   double bytes(mgm_prec p, int nrhs) const;
 };
@@ -63,5 +64,12 @@ void mg_convert_A(Context* c, CoarseOp& A);
 void mg_mfma_pack(Context* c, CoarseOp& A);
 size_t mg_mfma_bytes(const CoarseOp& A);
 void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs);
+void mg_mfma64_pack(Context* c, CoarseOp& A);
+size_t mg_mfma64_bytes(const CoarseOp& A);
+void coarse_apply_mfma64(const CoarseOp& A, const double2* x, double2* y, int nrhs);
+// FP32 copy in the same packed operand layout (made from the FP64 pack)
+void mg_mfma32_pack(Context* c, CoarseOp& A);
+size_t mg_mfma32_bytes(const CoarseOp& A);
+void coarse_apply_mfma32(const CoarseOp& A, const float2* x, float2* y, int nrhs);
 
 }  // namespace mgm

@@ -464,76 +464,28 @@ void mg_galerkin_coarse(Context* c, const CoarseOp& op, const Transfer& T, Coars
 
 // ------------------------------------------------------- coarse stencil
 
-// y(s) = sum_dir A[dir](s) x(nbr(s, dir)); one thread per (rhs, site, tile
-// of kTI rows), rhs fastest so lanes of one site share A (broadcast) and
-// consecutive sites read consecutive A addresses.
-constexpr int kTI = 8;
-
-template <class P, class PA>
-__global__ __launch_bounds__(256) void k_coarse_apply(const typename P::S* __restrict__ x,
-                                                      typename P::S* __restrict__ y,
-                                                      const typename PA::S* __restrict__ A, LGeom g, int d,
-                                                      int nrhs, int64_t nblocks) {
-  using R = typename P::R;
-  const int64_t blk = xcd_block(blockIdx.x, nblocks);
-  const int64_t tid = blk * blockDim.x + threadIdx.x;
-  const int64_t V = g.V;
-  const int ntile = (d + kTI - 1) / kTI;
-  if (tid >= V * nrhs * ntile) return;
-  const int r = (int)(tid % nrhs);
-  int64_t q = tid / nrhs;
-  const int64_t s = q % V;
-  const int it = (int)(q / V);
-  const int i0 = it * kTI;
-  int c[4];
-  coords_of(g, s, c);
-  cx<R> acc[kTI];
-#pragma unroll
-  for (int ii = 0; ii < kTI; ii++) acc[ii] = {0, 0};
-  for (int dir = 0; dir < 9; dir++) {
-    const int64_t sn = hop_neighbour(g, c, dir);
-    const typename PA::S* Ad = A + (int64_t)dir * d * d * V + s;
-    for (int j = 0; j < d; j++) {
-      cx<R> xv = P::ld(x, ((int64_t)j * V + sn) * nrhs + r);
-#pragma unroll
-      for (int ii = 0; ii < kTI; ii++) {
-        if (i0 + ii < d) {
-          cx<typename PA::R> av = PA::ld(Ad, ((int64_t)(i0 + ii) * d + j) * V);
-          fma_(acc[ii], cx<R>{(R)av.re, (R)av.im}, xv);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int ii = 0; ii < kTI; ii++)
-    if (i0 + ii < d) P::st(y, ((int64_t)(i0 + ii) * V + s) * nrhs + r, acc[ii]);
-}
+// y(s) = sum_dir A[dir](s) x(nbr(s, dir)) runs on the matrix cores
+// (coarse_mfma.hip): FP64 and FP32 with 16x16x4 MFMAs, BF16 operands with
+// FP32 accumulation for the mixed-precision preconditioner.
 
 double CoarseOp::bytes(mgm_prec p, int nrhs) const {
+  // algorithmic bytes: nine complex d x d blocks once, x and y once
   double wa = p == MGM_PREC_F64 ? 16.0 : p == MGM_PREC_F32 ? 8.0 : 4.0;
   double wv = p == MGM_PREC_F64 ? 16.0 : 8.0;
   return (double)g.V * (9.0 * d * d * wa + 2.0 * d * nrhs * wv);
 }
 
 void CoarseOp::apply(mgm_prec p, const void* x, void* y, int nrhs) const {
-  const int ntile = (d + kTI - 1) / kTI;
-  const int64_t n = g.V * nrhs * ntile;
-  const int64_t nb = (n + 255) / 256;
   if (p == MGM_PREC_F64) {
-    ProfScope ps(ctx, KC_COARSE_F64, bytes(p, nrhs));
-    hipLaunchKernelGGL((k_coarse_apply<F64, F64>), dim3((unsigned)nb), dim3(256), 0, ctx->stream,
-                       (const double2*)x, (double2*)y, A64, g, d, nrhs, nb);
+    coarse_apply_mfma64(*this, (const double2*)x, (double2*)y, nrhs);
   } else if (p == MGM_PREC_F32) {
-    ProfScope ps(ctx, KC_COARSE_F32, bytes(p, nrhs));
-    hipLaunchKernelGGL((k_coarse_apply<F32, F32>), dim3((unsigned)nb), dim3(256), 0, ctx->stream,
-                       (const float2*)x, (float2*)y, A32, g, d, nrhs, nb);
+    MGM_CHECK(A32 != nullptr, MGM_ERR_INVALID_ARG, "FP32 coarse stencil not built (mixed == 0)");
+    coarse_apply_mfma32(*this, (const float2*)x, (float2*)y, nrhs);
   } else if (p == MGM_PREC_BF16) {
     coarse_apply_mfma(*this, (const float2*)x, (float2*)y, nrhs);
-    return;
   } else {
     throw Error(MGM_ERR_INVALID_ARG, "coarse apply: unsupported precision");
   }
-  MGM_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------- conversions
@@ -549,10 +501,6 @@ void mg_convert_P(Context* c, Transfer& T) {
   MGM_LAUNCH_CHECK();
 }
 
-void mg_convert_A(Context* c, CoarseOp& A) {
-  int64_t n = 9 * (int64_t)A.d * A.d * A.g.V;
-  hipLaunchKernelGGL(k_c64_to_c32, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, A.A32, A.A64, n);
-  MGM_LAUNCH_CHECK();
-}
+void mg_convert_A(Context* c, CoarseOp& A) { mg_mfma32_pack(c, A); }
 
 }  // namespace mgm

@@ -17,14 +17,24 @@
 
 namespace mgm {
 
-static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu) {
+// Level operator as used inside a preconditioner: FP32 coarse levels may use
+// BF16 MFMA operands; the Arnoldi operator of a solve is always exact in p.
+static void op_apply(Hier& H, int l, mgm_prec p, bool inner, const SolveCfg& cfg, const void* x, void* y,
+                     int nrhs) {
+  if (inner && l >= 1 && p == MGM_PREC_F32 && cfg.coarse_bf16 && H.A[l].Abf != nullptr)
+    H.A[l].apply(MGM_PREC_BF16, x, y, nrhs);
+  else
+    H.apply(l, p, x, y, nrhs);
+}
+
+static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const SolveCfg& cfg) {
   LevelWS& w = H.ws(l, p);
   Context* c = H.ctx;
   Vec rho = b.with(w.rho), q = b.with(w.q);
   b_zero(c, y);
   b_copy(c, rho, b);
   for (int i = 0; i < nu; i++) {
-    H.apply(l, p, rho.p, q.p, b.nrhs);
+    op_apply(H, l, p, true, cfg, rho.p, q.p, b.nrhs);
     b_dot_norm(c, H.scratch, q, rho, w.qr, w.qq);
     b_mr_update(c, w.qr, w.qq, rho, q, y);
   }
@@ -39,7 +49,7 @@ static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg
     net_apply(H, *cfg.net, r, e);
     return;
   }
-  mr_smooth(H, l, p, r, e, cfg.smooth);
+  mr_smooth(H, l, p, r, e, cfg.smooth, cfg);
 }
 
 void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
@@ -52,14 +62,14 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
   const int nrhs = r.nrhs;
   Vec t = r.with(w.t);
   smooth(H, l, p, r, e, cfg);
-  H.apply(l, p, e.p, t.p, nrhs);
+  op_apply(H, l, p, true, cfg, e.p, t.p, nrhs);
   b_xpay(c, r, nullptr, -1.0, t);  // t = r - D e
   LevelWS& wc = H.ws(l + 1, p);
   Vec rc = H.vec(l + 1, p, wc.bc, nrhs), ec = H.vec(l + 1, p, wc.xc, nrhs);
   H.T[l].restrict_(p, t.p, rc.p, nrhs);
   fgmres_fixed(H, l + 1, p, rc, ec, cfg.coarse_iters, l + 1 < H.L - 1, cfg);
   H.T[l].prolong(p, ec.p, nullptr, e.p, nrhs, 2);  // e += P e_c
-  H.apply(l, p, e.p, t.p, nrhs);
+  op_apply(H, l, p, true, cfg, e.p, t.p, nrhs);
   b_xpay(c, r, nullptr, -1.0, t);
   Vec y = r.with(w.y);
   smooth(H, l, p, t, y, cfg);
@@ -69,7 +79,7 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
 // Arnoldi steps from a normalised V_0 and started Givens state.  stop (host,
 // per rhs) enables the lagged early exit when every estimate falls below it.
 static int arnoldi(Hier& H, int l, mgm_prec p, int nrhs, int kmax, bool precond, const SolveCfg& cfg,
-                   const double* stop) {
+                   const double* stop, bool inner) {
   Context* c = H.ctx;
   LevelWS& w = H.ws(l, p);
   Givens& G = w.G;
@@ -88,7 +98,7 @@ static int arnoldi(Hier& H, int l, mgm_prec p, int nrhs, int kmax, bool precond,
     char* Zj = precond ? (char*)w.Z + (size_t)j * stride * eb : Vj;
     char* W = (char*)w.V + (size_t)(j + 1) * stride * eb;
     if (precond) vcycle(H, l, p, base.with(Vj), base.with(Zj), cfg);
-    H.apply(l, p, Zj, W, nrhs);
+    op_apply(H, l, p, inner, cfg, Zj, W, nrhs);
     Vec Wv = base.with(W);
     b_multidot(c, H.scratch, base, stride, j + 1, Wv, G.h);
     b_multiaxpy(c, H.scratch, base, stride, j + 1, G.h, -1.0, Wv, nullptr);
@@ -129,7 +139,7 @@ static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool p
   b_copy(c, V0, b);
   b_normalize(c, V0, w.n2a, nullptr);
   k_gmres_start(c, w.G, w.n2a, nrhs);
-  int kk = arnoldi(H, l, p, nrhs, std::min(k, w.m), precond, cfg, nullptr);
+  int kk = arnoldi(H, l, p, nrhs, std::min(k, w.m), precond, cfg, nullptr, true);
   b_zero(c, x);
   b_multiaxpy(c, H.scratch, b.with(precond ? w.Z : w.V), H.n(l) * nrhs, kk, w.G.y, 1.0, x, nullptr);
 }
@@ -183,7 +193,7 @@ static void fgmres_tol(Hier& H, int l, mgm_prec p, Vec b, Vec x, double tol_rel,
     b_scale_rhs(c, V0, w.mask);
     k_gmres_start(c, w.G, w.n2b, nrhs);
     c->sync();  // the staging buffer is reused by arnoldi
-    int k = arnoldi(H, l, p, nrhs, std::min(w.m, maxsteps - steps), precond, cfg, stop.data());
+    int k = arnoldi(H, l, p, nrhs, std::min(w.m, maxsteps - steps), precond, cfg, stop.data(), false);
     b_multiaxpy(c, H.scratch, b.with(precond ? w.Z : w.V), H.n(l) * nrhs, k, w.G.y, 1.0, x, nullptr);
     steps += k;
     if (out) {
@@ -263,7 +273,7 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
 
 void solve(Hier& H, int l, const SolveCfg& cfg, const double2* b, double2* x, int nrhs, SolveOut* out) {
   MGM_CHECK(l >= 0 && l < H.L, MGM_ERR_INVALID_ARG, "level out of range");
-  MGM_CHECK(nrhs >= 1 && nrhs <= H.desc.max_nrhs, MGM_ERR_INVALID_ARG, "nrhs exceeds max_nrhs");
+  MGM_CHECK(nrhs >= 1 && nrhs <= H.cap(l), MGM_ERR_INVALID_ARG, "nrhs exceeds the capacity of the level");
   H.tv_valid = false;
   Vec bv = H.vec(l, MGM_PREC_F64, (void*)b, nrhs), xv = H.vec(l, MGM_PREC_F64, x, nrhs);
   const int m = H.desc.restart;
