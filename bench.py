@@ -134,7 +134,7 @@ def run(args):
     torch.cuda.synchronize()
     t_setup = time.time() - t0
     kind = "mg_mixed" if mixed else "mg"
-    sd = m.solve_desc(tol=1e-10, kind=kind, smooth=2, coarse_iters=8, inner_tol=1e-5, maxiter=5000,
+    sd = m.solve_desc(tol=1e-10, kind=kind, smooth=4, coarse_iters=4, inner_tol=1e-5, maxiter=5000,
                       coarse_bf16=True)
     batch = cfg["batch"]
 
@@ -232,7 +232,7 @@ def time_to_target(m, ctx, op, cfg, h_mixed, sd_mixed, args):
     # the configured probe counts
     h64 = m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=cfg["batch"][0],
                       max_nrhs_level=cfg["batch"], restart=cfg["restart"], mixed=0)
-    sd64 = m.solve_desc(tol=1e-10, kind="mg", smooth=2, coarse_iters=8, maxiter=5000)
+    sd64 = m.solve_desc(tol=1e-10, kind="mg", smooth=4, coarse_iters=4, maxiter=5000)
     p64 = pilot(h64, sd64)
     eps2 = p64["total_var"]
     out = {"eps2": eps2, "f64": final(h64, sd64, p64, eps2)}

@@ -210,38 +210,46 @@ __device__ __forceinline__ void block_store(double2 (&v)[K], double2* partial, i
   }
 }
 
-__global__ void k_finalize_c(const double2* partial, int nblk, int K, int nrhs, int cnt, double2* out,
-                             int64_t out_off) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
-  double sr = 0, si = 0;
-  for (int b = 0; b < nblk; b++) {
-    double2 v = partial[(int64_t)b * K * nrhs + i];
-    sr += v.x;
-    si += v.y;
-  }
-  out[out_off + i] = make_double2(sr, si);
-}
-__global__ void k_finalize_r(const double2* partial, int nblk, int K, int nrhs, double* out) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= K * nrhs) return;
-  double s = 0;
-  for (int b = 0; b < nblk; b++) s += partial[(int64_t)b * K * nrhs + i].x;
-  out[i] = s;
-}
-// q^H rho and |q|^2 -> separate outputs
-__global__ void k_finalize_dn(const double2* partial, int nblk, int nrhs, double2* qr, double* qq) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrhs) return;
-  double a = 0, b = 0, d = 0;
-  for (int k = 0; k < nblk; k++) {
-    double2 v = partial[(int64_t)k * 2 * nrhs + i];
+// Second stage of every reduction: one 64-lane wave per output entry; lane j
+// sums block partials j, j+64, ... and a fixed shuffle tree adds the lanes.
+__device__ __forceinline__ double2 wave_sum_partials(const double2* partial, int nblk, int stride, int i) {
+  double a = 0, b = 0;
+  for (int k = threadIdx.x; k < nblk; k += 64) {
+    double2 v = partial[(int64_t)k * stride + i];
     a += v.x;
     b += v.y;
-    d += partial[(int64_t)k * 2 * nrhs + nrhs + i].x;
   }
-  qr[i] = make_double2(a, b);
-  qq[i] = d;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  return make_double2(a, b);
+}
+
+// out[out_off + i] = sum_b partial[b][K][nrhs] entry i, for i < cnt (grid = cnt)
+__global__ void k_finalize_c(const double2* partial, int nblk, int K, int nrhs, int cnt, double2* out,
+                             int64_t out_off) {
+  const int i = blockIdx.x;
+  double2 v = wave_sum_partials(partial, nblk, K * nrhs, i);
+  if (threadIdx.x == 0) out[out_off + i] = v;
+}
+// real parts, i < K * nrhs (grid = K * nrhs)
+__global__ void k_finalize_r(const double2* partial, int nblk, int K, int nrhs, double* out) {
+  const int i = blockIdx.x;
+  double2 v = wave_sum_partials(partial, nblk, K * nrhs, i);
+  if (threadIdx.x == 0) out[i] = v.x;
+}
+// q^H rho (slot 0) and |q|^2 (slot 1) -> separate outputs (grid = 2 * nrhs)
+__global__ void k_finalize_dn(const double2* partial, int nblk, int nrhs, double2* qr, double* qq) {
+  const int i = blockIdx.x;
+  double2 v = wave_sum_partials(partial, nblk, 2 * nrhs, i);
+  if (threadIdx.x == 0) {
+    if (i < nrhs)
+      qr[i] = v;
+    else
+      qq[i - nrhs] = v.x;
+  }
 }
 
 static void need(Scratch& s, size_t entries) {
@@ -269,7 +277,7 @@ void b_dot(Context* c, Scratch& s, Vec x, Vec y, double2* out) {
   need(s, (size_t)pl.blocks * x.nrhs);
   DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_dot<P>, dim3(pl.blocks), dim3(256), 0, c->stream, x.p, y.p,
                                               x.nrhs, pl, s.partial));
-  hipLaunchKernelGGL(k_finalize_c, dim3(nblocks_for(x.nrhs, 64)), dim3(64), 0, c->stream, s.partial,
+  hipLaunchKernelGGL(k_finalize_c, dim3(x.nrhs), dim3(64), 0, c->stream, s.partial,
                      (int)pl.blocks, 1, x.nrhs, x.nrhs, out, (int64_t)0);
   MGM_LAUNCH_CHECK();
 }
@@ -292,7 +300,7 @@ void b_norm2(Context* c, Scratch& s, Vec x, double* out) {
   need(s, (size_t)pl.blocks * x.nrhs);
   DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_norm2<P>, dim3(pl.blocks), dim3(256), 0, c->stream, x.p,
                                               x.nrhs, pl, s.partial));
-  hipLaunchKernelGGL(k_finalize_r, dim3(nblocks_for(x.nrhs, 64)), dim3(64), 0, c->stream, s.partial,
+  hipLaunchKernelGGL(k_finalize_r, dim3(x.nrhs), dim3(64), 0, c->stream, s.partial,
                      (int)pl.blocks, 1, x.nrhs, out);
   MGM_LAUNCH_CHECK();
 }
@@ -322,7 +330,7 @@ void b_dot_norm(Context* c, Scratch& s, Vec q, Vec rho, double2* qr, double* qq)
   need(s, (size_t)pl.blocks * 2 * q.nrhs);
   DISPATCH_PREC(q.prec, P, hipLaunchKernelGGL(k_dot_norm<P>, dim3(pl.blocks), dim3(256), 0, c->stream, q.p,
                                               rho.p, q.nrhs, pl, s.partial));
-  hipLaunchKernelGGL(k_finalize_dn, dim3(nblocks_for(q.nrhs, 64)), dim3(64), 0, c->stream, s.partial,
+  hipLaunchKernelGGL(k_finalize_dn, dim3(2 * q.nrhs), dim3(64), 0, c->stream, s.partial,
                      (int)pl.blocks, q.nrhs, qr, qq);
   MGM_LAUNCH_CHECK();
 }
@@ -364,7 +372,7 @@ void b_multidot(Context* c, Scratch& s, Vec base, int64_t stride, int k, Vec w, 
       hipLaunchKernelGGL((k_multidot<P, 8>), dim3(pl.blocks), dim3(256), 0, c->stream, (const void*)b0, stride,
                          kk, w.p, w.nrhs, pl, s.partial);
     });
-    hipLaunchKernelGGL(k_finalize_c, dim3(nblocks_for(kk * w.nrhs, 64)), dim3(64), 0, c->stream, s.partial,
+    hipLaunchKernelGGL(k_finalize_c, dim3(kk * w.nrhs), dim3(64), 0, c->stream, s.partial,
                        (int)pl.blocks, KB, w.nrhs, kk * w.nrhs, out, (int64_t)i0 * w.nrhs);
     MGM_LAUNCH_CHECK();
   }
@@ -406,8 +414,67 @@ void b_multiaxpy(Context* c, Scratch& s, Vec base, int64_t stride, int k, const 
                                               (const void*)base.p, stride, k, h, sgn, w.p, w.nrhs, pl,
                                               s.partial, n2 ? 1 : 0));
   if (n2)
-    hipLaunchKernelGGL(k_finalize_r, dim3(nblocks_for(w.nrhs, 64)), dim3(64), 0, c->stream, s.partial,
+    hipLaunchKernelGGL(k_finalize_r, dim3(w.nrhs), dim3(64), 0, c->stream, s.partial,
                        (int)pl.blocks, 1, w.nrhs, n2);
+  MGM_LAUNCH_CHECK();
+}
+
+void b_finalize_dot_norm(Context* c, const double2* part, int nblk, int nrhs, double2* qr, double* qq) {
+  hipLaunchKernelGGL(k_finalize_dn, dim3(2 * nrhs), dim3(64), 0, c->stream, part, nblk, nrhs, qr, qq);
+  MGM_LAUNCH_CHECK();
+}
+
+// One sweep of the re-orthogonalising Gram-Schmidt step: w <- w - sum_i h_i V_i
+// and, from the same registers, out_i = V_i^H w (updated w), i < k <= kFusedGS.
+template <class P>
+__global__ void k_multiaxpy_dot(const void* base, int64_t stride, int k, const double2* h, void* w, int nrhs,
+                                RedPlan pl, double2* partial) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 v[kFusedGS];
+#pragma unroll
+  for (int i = 0; i < kFusedGS; i++) v[i] = make_double2(0, 0);
+  if (g < pl.J * nrhs) {
+    const int r = (int)(g % nrhs);
+    const int64_t j = g / nrhs;
+    const typename P::S* B = (const typename P::S*)base;
+    cx<double> hc[kFusedGS], a[kFusedGS];
+#pragma unroll
+    for (int i = 0; i < kFusedGS; i++) {
+      a[i] = {0, 0};
+      double2 hh = i < k ? h[(int64_t)i * nrhs + r] : make_double2(0, 0);
+      hc[i] = {-hh.x, -hh.y};
+    }
+    for (int64_t m = j; m < pl.m; m += pl.J) {
+      const int64_t e = m * nrhs + r;
+      cx<double> wv = ldd<P>(w, e);
+      cx<double> vv[kFusedGS];
+#pragma unroll
+      for (int i = 0; i < kFusedGS; i++)
+        if (i < k) {
+          vv[i] = ldd<P>(B + i * stride, e);
+          fma_(wv, hc[i], vv[i]);
+        }
+      std_<P>(w, e, wv);
+      const cx<double> ws = ldd<P>(w, e);  // dots of the stored (rounded) vector
+#pragma unroll
+      for (int i = 0; i < kFusedGS; i++)
+        if (i < k) fmac_(a[i], vv[i], ws);
+    }
+#pragma unroll
+    for (int i = 0; i < kFusedGS; i++) v[i] = make_double2(a[i].re, a[i].im);
+  }
+  block_store<kFusedGS>(v, partial, nrhs);
+}
+
+void b_multiaxpy_dot(Context* c, Scratch& s, Vec base, int64_t stride, int k, const double2* h, Vec w,
+                     double2* out) {
+  MGM_CHECK(k <= kFusedGS, MGM_ERR_INVALID_ARG, "fused Gram-Schmidt sweep limited to 16 vectors");
+  RedPlan pl = red_plan(w.n(), w.nrhs);
+  need(s, (size_t)pl.blocks * kFusedGS * w.nrhs);
+  DISPATCH_PREC(w.prec, P, hipLaunchKernelGGL(k_multiaxpy_dot<P>, dim3(pl.blocks), dim3(256), 0, c->stream,
+                                              (const void*)base.p, stride, k, h, w.p, w.nrhs, pl, s.partial));
+  hipLaunchKernelGGL(k_finalize_c, dim3(k * w.nrhs), dim3(64), 0, c->stream, s.partial, (int)pl.blocks, kFusedGS,
+                     w.nrhs, k * w.nrhs, out, (int64_t)0);
   MGM_LAUNCH_CHECK();
 }
 

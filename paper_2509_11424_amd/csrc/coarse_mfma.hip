@@ -141,16 +141,19 @@ struct M32 {
 };
 
 template <class M, int MT>
-__global__ __launch_bounds__(64) void k_coarse_mfma4(const typename M::C2* __restrict__ x,
+__global__ __launch_bounds__(256) void k_coarse_mfma4(const typename M::C2* __restrict__ x,
                                                      typename M::C2* __restrict__ y,
                                                      const typename M::C2* __restrict__ Ap, LGeom g, int d, int KC,
                                                      int nrhs, int ntr) {
   using R = typename M::R;
   using V4 = typename M::V4;
   using C2 = typename M::C2;
-  const int64_t s = blockIdx.x / ntr;
-  const int nt = blockIdx.x % ntr;
-  const int lane = threadIdx.x;
+  // one workgroup per site, one wave per 16-rhs tile: the tiles of a site
+  // stream the same A fragments through the CU's caches at the same time
+  const int64_t s = blockIdx.x;
+  const int nt = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (nt >= ntr) return;
   const int n = lane & 15, kq = lane >> 4;
   const int r = nt * 16 + n;
   const int64_t V = g.V;
@@ -194,12 +197,15 @@ __global__ __launch_bounds__(64) void k_coarse_mfma4(const typename M::C2* __res
 }
 
 template <int MT>
-__global__ __launch_bounds__(64) void k_coarse_mfma_bf16(const float2* __restrict__ x, float2* __restrict__ y,
+__global__ __launch_bounds__(256) void k_coarse_mfma_bf16(const float2* __restrict__ x, float2* __restrict__ y,
                                                          const uint16_t* __restrict__ Ap, LGeom g, int d, int KC,
                                                          int nrhs, int ntr) {
-  const int64_t s = blockIdx.x / ntr;
-  const int nt = blockIdx.x % ntr;
-  const int lane = threadIdx.x;
+  // one workgroup per site, one wave per 16-rhs tile: the tiles of a site
+  // stream the same A fragments through the CU's caches at the same time
+  const int64_t s = blockIdx.x;
+  const int nt = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (nt >= ntr) return;
   const int n = lane & 15, kq = lane >> 4;
   const int r = nt * 16 + n;
   const int64_t V = g.V;
@@ -263,9 +269,9 @@ __global__ __launch_bounds__(64) void k_coarse_mfma_bf16(const float2* __restric
 void coarse_apply_mfma64(const CoarseOp& A, const double2* x, double2* y, int nrhs) {
   MGeo m = mgeo(A.d);
   const int ntr = (nrhs + 15) / 16;
-  const unsigned nb = (unsigned)(A.g.V * ntr);
+  const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + 3) / 4)), tb(64 * std::min(ntr, 4));
   ProfScope ps(A.ctx, KC_COARSE_F64, A.bytes(MGM_PREC_F64, nrhs));
-  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M64, MTc>), dim3(nb), dim3(64), 0, A.ctx->stream, x, y,
+  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M64, MTc>), nb, tb, 0, A.ctx->stream, x, y,
                                        A.Ap64, A.g, A.d, m.KC64, nrhs, ntr));
   MGM_LAUNCH_CHECK();
 }
@@ -273,9 +279,9 @@ void coarse_apply_mfma64(const CoarseOp& A, const double2* x, double2* y, int nr
 void coarse_apply_mfma32(const CoarseOp& A, const float2* x, float2* y, int nrhs) {
   MGeo m = mgeo(A.d);
   const int ntr = (nrhs + 15) / 16;
-  const unsigned nb = (unsigned)(A.g.V * ntr);
+  const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + 3) / 4)), tb(64 * std::min(ntr, 4));
   ProfScope ps(A.ctx, KC_COARSE_F32, A.bytes(MGM_PREC_F32, nrhs));
-  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M32, MTc>), dim3(nb), dim3(64), 0, A.ctx->stream, x, y,
+  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M32, MTc>), nb, tb, 0, A.ctx->stream, x, y,
                                        A.A32, A.g, A.d, m.KC64, nrhs, ntr));
   MGM_LAUNCH_CHECK();
 }
@@ -298,9 +304,9 @@ void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs) 
   MGM_CHECK(A.Abf != nullptr, MGM_ERR_INVALID_ARG, "BF16 coarse stencil not built (mixed == 0)");
   MGeo m = mgeo(A.d);
   const int ntr = (nrhs + 15) / 16;
-  const unsigned nb = (unsigned)(A.g.V * ntr);
+  const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + 3) / 4)), tb(64 * std::min(ntr, 4));
   ProfScope ps(A.ctx, KC_COARSE_BF16, A.bytes(MGM_PREC_BF16, nrhs));
-  MT_DISPATCH(m.MT, hipLaunchKernelGGL(k_coarse_mfma_bf16<MTc>, dim3(nb), dim3(64), 0, A.ctx->stream, x, y,
+  MT_DISPATCH(m.MT, hipLaunchKernelGGL(k_coarse_mfma_bf16<MTc>, nb, tb, 0, A.ctx->stream, x, y,
                                        (const uint16_t*)A.Abf, A.g, A.d, m.KC16, nrhs, ntr));
   MGM_LAUNCH_CHECK();
 }

@@ -217,12 +217,15 @@ __global__ void k_cvt_r64_r16(__half* o, const double* in, int64_t n) {
 
 constexpr int kSlab = 4;  // time slices (one wave each) per 256-thread block
 
-template <class P>
+// DOT: also reduce q^H in and |q|^2 per rhs for the minimal-residual smoother
+// (q = D in), written per block to dpart[block][2][nrhs].
+template <class P, bool DOT>
 __global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
                                                 const typename P::S* __restrict__ in,
                                                 const typename P::S* __restrict__ U,
                                                 const typename P::RS* __restrict__ C, Geom g,
-                                                int nrhs, int64_t nblocks, int slab) {
+                                                int nrhs, int64_t nblocks, int slab,
+                                                double2* __restrict__ dpart) {
   using R = typename P::R;
   const int64_t blk = xcd_block(blockIdx.x, nblocks);
   const int64_t V = g.V;
@@ -240,7 +243,11 @@ __global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
   } else {
     tid = blk * blockDim.x + threadIdx.x;
   }
-  if (tid >= N) return;
+  // the reducing variant keeps every thread until the block reduction;
+  // threads past the end compute site 0 and contribute nothing
+  const bool active = tid < N;
+  if (!DOT && !active) return;
+  if (!active) tid = 0;
   const int64_t s = tid / nrhs;
   const int r = (int)(tid - s * nrhs);
   int c[4];
@@ -315,6 +322,8 @@ __global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
     }
   }
   // site-local term: clover blocks with the mass folded into the diagonal
+  cx<double> dqr = {0, 0};
+  double dqq = 0;
 #pragma unroll 1
   for (int chi = 0; chi < 2; chi++) {
     cx<R> p[6], q[6];
@@ -323,12 +332,44 @@ __global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
     clover_block<P>(C, V, s, chi, p, q);
 #pragma unroll
     for (int k = 0; k < 6; k++) {
-      if (chi == 0) acc[k] = acc[k] + q[k];
-      else acc[6 + k] = acc[6 + k] + q[k];
+      cx<R> o;
+      if (chi == 0) o = acc[k] = acc[k] + q[k];
+      else o = acc[6 + k] = acc[6 + k] + q[k];
+      if (DOT) {
+        // the rounded stored value enters the dots
+        typename P::S st_;
+        P::st(&st_, 0, o);
+        const cx<R> os = P::ld(&st_, 0);
+        fmac_(dqr, cx<double>{(double)os.re, (double)os.im}, cx<double>{(double)p[k].re, (double)p[k].im});
+        dqq += (double)os.re * os.re + (double)os.im * os.im;
+      }
     }
   }
+  if (active) {
 #pragma unroll
-  for (int k = 0; k < 12; k++) P::st(out, (int64_t)k * N + tid, acc[k]);
+    for (int k = 0; k < 12; k++) P::st(out, (int64_t)k * N + tid, acc[k]);
+  }
+  if (DOT) {
+    // per-rhs block sums in a fixed order
+    __shared__ double2 sh_qr[256];
+    __shared__ double sh_qq[256];
+    __shared__ int sh_r[256];
+    sh_qr[threadIdx.x] = make_double2(dqr.re, dqr.im);
+    sh_qq[threadIdx.x] = dqq;
+    sh_r[threadIdx.x] = active ? r : -1;
+    __syncthreads();
+    if ((int)threadIdx.x < nrhs) {
+      double a = 0, b = 0, n2 = 0;
+      for (int u = 0; u < (int)blockDim.x; u++)
+        if (sh_r[u] == (int)threadIdx.x) {
+          a += sh_qr[u].x;
+          b += sh_qr[u].y;
+          n2 += sh_qq[u];
+        }
+      dpart[((int64_t)blockIdx.x * 2) * nrhs + threadIdx.x] = make_double2(a, b);
+      dpart[((int64_t)blockIdx.x * 2 + 1) * nrhs + threadIdx.x] = make_double2(n2, 0.0);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ host
@@ -379,33 +420,51 @@ double FineOp::bytes(mgm_prec p, int nrhs) const {
   return (double)g.V * (36 * wc + 72 * wr + 24.0 * wc * nrhs);
 }
 
-void FineOp::apply(mgm_prec p, const void* x, void* y, int nrhs) const {
+int64_t FineOp::nblocks(int nrhs) const { return (g.V * nrhs + 255) / 256; }
+
+template <bool DOT>
+static void launch_dslash(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) {
+  const Geom& g = op.g;
   const int threads = 256;
-  const int64_t n = g.V * nrhs;
-  const int64_t nb = (n + threads - 1) / threads;
-  int kc = p == MGM_PREC_F64 ? KC_DSLASH_F64 : p == MGM_PREC_F32 ? KC_DSLASH_F32 : KC_DSLASH_F16;
+  const int64_t nb = op.nblocks(nrhs);
   // slab mapping needs whole 64-element chunks per slice and kSlab | T; it
   // then covers exactly nb * 256 = V * nrhs elements
   const int64_t per_slice = (g.V / g.T) * nrhs;
   const int slab = (per_slice % 64 == 0 && g.T % kSlab == 0 && threads == 64 * kSlab) ? 1 : 0;
-  ProfScope ps(ctx, kc, bytes(p, nrhs));
+  hipStream_t st = op.ctx->stream;
   switch (p) {
     case MGM_PREC_F64:
-      hipLaunchKernelGGL(k_dslash<F64>, dim3((unsigned)nb), dim3(threads), 0, ctx->stream,
-                         (double2*)y, (const double2*)x, U64, C64, g, nrhs, nb, slab);
+      hipLaunchKernelGGL((k_dslash<F64, DOT>), dim3((unsigned)nb), dim3(threads), 0, st, (double2*)y,
+                         (const double2*)x, op.U64, op.C64, g, nrhs, nb, slab, dpart);
       break;
     case MGM_PREC_F32:
-      hipLaunchKernelGGL(k_dslash<F32>, dim3((unsigned)nb), dim3(threads), 0, ctx->stream,
-                         (float2*)y, (const float2*)x, U32, C32, g, nrhs, nb, slab);
+      hipLaunchKernelGGL((k_dslash<F32, DOT>), dim3((unsigned)nb), dim3(threads), 0, st, (float2*)y,
+                         (const float2*)x, op.U32, op.C32, g, nrhs, nb, slab, dpart);
       break;
     case MGM_PREC_F16:
-      hipLaunchKernelGGL(k_dslash<F16>, dim3((unsigned)nb), dim3(threads), 0, ctx->stream,
-                         (__half2*)y, (const __half2*)x, U16, C16, g, nrhs, nb, slab);
+      hipLaunchKernelGGL((k_dslash<F16, DOT>), dim3((unsigned)nb), dim3(threads), 0, st, (__half2*)y,
+                         (const __half2*)x, op.U16, op.C16, g, nrhs, nb, slab, dpart);
       break;
     default:
       throw Error(MGM_ERR_INVALID_ARG, "dslash precision must be F64, F32 or F16");
   }
   MGM_LAUNCH_CHECK();
+}
+
+static int kclass_of(mgm_prec p) {
+  return p == MGM_PREC_F64 ? KC_DSLASH_F64 : p == MGM_PREC_F32 ? KC_DSLASH_F32 : KC_DSLASH_F16;
+}
+
+void FineOp::apply(mgm_prec p, const void* x, void* y, int nrhs) const {
+  ProfScope ps(ctx, kclass_of(p), bytes(p, nrhs));
+  launch_dslash<false>(*this, p, x, y, nrhs, nullptr);
+}
+
+void FineOp::apply_dot(mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) const {
+  // one block holds 256 elements; each rhs needs a reducing thread
+  MGM_CHECK(nrhs >= 1 && nrhs <= 256, MGM_ERR_INVALID_ARG, "fused dslash reduction supports 1..256 rhs");
+  ProfScope ps(ctx, kclass_of(p), bytes(p, nrhs));
+  launch_dslash<true>(*this, p, x, y, nrhs, dpart);
 }
 
 }  // namespace mgm

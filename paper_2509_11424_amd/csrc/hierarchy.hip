@@ -72,7 +72,7 @@ void Hier::layout(Arena& a) {
     const TGeom& t = T[l].t;
     size_t np = (size_t)t.c.V * 2 * t.rows * t.ntv;
     T[l].P64 = a.take_n<double2>(np);
-    if (mixed) T[l].P32 = a.take_n<float2>(np);
+    if (mixed) T[l].P16 = a.take_n<__half2>(np);
     CoarseOp& C = A[l + 1];
     size_t na = (size_t)9 * C.d * C.d * C.g.V;
     C.A64 = a.take_n<double2>(na);
@@ -88,8 +88,9 @@ void Hier::layout(Arena& a) {
   const int nmax = cap(L - 1), nfine = cap(0);
   const int red_n = std::max(nmax, ntv_max);
   const int m = desc.restart;
-  scratch.cap = (size_t)kRedBlocksMax * 8 * red_n;
+  scratch.cap = (size_t)kRedBlocksMax * kFusedGS * red_n;
   scratch.partial = a.take_n<double2>(scratch.cap);
+  dpart = a.take_n<double2>((size_t)fine->nblocks(nfine) * 2 * nfine);
   // estimator buffers (FP64)
   est.nmax = nmax;
   est.x.assign(L, nullptr);

@@ -65,6 +65,7 @@ struct Hier {
   std::vector<LevelWS> ws64, ws32, ws16;
   EstWS est;
   int* d_flag = nullptr;
+  double2* dpart = nullptr;  // per-block partial sums of the fused dslash reductions
   double* pinned = nullptr;  // host staging (est, norms)
   size_t pinned_n = 0;
   // setup buffers (alias the solver region)

@@ -26,7 +26,7 @@ struct Transfer {
   Context* ctx = nullptr;
   TGeom t{};
   double2* P64 = nullptr;
-  float2* P32 = nullptr;
+  __half2* P16 = nullptr;  // FP16 copy used by the mixed-precision V-cycle
   // restrict: y_c = P^H x ; prolong: mode 0 y = P x_c, 1 y = x - P x_c, 2 y += P x_c
   void restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const;
   void prolong(mgm_prec p, const void* xc, const void* x, void* y, int nrhs, int mode) const;

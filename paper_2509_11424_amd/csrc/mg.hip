@@ -153,8 +153,8 @@ void Transfer::restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const {
     hipLaunchKernelGGL((k_restrict<F64, F64>), dim3(nblocks_for(n, 256)), dim3(256), 0, ctx->stream,
                        (const double2*)x, (double2*)yc, P64, t, nrhs);
   else if (p == MGM_PREC_F32)
-    hipLaunchKernelGGL((k_restrict<F32, F32>), dim3(nblocks_for(n, 256)), dim3(256), 0, ctx->stream,
-                       (const float2*)x, (float2*)yc, P32, t, nrhs);
+    hipLaunchKernelGGL((k_restrict<F32, F16>), dim3(nblocks_for(n, 256)), dim3(256), 0, ctx->stream,
+                       (const float2*)x, (float2*)yc, P16, t, nrhs);
   else
     throw Error(MGM_ERR_INVALID_ARG, "restrict: precision must be F64 or F32");
   MGM_LAUNCH_CHECK();
@@ -167,8 +167,8 @@ void Transfer::prolong(mgm_prec p, const void* xc, const void* x, void* y, int n
     hipLaunchKernelGGL((k_prolong<F64, F64>), dim3(nblocks_for(n, 256)), dim3(256), 0, ctx->stream,
                        (const double2*)xc, (const double2*)x, (double2*)y, P64, t, nrhs, mode);
   else if (p == MGM_PREC_F32)
-    hipLaunchKernelGGL((k_prolong<F32, F32>), dim3(nblocks_for(n, 256)), dim3(256), 0, ctx->stream,
-                       (const float2*)xc, (const float2*)x, (float2*)y, P32, t, nrhs, mode);
+    hipLaunchKernelGGL((k_prolong<F32, F16>), dim3(nblocks_for(n, 256)), dim3(256), 0, ctx->stream,
+                       (const float2*)xc, (const float2*)x, (float2*)y, P16, t, nrhs, mode);
   else
     throw Error(MGM_ERR_INVALID_ARG, "prolong: precision must be F64 or F32");
   MGM_LAUNCH_CHECK();
@@ -490,14 +490,15 @@ void CoarseOp::apply(mgm_prec p, const void* x, void* y, int nrhs) const {
 
 // ---------------------------------------------------------- conversions
 
-__global__ void k_c64_to_c32(float2* o, const double2* in, int64_t n) {
+// P entries are O(1/sqrt(rows)), well inside the FP16 range
+__global__ void k_c64_to_c16(__half2* o, const double2* in, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) o[i] = make_float2((float)in[i].x, (float)in[i].y);
+  if (i < n) o[i] = __floats2half2_rn((float)in[i].x, (float)in[i].y);
 }
 
 void mg_convert_P(Context* c, Transfer& T) {
   int64_t n = T.t.c.V * 2 * (int64_t)T.t.rows * T.t.ntv;
-  hipLaunchKernelGGL(k_c64_to_c32, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, T.P32, T.P64, n);
+  hipLaunchKernelGGL(k_c64_to_c16, dim3(nblocks_for(n, 256)), dim3(256), 0, c->stream, T.P16, T.P64, n);
   MGM_LAUNCH_CHECK();
 }
 

@@ -34,8 +34,14 @@ static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const So
   b_zero(c, y);
   b_copy(c, rho, b);
   for (int i = 0; i < nu; i++) {
-    op_apply(H, l, p, true, cfg, rho.p, q.p, b.nrhs);
-    b_dot_norm(c, H.scratch, q, rho, w.qr, w.qq);
+    if (l == 0) {
+      // fine level: q^H rho and |q|^2 come out of the dslash itself
+      H.fine->apply_dot(p, rho.p, q.p, b.nrhs, H.dpart);
+      b_finalize_dot_norm(c, H.dpart, (int)H.fine->nblocks(b.nrhs), b.nrhs, w.qr, w.qq);
+    } else {
+      op_apply(H, l, p, true, cfg, rho.p, q.p, b.nrhs);
+      b_dot_norm(c, H.scratch, q, rho, w.qr, w.qq);
+    }
     b_mr_update(c, w.qr, w.qq, rho, q, y);
   }
 }
@@ -100,9 +106,15 @@ static int arnoldi(Hier& H, int l, mgm_prec p, int nrhs, int kmax, bool precond,
     if (precond) vcycle(H, l, p, base.with(Vj), base.with(Zj), cfg);
     op_apply(H, l, p, inner, cfg, Zj, W, nrhs);
     Vec Wv = base.with(W);
+    // classical Gram-Schmidt with one re-orthogonalisation: the first
+    // subtraction and the second projection share one sweep over the basis
     b_multidot(c, H.scratch, base, stride, j + 1, Wv, G.h);
-    b_multiaxpy(c, H.scratch, base, stride, j + 1, G.h, -1.0, Wv, nullptr);
-    b_multidot(c, H.scratch, base, stride, j + 1, Wv, G.h2);
+    if (j + 1 <= kFusedGS) {
+      b_multiaxpy_dot(c, H.scratch, base, stride, j + 1, G.h, Wv, G.h2);
+    } else {
+      b_multiaxpy(c, H.scratch, base, stride, j + 1, G.h, -1.0, Wv, nullptr);
+      b_multidot(c, H.scratch, base, stride, j + 1, Wv, G.h2);
+    }
     b_multiaxpy(c, H.scratch, base, stride, j + 1, G.h2, -1.0, Wv, w.n2a);
     b_normalize(c, Wv, w.n2a, nullptr);
     k_gmres_column(c, G, j, w.n2a, nrhs);
