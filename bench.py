@@ -11,10 +11,16 @@ reported separately.
 value = right-hand sides solved to 1e-10 per second (every level's solves
 counted), whole job.  The JSON line also carries the dslash roofline (HIP
 events around every dslash launch in the timed region) and the CPU-oracle
-baseline (fine-level solve rate, extrapolated).
+baseline (fine-level solve rate of the FP64 oracle, extrapolated from one
+operator application and an iteration count measured on a small lattice).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4|c3|c2]
                   [--form mixed|f64] [--cpu 0|1] [--ttt]
+
+Kernel micro-benchmarks (used for the profiler runs of single kernels):
+
+  python bench.py --micro dslash --prec f32[,f64,f16] --nrhs 8[,1,...] [--iters 50]
+  python bench.py --micro copy [--iters 50]      # plain 1 GiB device copy
 """
 from __future__ import annotations
 
@@ -197,6 +203,63 @@ def run(args):
     print(json.dumps(line), flush=True)
 
 
+def micro(args):
+    """Times one kernel alone: the fine dslash at the workload's lattice for
+    one precision and rhs count (HIP events on the library's stream), or a
+    plain 1 GiB device copy whose HBM counters calibrate the profiler's
+    FETCH_SIZE / WRITE_SIZE readings."""
+    import torch
+    if args.micro == "copy":
+        n = 1 << 27  # 2^27 doubles = 1 GiB
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.iters):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.iters
+        print(json.dumps({"micro": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "avg_ms": ms,
+                          "GBps": 16 * n / ms / 1e6}), flush=True)
+        return
+    cfg = CONFIGS[args.config]
+    from lattice_inputs import gauge_field
+    import paper_2509_11424_amd as m
+    U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])
+    ctx = m.Context(0)
+    op = m.Operator(ctx, U, cfg["m0"], cfg["csw"])
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    for prec in args.prec.split(","):
+        for nrhs in [int(v) for v in args.nrhs.split(",")]:
+            shape = (12, op.V, nrhs)
+            if prec == "f16":
+                x = torch.randn(shape + (2,), generator=g, device="cuda:0").to(torch.float16)
+            else:
+                x = torch.randn(shape, generator=g, device="cuda:0",
+                                dtype=torch.complex128 if prec == "f64" else torch.complex64)
+            y = torch.empty_like(x)
+            for _ in range(3):
+                op.apply(x, y, prec)
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            ctx.profile_reset()
+            for _ in range(args.iters):
+                op.apply(x, y, prec)
+            torch.cuda.synchronize()
+            q = ctx.profile_query("dslash_" + prec)
+            ctx.profile(False)
+            ms = q["ms"] / q["launches"]
+            bl = q["bytes"] / q["launches"]
+            print(json.dumps({"micro": "dslash", "prec": prec, "nrhs": nrhs, "lattice": "x".join(
+                map(str, cfg["dims"])), "launches": q["launches"], "avg_ms": ms, "bytes_per_launch": bl,
+                "GBps": bl / ms / 1e6, "frac": bl / ms / 1e6 / HBM_PEAK_GBS}), flush=True)
+            del x, y
+
+
 def time_to_target(m, ctx, op, cfg, h_mixed, sd_mixed, args):
     """Time to reach the variance of the plain FP64 orthogonal estimate at the
     configured probe counts (target eps^2), for plain FP64 MG and for the
@@ -252,12 +315,20 @@ def main():
     ap.add_argument("--form", default="mixed", choices=["mixed", "f64"])
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--ttt", action="store_true")
+    ap.add_argument("--micro", choices=["dslash", "copy"])
+    ap.add_argument("--prec", default="f32", help="comma list of f64, f32, f16")
+    ap.add_argument("--nrhs", default="8", help="comma list of rhs counts")
+    ap.add_argument("--iters", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the hot path is measured per GPU and probe sharding "
-              "across GPUs is described in DESIGN.md; use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the hot path is measured on one GPU's share of the "
+              "probes (probes shard across GPUs without communication until the final sums); "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    run(args)
+    if args.micro:
+        micro(args)
+    else:
+        run(args)
 
 
 if __name__ == "__main__":

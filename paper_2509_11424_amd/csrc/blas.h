@@ -31,7 +31,7 @@ struct Scratch {
   size_t cap = 0;  // complex entries
 };
 
-constexpr int kRedBlocksMax = 256;
+constexpr int kRedBlocksMax = 1024;
 
 // ---- elementwise ----
 void b_zero(Context* c, Vec x);
@@ -53,8 +53,9 @@ void b_mr_update(Context* c, const double2* qr, const double* qq, Vec rho, Vec q
 void b_dot(Context* c, Scratch& s, Vec x, Vec y, double2* out);          // out[r] = x^H y
 void b_norm2(Context* c, Scratch& s, Vec x, double* out);                // out[r] = |x|^2
 void b_dot_norm(Context* c, Scratch& s, Vec q, Vec rho, double2* qr, double* qq);  // q^H rho, |q|^2
-// sums per-block partials [nblk][2][nrhs] (q^H rho, |q|^2) written by a fused kernel
-void b_finalize_dot_norm(Context* c, const double2* part, int nblk, int nrhs, double2* qr, double* qq);
+// sums per-block partials [2][nrhs][nblk] (q^H rho, then |q|^2) written by a fused kernel
+void b_finalize_dot_norm(Context* c, Scratch& s, const double2* part, int64_t nblk, int nrhs, double2* qr,
+                         double* qq);
 // out[i*nrhs + r] = V_i^H w for i < k; basis V_i = base + i * stride (elements)
 void b_multidot(Context* c, Scratch& s, Vec base, int64_t stride, int k, Vec w, double2* out);
 // w += sgn * sum_i h[i*nrhs + r] V_i ; if n2 != nullptr also n2[r] = |w|^2 after the update

@@ -419,8 +419,38 @@ void b_multiaxpy(Context* c, Scratch& s, Vec base, int64_t stride, int k, const 
   MGM_LAUNCH_CHECK();
 }
 
-void b_finalize_dot_norm(Context* c, const double2* part, int nblk, int nrhs, double2* qr, double* qq) {
-  hipLaunchKernelGGL(k_finalize_dn, dim3(2 * nrhs), dim3(64), 0, c->stream, part, nblk, nrhs, qr, qq);
+// seg[g][o] = sum of data[o][j] over the g-th of G contiguous ranges of j
+// (grid G x nout, fixed-order tree in LDS)
+__global__ __launch_bounds__(256) void k_segment_sum(const double2* data, int64_t n, int nout, double2* seg) {
+  const int g = blockIdx.x, G = gridDim.x, o = blockIdx.y;
+  const int64_t per = (n + G - 1) / G, j0 = (int64_t)g * per, j1 = j0 + per < n ? j0 + per : n;
+  double a = 0, b = 0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) {
+    double2 v = data[(int64_t)o * n + j];
+    a += v.x;
+    b += v.y;
+  }
+  __shared__ double sa[256], sb[256];
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+      sb[threadIdx.x] += sb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) seg[(int64_t)g * nout + o] = make_double2(sa[0], sb[0]);
+}
+
+void b_finalize_dot_norm(Context* c, Scratch& s, const double2* part, int64_t nblk, int nrhs, double2* qr,
+                         double* qq) {
+  const int G = (int)std::min<int64_t>(64, std::max<int64_t>(1, nblk / 256));
+  need(s, (size_t)G * 2 * nrhs);
+  hipLaunchKernelGGL(k_segment_sum, dim3(G, 2 * nrhs), dim3(256), 0, c->stream, part, nblk, 2 * nrhs,
+                     s.partial);
+  hipLaunchKernelGGL(k_finalize_dn, dim3(2 * nrhs), dim3(64), 0, c->stream, s.partial, G, nrhs, qr, qq);
   MGM_LAUNCH_CHECK();
 }
 

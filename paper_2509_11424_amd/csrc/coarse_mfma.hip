@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_coarse_mfma4(const typename M::C2* __re
   for (int dir = 0; dir < 9; dir++) {
     const int64_t sn = nbr_c(g, c, dir);
     const C2* Ad = As + (int64_t)dir * KC * MT * 64;
-#pragma unroll 2
+#pragma unroll 4
     for (int kc = 0; kc < KC; kc++) {
       const int k = 4 * kc + kq;
       C2 xv = {0, 0};
@@ -198,8 +198,11 @@ __global__ __launch_bounds__(256) void k_coarse_mfma4(const typename M::C2* __re
 
 template <int MT>
 __global__ __launch_bounds__(256) void k_coarse_mfma_bf16(const float2* __restrict__ x, float2* __restrict__ y,
-                                                         const uint16_t* __restrict__ Ap, LGeom g, int d, int KC,
+                                                         const uint16_t* __restrict__ Ap, LGeom g, int d,
                                                          int nrhs, int ntr) {
+  // K chunks of 16 = ceil(d / 16) = MT: the chunk loop unrolls completely so
+  // every fragment load of a direction is in flight at once
+  constexpr int KC = MT;
   // one workgroup per site, one wave per 16-rhs tile: the tiles of a site
   // stream the same A fragments through the CU's caches at the same time
   const int64_t s = blockIdx.x;
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(256) void k_coarse_mfma_bf16(const float2* __restri
   for (int dir = 0; dir < 9; dir++) {
     const int64_t sn = nbr_c(g, c, dir);
     const uint16_t* Ad = As + (int64_t)dir * KC * MT * 512;
-#pragma unroll 1
+#pragma unroll
     for (int kc = 0; kc < KC; kc++) {
       s4_t br, bi;
 #pragma unroll
@@ -307,7 +310,7 @@ void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs) 
   const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + 3) / 4)), tb(64 * std::min(ntr, 4));
   ProfScope ps(A.ctx, KC_COARSE_BF16, A.bytes(MGM_PREC_BF16, nrhs));
   MT_DISPATCH(m.MT, hipLaunchKernelGGL(k_coarse_mfma_bf16<MTc>, nb, tb, 0, A.ctx->stream, x, y,
-                                       (const uint16_t*)A.Abf, A.g, A.d, m.KC16, nrhs, ntr));
+                                       (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr));
   MGM_LAUNCH_CHECK();
 }
 

@@ -218,7 +218,7 @@ __global__ void k_cvt_r64_r16(__half* o, const double* in, int64_t n) {
 constexpr int kSlab = 4;  // time slices (one wave each) per 256-thread block
 
 // DOT: also reduce q^H in and |q|^2 per rhs for the minimal-residual smoother
-// (q = D in), written per block to dpart[block][2][nrhs].
+// (q = D in), written per block to dpart[2][nrhs][block] (q^H in, then |q|^2).
 template <class P, bool DOT>
 __global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
                                                 const typename P::S* __restrict__ in,
@@ -366,8 +366,8 @@ __global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
           b += sh_qr[u].y;
           n2 += sh_qq[u];
         }
-      dpart[((int64_t)blockIdx.x * 2) * nrhs + threadIdx.x] = make_double2(a, b);
-      dpart[((int64_t)blockIdx.x * 2 + 1) * nrhs + threadIdx.x] = make_double2(n2, 0.0);
+      dpart[(int64_t)threadIdx.x * nblocks + blockIdx.x] = make_double2(a, b);
+      dpart[(int64_t)(nrhs + threadIdx.x) * nblocks + blockIdx.x] = make_double2(n2, 0.0);
     }
   }
 }
