@@ -251,6 +251,85 @@ typedef struct {
 mgm_status mgm_solve(mgm_hierarchy h, int32_t level, const mgm_solve_desc* desc,
                      const void* b_dev, void* x_dev, int32_t nrhs, mgm_solve_stats* stats);
 
+/* ------------------------------------------------ learned preconditioner */
+
+/*
+ * Gauge-covariant parallel-transport convolution (PTC) network used as the
+ * fine-level smoother of the multigrid preconditioner (solve kind NET).  The
+ * paper does not describe a learned preconditioner: this is the learned form
+ * of the hot path.  One layer maps c_in to c_out colour-triplet channels,
+ *
+ *   out_a(x) = sum_p sum_b W_p[a][b] (T_p in_b)(x),
+ *
+ * over nine paths p: 0 identity, 1 + mu forward transport U_mu(x) in(x + mu),
+ * 5 + mu backward transport U_mu(x - mu)^H in(x - mu) (mu = x, y, z, t; the
+ * antiperiodic time sign as in the Dirac operator).  Input and output are
+ * fine spinors (4 spin channels); layers are linear.  Inside the V-cycle the
+ * network replaces the fine smoother: M r = e_c + N(r - D e_c) with
+ * e_c = P D_c^-1 P^H r.  Vectors are FP32 complex, dof-major
+ * [(channel * 3 + colour)][site][rhs] (a spinor is channels 0..3).
+ *
+ * Weights: complex, interleaved, ordered [layer][path][c_out][c_in]; the
+ * gradient of a real loss L with respect to a complex weight w is reported as
+ * dL/dRe(w) + i dL/dIm(w).  The network keeps FP64 master weights and Adam
+ * state; kernels use an FP32 copy.
+ */
+#define MGM_NET_MAX_LAYERS 8
+
+typedef struct mgm_net_s* mgm_net;
+
+typedef struct {
+  int32_t nlayers;                          /* 1..MGM_NET_MAX_LAYERS */
+  int32_t width[MGM_NET_MAX_LAYERS + 1];    /* channels; width[0] = width[nlayers] = 4,
+                                               every width in {4, 8, 12, 16} */
+  uint64_t seed;                            /* initial weights (identity path plus small noise) */
+  int32_t max_nrhs;                         /* right-hand sides per application, 1..256 */
+  int32_t train_nrhs;                       /* training pairs (= batch), 0..256; 0: no training */
+} mgm_net_desc;
+
+typedef struct {
+  int32_t steps;       /* Adam steps (full batch) */
+  double lr;           /* learning rate */
+  double beta1, beta2, eps;  /* Adam constants (0: 0.9, 0.999, 1e-8) */
+  uint64_t seed;       /* Z4 draws of the training inputs */
+  double target_tol;   /* FP64 solves that make the training targets */
+} mgm_train_desc;
+
+typedef struct {
+  double loss_first;   /* loss at the initial weights */
+  double loss_last;    /* loss at the weights before the last update */
+  int32_t steps;
+  double seconds;      /* wall time including target generation */
+} mgm_train_stats;
+
+/* Device bytes of the network's workspace on operator op's lattice. */
+mgm_status mgm_net_workspace_size(mgm_operator op, const mgm_net_desc* desc, size_t* bytes);
+/* Creates the network in the caller's workspace (256-byte aligned device
+ * memory of at least the queried size, owned by the caller and kept until
+ * mgm_net_destroy).  op must outlive the network.  Bad widths or counts:
+ * MGM_ERR_INVALID_ARG; small workspace: MGM_ERR_WORKSPACE. */
+mgm_status mgm_net_create(mgm_operator op, const mgm_net_desc* desc, void* ws_dev, size_t ws_bytes,
+                          mgm_net* out);
+mgm_status mgm_net_num_weights(mgm_net net, int64_t* count);  /* complex weights */
+/* Host FP64 weights (2 * count doubles); set also resets the Adam state. */
+mgm_status mgm_net_set_weights(mgm_net net, const double* w_host);
+mgm_status mgm_net_get_weights(mgm_net net, double* w_host);
+/* y = N(r) for nrhs <= max_nrhs fine spinors (FP32 complex, device). */
+mgm_status mgm_net_apply(mgm_net net, const void* r_dev, void* y_dev, int32_t nrhs);
+/* Loss (1/nrhs) sum_j |N(r_j) - e_j|^2 / |e_j|^2 and its weight gradient
+ * (host, 2 * count doubles, same order as the weights) for nrhs <= train_nrhs
+ * pairs.  Needs train_nrhs > 0. */
+mgm_status mgm_net_loss_grad(mgm_net net, const void* r_dev, const void* e_dev, int32_t nrhs, double* loss,
+                             double* grad_host);
+/* Trains with full-batch Adam on train_nrhs pairs (r, e): r is the fine
+ * residual left by the coarse-grid correction of a Z4 vector
+ * (r = z - D P D_c^-1 P^H z) and e = D^-1 r from FP64 MG solves of hierarchy
+ * h, which must be built on the network's operator with max_nrhs >= train_nrhs
+ * on levels 0 and 1.  loss_history (host, steps doubles) may be NULL. */
+mgm_status mgm_net_train(mgm_net net, mgm_hierarchy h, const mgm_train_desc* desc, mgm_train_stats* stats,
+                         double* loss_history);
+void mgm_net_destroy(mgm_net net);
+
 /* --------------------------------------------------------------- estimate */
 
 typedef enum { MGM_OBS_TRACE = 0, MGM_OBS_CORR_PS = 1, MGM_OBS_LOOPS = 2 } mgm_observable;

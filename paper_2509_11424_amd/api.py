@@ -23,7 +23,8 @@ OBS = {"trace": 0, "corr": 1, "loops": 2}
 DEC = {"plain": 0, "oblique": 1, "orthogonal": 2}
 EXPORT = {"agg_map": 0, "P": 1, "coarse": 2, "tv": 3}
 KCLASS = {"dslash_f64": 0, "dslash_f32": 1, "dslash_f16": 2, "coarse_f64": 3, "coarse_f32": 4,
-          "coarse_bf16": 5, "transfer": 6}
+          "coarse_bf16": 5, "transfer": 6, "net": 7}
+NET_MAX_LAYERS = 8
 STATUS = {0: "MGM_OK", -1: "MGM_ERR_INVALID_ARG", -2: "MGM_ERR_SHAPE", -3: "MGM_ERR_WORKSPACE",
           -4: "MGM_ERR_NOT_CONVERGED", -5: "MGM_ERR_RANK_DEFICIENT", -6: "MGM_ERR_NUMERIC",
           -7: "MGM_ERR_HIP"}
@@ -78,6 +79,21 @@ class EstimateResult(C.Structure):
                 ("total_var", C.POINTER(C.c_double)), ("stats", SolveStats)]
 
 
+class NetDesc(C.Structure):
+    _fields_ = [("nlayers", C.c_int32), ("width", C.c_int32 * (NET_MAX_LAYERS + 1)), ("seed", C.c_uint64),
+                ("max_nrhs", C.c_int32), ("train_nrhs", C.c_int32)]
+
+
+class TrainDesc(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("seed", C.c_uint64), ("target_tol", C.c_double)]
+
+
+class TrainStats(C.Structure):
+    _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("steps", C.c_int32),
+                ("seconds", C.c_double)]
+
+
 _lib = None
 
 # (name, restype, argtypes)
@@ -121,6 +137,18 @@ _SIGS = [
     ("mgm_profile_query", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("mgm_hierarchy_destroy", None, [C.c_void_p]),
+    ("mgm_net_workspace_size", C.c_int, [C.c_void_p, C.POINTER(NetDesc), C.POINTER(C.c_size_t)]),
+    ("mgm_net_create", C.c_int, [C.c_void_p, C.POINTER(NetDesc), C.c_void_p, C.c_size_t,
+                                 C.POINTER(C.c_void_p)]),
+    ("mgm_net_num_weights", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("mgm_net_set_weights", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("mgm_net_get_weights", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("mgm_net_apply", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("mgm_net_loss_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                    C.c_void_p]),
+    ("mgm_net_train", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(TrainDesc), C.POINTER(TrainStats),
+                                C.c_void_p]),
+    ("mgm_net_destroy", None, [C.c_void_p]),
 ]
 
 EXPORTED = [s[0] for s in _SIGS]
@@ -449,3 +477,84 @@ def mlmc_allocate(var, cost, eps2: float) -> np.ndarray:
                                    cost.ctypes.data_as(C.POINTER(C.c_double)), eps2,
                                    out.ctypes.data_as(C.POINTER(C.c_int64))))
     return out
+
+
+class Net:
+    """Gauge-covariant PTC network (the learned fine-level smoother) on the
+    lattice of operator `op`.  widths = [4, c1, ..., 4]."""
+
+    def __init__(self, op: Operator, widths=(4, 16, 16, 16, 4), seed: int = 1, max_nrhs: int = 8,
+                 train_nrhs: int = 0):
+        self.op = op
+        self.ctx = op.ctx
+        d = NetDesc()
+        d.nlayers = len(widths) - 1
+        for i, w in enumerate(widths):
+            d.width[i] = int(w)
+        d.seed = seed
+        d.max_nrhs = max_nrhs
+        d.train_nrhs = train_nrhs
+        self.desc = d
+        self.widths = list(widths)
+        nb = C.c_size_t()
+        _check(lib().mgm_net_workspace_size(op.h, C.byref(d), C.byref(nb)))
+        self.ws = _empty_ws(nb.value, self.ctx.device)
+        h = C.c_void_p()
+        _check(lib().mgm_net_create(op.h, C.byref(d), C.c_void_p(_ptr(self.ws)), self.ws.numel(), C.byref(h)))
+        self.h = h
+        n = C.c_int64()
+        _check(lib().mgm_net_num_weights(h, C.byref(n)))
+        self.nweights = n.value
+
+    def _split(self, flat: np.ndarray) -> list:
+        out, off = [], 0
+        for l in range(len(self.widths) - 1):
+            ci, co = self.widths[l], self.widths[l + 1]
+            k = 9 * co * ci
+            out.append(flat[off:off + k].reshape(9, co, ci))
+            off += k
+        return out
+
+    def get_weights(self) -> list:
+        w = np.empty(2 * self.nweights, dtype=np.float64)
+        _check(lib().mgm_net_get_weights(self.h, w.ctypes.data_as(C.c_void_p)))
+        return self._split(w.view(np.complex128))
+
+    def set_weights(self, weights: list):
+        flat = np.concatenate([np.asarray(W, dtype=np.complex128).ravel() for W in weights])
+        if flat.size != self.nweights:
+            raise ValueError("expected %d complex weights, got %d" % (self.nweights, flat.size))
+        w = np.ascontiguousarray(flat).view(np.float64)
+        _check(lib().mgm_net_set_weights(self.h, w.ctypes.data_as(C.c_void_p)))
+
+    def apply(self, r, y=None):
+        """y = N(r) for complex64 dof-major spinors (12, V, nrhs)."""
+        import torch
+        if y is None:
+            y = torch.empty_like(r)
+        _check(lib().mgm_net_apply(self.h, C.c_void_p(_ptr(r)), C.c_void_p(_ptr(y)), r.shape[2]))
+        return y
+
+    def loss_grad(self, r, e):
+        """(loss, per-layer weight gradients) for complex64 pairs (12, V, n)."""
+        loss = C.c_double()
+        g = np.empty(2 * self.nweights, dtype=np.float64)
+        _check(lib().mgm_net_loss_grad(self.h, C.c_void_p(_ptr(r)), C.c_void_p(_ptr(e)), r.shape[2],
+                                       C.byref(loss), g.ctypes.data_as(C.c_void_p)))
+        return loss.value, self._split(g.view(np.complex128))
+
+    def train(self, hierarchy, steps: int = 100, lr: float = 1e-3, seed: int = 7, target_tol: float = 1e-8,
+              beta1: float = 0.0, beta2: float = 0.0, eps: float = 0.0):
+        d = TrainDesc()
+        d.steps, d.lr, d.seed, d.target_tol = steps, lr, seed, target_tol
+        d.beta1, d.beta2, d.eps = beta1, beta2, eps
+        st = TrainStats()
+        hist = np.zeros(steps, dtype=np.float64)
+        _check(lib().mgm_net_train(self.h, hierarchy.h, C.byref(d), C.byref(st), hist.ctypes.data_as(C.c_void_p)))
+        return {"loss_first": st.loss_first, "loss_last": st.loss_last, "steps": st.steps,
+                "seconds": st.seconds, "history": hist}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mgm_net_destroy(self.h)
+            self.h = None

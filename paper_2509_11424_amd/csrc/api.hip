@@ -509,4 +509,119 @@ mgm_status mgm_profile_query(mgm_context ctx, int32_t kclass, int64_t* launches,
 
 void mgm_hierarchy_destroy(mgm_hierarchy h) { delete h; }
 
+// -------------------------------------------------------------- network
+
+static void check_net_desc(mgm_operator op, const mgm_net_desc* d) {
+  MGM_CHECK(op != nullptr && d != nullptr, MGM_ERR_INVALID_ARG, "NULL argument");
+  MGM_CHECK(d->nlayers >= 1 && d->nlayers <= MGM_NET_MAX_LAYERS, MGM_ERR_INVALID_ARG, "nlayers must be 1..8");
+  MGM_CHECK(d->width[0] == 4 && d->width[d->nlayers] == 4, MGM_ERR_INVALID_ARG,
+            "the network maps spinors to spinors: width[0] = width[nlayers] = 4");
+  for (int l = 0; l <= d->nlayers; l++) {
+    const int w = d->width[l];
+    MGM_CHECK(w == 4 || w == 8 || w == 12 || w == 16, MGM_ERR_INVALID_ARG, "widths must be 4, 8, 12 or 16");
+  }
+  MGM_CHECK(d->max_nrhs >= 1 && d->max_nrhs <= 256, MGM_ERR_INVALID_ARG, "max_nrhs must be 1..256");
+  MGM_CHECK(d->train_nrhs >= 0 && d->train_nrhs <= 256, MGM_ERR_INVALID_ARG, "train_nrhs must be 0..256");
+}
+
+mgm_status mgm_net_workspace_size(mgm_operator op, const mgm_net_desc* desc, size_t* bytes) {
+  API_BEGIN
+  check_net_desc(op, desc);
+  MGM_CHECK(bytes != nullptr, MGM_ERR_INVALID_ARG, "bytes is NULL");
+  Net n;
+  n.op = &op->op;
+  n.desc = *desc;
+  Arena a;
+  n.layout(a);
+  *bytes = a.off;
+  API_END
+}
+
+mgm_status mgm_net_create(mgm_operator op, const mgm_net_desc* desc, void* ws_dev, size_t ws_bytes,
+                          mgm_net* out) {
+  API_BEGIN
+  check_net_desc(op, desc);
+  MGM_CHECK(ws_dev && out, MGM_ERR_INVALID_ARG, "NULL argument");
+  MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  auto* h = new mgm_net_s();
+  try {
+    h->op = op;
+    Net& n = h->n;
+    n.ctx = op->ctx;
+    n.op = &op->op;
+    n.desc = *desc;
+    Arena a;
+    a.base = (char*)ws_dev;
+    a.cap = ws_bytes;
+    n.layout(a);
+    MGM_HIP(hipHostMalloc((void**)&n.pinned, 64 * sizeof(double), hipHostMallocDefault));
+    n.upload_weights(net_initial_weights(n, desc->seed));
+  } catch (...) {
+    if (h->n.pinned) (void)hipHostFree(h->n.pinned);
+    delete h;
+    throw;
+  }
+  *out = h;
+  API_END
+}
+
+mgm_status mgm_net_num_weights(mgm_net net, int64_t* count) {
+  API_BEGIN
+  MGM_CHECK(net && count, MGM_ERR_INVALID_ARG, "NULL argument");
+  *count = net->n.nw;
+  API_END
+}
+
+mgm_status mgm_net_set_weights(mgm_net net, const double* w_host) {
+  API_BEGIN
+  MGM_CHECK(net && w_host, MGM_ERR_INVALID_ARG, "NULL argument");
+  std::vector<double> w(w_host, w_host + 2 * net->n.nw);
+  net->n.upload_weights(w);
+  API_END
+}
+
+mgm_status mgm_net_get_weights(mgm_net net, double* w_host) {
+  API_BEGIN
+  MGM_CHECK(net && w_host, MGM_ERR_INVALID_ARG, "NULL argument");
+  MGM_HIP(hipMemcpyAsync(w_host, net->n.w64, sizeof(double2) * net->n.nw, hipMemcpyDeviceToHost,
+                         net->n.ctx->stream));
+  net->n.ctx->sync();
+  API_END
+}
+
+mgm_status mgm_net_apply(mgm_net net, const void* r_dev, void* y_dev, int32_t nrhs) {
+  API_BEGIN
+  MGM_CHECK(net && r_dev && y_dev, MGM_ERR_INVALID_ARG, "NULL argument");
+  net->n.apply((const float2*)r_dev, (float2*)y_dev, nrhs);
+  API_END
+}
+
+mgm_status mgm_net_loss_grad(mgm_net net, const void* r_dev, const void* e_dev, int32_t nrhs, double* loss,
+                             double* grad_host) {
+  API_BEGIN
+  MGM_CHECK(net && r_dev && e_dev, MGM_ERR_INVALID_ARG, "NULL argument");
+  const double l = net->n.loss_grad((const float2*)r_dev, (const float2*)e_dev, nrhs);
+  if (loss) *loss = l;
+  if (grad_host) {
+    MGM_HIP(hipMemcpyAsync(grad_host, net->n.g64, sizeof(double2) * net->n.nw, hipMemcpyDeviceToHost,
+                           net->n.ctx->stream));
+    net->n.ctx->sync();
+  }
+  API_END
+}
+
+mgm_status mgm_net_train(mgm_net net, mgm_hierarchy h, const mgm_train_desc* desc, mgm_train_stats* stats,
+                         double* loss_history) {
+  API_BEGIN
+  MGM_CHECK(net && h && desc, MGM_ERR_INVALID_ARG, "NULL argument");
+  net_train(h->h, net->n, *desc, stats, loss_history);
+  API_END
+}
+
+void mgm_net_destroy(mgm_net net) {
+  if (!net) return;
+  if (net->n.pinned) (void)hipHostFree(net->n.pinned);
+  delete net;
+}
+
 }  // extern "C"

@@ -176,7 +176,8 @@ enum KClass {
   KC_COARSE_F32 = 4,
   KC_COARSE_BF16 = 5,
   KC_TRANSFER = 6,
-  KC_COUNT = 7
+  KC_NET = 7,
+  KC_COUNT = 8
 };
 
 struct Profiler {

@@ -48,13 +48,7 @@ static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const So
 
 static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool precond, const SolveCfg& cfg);
 
-// Fine-level smoothing step used by the V-cycle: MR steps, or the learned
-// network when configured.
 static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
-  if (l == 0 && cfg.net != nullptr && cfg.kind == MGM_SOLVE_NET) {
-    net_apply(H, *cfg.net, r, e);
-    return;
-  }
   mr_smooth(H, l, p, r, e, cfg.smooth, cfg);
 }
 
@@ -67,6 +61,21 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
   LevelWS& w = H.ws(l, p);
   const int nrhs = r.nrhs;
   Vec t = r.with(w.t);
+  if (l == 0 && cfg.net != nullptr && cfg.kind == MGM_SOLVE_NET) {
+    // learned smoother after the coarse-grid correction:
+    // M r = e_c + N(r - D e_c), e_c = P D_c^-1 P^H r
+    LevelWS& wc = H.ws(1, p);
+    Vec rc = H.vec(1, p, wc.bc, nrhs), ec = H.vec(1, p, wc.xc, nrhs);
+    H.T[0].restrict_(p, r.p, rc.p, nrhs);
+    fgmres_fixed(H, 1, p, rc, ec, cfg.coarse_iters, 1 < H.L - 1, cfg);
+    H.T[0].prolong(p, ec.p, nullptr, e.p, nrhs, 0);  // e = P e_c
+    op_apply(H, 0, p, true, cfg, e.p, t.p, nrhs);
+    b_xpay(c, r, nullptr, -1.0, t);
+    Vec y = r.with(w.y);
+    net_apply(H, *cfg.net, t, y);
+    b_axpy(c, nullptr, 1.0, y, e);
+    return;
+  }
   smooth(H, l, p, r, e, cfg);
   op_apply(H, l, p, true, cfg, e.p, t.p, nrhs);
   b_xpay(c, r, nullptr, -1.0, t);  // t = r - D e
@@ -254,16 +263,46 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
   b_zero(c, x);
   b_copy(c, r, b);
   const bool precond = l < H.L - 1;
+  // the learned smoother falls back to plain MG for the rest of the solve
+  // when an inner solve produces non-finite values or fails to halve the
+  // residual of some right-hand side
+  SolveCfg cur = cfg;
+  std::vector<double> prev(nrhs, -1.0);
+  auto fall_back = [&](bool restart) {
+    cur.net = nullptr;
+    cur.kind = MGM_SOLVE_MG_MIXED;
+    out->fallbacks += 1;
+    if (restart) {
+      b_zero(c, x);
+      b_copy(c, r, b);
+    }
+  };
   int steps = 0;
   for (int outer = 0; outer < 64 && steps < cfg.maxiter; outer++) {
     b_norm2(c, H.scratch, r, w64.n2a);
     MGM_HIP(hipMemcpyAsync(pin, w64.n2a, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
     c->sync();
+    if (cur.net) {
+      bool bad = false, nonfinite = false;
+      for (int i = 0; i < nrhs; i++) {
+        if (!std::isfinite(pin[i])) nonfinite = true;
+        else if (prev[i] > 0 && pin[i] > 0.25 * prev[i]) bad = true;
+      }
+      if (nonfinite || bad) {
+        fall_back(nonfinite);
+        if (nonfinite) {
+          b_norm2(c, H.scratch, r, w64.n2a);
+          MGM_HIP(hipMemcpyAsync(pin, w64.n2a, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
+          c->sync();
+        }
+      }
+    }
     bool all = true;
     for (int i = 0; i < nrhs; i++) {
       MGM_CHECK(std::isfinite(pin[i]), MGM_ERR_NUMERIC, "non-finite residual in defect correction");
       bool conv = b2[i] == 0.0 || std::sqrt(pin[i]) <= cfg.tol * std::sqrt(b2[i]);
       mask[i] = conv ? 0.0 : 1.0;
+      prev[i] = conv ? -1.0 : pin[i];
       if (!conv) all = false;
     }
     if (all) break;
@@ -271,7 +310,13 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
     b_scale_rhs(c, r, w64.mask);
     b_copy(c, r32, r);
     SolveOut inner;
-    fgmres_tol(H, l, MGM_PREC_F32, r32, e32, cfg.inner_tol, 4, cfg.maxiter - steps, precond, cfg, &inner);
+    try {
+      fgmres_tol(H, l, MGM_PREC_F32, r32, e32, cur.inner_tol, 4, cfg.maxiter - steps, precond, cur, &inner);
+    } catch (const Error& e) {
+      if (cur.net == nullptr || e.code != MGM_ERR_NUMERIC) throw;
+      fall_back(true);
+      continue;
+    }
     steps += inner.iterations;
     out->iterations += inner.iterations;
     out->restarts += inner.restarts;
