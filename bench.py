@@ -36,6 +36,38 @@ sys.path.insert(0, ROOT)
 METRIC = "RHS solved/s to 1e-10, dslash HBM GB/s; time-to-target-variance tr(D^-1)"
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the dominant kernel (FP32 dslash, nrhs 8, 32^3 x 64) from two
+# rocprofv3 --pmc runs, valid only for the kernel sources it was taken with
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_f32_nrhs8_32x32x32x64_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_11424_amd", "csrc", f)
+                  for f in ("dslash.hip", "fine_dev.h", "fine.h", "common.h")]
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Calibrated HBM bytes per launch, or None when the counters were taken
+    with other kernel sources (or not at all)."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#") and not line.startswith(" "):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_sources_sha256") != kernel_sources_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
 CONFIGS = {
     # 32^3 x 64, csw 1, roughness 0.6, m0 0.02; 4^4 (24 tv) then 2^4 (32 tv);
     # probes 20 / 100 / 400 on the fine / middle / coarsest difference levels
@@ -179,9 +211,11 @@ def run(args):
         "config": {"workload": cfg["name"], "lattice": "x".join(map(str, cfg["dims"])), "levels": L,
                    "probes": cfg["nprobe"], "batch": batch, "tol": 1e-10, "form": args.form},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_dslash<%s>" % (
-                         "F32" if mixed else "F64"), "avg_launch_ms": avg_ms, "launches": q["launches"],
-                     "bytes_per_launch": bytes_launch},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if (mixed and args.config == "c4") else None,
+                     "kernel": "k_dslash_rb<F32>" if mixed else "k_dslash<F64>", "avg_launch_ms": avg_ms,
+                     "launches": q["launches"], "bytes_per_launch": bytes_launch},
+        "hierarchy_workspace_gb": h.ws.numel() / 1e9,
         "setup_s": t_setup, "gauge_gen_s": t_gauge, "rhs_per_step": nrhs_step,
         "solver_iterations_per_step": results[-1]["stats"]["iterations"],
         "estimate": {"tr_Dinv": [results[-1]["total_mean"][0, 0].real, results[-1]["total_mean"][0, 0].imag],

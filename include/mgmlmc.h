@@ -218,8 +218,9 @@ mgm_status mgm_project_out(mgm_hierarchy h, int32_t level, const void* x_dev, vo
 
 typedef enum {
   MGM_SOLVE_MG = 0,        /* FP64 FGMRES preconditioned by an FP64 MG V-cycle */
-  MGM_SOLVE_MG_MIXED = 1,  /* FP64 defect correction around FP32 FGMRES with an
-                              FP16-smoother / BF16-MFMA-coarse V-cycle */
+  MGM_SOLVE_MG_MIXED = 1,  /* FP64 defect correction around FP32 FGMRES with a
+                              V-cycle of FP16-storage fine smoothing, FP16 P and
+                              BF16-MFMA coarse operators */
   MGM_SOLVE_GMRES = 2,     /* unpreconditioned FP64 GMRES */
   MGM_SOLVE_NET = 3        /* MG_MIXED with the learned smoother (mgm_net) */
 } mgm_solve_kind;
@@ -235,6 +236,9 @@ typedef struct {
   int32_t coarse_bf16; /* MG_MIXED / NET: coarse-level operators inside the V-cycle
                           use BF16 MFMA operands with FP32 accumulation (1) or
                           FP32 (0); the Arnoldi operator of every solve stays FP32 */
+  int32_t smoother_f16;/* MG_MIXED / NET: the fine-level MR smoother stores its
+                          vectors in FP16 (1; inputs scaled per rhs to unit RMS
+                          entries, FP32 arithmetic) or FP32 (0) */
 } mgm_solve_desc;
 
 typedef struct {

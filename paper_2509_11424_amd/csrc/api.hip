@@ -227,8 +227,9 @@ static void check_hdesc(mgm_operator op, const mgm_hierarchy_desc* d) {
                 "lattice not divisible into aggregates with coarse extent >= 2");
       dims[m] /= b;
     }
-    int rows = d->block[l][0] * d->block[l][1] * d->block[l][2] * d->block[l][3] * (dof / 2);
-    MGM_CHECK(rows * 16 <= 64 * 1024, MGM_ERR_SHAPE, "aggregate too large");
+    const int bvol = d->block[l][0] * d->block[l][1] * d->block[l][2] * d->block[l][3];
+    int rows = bvol * (dof / 2);
+    MGM_CHECK(rows * 16 <= 64 * 1024 && bvol <= 1024, MGM_ERR_SHAPE, "aggregate too large");
     MGM_CHECK(d->ntv[l] <= rows, MGM_ERR_RANK_DEFICIENT, "more test vectors than aggregate rows");
     dof = 2 * d->ntv[l];
   }
@@ -408,6 +409,7 @@ static SolveCfg cfg_of(const mgm_solve_desc* d) {
   c.coarse_iters = d->coarse_iters;
   c.inner_tol = d->inner_tol > 0 ? d->inner_tol : 1e-5;
   c.coarse_bf16 = d->coarse_bf16 != 0;
+  c.smooth_f16 = d->smoother_f16 != 0;
   c.net = (Net*)d->net;
   MGM_CHECK(c.kind != MGM_SOLVE_NET || c.net != nullptr, MGM_ERR_INVALID_ARG, "NET solve needs a network");
   return c;

@@ -24,6 +24,17 @@ __device__ __forceinline__ void std_(void* p, int64_t i, cx<double> v) {
   P::st((typename P::S*)p, i, cx<typename P::R>{(typename P::R)v.re, (typename P::R)v.im});
 }
 
+// rhs index of a grid-stride loop, advanced without 64-bit division
+struct RhsIter {
+  int r, step, nrhs;
+  __device__ RhsIter(int64_t i0, int64_t stride, int nr)
+      : r((int)(i0 % nr)), step((int)(stride % nr)), nrhs(nr) {}
+  __device__ void next() {
+    r += step;
+    if (r >= nrhs) r -= nrhs;
+  }
+};
+
 static inline unsigned ew_blocks(int64_t n) {
   int64_t b = (n + 255) / 256;
   return (unsigned)(b < 65536 * 4 ? b : 65536 * 4);
@@ -60,10 +71,41 @@ void b_copy(Context* c, Vec dst, Vec src) {
   MGM_LAUNCH_CHECK();
 }
 
+template <class PD, class PS>
+__global__ void k_copy_scaled(void* dst, const void* src, int64_t n, int nrhs, const double* s) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next()) std_<PD>(dst, i, s[it.r] * ldd<PS>(src, i));
+}
+void b_copy_scaled(Context* c, Vec dst, Vec src, const double* s) {
+  int64_t n = src.n();
+  MGM_CHECK(dst.n() == n && dst.nrhs == src.nrhs, MGM_ERR_INVALID_ARG, "copy: shape mismatch");
+  if (n == 0) return;
+  DISPATCH_PREC(dst.prec, PD, DISPATCH_PREC(src.prec, PS,
+      hipLaunchKernelGGL((k_copy_scaled<PD, PS>), dim3(ew_blocks(n)), dim3(256), 0, c->stream, dst.p, src.p, n,
+                         src.nrhs, s)));
+  MGM_LAUNCH_CHECK();
+}
+
+__global__ void k_unit_scales(const double* n2, double target2, int nrhs, double* s, double* inv) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const double d = n2[r];
+  const double f = d > 0.0 ? sqrt(target2 / d) : 0.0;
+  s[r] = f;
+  inv[r] = f > 0.0 ? 1.0 / f : 0.0;
+}
+void b_unit_scales(Context* c, const double* n2, double target2, int nrhs, double* s, double* inv) {
+  hipLaunchKernelGGL(k_unit_scales, dim3(nblocks_for(nrhs, 64)), dim3(64), 0, c->stream, n2, target2, nrhs, s, inv);
+  MGM_LAUNCH_CHECK();
+}
+
 template <class P>
 __global__ void k_axpy(const double2* a, double sgn, const void* x, void* y, int64_t n, int nrhs) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    int r = (int)(i % nrhs);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next()) {
+    const int r = it.r;
     cx<double> al = a ? cx<double>{a[r].x, a[r].y} : cx<double>{1.0, 0.0};
     al = sgn * al;
     cx<double> yv = ldd<P>(y, i);
@@ -82,8 +124,10 @@ void b_axpy(Context* c, const double2* a, double sgn, Vec x, Vec y) {
 
 template <class P>
 __global__ void k_xpay(const void* x, const double2* a, double sgn, void* y, int64_t n, int nrhs) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    int r = (int)(i % nrhs);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next()) {
+    const int r = it.r;
     cx<double> al = a ? cx<double>{a[r].x, a[r].y} : cx<double>{1.0, 0.0};
     al = sgn * al;
     cx<double> v = ldd<P>(x, i);
@@ -114,8 +158,10 @@ void b_scal(Context* c, Vec x, double s) {
 
 template <class P>
 __global__ void k_normalize(void* x, const double* n2, double* beta, int64_t n, int nrhs) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    int r = (int)(i % nrhs);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next()) {
+    const int r = it.r;
     double b = sqrt(n2[r]);
     double s = b > 0.0 ? 1.0 / b : 0.0;
     std_<P>(x, i, s * ldd<P>(x, i));
@@ -132,8 +178,9 @@ void b_normalize(Context* c, Vec x, const double* n2, double* beta) {
 
 template <class P>
 __global__ void k_scale_rhs(void* x, const double* m, int64_t n, int nrhs) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    std_<P>(x, i, m[i % nrhs] * ldd<P>(x, i));
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next()) std_<P>(x, i, m[it.r] * ldd<P>(x, i));
 }
 void b_scale_rhs(Context* c, Vec x, const double* m) {
   int64_t n = x.n();
@@ -144,12 +191,18 @@ void b_scale_rhs(Context* c, Vec x, const double* m) {
 }
 
 template <class P>
-__global__ void k_mr_update(const double2* qr, const double* qq, void* rho, const void* q, void* y, int64_t n,
-                            int nrhs) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    int r = (int)(i % nrhs);
-    double d = qq[r];
-    cx<double> al = d > 0.0 ? cx<double>{qr[r].x / d, qr[r].y / d} : cx<double>{0.0, 0.0};
+__global__ __launch_bounds__(256) void k_mr_update(const double2* qr, const double* qq, void* rho, const void* q,
+                                                   void* y, int64_t n, int nrhs) {
+  __shared__ double2 sa[256];  // alpha = qr / qq per rhs (nrhs <= 256)
+  for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
+    const double d = qq[r];
+    sa[r] = d > 0.0 ? make_double2(qr[r].x / d, qr[r].y / d) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next()) {
+    const cx<double> al = {sa[it.r].x, sa[it.r].y};
     cx<double> rv = ldd<P>(rho, i);
     cx<double> yv = ldd<P>(y, i);
     fma_(yv, al, rv);
@@ -162,6 +215,7 @@ __global__ void k_mr_update(const double2* qr, const double* qq, void* rho, cons
 void b_mr_update(Context* c, const double2* qr, const double* qq, Vec rho, Vec q, Vec y) {
   int64_t n = rho.n();
   if (n == 0) return;
+  MGM_CHECK(rho.nrhs >= 1 && rho.nrhs <= 256, MGM_ERR_INVALID_ARG, "at most 256 right-hand sides");
   DISPATCH_PREC(rho.prec, P, hipLaunchKernelGGL(k_mr_update<P>, dim3(ew_blocks(n)), dim3(256), 0, c->stream,
                                                 qr, qq, rho.p, q.p, y.p, n, rho.nrhs));
   MGM_LAUNCH_CHECK();

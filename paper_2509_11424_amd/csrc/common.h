@@ -102,6 +102,17 @@ struct F64 {
   __device__ __forceinline__ static void st(S* p, int64_t i, cx<R> v) { p[i] = make_double2(v.re, v.im); }
   __device__ __forceinline__ static R ldr(const double* p, int64_t i) { return p[i]; }
   using RS = double;  // stored real type
+  // RB consecutive elements starting at i (i a multiple of RB)
+  template <int RB>
+  __device__ __forceinline__ static void ldv(const S* p, int64_t i, cx<R> (&v)[RB]) {
+#pragma unroll
+    for (int j = 0; j < RB; j++) v[j] = ld(p, i + j);
+  }
+  template <int RB>
+  __device__ __forceinline__ static void stv(S* p, int64_t i, const cx<R> (&v)[RB]) {
+#pragma unroll
+    for (int j = 0; j < RB; j++) st(p, i + j, v[j]);
+  }
 };
 
 struct F32 {
@@ -115,6 +126,26 @@ struct F32 {
   __device__ __forceinline__ static void st(S* p, int64_t i, cx<R> v) { p[i] = make_float2(v.re, v.im); }
   using RS = float;
   __device__ __forceinline__ static R ldr(const float* p, int64_t i) { return p[i]; }
+  template <int RB>
+  __device__ __forceinline__ static void ldv(const S* p, int64_t i, cx<R> (&v)[RB]) {
+    if constexpr (RB == 2) {
+      const float4 a = *reinterpret_cast<const float4*>(p + i);  // 16-byte aligned: i even
+      v[0] = {a.x, a.y};
+      v[1] = {a.z, a.w};
+    } else {
+#pragma unroll
+      for (int j = 0; j < RB; j++) v[j] = ld(p, i + j);
+    }
+  }
+  template <int RB>
+  __device__ __forceinline__ static void stv(S* p, int64_t i, const cx<R> (&v)[RB]) {
+    if constexpr (RB == 2) {
+      *reinterpret_cast<float4*>(p + i) = make_float4(v[0].re, v[0].im, v[1].re, v[1].im);
+    } else {
+#pragma unroll
+      for (int j = 0; j < RB; j++) st(p, i + j, v[j]);
+    }
+  }
 };
 
 struct F16 {
@@ -130,6 +161,34 @@ struct F16 {
   }
   using RS = __half;
   __device__ __forceinline__ static R ldr(const __half* p, int64_t i) { return __half2float(p[i]); }
+  template <int RB>
+  __device__ __forceinline__ static void ldv(const S* p, int64_t i, cx<R> (&v)[RB]) {
+    if constexpr (RB == 2) {
+      const uint2 a = *reinterpret_cast<const uint2*>(p + i);  // 8-byte aligned: i even
+      __half2 h0, h1;
+      __builtin_memcpy(&h0, &a.x, 4);
+      __builtin_memcpy(&h1, &a.y, 4);
+      const float2 f0 = __half22float2(h0), f1 = __half22float2(h1);
+      v[0] = {f0.x, f0.y};
+      v[1] = {f1.x, f1.y};
+    } else {
+#pragma unroll
+      for (int j = 0; j < RB; j++) v[j] = ld(p, i + j);
+    }
+  }
+  template <int RB>
+  __device__ __forceinline__ static void stv(S* p, int64_t i, const cx<R> (&v)[RB]) {
+    if constexpr (RB == 2) {
+      const __half2 h0 = __floats2half2_rn(v[0].re, v[0].im), h1 = __floats2half2_rn(v[1].re, v[1].im);
+      uint2 a;
+      __builtin_memcpy(&a.x, &h0, 4);
+      __builtin_memcpy(&a.y, &h1, 4);
+      *reinterpret_cast<uint2*>(p + i) = a;
+    } else {
+#pragma unroll
+      for (int j = 0; j < RB; j++) st(p, i + j, v[j]);
+    }
+  }
 };
 
 inline size_t prec_bytes(mgm_prec p) {

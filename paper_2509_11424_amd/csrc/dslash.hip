@@ -372,6 +372,191 @@ __global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
   }
 }
 
+// Variant for FP32/FP16 with an even rhs count: one thread computes RB = 2
+// consecutive right-hand sides of one site, so the links, clover entries and
+// index arithmetic are shared by the two columns and the spinor loads become
+// 16-byte (FP32) or 8-byte (FP16) vector loads.  Same block order, DOT
+// reduction and output as k_dslash.
+template <class P, bool DOT, int RB>
+__global__ __launch_bounds__(256) void k_dslash_rb(typename P::S* __restrict__ out,
+                                                const typename P::S* __restrict__ in,
+                                                const typename P::S* __restrict__ U,
+                                                const typename P::RS* __restrict__ C, Geom g,
+                                                int nrhs, int64_t nblocks, int slab,
+                                                double2* __restrict__ dpart) {
+  using R = typename P::R;
+  const int64_t blk = xcd_block(blockIdx.x, nblocks);
+  const int64_t V = g.V;
+  const int64_t N = V * nrhs;       // elements per dof plane
+  const int nq = nrhs / RB;         // threads per site
+  const int64_t NT = V * nq;        // threads in the grid that carry work
+  int64_t tid;
+  if (slab) {
+    // Block = kSlab waves on kSlab consecutive time slices of one 64-thread
+    // chunk of a slice: the t-neighbours of the inner waves are loaded by
+    // sibling waves of the same block at about the same time.
+    const int64_t per_slice = (V / g.T) * nq;
+    const int64_t chunks = per_slice / 64;
+    const int64_t chunk = blk % chunks, tg = blk / chunks;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    tid = (tg * kSlab + w) * per_slice + chunk * 64 + lane;
+  } else {
+    tid = blk * blockDim.x + threadIdx.x;
+  }
+  // the reducing variant keeps every thread until the block reduction;
+  // threads past the end compute site 0 and contribute nothing
+  const bool active = tid < NT;
+  if (!DOT && !active) return;
+  if (!active) tid = 0;
+  const int64_t s = tid / nq;
+  const int r0 = (int)(tid - s * nq) * RB;
+  const int64_t es = s * nrhs + r0;  // this thread's first element in a plane
+  int c[4];
+  {
+    int64_t q = s;
+    c[0] = (int)(q % g.X); q /= g.X;
+    c[1] = (int)(q % g.Y); q /= g.Y;
+    c[2] = (int)(q % g.Z); q /= g.Z;
+    c[3] = (int)q;
+  }
+  const int64_t sy = g.X, sz = (int64_t)g.X * g.Y, st = sz * g.Z;
+
+  cx<R> acc[12][RB];
+#pragma unroll
+  for (int k = 0; k < 12; k++)
+#pragma unroll
+    for (int j = 0; j < RB; j++) acc[k][j] = {0, 0};
+  // The eight hops run as a loop that is not unrolled, so only one
+  // neighbour's spinor and link are live at a time (registers stay low and
+  // occupancy high enough to cover HBM latency).
+#pragma unroll 1
+  for (int hop = 0; hop < 8; hop++) {
+    const int mu = hop >> 1;
+    const bool fwd = (hop & 1) == 0;
+    const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
+    const int ex = mu == 0 ? g.X : mu == 1 ? g.Y : mu == 2 ? g.Z : g.T;
+    const int64_t sd = mu == 0 ? 1 : mu == 1 ? sy : mu == 2 ? sz : st;
+    const bool wrap = fwd ? (cm == ex - 1) : (cm == 0);
+    const int64_t span = (int64_t)(ex - 1) * sd;
+    const int64_t sn = fwd ? (wrap ? s - span : s + sd) : (wrap ? s + span : s - sd);
+    // -1/2 (1 -/+ g_mu), times -1 on hops across the time boundary
+    const R f = (mu == 3 && wrap && g.antiperiodic) ? (R)0.5 : (R)-0.5;
+    const R sg = fwd ? (R)-1 : (R)1;  // half spinor h = u + sg * A_mu l
+    const int64_t e = sn * nrhs + r0;
+    cx<R> h[2][3][RB];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      cx<R> u0[RB], u1[RB], l0[RB], l1[RB];
+      P::template ldv<RB>(in, (int64_t)(0 * 3 + a) * N + e, u0);
+      P::template ldv<RB>(in, (int64_t)(1 * 3 + a) * N + e, u1);
+      P::template ldv<RB>(in, (int64_t)(2 * 3 + a) * N + e, l0);
+      P::template ldv<RB>(in, (int64_t)(3 * 3 + a) * N + e, l1);
+#pragma unroll
+      for (int j = 0; j < RB; j++) {
+        cx<R> a0, a1;
+        A_times(mu, l0[j], l1[j], a0, a1);
+        h[0][a][j] = u0[j] + sg * a0;
+        h[1][a][j] = u1[j] + sg * a1;
+      }
+    }
+    // forward: U_mu(x) h ; backward: U_mu(x - mu)^H h
+    const typename P::S* Ub = U + (int64_t)(mu * 9) * V + (fwd ? s : sn);
+    cx<R> Um[3][3];
+#pragma unroll
+    for (int k = 0; k < 9; k++) Um[k / 3][k % 3] = P::ld(Ub, (int64_t)k * V);
+#pragma unroll
+    for (int j = 0; j < RB; j++)
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        cx<R> g0 = {0, 0}, g1 = {0, 0};
+        if (fwd) {
+#pragma unroll
+          for (int b = 0; b < 3; b++) {
+            fma_(g0, Um[a][b], h[0][b][j]);
+            fma_(g1, Um[a][b], h[1][b][j]);
+          }
+        } else {
+#pragma unroll
+          for (int b = 0; b < 3; b++) {  // (U^H)_{ab} = conj(U_{ba})
+            fmac_(g0, Um[b][a], h[0][b][j]);
+            fmac_(g1, Um[b][a], h[1][b][j]);
+          }
+        }
+        g0 = f * g0;
+        g1 = f * g1;
+        cx<R> d0, d1;
+        Ad_times(mu, g0, g1, d0, d1);  // lower spins: -A^H g (forward), +A^H g (backward)
+        acc[0 * 3 + a][j] = acc[0 * 3 + a][j] + g0;
+        acc[1 * 3 + a][j] = acc[1 * 3 + a][j] + g1;
+        acc[2 * 3 + a][j] = acc[2 * 3 + a][j] + sg * d0;
+        acc[3 * 3 + a][j] = acc[3 * 3 + a][j] + sg * d1;
+      }
+  }
+  // site-local term: clover blocks with the mass folded into the diagonal
+  cx<double> dqr[RB];
+  double dqq[RB];
+#pragma unroll
+  for (int j = 0; j < RB; j++) {
+    dqr[j] = {0, 0};
+    dqq[j] = 0;
+  }
+#pragma unroll 1
+  for (int chi = 0; chi < 2; chi++) {
+    cx<R> pv[6][RB];
+#pragma unroll
+    for (int k = 0; k < 6; k++) P::template ldv<RB>(in, (int64_t)(6 * chi + k) * N + es, pv[k]);
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+      cx<R> x6[6], q6[6];
+#pragma unroll
+      for (int k = 0; k < 6; k++) x6[k] = pv[k][j];
+      clover_block<P>(C, V, s, chi, x6, q6);
+#pragma unroll
+      for (int k = 0; k < 6; k++) {
+        cx<R> o;
+        if (chi == 0) o = acc[k][j] = acc[k][j] + q6[k];
+        else o = acc[6 + k][j] = acc[6 + k][j] + q6[k];
+        if (DOT) {
+          // the rounded stored value enters the dots
+          typename P::S st_;
+          P::st(&st_, 0, o);
+          const cx<R> os = P::ld(&st_, 0);
+          fmac_(dqr[j], cx<double>{(double)os.re, (double)os.im}, cx<double>{(double)x6[k].re, (double)x6[k].im});
+          dqq[j] += (double)os.re * os.re + (double)os.im * os.im;
+        }
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < 12; k++) P::template stv<RB>(out, (int64_t)k * N + es, acc[k]);
+  }
+  if (DOT) {
+    // per-rhs block sums in a fixed order
+    __shared__ double2 sh_qr[256 * RB];
+    __shared__ double sh_qq[256 * RB];
+    __shared__ int sh_r[256 * RB];
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+      sh_qr[threadIdx.x * RB + j] = make_double2(dqr[j].re, dqr[j].im);
+      sh_qq[threadIdx.x * RB + j] = dqq[j];
+      sh_r[threadIdx.x * RB + j] = active ? r0 + j : -1;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nrhs) {
+      double a = 0, b = 0, n2 = 0;
+      for (int u = 0; u < (int)blockDim.x * RB; u++)
+        if (sh_r[u] == (int)threadIdx.x) {
+          a += sh_qr[u].x;
+          b += sh_qr[u].y;
+          n2 += sh_qq[u];
+        }
+      dpart[(int64_t)threadIdx.x * nblocks + blockIdx.x] = make_double2(a, b);
+      dpart[(int64_t)(nrhs + threadIdx.x) * nblocks + blockIdx.x] = make_double2(n2, 0.0);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ host
 
 void FineOp::layout(Arena& a, const Geom& g, FineOp* op) {
@@ -420,35 +605,60 @@ double FineOp::bytes(mgm_prec p, int nrhs) const {
   return (double)g.V * (36 * wc + 72 * wr + 24.0 * wc * nrhs);
 }
 
-int64_t FineOp::nblocks(int nrhs) const { return (g.V * nrhs + 255) / 256; }
+// right-hand sides per thread: two for FP32/FP16 with an even count; the
+// reducing variant keeps one (its extra accumulators would cost occupancy)
+static int rb_of(mgm_prec p, int nrhs, bool dot) {
+  return (!dot && p != MGM_PREC_F64 && nrhs % 2 == 0) ? 2 : 1;
+}
 
-template <bool DOT>
-static void launch_dslash(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) {
+int64_t FineOp::nblocks(mgm_prec p, int nrhs, bool dot) const {
+  return (g.V * (nrhs / rb_of(p, nrhs, dot)) + 255) / 256;
+}
+
+template <bool DOT, int RB>
+static void launch_rb(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) {
   const Geom& g = op.g;
   const int threads = 256;
-  const int64_t nb = op.nblocks(nrhs);
-  // slab mapping needs whole 64-element chunks per slice and kSlab | T; it
-  // then covers exactly nb * 256 = V * nrhs elements
-  const int64_t per_slice = (g.V / g.T) * nrhs;
+  const int64_t nb = op.nblocks(p, nrhs, DOT);
+  // slab mapping needs whole 64-thread chunks per slice and kSlab | T; it
+  // then covers exactly nb * 256 = V * nrhs / RB threads
+  const int64_t per_slice = (g.V / g.T) * (nrhs / RB);
   const int slab = (per_slice % 64 == 0 && g.T % kSlab == 0 && threads == 64 * kSlab) ? 1 : 0;
   hipStream_t st = op.ctx->stream;
   switch (p) {
     case MGM_PREC_F64:
+      MGM_CHECK(RB == 1, MGM_ERR_INVALID_ARG, "FP64 dslash takes one rhs per thread");
       hipLaunchKernelGGL((k_dslash<F64, DOT>), dim3((unsigned)nb), dim3(threads), 0, st, (double2*)y,
                          (const double2*)x, op.U64, op.C64, g, nrhs, nb, slab, dpart);
       break;
     case MGM_PREC_F32:
-      hipLaunchKernelGGL((k_dslash<F32, DOT>), dim3((unsigned)nb), dim3(threads), 0, st, (float2*)y,
-                         (const float2*)x, op.U32, op.C32, g, nrhs, nb, slab, dpart);
+      if (RB == 2)
+        hipLaunchKernelGGL((k_dslash_rb<F32, DOT, 2>), dim3((unsigned)nb), dim3(threads), 0, st, (float2*)y,
+                           (const float2*)x, op.U32, op.C32, g, nrhs, nb, slab, dpart);
+      else
+        hipLaunchKernelGGL((k_dslash<F32, DOT>), dim3((unsigned)nb), dim3(threads), 0, st, (float2*)y,
+                           (const float2*)x, op.U32, op.C32, g, nrhs, nb, slab, dpart);
       break;
     case MGM_PREC_F16:
-      hipLaunchKernelGGL((k_dslash<F16, DOT>), dim3((unsigned)nb), dim3(threads), 0, st, (__half2*)y,
-                         (const __half2*)x, op.U16, op.C16, g, nrhs, nb, slab, dpart);
+      if (RB == 2)
+        hipLaunchKernelGGL((k_dslash_rb<F16, DOT, 2>), dim3((unsigned)nb), dim3(threads), 0, st, (__half2*)y,
+                           (const __half2*)x, op.U16, op.C16, g, nrhs, nb, slab, dpart);
+      else
+        hipLaunchKernelGGL((k_dslash<F16, DOT>), dim3((unsigned)nb), dim3(threads), 0, st, (__half2*)y,
+                           (const __half2*)x, op.U16, op.C16, g, nrhs, nb, slab, dpart);
       break;
     default:
       throw Error(MGM_ERR_INVALID_ARG, "dslash precision must be F64, F32 or F16");
   }
   MGM_LAUNCH_CHECK();
+}
+
+template <bool DOT>
+static void launch_dslash(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) {
+  if (rb_of(p, nrhs, DOT) == 2)
+    launch_rb<DOT, 2>(op, p, x, y, nrhs, dpart);
+  else
+    launch_rb<DOT, 1>(op, p, x, y, nrhs, dpart);
 }
 
 static int kclass_of(mgm_prec p) {

@@ -12,6 +12,22 @@ void Hier::apply(int l, mgm_prec p, const void* x, void* y, int nrhs) const {
     A[l].apply(p, x, y, nrhs);
 }
 
+// FP16 fine-level smoother: input, result, MR residual and product vectors
+static void carve_smooth16(Arena& a, LevelWS& w, int64_t n, int nmax) {
+  w.prec = MGM_PREC_F16;
+  w.nmax = nmax;
+  const size_t vb = (size_t)n * nmax * prec_bytes(MGM_PREC_F16);
+  w.r = a.take(vb);
+  w.t = a.take(vb);
+  w.rho = a.take(vb);
+  w.q = a.take(vb);
+  w.n2a = a.take_n<double>(nmax);
+  w.n2b = a.take_n<double>(nmax);
+  w.qr = a.take_n<double2>(nmax);
+  w.qq = a.take_n<double>(nmax);
+  w.mask = a.take_n<double>(nmax);
+}
+
 static void carve_ws(Arena& a, LevelWS& w, mgm_prec p, int64_t n, int nmax, int m, bool krylov) {
   w.prec = p;
   w.nmax = nmax;
@@ -90,7 +106,7 @@ void Hier::layout(Arena& a) {
   const int m = desc.restart;
   scratch.cap = (size_t)kRedBlocksMax * kFusedGS * red_n;
   scratch.partial = a.take_n<double2>(scratch.cap);
-  dpart = a.take_n<double2>((size_t)fine->nblocks(nfine) * 2 * nfine);
+  dpart = a.take_n<double2>((size_t)fine->nblocks(MGM_PREC_F64, nfine, true) * 2 * nfine);
   // estimator buffers (FP64)
   est.nmax = nmax;
   est.x.assign(L, nullptr);
@@ -130,6 +146,7 @@ void Hier::layout(Arena& a) {
     carve_ws(a, ws64[l], MGM_PREC_F64, n(l), cap(l), m, full64);
     if (mixed) carve_ws(a, ws32[l], MGM_PREC_F32, n(l), cap(l), m, true);
   }
+  if (mixed) carve_smooth16(a, ws16[0], n(0), cap(0));
   const size_t solver_end = a.off;
   a.off = base;
   tv.assign(L > 0 ? L - 1 : 0, nullptr);

@@ -117,6 +117,7 @@ struct SolveCfg {
   int coarse_iters = 12;
   double inner_tol = 1e-5;
   bool coarse_bf16 = false;
+  bool smooth_f16 = false;  // mixed kinds: FP16-storage fine MR smoother
   Net* net = nullptr;
 };
 

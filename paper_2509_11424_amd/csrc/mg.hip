@@ -2,6 +2,8 @@
 // the Galerkin coarse stencil (Sec. 2.2: R_l = P_l^H with unitary P_l,
 // D_{l+1} = P_l^H D_l P_l).
 #include "mg.h"
+
+#include <type_traits>
 #include "fine_dev.h"
 
 namespace mgm {
@@ -85,59 +87,173 @@ void mg_agg_map(Context* c, const TGeom& t, int64_t* out) {
 
 // ------------------------------------------------------------ transfers
 
-template <class P, class PM>
-__global__ void k_restrict(const typename P::S* __restrict__ x, typename P::S* __restrict__ yc,
-                           const typename PM::S* __restrict__ Pm, TGeom t, int nrhs) {
-  using R = typename P::R;
-  int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t Vc = t.c.V, Vf = t.f.V;
-  if (tid >= (int64_t)t.ntv * 2 * Vc * nrhs) return;
-  int k = (int)(tid % t.ntv);
-  int64_t q = tid / t.ntv;
-  int chi = (int)(q % 2);
-  q /= 2;
-  int64_t a = q % Vc;
-  int r = (int)(q / Vc);
-  cx<R> acc = {0, 0};
-  const typename PM::S* pb = Pm + ((a * 2 + chi) * t.rows) * (int64_t)t.ntv + k;
-  for (int loc = 0; loc < t.bvol; loc++) {
-    int64_t s = fine_site(t, a, loc);
-    for (int j = 0; j < t.half; j++) {
-      int row = loc * t.half + j;
-      cx<typename PM::R> pv = PM::ld(pb, (int64_t)row * t.ntv);
-      cx<R> xv = P::ld(x, ((int64_t)(chi * t.half + j) * Vf + s) * nrhs + r);
-      fmac_(acc, cx<R>{(R)pv.re, (R)pv.im}, xv);
-    }
-  }
-  P::st(yc, ((int64_t)(chi * t.ntv + k) * Vc + a) * nrhs + r, acc);
+// Transfers run one workgroup per (aggregate, chirality, rhs tile): the
+// aggregate's P block (rows x N_tv) is streamed once through LDS in chunks of
+// rows, so every P entry is read from HBM once per launch and reused by all
+// right-hand sides of the tile.
+constexpr int kTransferRT = 64;  // right-hand sides per workgroup
+constexpr int kTransferLDS = 24576;  // bytes of streamed P rows (and restricted inputs)
+
+__host__ __device__ inline int transfer_chunk_rows(int rows, int ntv, int rt, int cbytes, bool with_x) {
+  const int per_row = (ntv + (with_x ? rt : 0)) * cbytes;
+  int rc = kTransferLDS / per_row;
+  if (rc > rows) rc = rows;
+  return rc < 1 ? 1 : rc;
 }
 
-template <class P, class PM>
-__global__ void k_prolong(const typename P::S* __restrict__ xc, const typename P::S* __restrict__ x,
-                          typename P::S* __restrict__ y, const typename PM::S* __restrict__ Pm, TGeom t,
-                          int nrhs, int mode) {
-  using R = typename P::R;
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t Vc = t.c.V, Vf = t.f.V;
-  if (e >= (int64_t)t.f.dof * Vf * nrhs) return;
-  int r = (int)(e % nrhs);
-  int64_t q = e / nrhs;
-  int64_t s = q % Vf;
-  int dof = (int)(q / Vf);
-  int chi = dof / t.half, j = dof % t.half;
-  int64_t a;
-  int loc;
-  agg_of(t, s, a, loc);
-  int row = loc * t.half + j;
-  const typename PM::S* pb = Pm + ((a * 2 + chi) * t.rows + row) * (int64_t)t.ntv;
-  cx<R> acc = {0, 0};
-  for (int k = 0; k < t.ntv; k++) {
-    cx<typename PM::R> pv = PM::ld(pb, k);
-    fma_(acc, cx<R>{(R)pv.re, (R)pv.im}, P::ld(xc, ((int64_t)(chi * t.ntv + k) * Vc + a) * nrhs + r));
+// fine sites of aggregate a, in local (lexicographic) order, into LDS
+__device__ __forceinline__ void aggregate_sites(const TGeom& t, int64_t a, int64_t* sites) {
+  int ca[4];
+  coords_of(t.c, a, ca);
+  for (int loc = threadIdx.x; loc < t.bvol; loc += blockDim.x) {
+    int rem = loc, f[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+      const int l = rem % t.b[m];
+      rem /= t.b[m];
+      f[m] = ca[m] * t.b[m] + l;
+    }
+    sites[loc] = index_of(t.f, f);
   }
-  if (mode == 1) acc = P::ld(x, e) - acc;
-  else if (mode == 2) acc = P::ld(y, e) + acc;
-  P::st(y, e, acc);
+}
+
+// P rows [row0, row0 + nr) of one (aggregate, chirality) block into LDS as
+// complex R; FP16 blocks with K % 4 == 0 move 16 bytes (4 entries) per lane
+template <class PM, typename R>
+__device__ __forceinline__ void stage_p_rows(const typename PM::S* __restrict__ pb, int row0, int nr, int K,
+                                             cx<R>* sP) {
+  const int n = nr * K;
+  if constexpr (std::is_same<PM, F16>::value) {
+    if ((K & 3) == 0) {
+      const uint4* src = reinterpret_cast<const uint4*>(pb + (int64_t)row0 * K);
+      for (int i = threadIdx.x; i < n / 4; i += blockDim.x) {
+        const uint4 v = src[i];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          __half2 h;
+          __builtin_memcpy(&h, &w[e], 4);
+          const float2 f = __half22float2(h);
+          sP[4 * i + e] = {(R)f.x, (R)f.y};
+        }
+      }
+      return;
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const cx<typename PM::R> v = PM::ld(pb, (int64_t)row0 * K + i);
+    sP[i] = {(R)v.re, (R)v.im};
+  }
+}
+
+// y_c[chi k][a][r] = sum_rows conj(P[a][chi][row][k]) x[chi half + j][site(loc)][r]
+template <class P, class PM>
+__global__ __launch_bounds__(256) void k_restrict(const typename P::S* __restrict__ x, typename P::S* __restrict__ yc,
+                                                  const typename PM::S* __restrict__ Pm, TGeom t, int nrhs, int rc) {
+  using R = typename P::R;
+  extern __shared__ char smem[];
+  const int64_t a = blockIdx.x >> 1;
+  const int chi = blockIdx.x & 1;
+  const int r0 = blockIdx.y * kTransferRT;
+  const int rt = nrhs - r0 < kTransferRT ? nrhs - r0 : kTransferRT;
+  const int K = t.ntv, half = t.half, rows = t.rows;
+  const int64_t Vc = t.c.V, Vf = t.f.V;
+  int64_t* sS = reinterpret_cast<int64_t*>(smem);                      // [bvol] fine sites
+  cx<R>* sP = reinterpret_cast<cx<R>*>(smem + (size_t)t.bvol * 8);     // [rc][K]
+  cx<R>* sX = sP + (size_t)rc * K;                                      // [rc][rt]
+  const int O = K * rt;                          // outputs of this workgroup, r fastest
+  aggregate_sites(t, a, sS);
+  __syncthreads();
+  constexpr int MAXO = (32 * kTransferRT + 255) / 256;
+  cx<R> acc[MAXO];
+#pragma unroll
+  for (int m = 0; m < MAXO; m++) acc[m] = {0, 0};
+  const typename PM::S* pb = Pm + ((a * 2 + chi) * rows) * (int64_t)K;
+  for (int row0 = 0; row0 < rows; row0 += rc) {
+    const int nr = rows - row0 < rc ? rows - row0 : rc;
+    stage_p_rows<PM, R>(pb, row0, nr, K, sP);
+    for (int i = threadIdx.x; i < nr * rt; i += blockDim.x) {
+      const int ii = i / rt, r = i - ii * rt;
+      const int row = row0 + ii, loc = row / half, j = row - loc * half;
+      sX[i] = P::ld(x, ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + r);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MAXO; m++) {
+      const int o = threadIdx.x + m * 256;
+      if (o < O) {
+        const int k = o / rt, r = o - k * rt;
+        // four independent partial sums keep several LDS reads in flight
+        cx<R> s0 = acc[m], s1 = {0, 0}, s2 = {0, 0}, s3 = {0, 0};
+        int i = 0;
+        for (; i + 4 <= nr; i += 4) {
+          fmac_(s0, sP[i * K + k], sX[i * rt + r]);
+          fmac_(s1, sP[(i + 1) * K + k], sX[(i + 1) * rt + r]);
+          fmac_(s2, sP[(i + 2) * K + k], sX[(i + 2) * rt + r]);
+          fmac_(s3, sP[(i + 3) * K + k], sX[(i + 3) * rt + r]);
+        }
+        for (; i < nr; i++) fmac_(s0, sP[i * K + k], sX[i * rt + r]);
+        acc[m] = (s0 + s1) + (s2 + s3);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < MAXO; m++) {
+    const int o = threadIdx.x + m * 256;
+    if (o < O) {
+      const int k = o / rt, r = o - k * rt;
+      P::st(yc, ((int64_t)(chi * K + k) * Vc + a) * nrhs + r0 + r, acc[m]);
+    }
+  }
+}
+
+// y = P x_c (mode 0), x - P x_c (mode 1), y + P x_c (mode 2)
+template <class P, class PM>
+__global__ __launch_bounds__(256) void k_prolong(const typename P::S* __restrict__ xc, const typename P::S* __restrict__ x,
+                                                 typename P::S* __restrict__ y, const typename PM::S* __restrict__ Pm,
+                                                 TGeom t, int nrhs, int mode, int rc) {
+  using R = typename P::R;
+  extern __shared__ char smem[];
+  const int64_t a = blockIdx.x >> 1;
+  const int chi = blockIdx.x & 1;
+  const int r0 = blockIdx.y * kTransferRT;
+  const int rt = nrhs - r0 < kTransferRT ? nrhs - r0 : kTransferRT;
+  const int K = t.ntv, half = t.half, rows = t.rows;
+  const int64_t Vc = t.c.V, Vf = t.f.V;
+  int64_t* sS = reinterpret_cast<int64_t*>(smem);                      // [bvol] fine sites
+  cx<R>* sC = reinterpret_cast<cx<R>*>(smem + (size_t)t.bvol * 8);     // [K][rt] coarse values
+  cx<R>* sP = sC + (size_t)K * rt;                                      // [rc][K]
+  aggregate_sites(t, a, sS);
+  for (int i = threadIdx.x; i < K * rt; i += blockDim.x) {
+    const int k = i / rt, r = i - k * rt;
+    sC[i] = P::ld(xc, ((int64_t)(chi * K + k) * Vc + a) * nrhs + r0 + r);
+  }
+  const typename PM::S* pb = Pm + ((a * 2 + chi) * rows) * (int64_t)K;
+  for (int row0 = 0; row0 < rows; row0 += rc) {
+    const int nr = rows - row0 < rc ? rows - row0 : rc;
+    __syncthreads();  // previous chunk consumed (and sC written on the first pass)
+    stage_p_rows<PM, R>(pb, row0, nr, K, sP);
+    __syncthreads();
+    for (int o = threadIdx.x; o < nr * rt; o += blockDim.x) {
+      const int ii = o / rt, r = o - ii * rt;
+      cx<R> a0 = {0, 0}, a1 = {0, 0}, a2 = {0, 0}, a3 = {0, 0};
+      int k = 0;
+      for (; k + 4 <= K; k += 4) {
+        fma_(a0, sP[ii * K + k], sC[k * rt + r]);
+        fma_(a1, sP[ii * K + k + 1], sC[(k + 1) * rt + r]);
+        fma_(a2, sP[ii * K + k + 2], sC[(k + 2) * rt + r]);
+        fma_(a3, sP[ii * K + k + 3], sC[(k + 3) * rt + r]);
+      }
+      for (; k < K; k++) fma_(a0, sP[ii * K + k], sC[k * rt + r]);
+      cx<R> acc = (a0 + a1) + (a2 + a3);
+      const int row = row0 + ii, loc = row / half, j = row - loc * half;
+      const int64_t e = ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + r;
+      if (mode == 1) acc = P::ld(x, e) - acc;
+      else if (mode == 2) acc = P::ld(y, e) + acc;
+      P::st(y, e, acc);
+    }
+  }
 }
 
 double Transfer::bytes(mgm_prec p, int nrhs) const {
@@ -147,30 +263,42 @@ double Transfer::bytes(mgm_prec p, int nrhs) const {
 }
 
 void Transfer::restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const {
-  int64_t n = (int64_t)t.ntv * 2 * t.c.V * nrhs;
   ProfScope ps(ctx, KC_TRANSFER, bytes(p, nrhs));
-  if (p == MGM_PREC_F64)
-    hipLaunchKernelGGL((k_restrict<F64, F64>), dim3(nblocks_for(n, 256)), dim3(256), 0, ctx->stream,
-                       (const double2*)x, (double2*)yc, P64, t, nrhs);
-  else if (p == MGM_PREC_F32)
-    hipLaunchKernelGGL((k_restrict<F32, F16>), dim3(nblocks_for(n, 256)), dim3(256), 0, ctx->stream,
-                       (const float2*)x, (float2*)yc, P16, t, nrhs);
-  else
+  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(256);
+  const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
+  MGM_CHECK(t.ntv <= 32 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 32 test vectors and 1024 sites per aggregate");
+  if (p == MGM_PREC_F64) {
+    const int rc = transfer_chunk_rows(t.rows, t.ntv, rt, 16, true);
+    hipLaunchKernelGGL((k_restrict<F64, F64>), nb, tb, (size_t)t.bvol * 8 + (size_t)rc * (t.ntv + rt) * 16, ctx->stream,
+                       (const double2*)x, (double2*)yc, P64, t, nrhs, rc);
+  } else if (p == MGM_PREC_F32) {
+    const int rc = transfer_chunk_rows(t.rows, t.ntv, rt, 8, true);
+    hipLaunchKernelGGL((k_restrict<F32, F16>), nb, tb, (size_t)t.bvol * 8 + (size_t)rc * (t.ntv + rt) * 8, ctx->stream,
+                       (const float2*)x, (float2*)yc, P16, t, nrhs, rc);
+  } else {
     throw Error(MGM_ERR_INVALID_ARG, "restrict: precision must be F64 or F32");
+  }
   MGM_LAUNCH_CHECK();
 }
 
 void Transfer::prolong(mgm_prec p, const void* xc, const void* x, void* y, int nrhs, int mode) const {
-  int64_t n = (int64_t)t.f.dof * t.f.V * nrhs;
   ProfScope ps(ctx, KC_TRANSFER, bytes(p, nrhs));
-  if (p == MGM_PREC_F64)
-    hipLaunchKernelGGL((k_prolong<F64, F64>), dim3(nblocks_for(n, 256)), dim3(256), 0, ctx->stream,
-                       (const double2*)xc, (const double2*)x, (double2*)y, P64, t, nrhs, mode);
-  else if (p == MGM_PREC_F32)
-    hipLaunchKernelGGL((k_prolong<F32, F16>), dim3(nblocks_for(n, 256)), dim3(256), 0, ctx->stream,
-                       (const float2*)xc, (const float2*)x, (float2*)y, P16, t, nrhs, mode);
-  else
+  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(256);
+  const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
+  MGM_CHECK(t.ntv <= 32 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 32 test vectors and 1024 sites per aggregate");
+  if (p == MGM_PREC_F64) {
+    const int rc = transfer_chunk_rows(t.rows, t.ntv, rt, 16, false);
+    hipLaunchKernelGGL((k_prolong<F64, F64>), nb, tb, (size_t)t.bvol * 8 + ((size_t)t.ntv * rt + (size_t)rc * t.ntv) * 16, ctx->stream,
+                       (const double2*)xc, (const double2*)x, (double2*)y, P64, t, nrhs, mode, rc);
+  } else if (p == MGM_PREC_F32) {
+    const int rc = transfer_chunk_rows(t.rows, t.ntv, rt, 8, false);
+    hipLaunchKernelGGL((k_prolong<F32, F16>), nb, tb, (size_t)t.bvol * 8 + ((size_t)t.ntv * rt + (size_t)rc * t.ntv) * 8, ctx->stream,
+                       (const float2*)xc, (const float2*)x, (float2*)y, P16, t, nrhs, mode, rc);
+  } else {
     throw Error(MGM_ERR_INVALID_ARG, "prolong: precision must be F64 or F32");
+  }
   MGM_LAUNCH_CHECK();
 }
 

@@ -37,7 +37,7 @@ static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const So
     if (l == 0) {
       // fine level: q^H rho and |q|^2 come out of the dslash itself
       H.fine->apply_dot(p, rho.p, q.p, b.nrhs, H.dpart);
-      b_finalize_dot_norm(c, H.scratch, H.dpart, H.fine->nblocks(b.nrhs), b.nrhs, w.qr, w.qq);
+      b_finalize_dot_norm(c, H.scratch, H.dpart, H.fine->nblocks(p, b.nrhs, true), b.nrhs, w.qr, w.qq);
     } else {
       op_apply(H, l, p, true, cfg, rho.p, q.p, b.nrhs);
       b_dot_norm(c, H.scratch, q, rho, w.qr, w.qq);
@@ -48,7 +48,23 @@ static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const So
 
 static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool precond, const SolveCfg& cfg);
 
+// Fine-level smoothing of the mixed V-cycle in FP16 storage: the input is
+// scaled per rhs to unit RMS entries (MR is homogeneous of degree one, and
+// FP16 keeps its full precision away from the subnormal range), smoothed with
+// FP16 vectors and FP32 arithmetic, and scaled back into FP32.
 static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
+  if (l == 0 && p == MGM_PREC_F32 && cfg.smooth_f16 && cfg.smooth > 0 && H.ws16.size() > 0 &&
+      H.ws16[0].rho != nullptr) {
+    LevelWS& w = H.ws16[0];
+    Context* c = H.ctx;
+    Vec r16 = r.as(MGM_PREC_F16, w.r), y16 = r.as(MGM_PREC_F16, w.t);
+    b_norm2(c, H.scratch, r, w.n2a);
+    b_unit_scales(c, w.n2a, (double)r.nsite * r.dof, r.nrhs, w.mask, w.n2b);
+    b_copy_scaled(c, r16, r, w.mask);
+    mr_smooth(H, 0, MGM_PREC_F16, r16, y16, cfg.smooth, cfg);
+    b_copy_scaled(c, e, y16, w.n2b);
+    return;
+  }
   mr_smooth(H, l, p, r, e, cfg.smooth, cfg);
 }
 
