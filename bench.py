@@ -19,7 +19,7 @@ operator application and an iteration count measured on a small lattice).
 
 Kernel micro-benchmarks (used for the profiler runs of single kernels):
 
-  python bench.py --micro dslash --prec f32[,f64,f16] --nrhs 8[,1,...] [--iters 50]
+  python bench.py --micro dslash|dslash_dot --prec f32[,f64,f16] --nrhs 8[,1,...] [--iters 50]
   python bench.py --micro copy [--iters 50]      # plain 1 GiB device copy
 """
 from __future__ import annotations
@@ -36,9 +36,14 @@ sys.path.insert(0, ROOT)
 METRIC = "RHS solved/s to 1e-10, dslash HBM GB/s; time-to-target-variance tr(D^-1)"
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the dominant kernel (FP32 dslash, nrhs 8, 32^3 x 64) from two
-# rocprofv3 --pmc runs, valid only for the kernel sources it was taken with
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_f32_nrhs8_32x32x32x64_traffic.txt")
+# HBM traffic of the dominant dslash at nrhs 8 on 32^3 x 64 from two rocprofv3
+# --pmc runs, valid only for the kernel sources it was taken with
+TRAFFIC_FILES = {
+    "dslash_f16": os.path.join(ROOT, "profiles", "dslash_f16_dot_nrhs8_32x32x32x64_traffic.txt"),
+    "dslash_f32": os.path.join(ROOT, "profiles", "dslash_f32_nrhs8_32x32x32x64_traffic.txt"),
+}
+KERNEL_NAMES = {"dslash_f16": "k_dslash<F16, DOT> (fused MR-smoother dslash)",
+                "dslash_f32": "k_dslash_rb<F32> (two rhs per thread)", "dslash_f64": "k_dslash<F64>"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_11424_amd", "csrc", f)
                   for f in ("dslash.hip", "fine_dev.h", "fine.h", "common.h")]
 
@@ -52,12 +57,12 @@ def kernel_sources_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Calibrated HBM bytes per launch, or None when the counters were taken
-    with other kernel sources (or not at all)."""
+def measured_traffic(kclass):
+    """Calibrated HBM bytes per launch of the kernel class, or None when the
+    counters were taken with other kernel sources (or not at all)."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[kclass]) as f:
             for line in f:
                 if ":" in line and not line.startswith("#") and not line.startswith(" "):
                     k, v = line.split(":", 1)
@@ -162,6 +167,14 @@ def run(args):
                 os._exit(0)
     import torch
     import paper_2509_11424_amd as m
+    # a dedicated stream (default priority): torch work and the library share
+    # it, and the coarse-grid corrections can be captured into HIP graphs
+    stream = torch.cuda.Stream(device=0)
+    with torch.cuda.stream(stream):
+        _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch)
+
+
+def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     ctx = m.Context(0)
     op = m.Operator(ctx, U, cfg["m0"], cfg["csw"])
     L = len(cfg["blocks"]) + 1
@@ -172,8 +185,12 @@ def run(args):
     torch.cuda.synchronize()
     t_setup = time.time() - t0
     kind = "mg_mixed" if mixed else "mg"
+    # mixed form: FP16-storage fine smoother, BF16 MFMA coarse operators,
+    # autotuned launch shapes and graph-captured coarse-grid corrections
     sd = m.solve_desc(tol=1e-10, kind=kind, smooth=4, coarse_iters=4, inner_tol=1e-5, maxiter=5000,
-                      coarse_bf16=True)
+                      coarse_bf16=True, smoother_f16=True, graphs=bool(mixed))
+    if mixed:
+        ctx.autotune(True)
     batch = cfg["batch"]
 
     def step(first):
@@ -197,7 +214,8 @@ def run(args):
     ctx.profile(False)
     nrhs_step = rhs_per_step(cfg["nprobe"])
     value = nrhs_step * args.steps / dt
-    ds = "dslash_f32" if mixed else "dslash_f64"
+    # dominant kernel: the dslash precision class with the most time
+    ds = max(("dslash_f64", "dslash_f32", "dslash_f16"), key=lambda k: prof[k]["ms"])
     q = prof[ds]
     avg_ms = q["ms"] / max(q["launches"], 1)
     bytes_launch = q["bytes"] / max(q["launches"], 1)
@@ -212,8 +230,8 @@ def run(args):
                    "probes": cfg["nprobe"], "batch": batch, "tol": 1e-10, "form": args.form},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if (mixed and args.config == "c4") else None,
-                     "kernel": "k_dslash_rb<F32>" if mixed else "k_dslash<F64>", "avg_launch_ms": avg_ms,
+                     "traffic": measured_traffic(ds) if args.config == "c4" else None,
+                     "kernel": KERNEL_NAMES[ds], "avg_launch_ms": avg_ms,
                      "launches": q["launches"], "bytes_per_launch": bytes_launch},
         "hierarchy_workspace_gb": h.ws.numel() / 1e9,
         "setup_s": t_setup, "gauge_gen_s": t_gauge, "rhs_per_step": nrhs_step,
@@ -222,6 +240,9 @@ def run(args):
                      "var_of_mean": float(results[-1]["total_var"][0, 0])},
         "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
                         "GBps": (v["bytes"] / v["ms"] / 1e6) if v["ms"] > 0 else 0.0} for k, v in prof.items()},
+        "kernels_note": "HIP-event statistics of eagerly launched kernels; launches replayed from the captured "
+                        "coarse-grid-correction graphs are not timed per class",
+        "tuned_shapes": len(ctx.tune_report()) if mixed else 0,
     }
     if args.ttt:
         line["time_to_target"] = time_to_target(m, ctx, op, cfg, h, sd, args)
@@ -276,19 +297,25 @@ def micro(args):
                 x = torch.randn(shape, generator=g, device="cuda:0",
                                 dtype=torch.complex128 if prec == "f64" else torch.complex64)
             y = torch.empty_like(x)
+            def once():
+                if args.micro == "dslash_dot":
+                    op.apply_dot(x, y, prec)
+                else:
+                    op.apply(x, y, prec)
+
             for _ in range(3):
-                op.apply(x, y, prec)
+                once()
             torch.cuda.synchronize()
             ctx.profile(True)
             ctx.profile_reset()
             for _ in range(args.iters):
-                op.apply(x, y, prec)
+                once()
             torch.cuda.synchronize()
             q = ctx.profile_query("dslash_" + prec)
             ctx.profile(False)
             ms = q["ms"] / q["launches"]
             bl = q["bytes"] / q["launches"]
-            print(json.dumps({"micro": "dslash", "prec": prec, "nrhs": nrhs, "lattice": "x".join(
+            print(json.dumps({"micro": args.micro, "prec": prec, "nrhs": nrhs, "lattice": "x".join(
                 map(str, cfg["dims"])), "launches": q["launches"], "avg_ms": ms, "bytes_per_launch": bl,
                 "GBps": bl / ms / 1e6, "frac": bl / ms / 1e6 / HBM_PEAK_GBS}), flush=True)
             del x, y
@@ -349,7 +376,7 @@ def main():
     ap.add_argument("--form", default="mixed", choices=["mixed", "f64"])
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--ttt", action="store_true")
-    ap.add_argument("--micro", choices=["dslash", "copy"])
+    ap.add_argument("--micro", choices=["dslash", "dslash_dot", "copy"])
     ap.add_argument("--prec", default="f32", help="comma list of f64, f32, f16")
     ap.add_argument("--nrhs", default="8", help="comma list of rhs counts")
     ap.add_argument("--iters", type=int, default=50)

@@ -81,6 +81,16 @@ const char* mgm_version(void);
 mgm_status mgm_context_create(int device, void* hip_stream, mgm_context* out);
 /* Switches the stream used by later calls on this context. */
 mgm_status mgm_context_set_stream(mgm_context ctx, void* hip_stream);
+/* Launch-shape autotuner (project-written): when enabled, the first launch of
+ * a tunable kernel (fine dslash: rhs per thread and block order; coarse
+ * stencils: 16-rhs tiles per workgroup) for a given shape times every variant
+ * on that call's own arguments with HIP events (best of three) and keeps the
+ * fastest for the rest of the context's life.  Results do not depend on the
+ * variant beyond floating-point rounding order.  Off by default. */
+mgm_status mgm_context_set_autotune(mgm_context ctx, int32_t enable);
+/* Text table of the tuned shapes ("key variant ms_v0 ms_v1 ..." per line),
+ * NUL-terminated, truncated to `bytes`; *needed receives the full length. */
+mgm_status mgm_context_tune_report(mgm_context ctx, char* buf, size_t bytes, size_t* needed);
 void mgm_context_destroy(mgm_context ctx);
 
 /* --------------------------------------------------------- fine operator */
@@ -117,6 +127,19 @@ mgm_status mgm_operator_create(mgm_context ctx, const mgm_lattice_desc* desc,
 mgm_status mgm_operator_apply(mgm_operator op, mgm_prec prec, const void* x_dev, void* y_dev,
                               int32_t nrhs);
 
+/* Scratch bytes needed by mgm_operator_apply_dot for (prec, nrhs). */
+mgm_status mgm_operator_dot_workspace_size(mgm_operator op, mgm_prec prec, int32_t nrhs, size_t* bytes);
+
+/* y = D x as mgm_operator_apply, fused with the two reductions of a
+ * minimal-residual step: yx_dev[r] = y_r^H x_r (complex, FP64) and
+ * yy_dev[r] = |y_r|^2 (FP64) per right-hand side, summed in a fixed order from
+ * the stored (rounded) y.  ws_dev: caller-owned device scratch of
+ * mgm_operator_dot_workspace_size bytes, 256-byte aligned.  nrhs <= 256.
+ * Errors: INVALID_ARG, WORKSPACE, HIP. */
+mgm_status mgm_operator_apply_dot(mgm_operator op, mgm_prec prec, const void* x_dev, void* y_dev,
+                                  int32_t nrhs, void* ws_dev, size_t ws_bytes, void* yx_dev,
+                                  void* yy_dev);
+
 /* Number of lattice sites of the fine operator. */
 int64_t mgm_operator_sites(mgm_operator op);
 void mgm_operator_destroy(mgm_operator op);
@@ -128,7 +151,7 @@ void mgm_operator_destroy(mgm_operator op);
  * (Salmon et al., SC'11) at key (seed & 0xffffffff, seed >> 32) and counter
  * (i & 0xffffffff, i >> 32, p, stream).  `stream` = 256*level + kind with
  * kind 0 plain, 1 O_l, 2 F_l, 3 M_l, 4 coarsest, 5 correlator source,
- * 6 loop source, 7 test vector.  Writes nprobe vectors of n_site*dof entries
+ * 6 loop source, 7 test vector, 8 network training input.  Writes nprobe vectors of n_site*dof entries
  * in dof-major layout (probe p = first_probe + rhs; entry index
  * i = site*dof + dof_index) to out_dev in precision `prec` (F64 or F32).
  * Errors: INVALID_ARG, HIP. */
@@ -239,6 +262,11 @@ typedef struct {
   int32_t smoother_f16;/* MG_MIXED / NET: the fine-level MR smoother stores its
                           vectors in FP16 (1; inputs scaled per rhs to unit RMS
                           entries, FP32 arithmetic) or FP32 (0) */
+  int32_t graphs;      /* 1: the coarse-grid correction below each level (a fixed
+                          launch sequence per level, precision and batch) is
+                          captured into a HIP graph on its second use and
+                          replayed afterwards; needs a non-NULL context stream
+                          (ignored otherwise).  Results are identical to 0. */
 } mgm_solve_desc;
 
 typedef struct {

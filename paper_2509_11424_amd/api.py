@@ -52,7 +52,8 @@ class HierarchyDesc(C.Structure):
 class SolveDesc(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("kind", C.c_int32),
                 ("smooth", C.c_int32), ("coarse_iters", C.c_int32), ("inner_tol", C.c_double),
-                ("net", C.c_void_p), ("coarse_bf16", C.c_int32), ("smoother_f16", C.c_int32)]
+                ("net", C.c_void_p), ("coarse_bf16", C.c_int32), ("smoother_f16", C.c_int32),
+                ("graphs", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -103,6 +104,8 @@ _SIGS = [
     ("mgm_version", C.c_char_p, []),
     ("mgm_context_create", C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
     ("mgm_context_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("mgm_context_set_autotune", C.c_int, [C.c_void_p, C.c_int32]),
+    ("mgm_context_tune_report", C.c_int, [C.c_void_p, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     ("mgm_context_destroy", None, [C.c_void_p]),
     ("mgm_operator_workspace_size", C.c_int, [C.POINTER(LatticeDesc), C.POINTER(C.c_size_t)]),
     ("mgm_operator_create", C.c_int, [C.c_void_p, C.POINTER(LatticeDesc), C.c_void_p, C.c_void_p,
@@ -137,6 +140,9 @@ _SIGS = [
     ("mgm_profile_query", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("mgm_hierarchy_destroy", None, [C.c_void_p]),
+    ("mgm_operator_dot_workspace_size", C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.POINTER(C.c_size_t)]),
+    ("mgm_operator_apply_dot", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                         C.c_size_t, C.c_void_p, C.c_void_p]),
     ("mgm_net_workspace_size", C.c_int, [C.c_void_p, C.POINTER(NetDesc), C.POINTER(C.c_size_t)]),
     ("mgm_net_create", C.c_int, [C.c_void_p, C.POINTER(NetDesc), C.c_void_p, C.c_size_t,
                                  C.POINTER(C.c_void_p)]),
@@ -212,6 +218,21 @@ class Context:
     def set_stream(self, stream):
         _check(lib().mgm_context_set_stream(self.h, C.c_void_p(stream)))
 
+    def autotune(self, on: bool = True):
+        _check(lib().mgm_context_set_autotune(self.h, 1 if on else 0))
+
+    def tune_report(self) -> dict:
+        """{key: (variant, [ms per variant])} of the tuned launch shapes."""
+        need = C.c_size_t()
+        _check(lib().mgm_context_tune_report(self.h, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        _check(lib().mgm_context_tune_report(self.h, buf, need.value, C.byref(need)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            f = line.split()
+            out[f[0]] = (int(f[1]), [float(v) for v in f[2:]])
+        return out
+
     def profile(self, on: bool = True):
         _check(lib().mgm_profile_enable(self.h, 1 if on else 0))
 
@@ -271,6 +292,23 @@ class Operator:
                                         nrhs))
         return y
 
+    def apply_dot(self, x, y=None, prec: str = "f64"):
+        """y = D x with the fused per-rhs reductions; returns (y, y^H x, |y|^2)
+        as (tensor, complex128 tensor (nrhs,), float64 tensor (nrhs,))."""
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        nrhs = x.shape[2]
+        nb = C.c_size_t()
+        _check(lib().mgm_operator_dot_workspace_size(self.h, PREC[prec], nrhs, C.byref(nb)))
+        ws = _empty_ws(nb.value, self.ctx.device)
+        yx = torch.empty(nrhs, dtype=torch.complex128, device=x.device)
+        yy = torch.empty(nrhs, dtype=torch.float64, device=x.device)
+        _check(lib().mgm_operator_apply_dot(self.h, PREC[prec], C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)), nrhs,
+                                            C.c_void_p(_ptr(ws)), ws.numel(), C.c_void_p(_ptr(yx)),
+                                            C.c_void_p(_ptr(yy))))
+        return y, yx, yy
+
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.mgm_operator_destroy(self.h)
@@ -288,8 +326,9 @@ def draw_z4(ctx: Context, seed: int, stream: int, first_probe: int, nprobe: int,
 
 
 def solve_desc(tol=1e-12, maxiter=2000, kind="mg", smooth=2, coarse_iters=8, inner_tol=1e-5,
-               net=None, coarse_bf16=True, smoother_f16=True) -> SolveDesc:
+               net=None, coarse_bf16=True, smoother_f16=True, graphs=False) -> SolveDesc:
     d = SolveDesc()
+    d.graphs = 1 if graphs else 0
     d.coarse_bf16 = 1 if coarse_bf16 else 0
     d.smoother_f16 = 1 if smoother_f16 else 0
     d.tol = tol

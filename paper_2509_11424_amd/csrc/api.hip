@@ -45,6 +45,47 @@ void Context::prof_end(int kclass, double bytes, hipEvent_t a) {
   if (prof.pending.size() > 4096) prof_flush();
 }
 
+int Context::choose(const std::string& key, int nvar, const std::function<void(int)>& run) {
+  auto it = tune.table.find(key);
+  if (it != tune.table.end()) {
+    run(it->second.variant);
+    return it->second.variant;
+  }
+  if (!tune.enabled || capturing || nvar <= 1) {
+    run(0);
+    return 0;
+  }
+  const bool prof_was_on = prof.on;
+  prof.on = false;  // tuning launches stay out of the kernel-class statistics
+  Tuner::Entry e;
+  e.ms.assign(nvar, 0.0f);
+  hipEvent_t a = take_event(), b = take_event();
+  for (int v = 0; v < nvar; v++) {
+    run(v);  // warm-up
+    float best = 3.0e38f;
+    for (int rep = 0; rep < 3; rep++) {
+      MGM_HIP(hipEventRecord(a, stream));
+      run(v);
+      MGM_HIP(hipEventRecord(b, stream));
+      MGM_HIP(hipEventSynchronize(b));
+      float ms = 0;
+      MGM_HIP(hipEventElapsedTime(&ms, a, b));
+      best = ms < best ? ms : best;
+    }
+    e.ms[v] = best;
+  }
+  int bv = 0;
+  for (int v = 1; v < nvar; v++)
+    if (e.ms[v] < e.ms[bv]) bv = v;
+  e.variant = bv;
+  tune.table[key] = e;
+  prof.pool.push_back(a);
+  prof.pool.push_back(b);
+  prof.on = prof_was_on;
+  run(bv);  // the call's result comes from the chosen variant
+  return bv;
+}
+
 void Context::prof_flush() {
   if (prof.pending.empty()) return;
   sync();
@@ -118,6 +159,35 @@ mgm_status mgm_context_set_stream(mgm_context ctx, void* hip_stream) {
   API_END
 }
 
+mgm_status mgm_context_set_autotune(mgm_context ctx, int32_t enable) {
+  API_BEGIN
+  MGM_CHECK(ctx != nullptr, MGM_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->c.tune.enabled = enable != 0;
+  API_END
+}
+
+mgm_status mgm_context_tune_report(mgm_context ctx, char* buf, size_t bytes, size_t* needed) {
+  API_BEGIN
+  MGM_CHECK(ctx != nullptr, MGM_ERR_INVALID_ARG, "ctx is NULL");
+  std::string out;
+  for (auto& kv : ctx->c.tune.table) {
+    out += kv.first + " " + std::to_string(kv.second.variant);
+    for (float ms : kv.second.ms) {
+      char t[32];
+      std::snprintf(t, sizeof(t), " %.4f", ms);
+      out += t;
+    }
+    out += "\n";
+  }
+  if (needed) *needed = out.size() + 1;
+  if (buf && bytes > 0) {
+    const size_t n = std::min(bytes - 1, out.size());
+    std::memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  API_END
+}
+
 void mgm_context_destroy(mgm_context ctx) {
   if (!ctx) return;
   try {
@@ -187,6 +257,36 @@ mgm_status mgm_operator_apply(mgm_operator op, mgm_prec prec, const void* x, voi
   MGM_CHECK(op && x && y && nrhs >= 1, MGM_ERR_INVALID_ARG, "bad arguments");
   MGM_CHECK(x != y, MGM_ERR_INVALID_ARG, "x and y must not overlap");
   op->op.apply(prec, x, y, nrhs);
+  API_END
+}
+
+static size_t dot_ws_bytes(const FineOp& op, mgm_prec prec, int nrhs) {
+  // block partials [2][nrhs][blocks] plus the segment sums of the finalisation
+  return ((size_t)op.nblocks(prec, nrhs, true) * 2 * nrhs + (size_t)64 * 2 * nrhs) * sizeof(double2) + 256;
+}
+
+mgm_status mgm_operator_dot_workspace_size(mgm_operator op, mgm_prec prec, int32_t nrhs, size_t* bytes) {
+  API_BEGIN
+  MGM_CHECK(op && bytes && nrhs >= 1 && nrhs <= 256, MGM_ERR_INVALID_ARG, "bad arguments");
+  *bytes = dot_ws_bytes(op->op, prec, nrhs);
+  API_END
+}
+
+mgm_status mgm_operator_apply_dot(mgm_operator op, mgm_prec prec, const void* x, void* y, int32_t nrhs,
+                                  void* ws_dev, size_t ws_bytes, void* yx_dev, void* yy_dev) {
+  API_BEGIN
+  MGM_CHECK(op && x && y && ws_dev && yx_dev && yy_dev, MGM_ERR_INVALID_ARG, "NULL argument");
+  MGM_CHECK(nrhs >= 1 && nrhs <= 256, MGM_ERR_INVALID_ARG, "nrhs must be 1..256");
+  MGM_CHECK(x != y, MGM_ERR_INVALID_ARG, "x and y must not overlap");
+  MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  MGM_CHECK(ws_bytes >= dot_ws_bytes(op->op, prec, nrhs), MGM_ERR_WORKSPACE, "dot workspace too small");
+  const int64_t nb = op->op.nblocks(prec, nrhs, true);
+  double2* part = (double2*)ws_dev;
+  Scratch sc;
+  sc.partial = part + (size_t)nb * 2 * nrhs;
+  sc.cap = (size_t)64 * 2 * nrhs;
+  op->op.apply_dot(prec, x, y, nrhs, part);
+  b_finalize_dot_norm(op->ctx, sc, part, nb, nrhs, (double2*)yx_dev, (double*)yy_dev);
   API_END
 }
 
@@ -410,6 +510,7 @@ static SolveCfg cfg_of(const mgm_solve_desc* d) {
   c.inner_tol = d->inner_tol > 0 ? d->inner_tol : 1e-5;
   c.coarse_bf16 = d->coarse_bf16 != 0;
   c.smooth_f16 = d->smoother_f16 != 0;
+  c.graphs = d->graphs != 0;
   c.net = (Net*)d->net;
   MGM_CHECK(c.kind != MGM_SOLVE_NET || c.net != nullptr, MGM_ERR_INVALID_ARG, "NET solve needs a network");
   return c;

@@ -144,14 +144,15 @@ template <class M, int MT>
 __global__ __launch_bounds__(256) void k_coarse_mfma4(const typename M::C2* __restrict__ x,
                                                      typename M::C2* __restrict__ y,
                                                      const typename M::C2* __restrict__ Ap, LGeom g, int d, int KC,
-                                                     int nrhs, int ntr) {
+                                                     int nrhs, int ntr, int wpb) {
   using R = typename M::R;
   using V4 = typename M::V4;
   using C2 = typename M::C2;
-  // one workgroup per site, one wave per 16-rhs tile: the tiles of a site
-  // stream the same A fragments through the CU's caches at the same time
+  // one workgroup per site and group of wpb 16-rhs tiles (one wave each):
+  // the tiles of a site stream the same A fragments through the CU's caches
+  // at the same time
   const int64_t s = blockIdx.x;
-  const int nt = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int nt = blockIdx.y * wpb + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (nt >= ntr) return;
   const int n = lane & 15, kq = lane >> 4;
@@ -199,14 +200,15 @@ __global__ __launch_bounds__(256) void k_coarse_mfma4(const typename M::C2* __re
 template <int MT>
 __global__ __launch_bounds__(256) void k_coarse_mfma_bf16(const float2* __restrict__ x, float2* __restrict__ y,
                                                          const uint16_t* __restrict__ Ap, LGeom g, int d,
-                                                         int nrhs, int ntr) {
+                                                         int nrhs, int ntr, int wpb) {
   // K chunks of 16 = ceil(d / 16) = MT: the chunk loop unrolls completely so
   // every fragment load of a direction is in flight at once
   constexpr int KC = MT;
-  // one workgroup per site, one wave per 16-rhs tile: the tiles of a site
-  // stream the same A fragments through the CU's caches at the same time
+  // one workgroup per site and group of wpb 16-rhs tiles (one wave each):
+  // the tiles of a site stream the same A fragments through the CU's caches
+  // at the same time
   const int64_t s = blockIdx.x;
-  const int nt = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int nt = blockIdx.y * wpb + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (nt >= ntr) return;
   const int n = lane & 15, kq = lane >> 4;
@@ -269,24 +271,45 @@ __global__ __launch_bounds__(256) void k_coarse_mfma_bf16(const float2* __restri
     default: throw Error(MGM_ERR_SHAPE, "coarse dof must be <= 64"); \
   }
 
+// Waves (16-rhs tiles) per workgroup: 4 by default (the autotuner also tries
+// 2 and 1); v indexes the distinct candidates for ntr tiles.
+static int wpb_of(int ntr, int v) {
+  int cand[3] = {std::min(ntr, 4), std::min(ntr, 2), 1}, n = 0, out[3];
+  for (int c : cand) {
+    bool seen = false;
+    for (int k = 0; k < n; k++) seen |= out[k] == c;
+    if (!seen) out[n++] = c;
+  }
+  return out[v < n ? v : 0];
+}
+static int wpb_count(int ntr) { return ntr >= 4 ? 3 : ntr >= 2 ? 2 : 1; }
+
 void coarse_apply_mfma64(const CoarseOp& A, const double2* x, double2* y, int nrhs) {
   MGeo m = mgeo(A.d);
   const int ntr = (nrhs + 15) / 16;
-  const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + 3) / 4)), tb(64 * std::min(ntr, 4));
   ProfScope ps(A.ctx, KC_COARSE_F64, A.bytes(MGM_PREC_F64, nrhs));
-  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M64, MTc>), nb, tb, 0, A.ctx->stream, x, y,
-                                       A.Ap64, A.g, A.d, m.KC64, nrhs, ntr));
-  MGM_LAUNCH_CHECK();
+  A.ctx->choose("coarse64/" + std::to_string(A.g.V) + "/" + std::to_string(A.d) + "/" + std::to_string(nrhs),
+                wpb_count(ntr), [&](int v) {
+                  const int wpb = wpb_of(ntr, v);
+                  const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + wpb - 1) / wpb)), tb(64 * wpb);
+                  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M64, MTc>), nb, tb, 0, A.ctx->stream, x,
+                                                       y, A.Ap64, A.g, A.d, m.KC64, nrhs, ntr, wpb));
+                  MGM_LAUNCH_CHECK();
+                });
 }
 
 void coarse_apply_mfma32(const CoarseOp& A, const float2* x, float2* y, int nrhs) {
   MGeo m = mgeo(A.d);
   const int ntr = (nrhs + 15) / 16;
-  const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + 3) / 4)), tb(64 * std::min(ntr, 4));
   ProfScope ps(A.ctx, KC_COARSE_F32, A.bytes(MGM_PREC_F32, nrhs));
-  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M32, MTc>), nb, tb, 0, A.ctx->stream, x, y,
-                                       A.A32, A.g, A.d, m.KC64, nrhs, ntr));
-  MGM_LAUNCH_CHECK();
+  A.ctx->choose("coarse32/" + std::to_string(A.g.V) + "/" + std::to_string(A.d) + "/" + std::to_string(nrhs),
+                wpb_count(ntr), [&](int v) {
+                  const int wpb = wpb_of(ntr, v);
+                  const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + wpb - 1) / wpb)), tb(64 * wpb);
+                  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M32, MTc>), nb, tb, 0, A.ctx->stream, x,
+                                                       y, A.A32, A.g, A.d, m.KC64, nrhs, ntr, wpb));
+                  MGM_LAUNCH_CHECK();
+                });
 }
 
 __global__ void k_pack32(float2* __restrict__ out, const double2* __restrict__ packed64, int64_t n) {
@@ -307,11 +330,15 @@ void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs) 
   MGM_CHECK(A.Abf != nullptr, MGM_ERR_INVALID_ARG, "BF16 coarse stencil not built (mixed == 0)");
   MGeo m = mgeo(A.d);
   const int ntr = (nrhs + 15) / 16;
-  const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + 3) / 4)), tb(64 * std::min(ntr, 4));
   ProfScope ps(A.ctx, KC_COARSE_BF16, A.bytes(MGM_PREC_BF16, nrhs));
-  MT_DISPATCH(m.MT, hipLaunchKernelGGL(k_coarse_mfma_bf16<MTc>, nb, tb, 0, A.ctx->stream, x, y,
-                                       (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr));
-  MGM_LAUNCH_CHECK();
+  A.ctx->choose("coarsebf16/" + std::to_string(A.g.V) + "/" + std::to_string(A.d) + "/" + std::to_string(nrhs),
+                wpb_count(ntr), [&](int v) {
+                  const int wpb = wpb_of(ntr, v);
+                  const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + wpb - 1) / wpb)), tb(64 * wpb);
+                  MT_DISPATCH(m.MT, hipLaunchKernelGGL(k_coarse_mfma_bf16<MTc>, nb, tb, 0, A.ctx->stream, x, y,
+                                                       (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb));
+                  MGM_LAUNCH_CHECK();
+                });
 }
 
 }  // namespace mgm

@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <functional>
+#include <map>
 #include <vector>
 #include <stdexcept>
 #include <algorithm>
@@ -253,10 +255,25 @@ struct Profiler {
   double bytes[KC_COUNT] = {0};
 };
 
+// Launch-shape autotuner: the first call of a kernel for a shape key times
+// every variant on the call's own arguments (HIP events, best of three) and
+// keeps the fastest; later calls reuse it.  Off by default (variant 0), and
+// never active while a stream is being captured into a graph.
+struct Tuner {
+  bool enabled = false;
+  struct Entry {
+    int variant = 0;
+    std::vector<float> ms;  // timing of every variant
+  };
+  std::map<std::string, Entry> table;
+};
+
 struct Context {
   int device = 0;
   hipStream_t stream = nullptr;
   Profiler prof;
+  Tuner tune;
+  bool capturing = false;  // stream capture in progress: no timing, no tuning
   // pinned host staging
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
@@ -267,6 +284,8 @@ struct Context {
   void prof_end(int kclass, double bytes, hipEvent_t a);
   void prof_flush();
   void sync() { MGM_HIP(hipStreamSynchronize(stream)); }
+  // variant of `key` among nvar; run(v) launches variant v on the stream
+  int choose(const std::string& key, int nvar, const std::function<void(int)>& run);
 };
 
 // RAII timer around one launch of kernel class kc (no-op when profiling is off).
@@ -276,7 +295,7 @@ struct ProfScope {
   double bytes;
   hipEvent_t a = nullptr;
   ProfScope(Context* c_, int kc_, double b_) : c(c_), kc(kc_), bytes(b_) {
-    if (c->prof.on) c->prof_begin(kc, bytes, &a);
+    if (c->prof.on && !c->capturing) c->prof_begin(kc, bytes, &a);
   }
   ~ProfScope() {
     if (c->prof.on && a) c->prof_end(kc, bytes, a);

@@ -605,10 +605,12 @@ double FineOp::bytes(mgm_prec p, int nrhs) const {
   return (double)g.V * (36 * wc + 72 * wr + 24.0 * wc * nrhs);
 }
 
-// right-hand sides per thread: two for FP32/FP16 with an even count; the
-// reducing variant keeps one (its extra accumulators would cost occupancy)
+// right-hand sides per thread: two for FP32/FP16 with an even count, except
+// the reducing FP32 variant (its FP64 accumulators would push it below three
+// waves per SIMD)
 static int rb_of(mgm_prec p, int nrhs, bool dot) {
-  return (!dot && p != MGM_PREC_F64 && nrhs % 2 == 0) ? 2 : 1;
+  if (nrhs % 2 != 0 || p == MGM_PREC_F64) return 1;
+  return (p == MGM_PREC_F32 && dot) ? 1 : 2;
 }
 
 int64_t FineOp::nblocks(mgm_prec p, int nrhs, bool dot) const {
@@ -616,14 +618,15 @@ int64_t FineOp::nblocks(mgm_prec p, int nrhs, bool dot) const {
 }
 
 template <bool DOT, int RB>
-static void launch_rb(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) {
+static void launch_rb(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart,
+                      bool allow_slab) {
   const Geom& g = op.g;
   const int threads = 256;
-  const int64_t nb = op.nblocks(p, nrhs, DOT);
+  const int64_t nb = (g.V * (nrhs / RB) + 255) / 256;
   // slab mapping needs whole 64-thread chunks per slice and kSlab | T; it
   // then covers exactly nb * 256 = V * nrhs / RB threads
   const int64_t per_slice = (g.V / g.T) * (nrhs / RB);
-  const int slab = (per_slice % 64 == 0 && g.T % kSlab == 0 && threads == 64 * kSlab) ? 1 : 0;
+  const int slab = (allow_slab && per_slice % 64 == 0 && g.T % kSlab == 0 && threads == 64 * kSlab) ? 1 : 0;
   hipStream_t st = op.ctx->stream;
   switch (p) {
     case MGM_PREC_F64:
@@ -653,12 +656,24 @@ static void launch_rb(const FineOp& op, mgm_prec p, const void* x, void* y, int 
   MGM_LAUNCH_CHECK();
 }
 
+// Tuned launch shapes: variant 0 is the default (rb_of, slab order), 1 the
+// plain block order; the non-reducing FP32/FP16 kernels with an even rhs count
+// also try the other rhs-per-thread count (2, 3).  The reducing variant keeps
+// rb_of, whose block count sizes the partial sums.
 template <bool DOT>
 static void launch_dslash(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) {
-  if (rb_of(p, nrhs, DOT) == 2)
-    launch_rb<DOT, 2>(op, p, x, y, nrhs, dpart);
-  else
-    launch_rb<DOT, 1>(op, p, x, y, nrhs, dpart);
+  const int rb0 = rb_of(p, nrhs, DOT);
+  const bool alt = !DOT && p != MGM_PREC_F64 && nrhs % 2 == 0;
+  const std::string key = std::string(DOT ? "dslash_dot/" : "dslash/") + std::to_string((int)p) + "/" +
+                          std::to_string(op.g.V) + "/" + std::to_string(nrhs);
+  op.ctx->choose(key, alt ? 4 : 2, [&](int v) {
+    const int rb = v < 2 ? rb0 : 3 - rb0;
+    const bool slab = (v & 1) == 0;
+    if (rb == 2)
+      launch_rb<DOT, 2>(op, p, x, y, nrhs, dpart, slab);
+    else
+      launch_rb<DOT, 1>(op, p, x, y, nrhs, dpart, slab);
+  });
 }
 
 static int kclass_of(mgm_prec p) {

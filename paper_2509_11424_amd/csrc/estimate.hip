@@ -44,6 +44,7 @@ struct Run {
     cfg.inner_tol = d.solve.inner_tol > 0 ? d.solve.inner_tol : 1e-5;
     cfg.coarse_bf16 = d.solve.coarse_bf16 != 0;
     cfg.smooth_f16 = d.solve.smoother_f16 != 0;
+    cfg.graphs = d.solve.graphs != 0;
     cfg.net = (Net*)d.solve.net;
   }
   Vec v(int l, void* p, int nb) { return H.vec(l, MGM_PREC_F64, p, nb); }

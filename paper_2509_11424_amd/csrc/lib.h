@@ -78,6 +78,17 @@ struct Hier {
   double* setup_qq = nullptr;
   bool tv_valid = false;     // test vectors alias solver memory until the first solve
   Net* net = nullptr;
+  // captured coarse-grid corrections (level, precision, batch, settings):
+  // one eager use, capture on the second, replay afterwards
+  struct GraphEntry {
+    int uses = 0;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::map<std::string, GraphEntry> graphs;
+  ~Hier() {
+    for (auto& g : graphs)
+      if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+  }
 
   int64_t n(int l) const { return g[l].V * g[l].dof; }
   // right-hand-side capacity of level l (non-decreasing towards coarse levels)
@@ -118,6 +129,7 @@ struct SolveCfg {
   double inner_tol = 1e-5;
   bool coarse_bf16 = false;
   bool smooth_f16 = false;  // mixed kinds: FP16-storage fine MR smoother
+  bool graphs = false;      // replay captured coarse-grid corrections
   Net* net = nullptr;
 };
 

@@ -68,6 +68,49 @@ static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg
   mr_smooth(H, l, p, r, e, cfg.smooth, cfg);
 }
 
+// e_c = (cfg.coarse_iters FGMRES steps on level lc) r_c, between the level's
+// fixed coarse buffers.  Its launch sequence depends only on the level, the
+// precision, the batch and the settings, so with cfg.graphs it is captured
+// into a HIP graph on its second use and replayed from then on (the first,
+// eager use also lets the autotuner settle every launch shape inside).
+static void coarse_correction(Hier& H, int lc, mgm_prec p, Vec rc, Vec ec, const SolveCfg& cfg) {
+  Context* c = H.ctx;
+  const bool precond = lc < H.L - 1;
+  if (!cfg.graphs || c->capturing || c->stream == nullptr) {
+    fgmres_fixed(H, lc, p, rc, ec, cfg.coarse_iters, precond, cfg);
+    return;
+  }
+  const std::string key = std::to_string(lc) + "/" + std::to_string((int)p) + "/" + std::to_string(rc.nrhs) + "/" +
+                          std::to_string(cfg.coarse_iters) + "/" + std::to_string(cfg.smooth) + "/" +
+                          std::to_string((int)cfg.coarse_bf16) + "/" + (rc.p == H.ws(lc, p).bc ? "bc" : "other");
+  Hier::GraphEntry& g = H.graphs[key];
+  if (g.exec) {
+    MGM_HIP(hipGraphLaunch(g.exec, c->stream));
+    return;
+  }
+  if (g.uses++ == 0 || rc.p != H.ws(lc, p).bc || ec.p != H.ws(lc, p).xc) {
+    fgmres_fixed(H, lc, p, rc, ec, cfg.coarse_iters, precond, cfg);
+    return;
+  }
+  hipGraph_t graph = nullptr;
+  MGM_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
+  try {
+    fgmres_fixed(H, lc, p, rc, ec, cfg.coarse_iters, precond, cfg);
+  } catch (...) {
+    c->capturing = false;
+    (void)hipStreamEndCapture(c->stream, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  c->capturing = false;
+  MGM_HIP(hipStreamEndCapture(c->stream, &graph));
+  hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  MGM_CHECK(e == hipSuccess, MGM_ERR_HIP, std::string("graph instantiation failed: ") + hipGetErrorString(e));
+  MGM_HIP(hipGraphLaunch(g.exec, c->stream));
+}
+
 void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
   Context* c = H.ctx;
   if (l == H.L - 1) {
@@ -83,7 +126,7 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
     LevelWS& wc = H.ws(1, p);
     Vec rc = H.vec(1, p, wc.bc, nrhs), ec = H.vec(1, p, wc.xc, nrhs);
     H.T[0].restrict_(p, r.p, rc.p, nrhs);
-    fgmres_fixed(H, 1, p, rc, ec, cfg.coarse_iters, 1 < H.L - 1, cfg);
+    coarse_correction(H, 1, p, rc, ec, cfg);
     H.T[0].prolong(p, ec.p, nullptr, e.p, nrhs, 0);  // e = P e_c
     op_apply(H, 0, p, true, cfg, e.p, t.p, nrhs);
     b_xpay(c, r, nullptr, -1.0, t);
@@ -98,7 +141,7 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
   LevelWS& wc = H.ws(l + 1, p);
   Vec rc = H.vec(l + 1, p, wc.bc, nrhs), ec = H.vec(l + 1, p, wc.xc, nrhs);
   H.T[l].restrict_(p, t.p, rc.p, nrhs);
-  fgmres_fixed(H, l + 1, p, rc, ec, cfg.coarse_iters, l + 1 < H.L - 1, cfg);
+  coarse_correction(H, l + 1, p, rc, ec, cfg);
   H.T[l].prolong(p, ec.p, nullptr, e.p, nrhs, 2);  // e += P e_c
   op_apply(H, l, p, true, cfg, e.p, t.p, nrhs);
   b_xpay(c, r, nullptr, -1.0, t);

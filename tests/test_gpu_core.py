@@ -163,3 +163,59 @@ class _LocalStencil:
             out = out - 0.5 * ph_f * ((I4 - g[mu]) @ (pf @ Uf.T)).reshape(12)
             out = out - 0.5 * ph_b * ((I4 + g[mu]) @ (pb @ Ub.T)).reshape(12)
         return out
+
+
+@pytest.mark.parametrize("prec,nrhs", [("f64", 3), ("f32", 4), ("f32", 5), ("f16", 8)])
+def test_dslash_fused_reductions(ctx, prec, nrhs):
+    """mgm_operator_apply_dot: y = D x plus y^H x and |y|^2 per rhs, summed in
+    FP64 from the stored y.  The products are those of the stored values, so
+    the sums agree with numpy's up to summation order (1e-12 relative); y
+    agrees with the plain application within the precision's bound."""
+    import torch
+    import paper_2509_11424_amd as m
+    from oracle.dirac import WilsonClover
+    dims = (4, 4, 4, 8)
+    U = gauge_field(dims, 0.6, 21)
+    op = m.Operator(ctx, U, 0.03, 1.0)
+    xs = random_spinor(dims, 22, batch=nrhs)
+    xg = to_gpu(xs.reshape(nrhs, -1, 12))
+    if prec == "f64":
+        xin = xg
+    elif prec == "f32":
+        xin = xg.to(torch.complex64)
+    else:
+        xin = torch.view_as_real(xg).to(torch.float16).contiguous()
+    y, yx, yy = op.apply_dot(xin, prec=prec)
+    torch.cuda.synchronize()
+
+    def c128(t):
+        if prec == "f16":
+            t = torch.view_as_complex(t.float().contiguous())
+        return t.to(torch.complex128).cpu().numpy()
+
+    yn, xn = c128(y), c128(xin)
+    for r in range(nrhs):
+        a = np.vdot(yn[:, :, r].ravel(), xn[:, :, r].ravel())
+        b = np.vdot(yn[:, :, r].ravel(), yn[:, :, r].ravel()).real
+        assert abs(yx[r].item() - a) <= 1e-12 * abs(b)
+        assert abs(yy[r].item() - b) <= 1e-12 * b
+    want = WilsonClover(U, 0.03, 1.0).apply(xs).reshape(nrhs, -1, 12)
+    bound = {"f64": 1e-13, "f32": 2e-6, "f16": 4e-3}[prec]
+    assert rel(from_gpu(torch.from_numpy(yn)), want) < bound
+
+
+def test_dslash_odd_rhs_count_f32(ctx):
+    """An odd rhs count takes the one-rhs-per-thread kernel; even counts take
+    the two-rhs kernel: both agree with the oracle at the FP32 bound."""
+    import torch
+    import paper_2509_11424_amd as m
+    from oracle.dirac import WilsonClover
+    dims = (4, 4, 4, 8)
+    U = gauge_field(dims, 0.6, 23)
+    D = WilsonClover(U, 0.01, 1.0)
+    op = m.Operator(ctx, U, 0.01, 1.0)
+    for nrhs in (1, 3, 6):
+        xs = random_spinor(dims, 24 + nrhs, batch=nrhs)
+        want = D.apply(xs).reshape(nrhs, -1, 12)
+        y = op.apply(to_gpu(xs.reshape(nrhs, -1, 12)).to(torch.complex64), prec="f32").to(torch.complex128)
+        assert rel(from_gpu(y), want) < 2e-6
