@@ -39,9 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of the dominant dslash at nrhs 8 on 32^3 x 64 from two rocprofv3
 # --pmc runs, valid only for the kernel sources it was taken with
 TRAFFIC_FILES = {
-    "dslash_f16": os.path.join(ROOT, "profiles", "dslash_f16_dot_nrhs8_32x32x32x64_traffic.txt"),
-    "dslash_f32": os.path.join(ROOT, "profiles", "dslash_f32_nrhs8_32x32x32x64_traffic.txt"),
+    "dslash_f16": os.path.join(ROOT, "profiles", "dslash_f16_dot_32x32x32x64_traffic.txt"),
+    "dslash_f32": os.path.join(ROOT, "profiles", "dslash_f32_32x32x32x64_traffic.txt"),
 }
+PREC_BYTES = {"dslash_f64": 16, "dslash_f32": 8, "dslash_f16": 4}
 KERNEL_NAMES = {"dslash_f16": "k_dslash<F16, DOT> (fused MR-smoother dslash)",
                 "dslash_f32": "k_dslash_rb<F32> (two rhs per thread)", "dslash_f64": "k_dslash<F64>"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_11424_amd", "csrc", f)
@@ -57,9 +58,20 @@ def kernel_sources_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kclass):
-    """Calibrated HBM bytes per launch of the kernel class, or None when the
-    counters were taken with other kernel sources (or not at all)."""
+def dslash_bytes(kclass, V, nrhs):
+    """Algorithmic bytes of one fine dslash (links and clover once, spinors in
+    and out), as the library's FineOp::bytes."""
+    wc = PREC_BYTES[kclass]
+    return V * (36 * wc + 72 * wc / 2 + 24 * wc * nrhs)
+
+
+def measured_traffic(kclass, V, launches, total_bytes):
+    """Calibrated HBM bytes per launch of the kernel class in the timed region,
+    or None.  The counter file holds FETCH_SIZE / WRITE_SIZE per launch at the
+    rhs counts the timed region uses (8 and 4 on the fine level); the split of
+    the region's launches between them follows from its launch count and
+    algorithmic bytes.  None when the counters were taken with other kernel
+    sources or the launches do not split into those counts."""
     try:
         kv = {}
         with open(TRAFFIC_FILES[kclass]) as f:
@@ -69,9 +81,18 @@ def measured_traffic(kclass):
                     kv[k.strip()] = v.strip()
         if kv.get("kernel_sources_sha256") != kernel_sources_hash():
             return None
-        return float(kv["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+        fs, ws = float(kv["fetch_scale"]), float(kv["write_scale"])
+        t = {n: (float(kv["fetch_kib_nrhs%d" % n]) * fs + float(kv["write_kib_nrhs%d" % n]) * ws) * 1024.0
+             for n in (8, 4)}
+        b8, b4 = dslash_bytes(kclass, V, 8), dslash_bytes(kclass, V, 4)
+        n8 = (total_bytes - launches * b4) / (b8 - b4)
+        if abs(n8 - round(n8)) > 1e-3 * launches or n8 < -0.5 or n8 > launches + 0.5:
+            return None
+        n8 = int(round(n8))
+        return (n8 * t[8] + (launches - n8) * t[4]) / launches
+    except (OSError, KeyError, ValueError, ZeroDivisionError):
         return None
+
 
 CONFIGS = {
     # 32^3 x 64, csw 1, roughness 0.6, m0 0.02; 4^4 (24 tv) then 2^4 (32 tv);
@@ -187,8 +208,8 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     kind = "mg_mixed" if mixed else "mg"
     # mixed form: FP16-storage fine smoother, BF16 MFMA coarse operators,
     # autotuned launch shapes and graph-captured coarse-grid corrections
-    sd = m.solve_desc(tol=1e-10, kind=kind, smooth=4, coarse_iters=4, inner_tol=1e-5, maxiter=5000,
-                      coarse_bf16=True, smoother_f16=True, graphs=bool(mixed))
+    sd = m.solve_desc(tol=1e-10, kind=kind, smooth=6 if mixed else 4, coarse_iters=4, inner_tol=1e-5,
+                      maxiter=5000, coarse_bf16=True, smoother_f16=True, graphs=bool(mixed))
     if mixed:
         ctx.autotune(True)
     batch = cfg["batch"]
@@ -230,7 +251,8 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
                    "probes": cfg["nprobe"], "batch": batch, "tol": 1e-10, "form": args.form},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(ds) if args.config == "c4" else None,
+                     "traffic": measured_traffic(ds, op.V, q["launches"], q["bytes"]) if args.config == "c4"
+                     else None,
                      "kernel": KERNEL_NAMES[ds], "avg_launch_ms": avg_ms,
                      "launches": q["launches"], "bytes_per_launch": bytes_launch},
         "hierarchy_workspace_gb": h.ws.numel() / 1e9,

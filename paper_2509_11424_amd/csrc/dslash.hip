@@ -215,6 +215,79 @@ __global__ void k_cvt_r64_r16(__half* o, const double* in, int64_t n) {
 
 // ---------------------------------------------------------------- dslash
 
+// Per-rhs block sums of the fused reductions, written to dpart[2][nrhs][block]
+// (q^H in, then |q|^2).  When nq = nrhs / RB divides 64 (and nrhs <= 64),
+// lane % nq fixes a thread's rhs columns: a fixed xor-shuffle tree sums each
+// wave and the four wave rows are added in order.  Otherwise every thread's
+// entries go through LDS and thread t < nrhs sums those of rhs t in thread
+// order.  Both orders are fixed, so results are deterministic.
+template <int RB>
+__device__ __forceinline__ void dot_block_store(cx<double> (&dqr)[RB], double (&dqq)[RB], bool active, int r0,
+                                                int nrhs, int64_t nblocks, double2* __restrict__ dpart) {
+  const int nq = nrhs / RB;
+  if (!active) {
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+      dqr[j] = {0, 0};
+      dqq[j] = 0;
+    }
+  }
+  if (nrhs <= 64 && 64 % nq == 0) {
+    __shared__ double2 sw_qr[4][64];
+    __shared__ double sw_qq[4][64];
+    for (int off = 32; off >= nq; off >>= 1) {
+#pragma unroll
+      for (int j = 0; j < RB; j++) {
+        dqr[j].re += __shfl_xor(dqr[j].re, off, 64);
+        dqr[j].im += __shfl_xor(dqr[j].im, off, 64);
+        dqq[j] += __shfl_xor(dqq[j], off, 64);
+      }
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane < nq) {
+#pragma unroll
+      for (int j = 0; j < RB; j++) {
+        sw_qr[w][lane * RB + j] = make_double2(dqr[j].re, dqr[j].im);
+        sw_qq[w][lane * RB + j] = dqq[j];
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nrhs) {
+      const int t = threadIdx.x;
+      double a = 0, b = 0, n2 = 0;
+      for (int ww = 0; ww < (int)(blockDim.x >> 6); ww++) {
+        a += sw_qr[ww][t].x;
+        b += sw_qr[ww][t].y;
+        n2 += sw_qq[ww][t];
+      }
+      dpart[(int64_t)t * nblocks + blockIdx.x] = make_double2(a, b);
+      dpart[(int64_t)(nrhs + t) * nblocks + blockIdx.x] = make_double2(n2, 0.0);
+    }
+    return;
+  }
+  __shared__ double2 sh_qr[256 * RB];
+  __shared__ double sh_qq[256 * RB];
+  __shared__ int sh_r[256 * RB];
+#pragma unroll
+  for (int j = 0; j < RB; j++) {
+    sh_qr[threadIdx.x * RB + j] = make_double2(dqr[j].re, dqr[j].im);
+    sh_qq[threadIdx.x * RB + j] = dqq[j];
+    sh_r[threadIdx.x * RB + j] = active ? r0 + j : -1;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nrhs) {
+    double a = 0, b = 0, n2 = 0;
+    for (int u = 0; u < (int)blockDim.x * RB; u++)
+      if (sh_r[u] == (int)threadIdx.x) {
+        a += sh_qr[u].x;
+        b += sh_qr[u].y;
+        n2 += sh_qq[u];
+      }
+    dpart[(int64_t)threadIdx.x * nblocks + blockIdx.x] = make_double2(a, b);
+    dpart[(int64_t)(nrhs + threadIdx.x) * nblocks + blockIdx.x] = make_double2(n2, 0.0);
+  }
+}
+
 constexpr int kSlab = 4;  // time slices (one wave each) per 256-thread block
 
 // DOT: also reduce q^H in and |q|^2 per rhs for the minimal-residual smoother
@@ -350,25 +423,9 @@ __global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
     for (int k = 0; k < 12; k++) P::st(out, (int64_t)k * N + tid, acc[k]);
   }
   if (DOT) {
-    // per-rhs block sums in a fixed order
-    __shared__ double2 sh_qr[256];
-    __shared__ double sh_qq[256];
-    __shared__ int sh_r[256];
-    sh_qr[threadIdx.x] = make_double2(dqr.re, dqr.im);
-    sh_qq[threadIdx.x] = dqq;
-    sh_r[threadIdx.x] = active ? r : -1;
-    __syncthreads();
-    if ((int)threadIdx.x < nrhs) {
-      double a = 0, b = 0, n2 = 0;
-      for (int u = 0; u < (int)blockDim.x; u++)
-        if (sh_r[u] == (int)threadIdx.x) {
-          a += sh_qr[u].x;
-          b += sh_qr[u].y;
-          n2 += sh_qq[u];
-        }
-      dpart[(int64_t)threadIdx.x * nblocks + blockIdx.x] = make_double2(a, b);
-      dpart[(int64_t)(nrhs + threadIdx.x) * nblocks + blockIdx.x] = make_double2(n2, 0.0);
-    }
+    cx<double> qr1[1] = {dqr};
+    double qq1[1] = {dqq};
+    dot_block_store<1>(qr1, qq1, active, r, nrhs, nblocks, dpart);
   }
 }
 
@@ -531,30 +588,7 @@ __global__ __launch_bounds__(256) void k_dslash_rb(typename P::S* __restrict__ o
 #pragma unroll
     for (int k = 0; k < 12; k++) P::template stv<RB>(out, (int64_t)k * N + es, acc[k]);
   }
-  if (DOT) {
-    // per-rhs block sums in a fixed order
-    __shared__ double2 sh_qr[256 * RB];
-    __shared__ double sh_qq[256 * RB];
-    __shared__ int sh_r[256 * RB];
-#pragma unroll
-    for (int j = 0; j < RB; j++) {
-      sh_qr[threadIdx.x * RB + j] = make_double2(dqr[j].re, dqr[j].im);
-      sh_qq[threadIdx.x * RB + j] = dqq[j];
-      sh_r[threadIdx.x * RB + j] = active ? r0 + j : -1;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nrhs) {
-      double a = 0, b = 0, n2 = 0;
-      for (int u = 0; u < (int)blockDim.x * RB; u++)
-        if (sh_r[u] == (int)threadIdx.x) {
-          a += sh_qr[u].x;
-          b += sh_qr[u].y;
-          n2 += sh_qq[u];
-        }
-      dpart[(int64_t)threadIdx.x * nblocks + blockIdx.x] = make_double2(a, b);
-      dpart[(int64_t)(nrhs + threadIdx.x) * nblocks + blockIdx.x] = make_double2(n2, 0.0);
-    }
-  }
+  if (DOT) dot_block_store<RB>(dqr, dqq, active, r0, nrhs, nblocks, dpart);
 }
 
 // ------------------------------------------------------------------ host
@@ -605,12 +639,11 @@ double FineOp::bytes(mgm_prec p, int nrhs) const {
   return (double)g.V * (36 * wc + 72 * wr + 24.0 * wc * nrhs);
 }
 
-// right-hand sides per thread: two for FP32/FP16 with an even count, except
-// the reducing FP32 variant (its FP64 accumulators would push it below three
-// waves per SIMD)
+// right-hand sides per thread: two for FP32/FP16 with an even count; the
+// reducing variant keeps one (with two, its FP64 accumulators and LDS cost
+// more occupancy than the shared loads save: measured slower for both)
 static int rb_of(mgm_prec p, int nrhs, bool dot) {
-  if (nrhs % 2 != 0 || p == MGM_PREC_F64) return 1;
-  return (p == MGM_PREC_F32 && dot) ? 1 : 2;
+  return (!dot && p != MGM_PREC_F64 && nrhs % 2 == 0) ? 2 : 1;
 }
 
 int64_t FineOp::nblocks(mgm_prec p, int nrhs, bool dot) const {

@@ -1,0 +1,45 @@
+"""Host-side pieces of bench.py (no GPU): workload table, step accounting,
+algorithmic bytes, the traffic gate and the one-GPU guard."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_workload_and_rhs_accounting():
+    import bench
+    c4 = bench.CONFIGS["c4"]
+    assert c4["dims"] == (32, 32, 32, 64) and c4["nprobe"] == [20, 100, 400]
+    # O_l and F_l per non-coarsest level (F_l solves on l and l + 1), coarsest once
+    assert bench.rhs_per_step([20, 100, 400]) == 3 * 20 + 3 * 100 + 400
+
+
+def test_dslash_algorithmic_bytes():
+    import bench
+    V = 32 * 32 * 32 * 64
+    # FP32, one rhs: 768 bytes per site (links 288, clover 288, spinor in + out 192)
+    assert bench.dslash_bytes("dslash_f32", V, 1) == 768 * V
+    assert bench.dslash_bytes("dslash_f64", V, 1) == 1536 * V
+    assert bench.dslash_bytes("dslash_f16", V, 1) == 384 * V
+
+
+def test_traffic_gate_rejects_other_sources(tmp_path, monkeypatch):
+    import bench
+    f = tmp_path / "t.txt"
+    f.write_text("kernel_sources_sha256: 0000\nfetch_scale: 2\nwrite_scale: 1\n"
+                 "fetch_kib_nrhs8: 1\nwrite_kib_nrhs8: 1\nfetch_kib_nrhs4: 1\nwrite_kib_nrhs4: 1\n")
+    monkeypatch.setitem(bench.TRAFFIC_FILES, "dslash_f16", str(f))
+    V = 1024
+    assert bench.measured_traffic("dslash_f16", V, 3, 3 * bench.dslash_bytes("dslash_f16", V, 8)) is None
+    f.write_text(f.read_text().replace("0000", bench.kernel_sources_hash()))
+    t = bench.measured_traffic("dslash_f16", V, 3, 2 * bench.dslash_bytes("dslash_f16", V, 8)
+                               + bench.dslash_bytes("dslash_f16", V, 4))
+    assert abs(t - 3 * 1024.0) < 1e-9  # (1 * 2 + 1) KiB at every rhs count
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
