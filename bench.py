@@ -15,7 +15,7 @@ baseline (fine-level solve rate of the FP64 oracle, extrapolated from one
 operator application and an iteration count measured on a small lattice).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4|c3|c2]
-                  [--form mixed|f64] [--cpu 0|1] [--ttt]
+                  [--form mixed|f64] [--cpu 0|1] [--ttt] [--learned [--net-widths 4 8 8 4]]
 
 Kernel micro-benchmarks (used for the profiler runs of single kernels):
 
@@ -266,6 +266,8 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
                         "coarse-grid-correction graphs are not timed per class",
         "tuned_shapes": len(ctx.tune_report()) if mixed else 0,
     }
+    if args.learned:
+        line["learned"] = learned_form(m, ctx, op, cfg, h, sd, args, torch)
     if args.ttt:
         line["time_to_target"] = time_to_target(m, ctx, op, cfg, h, sd, args)
         h = None
@@ -343,6 +345,52 @@ def micro(args):
             del x, y
 
 
+def learned_form(m, ctx, op, cfg, h, sd_mixed, args, torch):
+    """Learned preconditioner at the workload's size: a PTC network trained on
+    a small lattice of the same ensemble parameters (the weights are
+    volume-independent), then used as the fine smoother of the mixed solver
+    on the full lattice; compared with the MR-smoothed mixed solve on the same
+    right-hand sides, and one full estimate step with it."""
+    from lattice_inputs import gauge_field
+    small = (8, 8, 8, 8)
+    Us = gauge_field(small, cfg["eps"], cfg["gseed"] + 500)
+    ops = m.Operator(ctx, Us, cfg["m0"], cfg["csw"])
+    hs = m.Hierarchy(ops, [(4, 4, 4, 4)], [cfg["ntv"][0]], seed=cfg["pseed"] + 2000, max_nrhs=16, restart=16,
+                     mixed=2)
+    widths = tuple(args.net_widths)
+    ns = m.Net(ops, widths=widths, seed=cfg["pseed"] + 3000, max_nrhs=16, train_nrhs=16)
+    t0 = time.time()
+    tr = ns.train(hs, steps=args.net_steps, lr=3e-3, seed=cfg["pseed"] + 4000, target_tol=1e-8)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    net = m.Net(op, widths=widths, seed=1, max_nrhs=cfg["batch"][0])
+    net.set_weights(ns.get_weights())
+    del ns, hs, ops
+    sd_net = m.solve_desc(tol=1e-10, kind="net", net=net, smooth=sd_mixed.smooth, coarse_iters=sd_mixed.coarse_iters,
+                          inner_tol=1e-5, maxiter=5000, coarse_bf16=True, smoother_f16=True, graphs=True)
+    s_, d_, _ = h.level_info(0)
+    b = m.draw_z4(ctx, cfg["pseed"] + 5000, 0, 0, cfg["batch"][0], s_, d_, "f64")
+    out = {"widths": list(widths), "train_lattice": "x".join(map(str, small)), "train_steps": args.net_steps,
+           "train_pairs": 16, "train_s": t_train, "loss_first": tr["loss_first"], "loss_last": tr["loss_last"]}
+    for name, desc in (("mr_smoother", sd_mixed), ("network", sd_net)):
+        h.solve(0, b, desc)  # warm-up (tuning, graph capture)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        x, st = h.solve(0, b, desc)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.time() - t0, "iterations": st["iterations"], "fallbacks": st["fallbacks"],
+                     "max_rel_residual": st["max_rel_residual"]}
+    torch.cuda.synchronize()
+    t0 = time.time()
+    r = h.estimate("trace", "orthogonal", cfg["nprobe"], seed=cfg["pseed"] + 6000, batch=cfg["batch"],
+                   solve=sd_net, samples=False)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    out["estimate_step"] = {"seconds": dt, "rhs_per_s": rhs_per_step(cfg["nprobe"]) / dt,
+                            "fallbacks": r["stats"]["fallbacks"]}
+    return out
+
+
 def time_to_target(m, ctx, op, cfg, h_mixed, sd_mixed, args):
     """Time to reach the variance of the plain FP64 orthogonal estimate at the
     configured probe counts (target eps^2), for plain FP64 MG and for the
@@ -398,6 +446,9 @@ def main():
     ap.add_argument("--form", default="mixed", choices=["mixed", "f64"])
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--ttt", action="store_true")
+    ap.add_argument("--learned", action="store_true", help="also measure the learned-preconditioner form")
+    ap.add_argument("--net-widths", type=int, nargs="+", default=[4, 8, 8, 4])
+    ap.add_argument("--net-steps", type=int, default=150)
     ap.add_argument("--micro", choices=["dslash", "dslash_dot", "copy"])
     ap.add_argument("--prec", default="f32", help="comma list of f64, f32, f16")
     ap.add_argument("--nrhs", default="8", help="comma list of rhs counts")
