@@ -390,8 +390,8 @@ void b_dot_norm(Context* c, Scratch& s, Vec q, Vec rho, double2* qr, double* qq)
 }
 
 template <class P, int KB>
-__global__ void k_multidot(const void* base, int64_t stride, int k, const void* w, int nrhs, RedPlan pl,
-                           double2* partial) {
+__global__ __launch_bounds__(256) void k_multidot(const void* base, int64_t stride, int k, const void* w, int nrhs,
+                                                  RedPlan pl, double2* partial) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double2 v[KB];
 #pragma unroll
@@ -415,19 +415,34 @@ __global__ void k_multidot(const void* base, int64_t stride, int k, const void* 
   }
   block_store<KB>(v, partial, nrhs);
 }
+template <class P>
+static void launch_multidot(Context* c, const typename P::S* b0, int64_t stride, int kk, Vec w, RedPlan pl,
+                            double2* partial) {
+  const dim3 nb(pl.blocks), tb(256);
+  switch (kk) {
+    case 1: hipLaunchKernelGGL((k_multidot<P, 1>), nb, tb, 0, c->stream, b0, stride, kk, w.p, w.nrhs, pl, partial); break;
+    case 2: hipLaunchKernelGGL((k_multidot<P, 2>), nb, tb, 0, c->stream, b0, stride, kk, w.p, w.nrhs, pl, partial); break;
+    case 3: hipLaunchKernelGGL((k_multidot<P, 3>), nb, tb, 0, c->stream, b0, stride, kk, w.p, w.nrhs, pl, partial); break;
+    case 4: hipLaunchKernelGGL((k_multidot<P, 4>), nb, tb, 0, c->stream, b0, stride, kk, w.p, w.nrhs, pl, partial); break;
+    case 5: hipLaunchKernelGGL((k_multidot<P, 5>), nb, tb, 0, c->stream, b0, stride, kk, w.p, w.nrhs, pl, partial); break;
+    case 6: hipLaunchKernelGGL((k_multidot<P, 6>), nb, tb, 0, c->stream, b0, stride, kk, w.p, w.nrhs, pl, partial); break;
+    case 7: hipLaunchKernelGGL((k_multidot<P, 7>), nb, tb, 0, c->stream, b0, stride, kk, w.p, w.nrhs, pl, partial); break;
+    default: hipLaunchKernelGGL((k_multidot<P, 8>), nb, tb, 0, c->stream, b0, stride, kk, w.p, w.nrhs, pl, partial); break;
+  }
+}
+
 void b_multidot(Context* c, Scratch& s, Vec base, int64_t stride, int k, Vec w, double2* out) {
   RedPlan pl = red_plan(w.n(), w.nrhs);
   const int KB = 8;
   need(s, (size_t)pl.blocks * KB * w.nrhs);
   for (int i0 = 0; i0 < k; i0 += KB) {
-    int kk = k - i0 < KB ? k - i0 : KB;
-    DISPATCH_PREC(w.prec, P, {
-      const typename P::S* b0 = (const typename P::S*)base.p + i0 * stride;
-      hipLaunchKernelGGL((k_multidot<P, 8>), dim3(pl.blocks), dim3(256), 0, c->stream, (const void*)b0, stride,
-                         kk, w.p, w.nrhs, pl, s.partial);
-    });
+    const int kk = k - i0 < KB ? k - i0 : KB;
+    // the chunk's exact size as a template parameter: registers and
+    // block-reduction rounds follow the vectors in use
+    DISPATCH_PREC(w.prec, P, launch_multidot<P>(c, (const typename P::S*)base.p + i0 * stride, stride, kk, w, pl,
+                                                 s.partial));
     hipLaunchKernelGGL(k_finalize_c, dim3(kk * w.nrhs), dim3(64), 0, c->stream, s.partial,
-                       (int)pl.blocks, KB, w.nrhs, kk * w.nrhs, out, (int64_t)i0 * w.nrhs);
+                       (int)pl.blocks, kk, w.nrhs, kk * w.nrhs, out, (int64_t)i0 * w.nrhs);
     MGM_LAUNCH_CHECK();
   }
 }
@@ -510,54 +525,69 @@ void b_finalize_dot_norm(Context* c, Scratch& s, const double2* part, int64_t nb
 
 // One sweep of the re-orthogonalising Gram-Schmidt step: w <- w - sum_i h_i V_i
 // and, from the same registers, out_i = V_i^H w (updated w), i < k <= kFusedGS.
-template <class P>
-__global__ void k_multiaxpy_dot(const void* base, int64_t stride, int k, const double2* h, void* w, int nrhs,
-                                RedPlan pl, double2* partial) {
+// One sweep of w -= sum_i h_i V_i and a_i = V_i^H w (updated) for K basis
+// vectors; K is a template parameter so registers and block-reduction rounds
+// scale with the basis actually in use.
+template <class P, int K>
+__global__ __launch_bounds__(256) void k_multiaxpy_dot(const void* base, int64_t stride, const double2* h, void* w,
+                                                       int nrhs, RedPlan pl, double2* partial) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double2 v[kFusedGS];
+  double2 v[K];
 #pragma unroll
-  for (int i = 0; i < kFusedGS; i++) v[i] = make_double2(0, 0);
+  for (int i = 0; i < K; i++) v[i] = make_double2(0, 0);
   if (g < pl.J * nrhs) {
     const int r = (int)(g % nrhs);
     const int64_t j = g / nrhs;
     const typename P::S* B = (const typename P::S*)base;
-    cx<double> hc[kFusedGS], a[kFusedGS];
+    cx<double> hc[K], a[K];
 #pragma unroll
-    for (int i = 0; i < kFusedGS; i++) {
+    for (int i = 0; i < K; i++) {
       a[i] = {0, 0};
-      double2 hh = i < k ? h[(int64_t)i * nrhs + r] : make_double2(0, 0);
+      const double2 hh = h[(int64_t)i * nrhs + r];
       hc[i] = {-hh.x, -hh.y};
     }
     for (int64_t m = j; m < pl.m; m += pl.J) {
       const int64_t e = m * nrhs + r;
       cx<double> wv = ldd<P>(w, e);
-      cx<double> vv[kFusedGS];
+      cx<double> vv[K];
 #pragma unroll
-      for (int i = 0; i < kFusedGS; i++)
-        if (i < k) {
-          vv[i] = ldd<P>(B + i * stride, e);
-          fma_(wv, hc[i], vv[i]);
-        }
-      std_<P>(w, e, wv);
-      const cx<double> ws = ldd<P>(w, e);  // dots of the stored (rounded) vector
+      for (int i = 0; i < K; i++) {
+        vv[i] = ldd<P>(B + i * stride, e);
+        fma_(wv, hc[i], vv[i]);
+      }
+      // the dots use the stored (rounded) value, rounded here in registers
+      typename P::S st_;
+      P::st(&st_, 0, cx<typename P::R>{(typename P::R)wv.re, (typename P::R)wv.im});
+      const cx<typename P::R> wr = P::ld(&st_, 0);
+      const cx<double> ws = {(double)wr.re, (double)wr.im};
+      *((typename P::S*)w + e) = st_;
 #pragma unroll
-      for (int i = 0; i < kFusedGS; i++)
-        if (i < k) fmac_(a[i], vv[i], ws);
+      for (int i = 0; i < K; i++) fmac_(a[i], vv[i], ws);
     }
 #pragma unroll
-    for (int i = 0; i < kFusedGS; i++) v[i] = make_double2(a[i].re, a[i].im);
+    for (int i = 0; i < K; i++) v[i] = make_double2(a[i].re, a[i].im);
   }
-  block_store<kFusedGS>(v, partial, nrhs);
+  block_store<K>(v, partial, nrhs);
 }
 
 void b_multiaxpy_dot(Context* c, Scratch& s, Vec base, int64_t stride, int k, const double2* h, Vec w,
                      double2* out) {
-  MGM_CHECK(k <= kFusedGS, MGM_ERR_INVALID_ARG, "fused Gram-Schmidt sweep limited to 16 vectors");
+  MGM_CHECK(k >= 1 && k <= kFusedGS, MGM_ERR_INVALID_ARG, "fused Gram-Schmidt sweep takes 1..16 vectors");
   RedPlan pl = red_plan(w.n(), w.nrhs);
-  need(s, (size_t)pl.blocks * kFusedGS * w.nrhs);
-  DISPATCH_PREC(w.prec, P, hipLaunchKernelGGL(k_multiaxpy_dot<P>, dim3(pl.blocks), dim3(256), 0, c->stream,
-                                              (const void*)base.p, stride, k, h, w.p, w.nrhs, pl, s.partial));
-  hipLaunchKernelGGL(k_finalize_c, dim3(k * w.nrhs), dim3(64), 0, c->stream, s.partial, (int)pl.blocks, kFusedGS,
+  need(s, (size_t)pl.blocks * k * w.nrhs);
+#define MGM_GS_CASE(KK)                                                                                      \
+  case KK:                                                                                                   \
+    DISPATCH_PREC(w.prec, P, hipLaunchKernelGGL((k_multiaxpy_dot<P, KK>), dim3(pl.blocks), dim3(256), 0,    \
+                                                c->stream, (const void*)base.p, stride, h, w.p, w.nrhs, pl,   \
+                                                s.partial));                                                  \
+    break;
+  switch (k) {
+    MGM_GS_CASE(1) MGM_GS_CASE(2) MGM_GS_CASE(3) MGM_GS_CASE(4) MGM_GS_CASE(5) MGM_GS_CASE(6) MGM_GS_CASE(7)
+    MGM_GS_CASE(8) MGM_GS_CASE(9) MGM_GS_CASE(10) MGM_GS_CASE(11) MGM_GS_CASE(12) MGM_GS_CASE(13)
+    MGM_GS_CASE(14) MGM_GS_CASE(15) MGM_GS_CASE(16)
+  }
+#undef MGM_GS_CASE
+  hipLaunchKernelGGL(k_finalize_c, dim3(k * w.nrhs), dim3(64), 0, c->stream, s.partial, (int)pl.blocks, k,
                      w.nrhs, k * w.nrhs, out, (int64_t)0);
   MGM_LAUNCH_CHECK();
 }
