@@ -208,7 +208,9 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     kind = "mg_mixed" if mixed else "mg"
     # mixed form: FP16-storage fine smoother, BF16 MFMA coarse operators,
     # autotuned launch shapes and graph-captured coarse-grid corrections
-    sd = m.solve_desc(tol=1e-10, kind=kind, smooth=6 if mixed else 4, coarse_iters=4, inner_tol=1e-5,
+    # smoothing 6 / 2 (fine / coarser levels) and 3 coarse-solve steps: the
+    # fastest settings measured for both the FP64 and the mixed fine solves
+    sd = m.solve_desc(tol=1e-10, kind=kind, smooth=6, smooth_coarse=2, coarse_iters=3, inner_tol=1e-5,
                       maxiter=5000, coarse_bf16=True, smoother_f16=True, graphs=bool(mixed))
     if mixed:
         ctx.autotune(True)
@@ -366,8 +368,9 @@ def learned_form(m, ctx, op, cfg, h, sd_mixed, args, torch):
     net = m.Net(op, widths=widths, seed=1, max_nrhs=cfg["batch"][0])
     net.set_weights(ns.get_weights())
     del ns, hs, ops
-    sd_net = m.solve_desc(tol=1e-10, kind="net", net=net, smooth=sd_mixed.smooth, coarse_iters=sd_mixed.coarse_iters,
-                          inner_tol=1e-5, maxiter=5000, coarse_bf16=True, smoother_f16=True, graphs=True)
+    sd_net = m.solve_desc(tol=1e-10, kind="net", net=net, smooth=sd_mixed.smooth, smooth_coarse=sd_mixed.smooth_coarse,
+                          coarse_iters=sd_mixed.coarse_iters, inner_tol=1e-5, maxiter=5000, coarse_bf16=True,
+                          smoother_f16=True, graphs=True)
     s_, d_, _ = h.level_info(0)
     b = m.draw_z4(ctx, cfg["pseed"] + 5000, 0, 0, cfg["batch"][0], s_, d_, "f64")
     out = {"widths": list(widths), "train_lattice": "x".join(map(str, small)), "train_steps": args.net_steps,
@@ -426,7 +429,7 @@ def time_to_target(m, ctx, op, cfg, h_mixed, sd_mixed, args):
     # the configured probe counts
     h64 = m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=cfg["batch"][0],
                       max_nrhs_level=cfg["batch"], restart=cfg["restart"], mixed=0)
-    sd64 = m.solve_desc(tol=1e-10, kind="mg", smooth=4, coarse_iters=4, maxiter=5000)
+    sd64 = m.solve_desc(tol=1e-10, kind="mg", smooth=6, smooth_coarse=2, coarse_iters=3, maxiter=5000)
     p64 = pilot(h64, sd64)
     eps2 = p64["total_var"]
     out = {"eps2": eps2, "f64": final(h64, sd64, p64, eps2)}

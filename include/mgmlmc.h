@@ -252,7 +252,8 @@ typedef struct {
   double tol;          /* stop when every |b - D x| / |b| <= tol (true FP64 residual) */
   int32_t maxiter;     /* outer iteration cap */
   int32_t kind;        /* mgm_solve_kind */
-  int32_t smooth;      /* minimal-residual smoothing steps (pre and post) */
+  int32_t smooth;      /* minimal-residual smoothing steps (pre and post) on the
+                          fine level (level 0) */
   int32_t coarse_iters;/* iterations of the coarse-level solve inside a V-cycle */
   double inner_tol;    /* MG_MIXED: relative reduction per FP32 inner solve */
   void* net;           /* MGM_SOLVE_NET: network handle (mgm_net), else NULL */
@@ -262,6 +263,7 @@ typedef struct {
   int32_t smoother_f16;/* MG_MIXED / NET: the fine-level MR smoother stores its
                           vectors in FP16 (1; inputs scaled per rhs to unit RMS
                           entries, FP32 arithmetic) or FP32 (0) */
+  int32_t smooth_coarse; /* MR smoothing steps on levels >= 1 (0: the same as smooth) */
   int32_t graphs;      /* 1: the coarse-grid correction below each level (a fixed
                           launch sequence per level, precision and batch) is
                           captured into a HIP graph on its second use and

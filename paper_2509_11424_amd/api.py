@@ -53,7 +53,7 @@ class SolveDesc(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("kind", C.c_int32),
                 ("smooth", C.c_int32), ("coarse_iters", C.c_int32), ("inner_tol", C.c_double),
                 ("net", C.c_void_p), ("coarse_bf16", C.c_int32), ("smoother_f16", C.c_int32),
-                ("graphs", C.c_int32)]
+                ("smooth_coarse", C.c_int32), ("graphs", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -326,8 +326,9 @@ def draw_z4(ctx: Context, seed: int, stream: int, first_probe: int, nprobe: int,
 
 
 def solve_desc(tol=1e-12, maxiter=2000, kind="mg", smooth=2, coarse_iters=8, inner_tol=1e-5,
-               net=None, coarse_bf16=True, smoother_f16=True, graphs=False) -> SolveDesc:
+               net=None, coarse_bf16=True, smoother_f16=True, graphs=False, smooth_coarse=0) -> SolveDesc:
     d = SolveDesc()
+    d.smooth_coarse = smooth_coarse
     d.graphs = 1 if graphs else 0
     d.coarse_bf16 = 1 if coarse_bf16 else 0
     d.smoother_f16 = 1 if smoother_f16 else 0

@@ -499,13 +499,15 @@ mgm_status mgm_project_out(mgm_hierarchy h, int32_t level, const void* x, void* 
 
 static SolveCfg cfg_of(const mgm_solve_desc* d) {
   MGM_CHECK(d != nullptr, MGM_ERR_INVALID_ARG, "solve desc is NULL");
-  MGM_CHECK(d->tol > 0 && d->maxiter >= 1 && d->smooth >= 0 && d->coarse_iters >= 1, MGM_ERR_INVALID_ARG,
+  MGM_CHECK(d->tol > 0 && d->maxiter >= 1 && d->smooth >= 0 && d->smooth_coarse >= 0 && d->coarse_iters >= 1,
+            MGM_ERR_INVALID_ARG,
             "bad solve parameters");
   SolveCfg c;
   c.tol = d->tol;
   c.maxiter = d->maxiter;
   c.kind = d->kind;
   c.smooth = d->smooth;
+  c.smooth_coarse = d->smooth_coarse;
   c.coarse_iters = d->coarse_iters;
   c.inner_tol = d->inner_tol > 0 ? d->inner_tol : 1e-5;
   c.coarse_bf16 = d->coarse_bf16 != 0;

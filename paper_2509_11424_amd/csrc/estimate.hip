@@ -40,6 +40,7 @@ struct Run {
     cfg.maxiter = d.solve.maxiter;
     cfg.kind = d.solve.kind;
     cfg.smooth = d.solve.smooth;
+    cfg.smooth_coarse = d.solve.smooth_coarse;
     cfg.coarse_iters = d.solve.coarse_iters;
     cfg.inner_tol = d.solve.inner_tol > 0 ? d.solve.inner_tol : 1e-5;
     cfg.coarse_bf16 = d.solve.coarse_bf16 != 0;

@@ -129,6 +129,7 @@ struct SolveCfg {
   double inner_tol = 1e-5;
   bool coarse_bf16 = false;
   bool smooth_f16 = false;  // mixed kinds: FP16-storage fine MR smoother
+  int smooth_coarse = 0;    // MR steps on levels >= 1 (0: smooth)
   bool graphs = false;      // replay captured coarse-grid corrections
   Net* net = nullptr;
 };

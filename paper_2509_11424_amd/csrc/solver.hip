@@ -65,7 +65,8 @@ static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg
     b_copy_scaled(c, e, y16, w.n2b);
     return;
   }
-  mr_smooth(H, l, p, r, e, cfg.smooth, cfg);
+  const int nu = (l > 0 && cfg.smooth_coarse > 0) ? cfg.smooth_coarse : cfg.smooth;
+  mr_smooth(H, l, p, r, e, nu, cfg);
 }
 
 // e_c = (cfg.coarse_iters FGMRES steps on level lc) r_c, between the level's
@@ -82,6 +83,7 @@ static void coarse_correction(Hier& H, int lc, mgm_prec p, Vec rc, Vec ec, const
   }
   const std::string key = std::to_string(lc) + "/" + std::to_string((int)p) + "/" + std::to_string(rc.nrhs) + "/" +
                           std::to_string(cfg.coarse_iters) + "/" + std::to_string(cfg.smooth) + "/" +
+                          std::to_string(cfg.smooth_coarse) + "/" +
                           std::to_string((int)cfg.coarse_bf16) + "/" + (rc.p == H.ws(lc, p).bc ? "bc" : "other");
   Hier::GraphEntry& g = H.graphs[key];
   if (g.exec) {
