@@ -20,6 +20,7 @@ operator application and an iteration count measured on a small lattice).
 Kernel micro-benchmarks (used for the profiler runs of single kernels):
 
   python bench.py --micro dslash|dslash_dot --prec f32[,f64,f16] --nrhs 8[,1,...] [--iters 50]
+                  [--tune | --variant V]   # autotune the launch shape, or pin variant V
   python bench.py --micro copy [--iters 50]      # plain 1 GiB device copy
 """
 from __future__ import annotations
@@ -329,8 +330,15 @@ def micro(args):
                 else:
                     op.apply(x, y, prec)
 
+            key = "%s/%d/%d/%d" % ("dslash_dot" if args.micro == "dslash_dot" else "dslash",
+                                   m.api.PREC[prec], op.V, nrhs)
+            if args.variant is not None:
+                ctx.tune_set(key, args.variant)
+            if args.tune:
+                ctx.autotune(True)
             for _ in range(3):
                 once()
+            ctx.autotune(False)
             torch.cuda.synchronize()
             ctx.profile(True)
             ctx.profile_reset()
@@ -341,9 +349,13 @@ def micro(args):
             ctx.profile(False)
             ms = q["ms"] / q["launches"]
             bl = q["bytes"] / q["launches"]
-            print(json.dumps({"micro": args.micro, "prec": prec, "nrhs": nrhs, "lattice": "x".join(
+            line = {"micro": args.micro, "prec": prec, "nrhs": nrhs, "lattice": "x".join(
                 map(str, cfg["dims"])), "launches": q["launches"], "avg_ms": ms, "bytes_per_launch": bl,
-                "GBps": bl / ms / 1e6, "frac": bl / ms / 1e6 / HBM_PEAK_GBS}), flush=True)
+                "GBps": bl / ms / 1e6, "frac": bl / ms / 1e6 / HBM_PEAK_GBS}
+            rep = ctx.tune_report().get(key)
+            if rep is not None:
+                line["variant"], line["variant_ms"] = rep[0], rep[1]
+            print(json.dumps(line), flush=True)
             del x, y
 
 
@@ -453,6 +465,8 @@ def main():
     ap.add_argument("--net-widths", type=int, nargs="+", default=[4, 8, 8, 4])
     ap.add_argument("--net-steps", type=int, default=150)
     ap.add_argument("--micro", choices=["dslash", "dslash_dot", "copy"])
+    ap.add_argument("--tune", action="store_true", help="micro: autotune the launch shape first")
+    ap.add_argument("--variant", type=int, default=None, help="micro: pin this launch variant")
     ap.add_argument("--prec", default="f32", help="comma list of f64, f32, f16")
     ap.add_argument("--nrhs", default="8", help="comma list of rhs counts")
     ap.add_argument("--iters", type=int, default=50)

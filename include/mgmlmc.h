@@ -82,15 +82,23 @@ mgm_status mgm_context_create(int device, void* hip_stream, mgm_context* out);
 /* Switches the stream used by later calls on this context. */
 mgm_status mgm_context_set_stream(mgm_context ctx, void* hip_stream);
 /* Launch-shape autotuner (project-written): when enabled, the first launch of
- * a tunable kernel (fine dslash: rhs per thread and block order; coarse
- * stencils: 16-rhs tiles per workgroup) for a given shape times every variant
- * on that call's own arguments with HIP events (best of three) and keeps the
- * fastest for the rest of the context's life.  Results do not depend on the
- * variant beyond floating-point rounding order.  Off by default. */
+ * a tunable kernel (fine dslash: rhs per thread and block order of the
+ * site-parallel kernel, then the tile, z-run and rhs group of the
+ * plane-marching kernel; coarse stencils: 16-rhs tiles per workgroup) for a
+ * given shape times every variant on that call's own arguments with HIP
+ * events (best of three) and keeps the fastest for the rest of the context's
+ * life.  Results do not depend on the variant beyond floating-point rounding
+ * order.  Off by default (variant 0). */
 mgm_status mgm_context_set_autotune(mgm_context ctx, int32_t enable);
 /* Text table of the tuned shapes ("key variant ms_v0 ms_v1 ..." per line),
  * NUL-terminated, truncated to `bytes`; *needed receives the full length. */
 mgm_status mgm_context_tune_report(mgm_context ctx, char* buf, size_t bytes, size_t* needed);
+/* Pins launch variant `variant` (>= 0) for shape `key` (a key of the tune
+ * report, e.g. from an earlier run), as if the autotuner had chosen it; later
+ * launches of that shape use it whether or not tuning is enabled.  A variant
+ * beyond the shape's count makes those launches fail with INVALID_ARG.
+ * Errors: INVALID_ARG (NULL key, negative variant). */
+mgm_status mgm_context_tune_set(mgm_context ctx, const char* key, int32_t variant);
 void mgm_context_destroy(mgm_context ctx);
 
 /* --------------------------------------------------------- fine operator */

@@ -106,6 +106,7 @@ _SIGS = [
     ("mgm_context_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
     ("mgm_context_set_autotune", C.c_int, [C.c_void_p, C.c_int32]),
     ("mgm_context_tune_report", C.c_int, [C.c_void_p, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    ("mgm_context_tune_set", C.c_int, [C.c_void_p, C.c_char_p, C.c_int32]),
     ("mgm_context_destroy", None, [C.c_void_p]),
     ("mgm_operator_workspace_size", C.c_int, [C.POINTER(LatticeDesc), C.POINTER(C.c_size_t)]),
     ("mgm_operator_create", C.c_int, [C.c_void_p, C.POINTER(LatticeDesc), C.c_void_p, C.c_void_p,
@@ -232,6 +233,10 @@ class Context:
             f = line.split()
             out[f[0]] = (int(f[1]), [float(v) for v in f[2:]])
         return out
+
+    def tune_set(self, key: str, variant: int):
+        """Pins launch variant `variant` for the tuned shape `key`."""
+        _check(lib().mgm_context_tune_set(self.h, key.encode(), int(variant)))
 
     def profile(self, on: bool = True):
         _check(lib().mgm_profile_enable(self.h, 1 if on else 0))

@@ -45,15 +45,17 @@ void Context::prof_end(int kclass, double bytes, hipEvent_t a) {
   if (prof.pending.size() > 4096) prof_flush();
 }
 
-int Context::choose(const std::string& key, int nvar, const std::function<void(int)>& run) {
+int Context::choose(const std::string& key, int nvar, const std::function<void(int)>& run, int dflt) {
   auto it = tune.table.find(key);
   if (it != tune.table.end()) {
+    MGM_CHECK(it->second.variant < nvar, MGM_ERR_INVALID_ARG,
+              "pinned launch variant " + std::to_string(it->second.variant) + " out of range for " + key);
     run(it->second.variant);
     return it->second.variant;
   }
   if (!tune.enabled || capturing || nvar <= 1) {
-    run(0);
-    return 0;
+    run(dflt);
+    return dflt;
   }
   const bool prof_was_on = prof.on;
   prof.on = false;  // tuning launches stay out of the kernel-class statistics
@@ -148,6 +150,7 @@ mgm_status mgm_context_create(int device, void* hip_stream, mgm_context* out) {
   hipDeviceProp_t prop;
   MGM_HIP(hipGetDeviceProperties(&prop, device));
   c->c.cu_count = prop.multiProcessorCount;
+  c->c.max_lds = prop.sharedMemPerBlock;
   *out = c;
   API_END
 }
@@ -185,6 +188,16 @@ mgm_status mgm_context_tune_report(mgm_context ctx, char* buf, size_t bytes, siz
     std::memcpy(buf, out.data(), n);
     buf[n] = 0;
   }
+  API_END
+}
+
+mgm_status mgm_context_tune_set(mgm_context ctx, const char* key, int32_t variant) {
+  API_BEGIN
+  MGM_CHECK(ctx != nullptr && key != nullptr, MGM_ERR_INVALID_ARG, "NULL argument");
+  MGM_CHECK(variant >= 0, MGM_ERR_INVALID_ARG, "variant must be >= 0");
+  Tuner::Entry e;
+  e.variant = variant;
+  ctx->c.tune.table[key] = e;
   API_END
 }
 
@@ -285,8 +298,8 @@ mgm_status mgm_operator_apply_dot(mgm_operator op, mgm_prec prec, const void* x,
   Scratch sc;
   sc.partial = part + (size_t)nb * 2 * nrhs;
   sc.cap = (size_t)64 * 2 * nrhs;
-  op->op.apply_dot(prec, x, y, nrhs, part);
-  b_finalize_dot_norm(op->ctx, sc, part, nb, nrhs, (double2*)yx_dev, (double*)yy_dev);
+  const int64_t nrun = op->op.apply_dot(prec, x, y, nrhs, part);
+  b_finalize_dot_norm(op->ctx, sc, part, nrun, nrhs, (double2*)yx_dev, (double*)yy_dev);
   API_END
 }
 

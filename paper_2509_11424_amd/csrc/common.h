@@ -77,17 +77,30 @@ template <typename R>
 __host__ __device__ __forceinline__ cx<R> times_mi(cx<R> a) { return {a.im, -a.re}; }
 template <typename R>
 __host__ __device__ __forceinline__ R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
-// acc += a * b
+// fused a * b + c (one rounding)
+__host__ __device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc += a * b as four fused multiply-adds
 template <typename R>
 __host__ __device__ __forceinline__ void fma_(cx<R>& acc, cx<R> a, cx<R> b) {
-  acc.re += a.re * b.re - a.im * b.im;
-  acc.im += a.re * b.im + a.im * b.re;
+  acc.re = fmar(a.re, b.re, acc.re);
+  acc.re = fmar(-a.im, b.im, acc.re);
+  acc.im = fmar(a.re, b.im, acc.im);
+  acc.im = fmar(a.im, b.re, acc.im);
 }
 // acc += conj(a) * b
 template <typename R>
 __host__ __device__ __forceinline__ void fmac_(cx<R>& acc, cx<R> a, cx<R> b) {
-  acc.re += a.re * b.re + a.im * b.im;
-  acc.im += a.re * b.im - a.im * b.re;
+  acc.re = fmar(a.re, b.re, acc.re);
+  acc.re = fmar(a.im, b.im, acc.re);
+  acc.im = fmar(a.re, b.im, acc.im);
+  acc.im = fmar(-a.im, b.re, acc.im);
+}
+// acc += s * a for a real scalar s
+template <typename R>
+__host__ __device__ __forceinline__ void axpy_(cx<R>& acc, R s, cx<R> a) {
+  acc.re = fmar(s, a.re, acc.re);
+  acc.im = fmar(s, a.im, acc.im);
 }
 
 // -------------------------------------------------------- storage formats
@@ -278,14 +291,16 @@ struct Context {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   int cu_count = 256;
+  size_t max_lds = 65536;  // LDS bytes one workgroup may allocate
   void* host_stage(size_t bytes);
   hipEvent_t take_event();
   void prof_begin(int kclass, double bytes, hipEvent_t* a);
   void prof_end(int kclass, double bytes, hipEvent_t a);
   void prof_flush();
   void sync() { MGM_HIP(hipStreamSynchronize(stream)); }
-  // variant of `key` among nvar; run(v) launches variant v on the stream
-  int choose(const std::string& key, int nvar, const std::function<void(int)>& run);
+  // variant of `key` among nvar; run(v) launches variant v on the stream;
+  // `dflt` is the variant used while the autotuner is off
+  int choose(const std::string& key, int nvar, const std::function<void(int)>& run, int dflt = 0);
 };
 
 // RAII timer around one launch of kernel class kc (no-op when profiling is off).

@@ -384,14 +384,13 @@ __global__ __launch_bounds__(256) void k_dslash(typename P::S* __restrict__ out,
           fmac_(g1, Um[b][a], h[1][b]);
         }
       }
-      g0 = f * g0;
-      g1 = f * g1;
       cx<R> d0, d1;
       Ad_times(mu, g0, g1, d0, d1);  // lower spins: -A^H g (forward), +A^H g (backward)
-      acc[0 * 3 + a] = acc[0 * 3 + a] + g0;
-      acc[1 * 3 + a] = acc[1 * 3 + a] + g1;
-      acc[2 * 3 + a] = acc[2 * 3 + a] + sg * d0;
-      acc[3 * 3 + a] = acc[3 * 3 + a] + sg * d1;
+      const R fs = f * sg;
+      axpy_(acc[0 * 3 + a], f, g0);
+      axpy_(acc[1 * 3 + a], f, g1);
+      axpy_(acc[2 * 3 + a], fs, d0);
+      axpy_(acc[3 * 3 + a], fs, d1);
     }
   }
   // site-local term: clover blocks with the mass folded into the diagonal
@@ -539,14 +538,13 @@ __global__ __launch_bounds__(256) void k_dslash_rb(typename P::S* __restrict__ o
             fmac_(g1, Um[b][a], h[1][b][j]);
           }
         }
-        g0 = f * g0;
-        g1 = f * g1;
         cx<R> d0, d1;
         Ad_times(mu, g0, g1, d0, d1);  // lower spins: -A^H g (forward), +A^H g (backward)
-        acc[0 * 3 + a][j] = acc[0 * 3 + a][j] + g0;
-        acc[1 * 3 + a][j] = acc[1 * 3 + a][j] + g1;
-        acc[2 * 3 + a][j] = acc[2 * 3 + a][j] + sg * d0;
-        acc[3 * 3 + a][j] = acc[3 * 3 + a][j] + sg * d1;
+        const R fs = f * sg;
+        axpy_(acc[0 * 3 + a][j], f, g0);
+        axpy_(acc[1 * 3 + a][j], f, g1);
+        axpy_(acc[2 * 3 + a][j], fs, d0);
+        axpy_(acc[3 * 3 + a][j], fs, d1);
       }
   }
   // site-local term: clover blocks with the mass folded into the diagonal
@@ -589,6 +587,385 @@ __global__ __launch_bounds__(256) void k_dslash_rb(typename P::S* __restrict__ o
     for (int k = 0; k < 12; k++) P::template stv<RB>(out, (int64_t)k * N + es, acc[k]);
   }
   if (DOT) dot_block_store<RB>(dqr, dqq, active, r0, nrhs, nblocks, dpart);
+}
+
+// ------------------------------------------------- plane-marching dslash
+//
+// One block owns a tile of TY full x-rows of one time slice, for a group of
+// nbr consecutive right-hand sides, and marches through zs consecutive
+// z-planes.  Each plane of the input is read
+// from HBM once by its owner: it is staged in LDS, with one halo row on each
+// side in y, for the x- and y-hops; kept in registers as the centre of the
+// next step; and its backward z-hop contribution to the next plane is formed
+// while it is in registers.  The t-hops read the same tile of the adjacent
+// time slices, which belong to the neighbouring blocks in block order (the
+// time slice is the fastest block index), so they are loaded by blocks
+// resident on the same XCD at about the same step.  Every hop and the clover
+// term use the same arithmetic as k_dslash; the terms are summed in another
+// order (the backward z hop first, as it is formed one step early, and the
+// forward z hop last, after the loads of the next plane are in flight), so
+// the two kernels agree to rounding.
+
+// gg = U h (forward) or U^H h (backward) for the half spinor h = u -/+ A_mu l
+// of ps
+template <class P>
+__device__ __forceinline__ void hop_half(int mu, bool fwd, const cx<typename P::R> (&ps)[12],
+                                         const cx<typename P::R> (&Um)[3][3], cx<typename P::R> (&gg)[2][3]) {
+  using R = typename P::R;
+  const R sg = fwd ? (R)-1 : (R)1;
+  cx<R> h[2][3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    cx<R> a0, a1;
+    A_times(mu, ps[6 + a], ps[9 + a], a0, a1);
+    h[0][a] = ps[a] + sg * a0;
+    h[1][a] = ps[3 + a] + sg * a1;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    cx<R> g0 = {0, 0}, g1 = {0, 0};
+    if (fwd) {
+#pragma unroll
+      for (int b = 0; b < 3; b++) {
+        fma_(g0, Um[a][b], h[0][b]);
+        fma_(g1, Um[a][b], h[1][b]);
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < 3; b++) {
+        fmac_(g0, Um[b][a], h[0][b]);
+        fmac_(g1, Um[b][a], h[1][b]);
+      }
+    }
+    gg[0][a] = g0;
+    gg[1][a] = g1;
+  }
+}
+
+// acc += f (1 -/+ g_mu) expansion of gg (f = -1/2, or +1/2 across the
+// antiperiodic time boundary)
+template <class P>
+__device__ __forceinline__ void hop_add(int mu, bool fwd, typename P::R f, const cx<typename P::R> (&gg)[2][3],
+                                        cx<typename P::R> (&acc)[12]) {
+  using R = typename P::R;
+  const R fs = fwd ? -f : f;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    cx<R> d0, d1;
+    Ad_times(mu, gg[0][a], gg[1][a], d0, d1);
+    axpy_(acc[0 * 3 + a], f, gg[0][a]);
+    axpy_(acc[1 * 3 + a], f, gg[1][a]);
+    axpy_(acc[2 * 3 + a], fs, d0);
+    axpy_(acc[3 * 3 + a], fs, d1);
+  }
+}
+
+// Buffer loads for the marching kernel: one SGPR descriptor per array and a
+// 32-bit byte offset per lane (plus a uniform offset per dof plane), so the
+// twelve planes of a spinor share one address register.  Every array it
+// reads is below 4 GiB (checked on the host); an offset past the end would
+// read zero, never fault.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <class P>
+struct BufIO;
+template <>
+struct BufIO<F32> {
+  using S = float2;
+  static constexpr uint32_t SB = 8, RB = 4;  // bytes of a complex / real element
+  __device__ __forceinline__ static S raw(Rsrc r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+  }
+  __device__ __forceinline__ static cx<float> cvt(S v) { return {v.x, v.y}; }
+  __device__ __forceinline__ static float re(Rsrc r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+  }
+  __device__ __forceinline__ static void st(Rsrc r, uint32_t vo, uint32_t so, cx<float> v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), make_float2(v.re, v.im)), r, (int)vo, (int)so, 0);
+  }
+};
+template <>
+struct BufIO<F16> {
+  using S = __half2;
+  static constexpr uint32_t SB = 4, RB = 2;
+  __device__ __forceinline__ static S raw(Rsrc r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+  }
+  __device__ __forceinline__ static cx<float> cvt(S v) {
+    const float2 f = __half22float2(v);
+    return {f.x, f.y};
+  }
+  __device__ __forceinline__ static float re(Rsrc r, uint32_t vo, uint32_t so) {
+    return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0)));
+  }
+  __device__ __forceinline__ static void st(Rsrc r, uint32_t vo, uint32_t so, cx<float> v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, __floats2half2_rn(v.re, v.im)), r, (int)vo,
+                                          (int)so, 0);
+  }
+};
+
+// link U_mu at the site whose byte offset (in a link plane) is vo
+template <class P>
+__device__ __forceinline__ void buf_link(Rsrc ru, uint32_t plane_b, int mu, uint32_t vo,
+                                         cx<typename P::R> (&Um)[3][3]) {
+#pragma unroll
+  for (int k = 0; k < 9; k++)
+    Um[k / 3][k % 3] = BufIO<P>::cvt(BufIO<P>::raw(ru, vo, (uint32_t)(mu * 9 + k) * plane_b));
+}
+
+// Hermitian 6x6 clover block times p (same arithmetic as clover_block)
+template <class P>
+__device__ __forceinline__ void buf_clover(Rsrc rc, uint32_t plane_b, uint32_t vo, int chi,
+                                           const cx<typename P::R>* x, cx<typename P::R>* y) {
+  using R = typename P::R;
+  const uint32_t b0 = (uint32_t)(36 * chi) * plane_b;
+#pragma unroll
+  for (int i = 0; i < 6; i++) {
+    R d = BufIO<P>::re(rc, vo, b0 + (uint32_t)i * plane_b);
+    y[i] = d * x[i];
+  }
+  int q = 0;
+#pragma unroll
+  for (int i = 1; i < 6; i++)
+#pragma unroll
+    for (int j = 0; j < i; j++, q++) {
+      cx<R> cij = {BufIO<P>::re(rc, vo, b0 + (uint32_t)(6 + 2 * q) * plane_b),
+                   BufIO<P>::re(rc, vo, b0 + (uint32_t)(7 + 2 * q) * plane_b)};
+      fma_(y[i], cij, x[j]);
+      fmac_(y[j], cij, x[i]);
+    }
+}
+
+// Launch: blockDim = X * TY * nbr (a multiple of 64, at most MAXT), grid =
+// (nrhs / nbr) * T * (Y / TY) * (Z / zs), dynamic LDS = 12 * (TY + 2) * X *
+// nbr elements of P::S (at least the DOT reduction's 16 * 64 * 24 bytes);
+// nbr divides nrhs and 64; TY is even; 12 * V * nrhs spinor elements, the
+// links and the clover each below 4 GiB.
+template <class P, bool DOT, int TY, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict__ out,
+                                                       const typename P::S* __restrict__ in,
+                                                       const typename P::S* __restrict__ U,
+                                                       const typename P::RS* __restrict__ C, Geom g, int nrhs,
+                                                       int nbr, int zs, int64_t nblocks,
+                                                       double2* __restrict__ dpart) {
+  using R = typename P::R;
+  using S = typename P::S;
+  using IO = BufIO<P>;
+  extern __shared__ __align__(16) unsigned char march_smem[];
+  S* pl = reinterpret_cast<S*>(march_smem);  // [12][TY + 2][X * nbr]
+  constexpr int kRows = TY + 2;
+  const uint32_t V = (uint32_t)g.V, N = V * (uint32_t)nrhs;
+  const uint32_t spb = N * IO::SB;   // bytes per spinor dof plane
+  const uint32_t upb = V * IO::SB;   // bytes per link plane
+  const uint32_t cpb = V * IO::RB;   // bytes per clover plane
+  const Rsrc rin = make_rsrc(in, 12 * spb), rout = make_rsrc(out, 12 * spb);
+  const Rsrc ru = make_rsrc(U, 36 * upb), rc = make_rsrc(C, 72 * cpb);
+  const int rowlen = g.X * nbr;
+  const int64_t blk = xcd_block(blockIdx.x, nblocks);
+  const int nsub = nrhs / nbr;
+  const int rb0 = (int)(blk % nsub) * nbr;  // first rhs of the group
+  const int t = (int)((blk / nsub) % g.T);
+  const int rest = (int)(blk / nsub / g.T);
+  const int ntile = g.Y / TY;
+  const int y0 = (rest % ntile) * TY;
+  const int z0 = (rest / ntile) * zs;
+  const int tid = threadIdx.x;
+  const int rl = tid % nbr, r = rb0 + rl;
+  const int col = tid % rowlen;  // x * nbr + rl
+  const int xs = col / nbr;
+  const int yl = tid / rowlen;
+  const int y = y0 + yl;
+  const uint32_t sy = g.X, sz = (uint32_t)g.X * g.Y, st = sz * g.Z;
+  const int xp = xs == g.X - 1 ? 0 : xs + 1, xm = xs == 0 ? g.X - 1 : xs - 1;
+  const int ym = y == 0 ? g.Y - 1 : y - 1;
+  const int tp = t == g.T - 1 ? 0 : t + 1, tm = t == 0 ? g.T - 1 : t - 1;
+  const R ftp = (t == g.T - 1 && g.antiperiodic) ? (R)0.5 : (R)-0.5;
+  const R ftm = (t == 0 && g.antiperiodic) ? (R)0.5 : (R)-0.5;
+  const int hy0 = y0 == 0 ? g.Y - 1 : y0 - 1, hy1 = y0 + TY == g.Y ? 0 : y0 + TY;
+  const uint32_t rowoff = (uint32_t)y * sy + xs;  // (x, y) part of a site index
+  // LDS element of dof k, LDS row lr, column c
+  auto lidx = [&](int k, int lr, int c) { return (k * kRows + lr) * rowlen + c; };
+  // Halo rows: 12 dof x 2 rows = 24 row-planes; thread (yl, col) stages
+  // row-plane q = yl + TY j (all q < 24) at its own column, i.e. dof
+  // yl / 2 + (TY / 2) j of halo row yl % 2 (TY is even).
+  const int hrow = yl & 1, hk0 = yl >> 1;
+  const uint32_t hyoff = (uint32_t)(hrow ? hy1 : hy0) * sy;
+  auto stage_halo = [&](int zz) {
+    // the per-thread dof offset goes into the lane offset, the per-j one
+    // into the uniform offset
+    const uint32_t vo = (((uint32_t)zz * sz + (uint32_t)t * st + hyoff + xs) * nrhs + r) * IO::SB +
+                        (uint32_t)hk0 * spb;
+#pragma unroll
+    for (int j = 0; j < (24 + TY - 1) / TY; j++) {
+      const int k = hk0 + (TY / 2) * j;
+      if (24 % TY == 0 || k < 12)
+        pl[lidx(k, hrow ? kRows - 1 : 0, col)] = IO::raw(rin, vo, (uint32_t)((TY / 2) * j) * spb);
+    }
+  };
+  // The accumulator of a plane starts as the backward z-hop contribution of
+  // the plane before it, formed while that plane is in registers.
+  cx<R> acc[12];
+  {
+    const int zm = z0 == 0 ? g.Z - 1 : z0 - 1;
+    const uint32_t sm = (uint32_t)zm * sz + (uint32_t)t * st + rowoff;
+    cx<R> pm[12], Um[3][3], gg[2][3];
+#pragma unroll
+    for (int k = 0; k < 12; k++) pm[k] = IO::cvt(IO::raw(rin, (sm * nrhs + r) * IO::SB, (uint32_t)k * spb));
+    buf_link<P>(ru, upb, 2, sm * IO::SB, Um);
+    hop_half<P>(2, false, pm, Um, gg);
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = {0, 0};
+    hop_add<P>(2, false, (R)-0.5, gg, acc);
+    const uint32_t s0 = (uint32_t)z0 * sz + (uint32_t)t * st + rowoff;
+#pragma unroll
+    for (int k = 0; k < 12; k++) pl[lidx(k, yl + 1, col)] = IO::raw(rin, (s0 * nrhs + r) * IO::SB, (uint32_t)k * spb);
+    stage_halo(z0);
+  }
+  cx<double> dqr = {0, 0};
+  double dqq = 0;
+#pragma unroll 1
+  for (int i = 0; i < zs; i++) {
+    const int z = z0 + i;
+    const int zp = z == g.Z - 1 ? 0 : z + 1;
+    const uint32_t s = (uint32_t)z * sz + (uint32_t)t * st + rowoff;
+    __syncthreads();  // plane z staged
+    // x and y hops from LDS
+#pragma unroll 1
+    for (int hop = 0; hop < 4; hop++) {
+      const int mu = hop >> 1;
+      const bool fwd = (hop & 1) == 0;
+      int lrow, lcol;
+      uint32_t ls;  // site owning the link
+      if (mu == 0) {
+        lrow = yl + 1;
+        lcol = (fwd ? xp : xm) * nbr + rl;
+        ls = fwd ? s : s - xs + xm;
+      } else {
+        lrow = fwd ? yl + 2 : yl;
+        lcol = col;
+        ls = fwd ? s : s + (uint32_t)(ym - y) * sy;
+      }
+      cx<R> ps[12], Um[3][3], gg[2][3];
+#pragma unroll
+      for (int k = 0; k < 12; k++) ps[k] = IO::cvt(pl[lidx(k, lrow, lcol)]);
+      buf_link<P>(ru, upb, mu, ls * IO::SB, Um);
+      hop_half<P>(mu, fwd, ps, Um, gg);
+      hop_add<P>(mu, fwd, (R)-0.5, gg, acc);
+    }
+    // t hops from the adjacent slices
+#pragma unroll 1
+    for (int hop = 0; hop < 2; hop++) {
+      const bool fwd = hop == 0;
+      const uint32_t sn = (uint32_t)z * sz + (uint32_t)(fwd ? tp : tm) * st + rowoff;
+      cx<R> ps[12], Um[3][3], gg[2][3];
+#pragma unroll
+      for (int k = 0; k < 12; k++) ps[k] = IO::cvt(IO::raw(rin, (sn * nrhs + r) * IO::SB, (uint32_t)k * spb));
+      buf_link<P>(ru, upb, 3, (fwd ? s : sn) * IO::SB, Um);
+      hop_half<P>(3, fwd, ps, Um, gg);
+      hop_add<P>(3, fwd, fwd ? ftp : ftm, gg, acc);
+    }
+    // next plane (kept raw for staging); its loads overlap the clover term
+    S nx[12];
+    {
+      const uint32_t vn = (((uint32_t)zp * sz + (uint32_t)t * st + rowoff) * nrhs + r) * IO::SB;
+#pragma unroll
+      for (int k = 0; k < 12; k++) nx[k] = IO::raw(rin, vn, (uint32_t)k * spb);
+    }
+    // site-local term with the centre from LDS
+#pragma unroll 1
+    for (int chi = 0; chi < 2; chi++) {
+      cx<R> p6[6], q6[6];
+#pragma unroll
+      for (int k = 0; k < 6; k++) p6[k] = IO::cvt(pl[lidx(6 * chi + k, yl + 1, col)]);
+      buf_clover<P>(rc, cpb, s * IO::RB, chi, p6, q6);
+#pragma unroll
+      for (int k = 0; k < 6; k++) {
+        if (chi == 0) acc[k] = acc[k] + q6[k];
+        else acc[6 + k] = acc[6 + k] + q6[k];
+      }
+    }
+    // forward z hop from the next plane
+    {
+      cx<R> ps[12], Um[3][3], gg[2][3];
+#pragma unroll
+      for (int k = 0; k < 12; k++) ps[k] = IO::cvt(nx[k]);
+      buf_link<P>(ru, upb, 2, s * IO::SB, Um);
+      hop_half<P>(2, true, ps, Um, gg);
+      hop_add<P>(2, true, (R)-0.5, gg, acc);
+    }
+    // backward z hop of this plane (into the next one's accumulator), then
+    // the store; the fused dots take the rounded stored values
+    {
+      cx<R> pv[12], gg[2][3];
+#pragma unroll
+      for (int k = 0; k < 12; k++) pv[k] = IO::cvt(pl[lidx(k, yl + 1, col)]);
+      {
+        cx<R> Um[3][3];
+        buf_link<P>(ru, upb, 2, s * IO::SB, Um);
+        hop_half<P>(2, false, pv, Um, gg);
+      }
+      const uint32_t vo = (s * nrhs + r) * IO::SB;
+      cx<R> sqr = {0, 0};  // this site's dots in the working precision,
+      R sqq = 0;           // accumulated over the march in FP64
+#pragma unroll
+      for (int k = 0; k < 12; k++) {
+        IO::st(rout, vo, (uint32_t)k * spb, acc[k]);
+        if (DOT) {
+          S st_;
+          P::st(&st_, 0, acc[k]);
+          const cx<R> os = P::ld(&st_, 0);
+          fmac_(sqr, os, pv[k]);
+          sqq += os.re * os.re + os.im * os.im;
+        }
+      }
+      if (DOT) {
+        dqr.re += (double)sqr.re;
+        dqr.im += (double)sqr.im;
+        dqq += (double)sqq;
+      }
+#pragma unroll
+      for (int k = 0; k < 12; k++) acc[k] = {0, 0};
+      hop_add<P>(2, false, (R)-0.5, gg, acc);
+    }
+    __syncthreads();  // every read of plane z done
+    if (i + 1 < zs) {
+#pragma unroll
+      for (int k = 0; k < 12; k++) pl[lidx(k, yl + 1, col)] = nx[k];
+      stage_halo(zp);
+    }
+  }
+  if (DOT) {
+    // per-rhs block sums: lane % nbr is the rhs within the group (nbr divides
+    // 64); the LDS plane is free again after the last barrier.  Columns of
+    // the other groups' rhs get zeros.
+    for (int off = 32; off >= nbr; off >>= 1) {
+      dqr.re += __shfl_xor(dqr.re, off, 64);
+      dqr.im += __shfl_xor(dqr.im, off, 64);
+      dqq += __shfl_xor(dqq, off, 64);
+    }
+    double2* sw_qr = reinterpret_cast<double2*>(march_smem);  // [16][64]
+    double* sw_qq = reinterpret_cast<double*>(march_smem + 16 * 64 * sizeof(double2));
+    const int w = tid >> 6, lane = tid & 63;
+    if (lane < nbr) {
+      sw_qr[w * 64 + lane] = make_double2(dqr.re, dqr.im);
+      sw_qq[w * 64 + lane] = dqq;
+    }
+    __syncthreads();
+    if (tid < nrhs) {
+      double a = 0, b = 0, n2 = 0;
+      if (tid >= rb0 && tid < rb0 + nbr) {
+        for (int ww = 0; ww < (int)(blockDim.x >> 6); ww++) {
+          a += sw_qr[ww * 64 + tid - rb0].x;
+          b += sw_qr[ww * 64 + tid - rb0].y;
+          n2 += sw_qq[ww * 64 + tid - rb0];
+        }
+      }
+      dpart[(int64_t)tid * nblocks + blockIdx.x] = make_double2(a, b);
+      dpart[(int64_t)(nrhs + tid) * nblocks + blockIdx.x] = make_double2(n2, 0.0);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ host
@@ -689,24 +1066,112 @@ static void launch_rb(const FineOp& op, mgm_prec p, const void* x, void* y, int 
   MGM_LAUNCH_CHECK();
 }
 
-// Tuned launch shapes: variant 0 is the default (rb_of, slab order), 1 the
-// plain block order; the non-reducing FP32/FP16 kernels with an even rhs count
-// also try the other rhs-per-thread count (2, 3).  The reducing variant keeps
-// rb_of, whose block count sizes the partial sums.
+// Plane-marching shapes (rows per tile, z-planes per block, rhs per block),
+// tried in this order.  A shape applies when the tile's thread count
+// X * TY * nbr is a multiple of 64 and at most 1024, TY divides Y, zs divides
+// Z, nbr divides nrhs and 64, the arrays stay below 4 GiB and the LDS it needs
+// fits the device; FP64 keeps the site-parallel kernels (its registers would
+// not fit 1024-thread blocks).
+struct MarchShape {
+  int ty, zs, nbr;
+};
+static const MarchShape kMarchShapes[] = {
+    {4, 16, 8}, {4, 8, 8},  {8, 16, 4},  {8, 8, 4}, {16, 16, 2}, {16, 8, 2}, {8, 8, 2},
+    {4, 8, 4},  {4, 8, 2},  {16, 16, 1}, {16, 8, 1}, {8, 8, 1},  {4, 8, 1},  {2, 8, 8}};
+
+static size_t march_lds(const Geom& g, mgm_prec p, const MarchShape& m, bool dot) {
+  size_t b = (size_t)12 * (m.ty + 2) * g.X * m.nbr * prec_bytes(p);
+  if (dot) b = std::max(b, (size_t)16 * 64 * (sizeof(double2) + sizeof(double)));
+  return b;
+}
+
+static bool march_ok(const FineOp& op, mgm_prec p, int nrhs, const MarchShape& m, bool dot) {
+  const Geom& g = op.g;
+  if (p != MGM_PREC_F32 && p != MGM_PREC_F16) return false;
+  if (m.nbr > nrhs || nrhs % m.nbr != 0 || 64 % m.nbr != 0) return false;
+  const int64_t th = (int64_t)g.X * m.ty * m.nbr;
+  if (th % 64 != 0 || th > 1024) return false;
+  if (g.Y % m.ty != 0 || g.Z % m.zs != 0) return false;
+  const double lim = 4294967295.0, cb = (double)prec_bytes(p);
+  if (12.0 * g.V * nrhs * cb > lim || 36.0 * g.V * cb > lim || 72.0 * g.V * cb / 2 > lim) return false;
+  return march_lds(g, p, m, dot) <= op.ctx->max_lds;
+}
+
+template <class P, bool DOT, int TY>
+static void launch_march_p(const FineOp& op, const typename P::S* U, const typename P::RS* C, const void* x,
+                           void* y, int nrhs, const MarchShape& m, int64_t nb, int threads, size_t lds,
+                           double2* dpart) {
+  auto* k = k_dslash_march<P, DOT, TY, 1024>;
+  if (lds > 65536)
+    MGM_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(threads), lds, op.ctx->stream, (typename P::S*)y,
+                     (const typename P::S*)x, U, C, op.g, nrhs, m.nbr, m.zs, nb, dpart);
+  MGM_LAUNCH_CHECK();
+}
+
+// Returns the number of blocks (partial-sum columns of the reducing variant).
 template <bool DOT>
-static void launch_dslash(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) {
+static int64_t launch_march(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart,
+                            const MarchShape& m) {
+  const Geom& g = op.g;
+  const int threads = g.X * m.ty * m.nbr;
+  const int64_t nb = (int64_t)(nrhs / m.nbr) * g.T * (g.Y / m.ty) * (g.Z / m.zs);
+  const size_t lds = march_lds(g, p, m, DOT);
+#define MGM_MARCH_TY(PT, UU, CC)                                                                  \
+  switch (m.ty) {                                                                                 \
+    case 2: launch_march_p<PT, DOT, 2>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart); break;   \
+    case 4: launch_march_p<PT, DOT, 4>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart); break;   \
+    case 8: launch_march_p<PT, DOT, 8>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart); break;   \
+    case 16: launch_march_p<PT, DOT, 16>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart); break; \
+    default: throw Error(MGM_ERR_SHAPE, "unsupported plane-marching tile");                       \
+  }
+  if (p == MGM_PREC_F32) {
+    MGM_MARCH_TY(F32, op.U32, op.C32)
+  } else {
+    MGM_MARCH_TY(F16, op.U16, op.C16)
+  }
+#undef MGM_MARCH_TY
+  return nb;
+}
+
+// Tuned launch shapes.  Site-parallel variants first: 0 (rb_of, slab
+// order), 1 the plain block order, and the non-reducing FP32/FP16 kernels
+// with an even rhs count also try the other rhs-per-thread count (2, 3);
+// then every plane-marching shape that applies.  Untuned, FP16 takes the
+// first plane-marching shape that applies (measured fastest for the fused
+// smoother's 8 and 4 rhs on 32^3 x 64), FP32 and FP64 variant 0.  Returns the
+// block count of the variant that ran.
+template <bool DOT>
+static int64_t launch_dslash(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) {
   const int rb0 = rb_of(p, nrhs, DOT);
   const bool alt = !DOT && p != MGM_PREC_F64 && nrhs % 2 == 0;
+  const int nsite = alt ? 4 : 2;
+  std::vector<MarchShape> shapes;
+  for (const MarchShape& m : kMarchShapes)
+    if (march_ok(op, p, nrhs, m, DOT)) shapes.push_back(m);
   const std::string key = std::string(DOT ? "dslash_dot/" : "dslash/") + std::to_string((int)p) + "/" +
                           std::to_string(op.g.V) + "/" + std::to_string(nrhs);
-  op.ctx->choose(key, alt ? 4 : 2, [&](int v) {
+  int64_t nb = 0;
+  const int dflt = (p == MGM_PREC_F16 && !shapes.empty()) ? nsite : 0;
+  op.ctx->choose(
+      key, nsite + (int)shapes.size(),
+      [&](int v) {
+    MGM_CHECK(v >= 0 && v < nsite + (int)shapes.size(), MGM_ERR_INVALID_ARG,
+              "dslash launch variant out of range for this shape");
+    if (v >= nsite) {
+      nb = launch_march<DOT>(op, p, x, y, nrhs, dpart, shapes[v - nsite]);
+      return;
+    }
     const int rb = v < 2 ? rb0 : 3 - rb0;
     const bool slab = (v & 1) == 0;
     if (rb == 2)
       launch_rb<DOT, 2>(op, p, x, y, nrhs, dpart, slab);
     else
       launch_rb<DOT, 1>(op, p, x, y, nrhs, dpart, slab);
-  });
+    nb = (op.g.V * (nrhs / rb) + 255) / 256;
+      },
+      dflt);
+  return nb;
 }
 
 static int kclass_of(mgm_prec p) {
@@ -718,11 +1183,11 @@ void FineOp::apply(mgm_prec p, const void* x, void* y, int nrhs) const {
   launch_dslash<false>(*this, p, x, y, nrhs, nullptr);
 }
 
-void FineOp::apply_dot(mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) const {
+int64_t FineOp::apply_dot(mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) const {
   // one block holds 256 elements; each rhs needs a reducing thread
   MGM_CHECK(nrhs >= 1 && nrhs <= 256, MGM_ERR_INVALID_ARG, "fused dslash reduction supports 1..256 rhs");
   ProfScope ps(ctx, kclass_of(p), bytes(p, nrhs));
-  launch_dslash<true>(*this, p, x, y, nrhs, dpart);
+  return launch_dslash<true>(*this, p, x, y, nrhs, dpart);
 }
 
 }  // namespace mgm

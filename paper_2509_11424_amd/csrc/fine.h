@@ -29,10 +29,12 @@ struct FineOp {
   // y = D x, nrhs vectors in dof-major layout of precision p
   void apply(mgm_prec p, const void* x, void* y, int nrhs) const;
   // the same, also writing per-block sums of y^H x and |y|^2 per rhs to
-  // dpart[2][nrhs][nblocks(p, nrhs)] (finalised by b_finalize_dot_norm)
-  void apply_dot(mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) const;
-  // 256-thread blocks of one launch, plain (dot = false) or reducing; at most
-  // (V * nrhs + 255) / 256
+  // dpart[2][nrhs][nb] (finalised by b_finalize_dot_norm); returns nb, the
+  // block count of the launch shape that ran (at most nblocks(p, nrhs, true))
+  int64_t apply_dot(mgm_prec p, const void* x, void* y, int nrhs, double2* dpart) const;
+  // 256-thread blocks of the site-parallel launch, plain (dot = false) or
+  // reducing: (V * nrhs / rhs-per-thread + 255) / 256, an upper bound of every
+  // launch shape's block count (sizes the partial sums)
   int64_t nblocks(mgm_prec p, int nrhs, bool dot) const;
   // algorithmic bytes of one application (fields once, spinors in and out)
   double bytes(mgm_prec p, int nrhs) const;

@@ -36,8 +36,8 @@ static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const So
   for (int i = 0; i < nu; i++) {
     if (l == 0) {
       // fine level: q^H rho and |q|^2 come out of the dslash itself
-      H.fine->apply_dot(p, rho.p, q.p, b.nrhs, H.dpart);
-      b_finalize_dot_norm(c, H.scratch, H.dpart, H.fine->nblocks(p, b.nrhs, true), b.nrhs, w.qr, w.qq);
+      const int64_t nb = H.fine->apply_dot(p, rho.p, q.p, b.nrhs, H.dpart);
+      b_finalize_dot_norm(c, H.scratch, H.dpart, nb, b.nrhs, w.qr, w.qq);
     } else {
       op_apply(H, l, p, true, cfg, rho.p, q.p, b.nrhs);
       b_dot_norm(c, H.scratch, q, rho, w.qr, w.qq);

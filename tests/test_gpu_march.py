@@ -1,0 +1,187 @@
+"""Plane-marching fine dslash: a block keeps a tile of x-rows of one time
+slice in LDS and registers while it marches along z.  Every launch shape that
+applies to a lattice (tile rows, z-run, rhs group) is pinned in turn with
+mgm_context_tune_set and checked
+
+* against the site-parallel kernel (variant 0): the same per-hop arithmetic
+  summed in another order, so FP32 agrees to a few units of FP32 rounding and
+  FP16 (rounded once on store) to one FP16 ulp per element;
+* against the oracle's operator within the storage precision's bound (the
+  bounds of the site-parallel kernel's own parity tests);
+* for the reducing variant, y^H x and |y|^2 against numpy's sums of the
+  stored y (the kernel sums each site's twelve products in FP32, the sites in
+  FP64: 1e-6 of ||y|| ||x||).
+
+Lattices: 8x16x8x4 (one z-run covering the whole z extent, so the first plane's
+backward neighbour wraps) and 16x4x16x6 (two z-runs, T not a multiple of four).
+The last test runs the bench's launch configuration, 32^3 x 64 at eight FP16
+right-hand sides, against the FP64 dslash.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from gpu_common import to_gpu, from_gpu, rel  # noqa: E402
+from lattice_inputs import gauge_field, random_spinor  # noqa: E402
+
+BOUND = {"f32": 2e-6, "f16": 4e-3}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2509_11424_amd as m
+    return m.Context(0)  # own context: pinned shapes must not leak into other tests
+
+
+class Lat:
+    def __init__(self, ctx, dims, seed):
+        import paper_2509_11424_amd as m
+        from oracle.dirac import WilsonClover
+        self.dims = dims
+        self.U = gauge_field(dims, 0.6, seed)
+        self.op = m.Operator(ctx, self.U, 0.03, 1.0)
+        self.D = WilsonClover(self.U, 0.03, 1.0)
+        self.V = self.op.V
+
+
+@pytest.fixture(scope="module")
+def lats(ctx):
+    return {"8x16x8x4": Lat(ctx, (8, 16, 8, 4), 41), "16x4x16x6": Lat(ctx, (16, 4, 16, 6), 42)}
+
+
+def _inputs(lat, prec, nrhs, seed):
+    import torch
+    xs = random_spinor(lat.dims, seed, batch=nrhs)
+    xg = to_gpu(xs.reshape(nrhs, -1, 12))
+    if prec == "f32":
+        return xs, xg.to(torch.complex64)
+    return xs, torch.view_as_real(xg).to(torch.float16).contiguous()
+
+
+def _c128(t, prec):
+    import torch
+    if prec == "f16":
+        t = torch.view_as_complex(t.float().contiguous())
+    return t.to(torch.complex128)
+
+
+def _variants(ctx, key, run):
+    """Tunes `key` once (listing its variants), returns the variant count."""
+    ctx.autotune(True)
+    try:
+        run()
+    finally:
+        ctx.autotune(False)
+    import torch
+    torch.cuda.synchronize()
+    rep = ctx.tune_report()
+    assert key in rep, (key, list(rep))
+    return len(rep[key][1])
+
+
+def _close_to_site_parallel(y, y0, prec):
+    a, b = y.cpu().numpy(), y0.cpu().numpy()
+    if prec == "f32":
+        assert rel(a, b) < 1e-6
+        assert np.all(np.abs(a - b) <= 1e-5 * np.abs(b) + 1e-6 * np.abs(b).max())
+    else:
+        # one FP16 ulp (2^-10 relative) per element, plus the subnormal floor
+        assert np.all(np.abs(a - b) <= 2.0 ** -10 * np.abs(b) + 2.0 ** -24 + 1e-7 * np.abs(b).max())
+
+
+@pytest.mark.parametrize("lname", ["8x16x8x4", "16x4x16x6"])
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+@pytest.mark.parametrize("nrhs", [1, 4, 8])
+def test_march_shapes_apply(ctx, lats, lname, prec, nrhs):
+    import torch
+    import paper_2509_11424_amd as m
+    lat = lats[lname]
+    xs, x = _inputs(lat, prec, nrhs, 50 + nrhs)
+    key = "dslash/%d/%d/%d" % (m.api.PREC[prec], lat.V, nrhs)
+    y = torch.empty_like(x)
+    nvar = _variants(ctx, key, lambda: lat.op.apply(x, y, prec))
+    ctx.tune_set(key, 0)
+    y0 = lat.op.apply(x, prec=prec)
+    torch.cuda.synchronize()
+    want = lat.D.apply(xs).reshape(nrhs, -1, 12)
+    n_march = 0
+    for v in range(1, nvar):
+        ctx.tune_set(key, v)
+        yv = lat.op.apply(x, prec=prec)
+        torch.cuda.synchronize()
+        _close_to_site_parallel(yv, y0, prec)
+        assert rel(from_gpu(_c128(yv, prec)), want) < BOUND[prec], v
+        n_march += 1
+    ctx.tune_set(key, 0)
+    assert n_march >= 1  # every case here has at least one plane-marching shape
+
+
+@pytest.mark.parametrize("lname", ["8x16x8x4", "16x4x16x6"])
+@pytest.mark.parametrize("prec,nrhs", [("f16", 8), ("f16", 4), ("f32", 4), ("f16", 1)])
+def test_march_shapes_fused_reductions(ctx, lats, lname, prec, nrhs):
+    import torch
+    import paper_2509_11424_amd as m
+    lat = lats[lname]
+    xs, x = _inputs(lat, prec, nrhs, 70 + nrhs)
+    key = "dslash_dot/%d/%d/%d" % (m.api.PREC[prec], lat.V, nrhs)
+    nvar = _variants(ctx, key, lambda: lat.op.apply_dot(x, prec=prec))
+    ctx.tune_set(key, 0)
+    y0, _, _ = lat.op.apply_dot(x, prec=prec)
+    torch.cuda.synchronize()
+    want = lat.D.apply(xs).reshape(nrhs, -1, 12)
+    xn = _c128(x, prec).cpu().numpy()
+    assert nvar >= 3  # two site-parallel orders, then the plane-marching shapes
+    for v in range(nvar):
+        ctx.tune_set(key, v)
+        y, yx, yy = lat.op.apply_dot(x, prec=prec)
+        torch.cuda.synchronize()
+        _close_to_site_parallel(y, y0, prec)
+        yn = _c128(y, prec).cpu().numpy()
+        assert rel(from_gpu(torch.from_numpy(yn)), want) < BOUND[prec], v
+        for r in range(nrhs):
+            a = np.vdot(yn[:, :, r].ravel(), xn[:, :, r].ravel())
+            b = np.vdot(yn[:, :, r].ravel(), yn[:, :, r].ravel()).real
+            nx = np.linalg.norm(xn[:, :, r])
+            assert abs(yx[r].item() - a) <= 1e-6 * np.sqrt(b) * nx, (v, r)
+            assert abs(yy[r].item() - b) <= 1e-6 * b, (v, r)
+    ctx.tune_set(key, 0)
+
+
+def test_march_full_size_f16_eight_rhs(ctx):
+    """32^3 x 64 at eight FP16 right-hand sides (the fused smoother's launch in
+    the bench): every shape against the FP64 dslash of the same rounded input
+    and against variant 0, and its dots against torch's sums."""
+    import torch
+    import paper_2509_11424_amd as m
+    dims = (32, 32, 32, 64)
+    U = gauge_field(dims, 0.6, 14)
+    op = m.Operator(ctx, U, 0.02, 1.0)
+    V, nrhs = op.V, 8
+    g = torch.Generator(device="cuda:0").manual_seed(3)
+    x = torch.randn((12, V, nrhs, 2), generator=g, device="cuda:0").to(torch.float16)
+    xc = torch.view_as_complex(x.float().contiguous()).to(torch.complex128)
+    ref = op.apply(xc, prec="f64")
+    key = "dslash_dot/%d/%d/%d" % (m.api.PREC["f16"], V, nrhs)
+    nvar = _variants(ctx, key, lambda: op.apply_dot(x, prec="f16"))
+    assert nvar >= 3
+    ctx.tune_set(key, 0)
+    y0, _, _ = op.apply_dot(x, prec="f16")
+    y0c = torch.view_as_complex(y0.float().contiguous()).to(torch.complex128)
+    for v in range(nvar):
+        ctx.tune_set(key, v)
+        y, yx, yy = op.apply_dot(x, prec="f16")
+        yc = torch.view_as_complex(y.float().contiguous()).to(torch.complex128)
+        d = (yc - ref).norm() / ref.norm()
+        assert d.item() < BOUND["f16"], v
+        # per element within one FP16 ulp of variant 0
+        bad = ((yc - y0c).abs() > 2.0 ** -9 * y0c.abs() + 1e-6).sum().item()
+        assert bad == 0, (v, bad)
+        a = (yc.conj() * xc).sum(dim=(0, 1))
+        b = (yc.abs() ** 2).sum(dim=(0, 1))
+        nx = (xc.abs() ** 2).sum(dim=(0, 1)).sqrt()
+        assert torch.all((yx - a).abs() <= 1e-6 * b.sqrt() * nx), v
+        assert torch.all((yy - b).abs() <= 1e-6 * b), v
+    ctx.tune_set(key, 0)
+    del x, xc, ref, y0, y0c
+    torch.cuda.empty_cache()
