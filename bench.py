@@ -36,6 +36,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RHS solved/s to 1e-10, dslash HBM GB/s; time-to-target-variance tr(D^-1)"
 HBM_PEAK_GBS = 8000.0
+# Vector FMA peak without packed FP32 math (the build disables packed FP32):
+# 256 CUs x 4 SIMD16 x 16 lanes x 2 flop x 2.4 GHz, the same for FP32 and FP64
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+DSLASH_FLOP = 1896  # per site and rhs: 8 hops x 168 + clover 552
 
 # HBM traffic of the dominant dslash at nrhs 8 on 32^3 x 64 from two rocprofv3
 # --pmc runs, valid only for the kernel sources it was taken with
@@ -46,6 +50,13 @@ TRAFFIC_FILES = {
 PREC_BYTES = {"dslash_f64": 16, "dslash_f32": 8, "dslash_f16": 4}
 KERNEL_NAMES = {"dslash_f16": "k_dslash<F16, DOT> (fused MR-smoother dslash)",
                 "dslash_f32": "k_dslash_rb<F32> (two rhs per thread)", "dslash_f64": "k_dslash<F64>"}
+N_SITE_VARIANTS_DOT = 2  # site-parallel launch variants of the reducing dslash; plane-marching ones follow
+
+
+def kernel_name(kclass, variants):
+    if kclass == "dslash_f16" and variants and min(variants.values()) >= N_SITE_VARIANTS_DOT:
+        return "k_dslash_march<F16, DOT> (fused MR-smoother dslash, plane-marching)"
+    return KERNEL_NAMES[kclass]
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_11424_amd", "csrc", f)
                   for f in ("dslash.hip", "fine_dev.h", "fine.h", "common.h")]
 
@@ -59,6 +70,14 @@ def kernel_sources_hash():
     return h.hexdigest()
 
 
+def dslash_flops(kclass, V, launches, total_bytes):
+    """Algorithmic flops of `launches` dslash applications whose algorithmic
+    bytes sum to total_bytes (the rhs count of each follows from its bytes)."""
+    wc = PREC_BYTES[kclass]
+    rhs_total = (total_bytes / V - launches * (36 * wc + 36 * wc)) / (24 * wc)
+    return DSLASH_FLOP * V * rhs_total
+
+
 def dslash_bytes(kclass, V, nrhs):
     """Algorithmic bytes of one fine dslash (links and clover once, spinors in
     and out), as the library's FineOp::bytes."""
@@ -66,22 +85,35 @@ def dslash_bytes(kclass, V, nrhs):
     return V * (36 * wc + 72 * wc / 2 + 24 * wc * nrhs)
 
 
-def measured_traffic(kclass, V, launches, total_bytes):
-    """Calibrated HBM bytes per launch of the kernel class in the timed region,
-    or None.  The counter file holds FETCH_SIZE / WRITE_SIZE per launch at the
-    rhs counts the timed region uses (8 and 4 on the fine level); the split of
-    the region's launches between them follows from its launch count and
-    algorithmic bytes.  None when the counters were taken with other kernel
-    sources or the launches do not split into those counts."""
+def traffic_record(kclass):
+    """key: value lines of the counter file of a kernel class ({} if none)."""
+    kv = {}
     try:
-        kv = {}
         with open(TRAFFIC_FILES[kclass]) as f:
             for line in f:
                 if ":" in line and not line.startswith("#") and not line.startswith(" "):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
+    except (OSError, KeyError):
+        pass
+    return kv
+
+
+def measured_traffic(kclass, V, launches, total_bytes, variants=None):
+    """Calibrated HBM bytes per launch of the kernel class in the timed region,
+    or None.  The counter file holds FETCH_SIZE / WRITE_SIZE per launch at the
+    rhs counts the timed region uses (8 and 4 on the fine level), taken with
+    the launch variants it names; the split of the region's launches between
+    the counts follows from its launch count and algorithmic bytes.  None when
+    the counters were taken with other kernel sources or launch variants, or
+    the launches do not split into those counts."""
+    try:
+        kv = traffic_record(kclass)
         if kv.get("kernel_sources_sha256") != kernel_sources_hash():
             return None
+        for n, v in (variants or {}).items():
+            if "variant_nrhs%d" % n in kv and int(kv["variant_nrhs%d" % n]) != v:
+                return None
         fs, ws = float(kv["fetch_scale"]), float(kv["write_scale"])
         t = {n: (float(kv["fetch_kib_nrhs%d" % n]) * fs + float(kv["write_kib_nrhs%d" % n]) * ws) * 1024.0
              for n in (8, 4)}
@@ -196,6 +228,26 @@ def run(args):
         _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch)
 
 
+def roofline(ds, V, q, achieved_gbs, avg_ms, bytes_launch, variants, traffic):
+    """Roofline of the dominant dslash against whichever roof is tighter for
+    its algorithmic counts: FP32/FP64 vector FMA (unpacked) or HBM."""
+    flops_launch = dslash_flops(ds, V, q["launches"], q["bytes"]) / max(q["launches"], 1)
+    tflops = flops_launch / (avg_ms * 1e-3) / 1e12 if q["launches"] else 0.0
+    t_alu = flops_launch / (VALU_PEAK_TFLOPS * 1e12)
+    t_hbm = bytes_launch / (HBM_PEAK_GBS * 1e9)
+    hbm = {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS}
+    alu = {"achieved": tflops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / VALU_PEAK_TFLOPS}
+    main, other, bound = (alu, hbm, "alu") if t_alu > t_hbm else (hbm, alu, "hbm")
+    out = {"bound": bound}
+    out.update(main)
+    out.update({"traffic": traffic, "kernel": kernel_name(ds, variants), "launch_variants": variants,
+                "avg_launch_ms": avg_ms, "launches": q["launches"], "bytes_per_launch": bytes_launch,
+                "flop_per_launch": flops_launch, "other_roof": dict(other, bound="hbm" if bound == "alu" else "alu"),
+                "peak_note": "alu peak = unpacked vector FMA (packed FP32 is disabled in the build; "
+                             "the packed FP32 figure is 157.3 TFLOP/s)"})
+    return out
+
+
 def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     ctx = m.Context(0)
     op = m.Operator(ctx, U, cfg["m0"], cfg["csw"])
@@ -213,7 +265,14 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     # fastest settings measured for both the FP64 and the mixed fine solves
     sd = m.solve_desc(tol=1e-10, kind=kind, smooth=6, smooth_coarse=2, coarse_iters=3, inner_tol=1e-5,
                       maxiter=5000, coarse_bf16=True, smoother_f16=True, graphs=bool(mixed))
+    dot_keys = {n: "dslash_dot/%d/%d/%d" % (m.api.PREC["f16"], op.V, n) for n in (8, 4)}
     if mixed:
+        # the fused smoother dslash keeps the launch shapes its HBM counters
+        # were recorded with (the fastest measured); everything else is tuned
+        rec = traffic_record("dslash_f16")
+        for n, key in dot_keys.items():
+            if "variant_nrhs%d" % n in rec:
+                ctx.tune_set(key, int(rec["variant_nrhs%d" % n]))
         ctx.autotune(True)
     batch = cfg["batch"]
 
@@ -241,6 +300,8 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     # dominant kernel: the dslash precision class with the most time
     ds = max(("dslash_f64", "dslash_f32", "dslash_f16"), key=lambda k: prof[k]["ms"])
     q = prof[ds]
+    rep = ctx.tune_report()
+    variants = {n: rep[k][0] for n, k in dot_keys.items() if k in rep} if ds == "dslash_f16" else {}
     avg_ms = q["ms"] / max(q["launches"], 1)
     bytes_launch = q["bytes"] / max(q["launches"], 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if q["launches"] else 0.0
@@ -252,12 +313,9 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
         "data": "synthetic",
         "config": {"workload": cfg["name"], "lattice": "x".join(map(str, cfg["dims"])), "levels": L,
                    "probes": cfg["nprobe"], "batch": batch, "tol": 1e-10, "form": args.form},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(ds, op.V, q["launches"], q["bytes"]) if args.config == "c4"
-                     else None,
-                     "kernel": KERNEL_NAMES[ds], "avg_launch_ms": avg_ms,
-                     "launches": q["launches"], "bytes_per_launch": bytes_launch},
+        "roofline": roofline(ds, op.V, q, achieved, avg_ms, bytes_launch, variants,
+                             measured_traffic(ds, op.V, q["launches"], q["bytes"], variants)
+                             if args.config == "c4" else None),
         "hierarchy_workspace_gb": h.ws.numel() / 1e9,
         "setup_s": t_setup, "gauge_gen_s": t_gauge, "rhs_per_step": nrhs_step,
         "solver_iterations_per_step": results[-1]["stats"]["iterations"],

@@ -43,3 +43,36 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_traffic_gate_rejects_other_launch_variants(tmp_path, monkeypatch):
+    import bench
+    f = tmp_path / "t.txt"
+    f.write_text("kernel_sources_sha256: %s\nfetch_scale: 2\nwrite_scale: 1\nvariant_nrhs8: 2\nvariant_nrhs4: 2\n"
+                 "fetch_kib_nrhs8: 1\nwrite_kib_nrhs8: 1\nfetch_kib_nrhs4: 1\nwrite_kib_nrhs4: 1\n"
+                 % bench.kernel_sources_hash())
+    monkeypatch.setitem(bench.TRAFFIC_FILES, "dslash_f16", str(f))
+    V = 1024
+    total = 3 * bench.dslash_bytes("dslash_f16", V, 8)
+    assert bench.measured_traffic("dslash_f16", V, 3, total, {8: 2, 4: 2}) == 3 * 1024.0
+    assert bench.measured_traffic("dslash_f16", V, 3, total, {8: 3, 4: 2}) is None
+    assert bench.traffic_record("dslash_f16")["variant_nrhs8"] == "2"
+    assert bench.kernel_name("dslash_f16", {8: 2, 4: 2}).startswith("k_dslash_march")
+    assert bench.kernel_name("dslash_f16", {8: 0, 4: 2}).startswith("k_dslash<")
+
+
+def test_roofline_takes_the_tighter_roof():
+    import bench
+    V = 32 * 32 * 32 * 64
+    b8 = bench.dslash_bytes("dslash_f16", V, 8)
+    # 1896 flop per site and rhs: at 8 FP16 rhs the unpacked-FMA floor (0.40 ms)
+    # is above the HBM floor of the algorithmic bytes (0.28 ms)
+    assert abs(bench.dslash_flops("dslash_f16", V, 2, 2 * b8) - 2 * 8 * 1896 * V) < 1
+    q = {"launches": 1, "bytes": b8}
+    r = bench.roofline("dslash_f16", V, q, b8 / 1e-3 / 1e9, 1.0, b8, {}, None)
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["other_roof"]["bound"] == "hbm"
+    assert abs(r["frac"] - 8 * 1896 * V / 1e-3 / 1e12 / bench.VALU_PEAK_TFLOPS) < 1e-12
+    # FP64 at one rhs: 1536 bytes per site for 1896 flop, HBM is the tighter roof
+    b1 = bench.dslash_bytes("dslash_f64", V, 1)
+    r = bench.roofline("dslash_f64", V, {"launches": 1, "bytes": b1}, 1.0, 1.0, b1, {}, None)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
