@@ -99,10 +99,17 @@ def traffic_record(kclass):
     return kv
 
 
+def rhs_counts(kv):
+    """The two rhs counts of the timed region's launches that a counter file
+    covers (larger first; 8 and 4 when it does not say)."""
+    c = [int(v) for v in kv.get("rhs_counts", "8 4").split()]
+    return max(c), min(c)
+
+
 def measured_traffic(kclass, V, launches, total_bytes, variants=None):
     """Calibrated HBM bytes per launch of the kernel class in the timed region,
     or None.  The counter file holds FETCH_SIZE / WRITE_SIZE per launch at the
-    rhs counts the timed region uses (8 and 4 on the fine level), taken with
+    two rhs counts the timed region uses on the fine level, taken with
     the launch variants it names; the split of the region's launches between
     the counts follows from its launch count and algorithmic bytes.  None when
     the counters were taken with other kernel sources or launch variants, or
@@ -114,15 +121,16 @@ def measured_traffic(kclass, V, launches, total_bytes, variants=None):
         for n, v in (variants or {}).items():
             if "variant_nrhs%d" % n in kv and int(kv["variant_nrhs%d" % n]) != v:
                 return None
+        hi, lo = rhs_counts(kv)
         fs, ws = float(kv["fetch_scale"]), float(kv["write_scale"])
         t = {n: (float(kv["fetch_kib_nrhs%d" % n]) * fs + float(kv["write_kib_nrhs%d" % n]) * ws) * 1024.0
-             for n in (8, 4)}
-        b8, b4 = dslash_bytes(kclass, V, 8), dslash_bytes(kclass, V, 4)
-        n8 = (total_bytes - launches * b4) / (b8 - b4)
-        if abs(n8 - round(n8)) > 1e-3 * launches or n8 < -0.5 or n8 > launches + 0.5:
+             for n in (hi, lo)}
+        bh, bl = dslash_bytes(kclass, V, hi), dslash_bytes(kclass, V, lo)
+        nh = (total_bytes - launches * bl) / (bh - bl)
+        if abs(nh - round(nh)) > 1e-3 * launches or nh < -0.5 or nh > launches + 0.5:
             return None
-        n8 = int(round(n8))
-        return (n8 * t[8] + (launches - n8) * t[4]) / launches
+        nh = int(round(nh))
+        return (nh * t[hi] + (launches - nh) * t[lo]) / launches
     except (OSError, KeyError, ValueError, ZeroDivisionError):
         return None
 
@@ -130,8 +138,13 @@ def measured_traffic(kclass, V, launches, total_bytes, variants=None):
 CONFIGS = {
     # 32^3 x 64, csw 1, roughness 0.6, m0 0.02; 4^4 (24 tv) then 2^4 (32 tv);
     # probes 20 / 100 / 400 on the fine / middle / coarsest difference levels
+    # batch: rhs per solve batch on each level in the mixed form (16 on the
+    # fine level: the largest tried that fits, 187 GB of workspace); the FP64
+    # form of the time-to-target comparison keeps 8 (its FP64 Krylov
+    # workspace would need about 245 GB at 16)
     "c4": dict(dims=(32, 32, 32, 64), eps=0.6, m0=0.02, csw=1.0, gseed=14, blocks=[(4, 4, 4, 4), (2, 2, 2, 2)],
-               ntv=[24, 32], nprobe=[20, 100, 400], pseed=104, batch=[8, 32, 64], restart=12,
+               ntv=[24, 32], nprobe=[20, 100, 400], pseed=104, batch=[16, 32, 64], batch_f64=[8, 32, 64],
+               restart=12,
                name="32^3x64 Wilson-clover (csw 1, roughness 0.6, m0 0.02), 3-level orthogonal MG-MLMC "
                     "tr(D^-1), aggregates 4^4/2^4, N_tv 24/32, probes 20/100/400"),
     "c3": dict(dims=(16, 16, 16, 16), eps=0.6, m0=0.01, csw=1.0, gseed=13, blocks=[(2, 2, 2, 2)], ntv=[12],
@@ -203,7 +216,9 @@ def cpu_baseline(cfg, out_path):
 
 def run(args):
     import numpy as np
-    cfg = CONFIGS[args.config]
+    cfg = dict(CONFIGS[args.config])
+    if args.batch:
+        cfg["batch"] = list(args.batch)
     from lattice_inputs import gauge_field
     t0 = time.time()
     U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])
@@ -265,7 +280,8 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     # fastest settings measured for both the FP64 and the mixed fine solves
     sd = m.solve_desc(tol=1e-10, kind=kind, smooth=6, smooth_coarse=2, coarse_iters=3, inner_tol=1e-5,
                       maxiter=5000, coarse_bf16=True, smoother_f16=True, graphs=bool(mixed))
-    dot_keys = {n: "dslash_dot/%d/%d/%d" % (m.api.PREC["f16"], op.V, n) for n in (8, 4)}
+    dot_keys = {n: "dslash_dot/%d/%d/%d" % (m.api.PREC["f16"], op.V, n)
+                for n in rhs_counts(traffic_record("dslash_f16"))}
     if mixed:
         # the fused smoother dslash keeps the launch shapes its HBM counters
         # were recorded with (the fastest measured); everything else is tuned
@@ -330,8 +346,14 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     if args.learned:
         line["learned"] = learned_form(m, ctx, op, cfg, h, sd, args, torch)
     if args.ttt:
-        line["time_to_target"] = time_to_target(m, ctx, op, cfg, h, sd, args)
-        h = None
+        del h, results
+        torch.cuda.empty_cache()
+
+        def make_mixed():
+            return m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=cfg["batch"][0],
+                               max_nrhs_level=cfg["batch"], restart=cfg["restart"], mixed=1)
+
+        line["time_to_target"] = time_to_target(m, ctx, op, cfg, make_mixed, sd, args)
     if cpu_pid:
         os.waitpid(cpu_pid, 0)
         try:
@@ -464,7 +486,7 @@ def learned_form(m, ctx, op, cfg, h, sd_mixed, args, torch):
     return out
 
 
-def time_to_target(m, ctx, op, cfg, h_mixed, sd_mixed, args):
+def time_to_target(m, ctx, op, cfg, make_mixed, sd_mixed, args):
     """Time to reach the variance of the plain FP64 orthogonal estimate at the
     configured probe counts (target eps^2), for plain FP64 MG and for the
     mixed form with MLMC-optimal sample sizes (Sec. 2.2, eq. MLMC-Nl)."""
@@ -473,39 +495,46 @@ def time_to_target(m, ctx, op, cfg, h_mixed, sd_mixed, args):
     L = len(cfg["nprobe"])
     lv = list(range(L - 1)) + list(range(L - 1)) + [L - 1]
 
-    def pilot(h, sd):
+    def pilot(h, sd, batch):
         torch.cuda.synchronize()
         t0 = time.time()
-        r = h.estimate("trace", "orthogonal", cfg["nprobe"], seed=cfg["pseed"] + 7, batch=cfg["batch"],
+        r = h.estimate("trace", "orthogonal", cfg["nprobe"], seed=cfg["pseed"] + 7, batch=batch,
                        solve=sd, samples=False)
         torch.cuda.synchronize()
         return {"seconds": time.time() - t0, "var": r["var"][:, 0, 0], "cost": r["cost_s"],
                 "total_var": float(r["total_var"][0, 0])}
 
-    def final(h, sd, p, eps2):
+    def final(h, sd, p, eps2, batch):
         # MLMC-optimal N per term; terms of one probe group share the largest
         n = m.mlmc_allocate(np.maximum(p["var"], 1e-30), np.maximum(p["cost"], 1e-9), eps2)
         npl = [int(max(n[i] for i in range(len(lv)) if lv[i] == g)) for g in range(L)]
         torch.cuda.synchronize()
         t0 = time.time()
-        r = h.estimate("trace", "orthogonal", npl, seed=cfg["pseed"] + 11, batch=cfg["batch"], solve=sd,
+        r = h.estimate("trace", "orthogonal", npl, seed=cfg["pseed"] + 11, batch=batch, solve=sd,
                        samples=False)
         torch.cuda.synchronize()
         return {"seconds": time.time() - t0, "nprobe": npl, "achieved_var": float(r["total_var"][0, 0]),
                 "pilot_seconds": p["seconds"]}
 
-    pm = pilot(h_mixed, sd_mixed)
-    # FP64 hierarchy and pilot; eps^2 is the plain FP64 estimate's variance at
-    # the configured probe counts
-    h64 = m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=cfg["batch"][0],
-                      max_nrhs_level=cfg["batch"], restart=cfg["restart"], mixed=0)
+    # one hierarchy at a time: the FP64 one first (its pilot fixes eps^2, the
+    # variance of the plain FP64 estimate at the configured probe counts),
+    # then the mixed one, built anew
+    b64 = cfg.get("batch_f64", cfg["batch"])
+    h64 = m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=b64[0],
+                      max_nrhs_level=b64, restart=cfg["restart"], mixed=0)
     sd64 = m.solve_desc(tol=1e-10, kind="mg", smooth=6, smooth_coarse=2, coarse_iters=3, maxiter=5000)
-    p64 = pilot(h64, sd64)
+    p64 = pilot(h64, sd64, b64)
     eps2 = p64["total_var"]
-    out = {"eps2": eps2, "f64": final(h64, sd64, p64, eps2)}
+    out = {"eps2": eps2, "f64": final(h64, sd64, p64, eps2, b64)}
+    out["f64"]["batch"] = b64
     del h64
     torch.cuda.empty_cache()
-    out["mixed"] = final(h_mixed, sd_mixed, pm, eps2)
+    h_mixed = make_mixed()
+    pm = pilot(h_mixed, sd_mixed, cfg["batch"])
+    out["mixed"] = final(h_mixed, sd_mixed, pm, eps2, cfg["batch"])
+    out["mixed"]["batch"] = cfg["batch"]
+    del h_mixed
+    torch.cuda.empty_cache()
     out["ratio_f64_over_mixed"] = out["f64"]["seconds"] / out["mixed"]["seconds"]
     return out
 
@@ -516,6 +545,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c4", choices=sorted(CONFIGS))
+    ap.add_argument("--batch", type=int, nargs="+", default=None,
+                    help="right-hand sides per batch on each level (default: the configuration's)")
     ap.add_argument("--form", default="mixed", choices=["mixed", "f64"])
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--ttt", action="store_true")

@@ -76,3 +76,17 @@ def test_roofline_takes_the_tighter_roof():
     b1 = bench.dslash_bytes("dslash_f64", V, 1)
     r = bench.roofline("dslash_f64", V, {"launches": 1, "bytes": b1}, 1.0, 1.0, b1, {}, None)
     assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+
+
+def test_traffic_split_follows_the_recorded_rhs_counts(tmp_path, monkeypatch):
+    import bench
+    f = tmp_path / "t.txt"
+    f.write_text("kernel_sources_sha256: %s\nrhs_counts: 16 4\nfetch_scale: 2\nwrite_scale: 1\n"
+                 "fetch_kib_nrhs16: 3\nwrite_kib_nrhs16: 0\nfetch_kib_nrhs4: 1\nwrite_kib_nrhs4: 0\n"
+                 % bench.kernel_sources_hash())
+    monkeypatch.setitem(bench.TRAFFIC_FILES, "dslash_f16", str(f))
+    V = 1024
+    # two launches at 16 rhs and one at 4: (2 * 6 + 2) KiB / 3
+    total = 2 * bench.dslash_bytes("dslash_f16", V, 16) + bench.dslash_bytes("dslash_f16", V, 4)
+    assert abs(bench.measured_traffic("dslash_f16", V, 3, total) - 14 * 1024.0 / 3) < 1e-9
+    assert bench.rhs_counts(bench.traffic_record("dslash_f16")) == (16, 4)
