@@ -356,6 +356,15 @@ mgm_status mgm_net_num_weights(mgm_net net, int64_t* count);  /* complex weights
 /* Host FP64 weights (2 * count doubles); set also resets the Adam state. */
 mgm_status mgm_net_set_weights(mgm_net net, const double* w_host);
 mgm_status mgm_net_get_weights(mgm_net net, double* w_host);
+/* Writes the network's layer count, widths and FP64 master weights to the
+ * file `path` (a small binary file: the 8 bytes "MGMNET01", int32 nlayers,
+ * int32 width[9], int64 count, then 2 * count little-endian doubles).
+ * Errors: INVALID_ARG (NULL), HIP, NUMERIC (the file cannot be written). */
+mgm_status mgm_net_save(mgm_net net, const char* path);
+/* Reads such a file into the network (as mgm_net_set_weights, resetting the
+ * Adam state).  A file for other layers or widths: MGM_ERR_SHAPE; a missing,
+ * short or foreign file: MGM_ERR_INVALID_ARG. */
+mgm_status mgm_net_load(mgm_net net, const char* path);
 /* y = N(r) for nrhs <= max_nrhs fine spinors (FP32 complex, device). */
 mgm_status mgm_net_apply(mgm_net net, const void* r_dev, void* y_dev, int32_t nrhs);
 /* Loss (1/nrhs) sum_j |N(r_j) - e_j|^2 / |e_j|^2 and its weight gradient

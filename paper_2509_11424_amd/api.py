@@ -148,6 +148,8 @@ _SIGS = [
     ("mgm_net_create", C.c_int, [C.c_void_p, C.POINTER(NetDesc), C.c_void_p, C.c_size_t,
                                  C.POINTER(C.c_void_p)]),
     ("mgm_net_num_weights", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("mgm_net_save", C.c_int, [C.c_void_p, C.c_char_p]),
+    ("mgm_net_load", C.c_int, [C.c_void_p, C.c_char_p]),
     ("mgm_net_set_weights", C.c_int, [C.c_void_p, C.c_void_p]),
     ("mgm_net_get_weights", C.c_int, [C.c_void_p, C.c_void_p]),
     ("mgm_net_apply", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
@@ -565,6 +567,14 @@ class Net:
         w = np.empty(2 * self.nweights, dtype=np.float64)
         _check(lib().mgm_net_get_weights(self.h, w.ctypes.data_as(C.c_void_p)))
         return self._split(w.view(np.complex128))
+
+    def save(self, path: str):
+        """Writes the layer widths and FP64 weights to `path`."""
+        _check(lib().mgm_net_save(self.h, os.fsencode(path)))
+
+    def load(self, path: str):
+        """Reads weights written by save() for a network of the same widths."""
+        _check(lib().mgm_net_load(self.h, os.fsencode(path)))
 
     def set_weights(self, weights: list):
         flat = np.concatenate([np.asarray(W, dtype=np.complex128).ravel() for W in weights])

@@ -707,6 +707,59 @@ mgm_status mgm_net_get_weights(mgm_net net, double* w_host) {
   API_END
 }
 
+static const char kNetMagic[8] = {'M', 'G', 'M', 'N', 'E', 'T', '0', '1'};
+
+mgm_status mgm_net_save(mgm_net net, const char* path) {
+  API_BEGIN
+  MGM_CHECK(net && path, MGM_ERR_INVALID_ARG, "NULL argument");
+  std::vector<double> w(2 * (size_t)net->n.nw);
+  MGM_HIP(hipMemcpyAsync(w.data(), net->n.w64, sizeof(double2) * net->n.nw, hipMemcpyDeviceToHost,
+                         net->n.ctx->stream));
+  net->n.ctx->sync();
+  std::FILE* f = std::fopen(path, "wb");
+  MGM_CHECK(f != nullptr, MGM_ERR_NUMERIC, std::string("cannot open ") + path + " for writing");
+  const int32_t L = net->n.L;
+  int32_t width[kNetMaxLayers + 1] = {};
+  for (int i = 0; i <= L; i++) width[i] = net->n.width[i];
+  const int64_t nw = net->n.nw;
+  bool ok = std::fwrite(kNetMagic, 1, 8, f) == 8 && std::fwrite(&L, sizeof L, 1, f) == 1 &&
+            std::fwrite(width, sizeof width, 1, f) == 1 && std::fwrite(&nw, sizeof nw, 1, f) == 1 &&
+            std::fwrite(w.data(), sizeof(double), w.size(), f) == w.size();
+  ok = (std::fclose(f) == 0) && ok;
+  MGM_CHECK(ok, MGM_ERR_NUMERIC, std::string("write to ") + path + " failed");
+  API_END
+}
+
+mgm_status mgm_net_load(mgm_net net, const char* path) {
+  API_BEGIN
+  MGM_CHECK(net && path, MGM_ERR_INVALID_ARG, "NULL argument");
+  std::FILE* f = std::fopen(path, "rb");
+  MGM_CHECK(f != nullptr, MGM_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t L = 0;
+  int32_t width[kNetMaxLayers + 1] = {};
+  int64_t nw = 0;
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kNetMagic, 8) == 0 &&
+            std::fread(&L, sizeof L, 1, f) == 1 && std::fread(width, sizeof width, 1, f) == 1 &&
+            std::fread(&nw, sizeof nw, 1, f) == 1;
+  if (!ok) {
+    std::fclose(f);
+    throw Error(MGM_ERR_INVALID_ARG, std::string(path) + " is not a network weight file");
+  }
+  bool same = L == net->n.L && nw == net->n.nw;
+  for (int i = 0; same && i <= L && i <= kNetMaxLayers; i++) same = width[i] == net->n.width[i];
+  if (!same) {
+    std::fclose(f);
+    throw Error(MGM_ERR_SHAPE, std::string(path) + " holds a network of other layers or widths");
+  }
+  std::vector<double> w(2 * (size_t)nw);
+  ok = std::fread(w.data(), sizeof(double), w.size(), f) == w.size();
+  std::fclose(f);
+  MGM_CHECK(ok, MGM_ERR_INVALID_ARG, std::string(path) + " is truncated");
+  net->n.upload_weights(w);
+  API_END
+}
+
 mgm_status mgm_net_apply(mgm_net net, const void* r_dev, void* y_dev, int32_t nrhs) {
   API_BEGIN
   MGM_CHECK(net && r_dev && y_dev, MGM_ERR_INVALID_ARG, "NULL argument");

@@ -123,6 +123,32 @@ def test_training_reduces_the_loss(trained):
     assert hist[-1] <= hist[0]
 
 
+def test_saved_weights_load_into_a_fresh_network(lat, trained, tmp_path):
+    """mgm_net_save / mgm_net_load: a fresh network of the same widths loads
+    the trained weights exactly and applies them identically; other widths
+    and foreign files are refused."""
+    import torch
+    import paper_2509_11424_amd as m
+    p = lat
+    h, net, _ = trained
+    f = str(tmp_path / "w.bin")
+    net.save(f)
+    fresh = m.Net(p.op, widths=(4, 8, 8, 4), seed=99, max_nrhs=8, train_nrhs=8)
+    fresh.load(f)
+    for a, b in zip(net.get_weights(), fresh.get_weights()):
+        assert np.array_equal(a, b)
+    r = _to_f32_gpu(_rand(p.V, 3, 67))
+    torch.cuda.synchronize()
+    assert torch.equal(net.apply(r), fresh.apply(r))
+    other = m.Net(p.op, widths=(4, 12, 4), seed=1, max_nrhs=8, train_nrhs=8)
+    with pytest.raises(RuntimeError, match="SHAPE"):
+        other.load(f)
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"not a weight file")
+    with pytest.raises(RuntimeError, match="INVALID_ARG"):
+        fresh.load(str(bad))
+
+
 def test_net_preconditioned_solve_converges(lat, trained):
     import paper_2509_11424_amd as m
     p = lat
