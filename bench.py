@@ -139,11 +139,12 @@ CONFIGS = {
     # 32^3 x 64, csw 1, roughness 0.6, m0 0.02; 4^4 (24 tv) then 2^4 (32 tv);
     # probes 20 / 100 / 400 on the fine / middle / coarsest difference levels
     # batch: rhs per solve batch on each level in the mixed form (16 on the
-    # fine level: the largest tried that fits, 187 GB of workspace); the FP64
-    # form of the time-to-target comparison keeps 8 (its FP64 Krylov
-    # workspace would need about 245 GB at 16)
+    # fine level: the largest tried that fits, 198 GB of workspace; all 100
+    # middle-level probes of a term at once; 80 on the coarsest); the FP64
+    # form of the time-to-target comparison keeps 8 on the fine level (its
+    # FP64 Krylov workspace would need about 245 GB at 16)
     "c4": dict(dims=(32, 32, 32, 64), eps=0.6, m0=0.02, csw=1.0, gseed=14, blocks=[(4, 4, 4, 4), (2, 2, 2, 2)],
-               ntv=[24, 32], nprobe=[20, 100, 400], pseed=104, batch=[16, 32, 64], batch_f64=[8, 32, 64],
+               ntv=[24, 32], nprobe=[20, 100, 400], pseed=104, batch=[16, 100, 80], batch_f64=[8, 100, 80],
                restart=12,
                name="32^3x64 Wilson-clover (csw 1, roughness 0.6, m0 0.02), 3-level orthogonal MG-MLMC "
                     "tr(D^-1), aggregates 4^4/2^4, N_tv 24/32, probes 20/100/400"),
