@@ -19,7 +19,7 @@ operator application and an iteration count measured on a small lattice).
 
 Kernel micro-benchmarks (used for the profiler runs of single kernels):
 
-  python bench.py --micro dslash|dslash_dot --prec f32[,f64,f16] --nrhs 8[,1,...] [--iters 50]
+  python bench.py --micro dslash|dslash_dot|step --prec f32[,f64,f16] --nrhs 8[,1,...] [--iters 50]
                   [--tune | --variant V]   # autotune the launch shape, or pin variant V
   python bench.py --micro copy [--iters 50]      # plain 1 GiB device copy
 """
@@ -40,20 +40,31 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMD16 x 16 lanes x 2 flop x 2.4 GHz, the same for FP32 and FP64
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 DSLASH_FLOP = 1896  # per site and rhs: 8 hops x 168 + clover 552
+# the fused smoother step adds r - omega q and x + omega r: 12 complex
+# multiply-adds each
+FLOP_PER_UNIT = {"dslash_f64": DSLASH_FLOP, "dslash_f32": DSLASH_FLOP, "dslash_f16": DSLASH_FLOP,
+                 "dslash_step": DSLASH_FLOP + 2 * 12 * 8}
 
 # HBM traffic of the dominant dslash at nrhs 8 on 32^3 x 64 from two rocprofv3
 # --pmc runs, valid only for the kernel sources it was taken with
 TRAFFIC_FILES = {
-    "dslash_f16": os.path.join(ROOT, "profiles", "dslash_f16_dot_32x32x32x64_traffic.txt"),
-    "dslash_f32": os.path.join(ROOT, "profiles", "dslash_f32_32x32x32x64_traffic.txt"),
+    "dslash_step": os.path.join(ROOT, "profiles", "smoother_step_f16_32x32x32x64_traffic.txt"),
 }
-PREC_BYTES = {"dslash_f64": 16, "dslash_f32": 8, "dslash_f16": 4}
+PREC_BYTES = {"dslash_f64": 16, "dslash_f32": 8, "dslash_f16": 4, "dslash_step": 4}
+# spinor volumes moved per rhs: the dslash reads x and writes y; the fused
+# smoother step reads r and writes r', and reads and writes x
+SPINOR_VOLUMES = {"dslash_f64": 2, "dslash_f32": 2, "dslash_f16": 2, "dslash_step": 4}
 KERNEL_NAMES = {"dslash_f16": "k_dslash<F16, DOT> (fused MR-smoother dslash)",
-                "dslash_f32": "k_dslash_rb<F32> (two rhs per thread)", "dslash_f64": "k_dslash<F64>"}
+                "dslash_f32": "k_dslash_rb<F32> (two rhs per thread)", "dslash_f64": "k_dslash<F64>",
+                "dslash_step": "k_dslash_march<F16, DOT, MR> (fused FP16 smoother step: dslash, dots, "
+                               "r and x updates)"}
 N_SITE_VARIANTS_DOT = 2  # site-parallel launch variants of the reducing dslash; plane-marching ones follow
+TUNE_PREFIX = {"dslash_step": "dslash_step"}  # tune-table key prefix of each class with recorded counters
 
 
 def kernel_name(kclass, variants):
+    if kclass == "dslash_step":
+        return KERNEL_NAMES[kclass]
     if kclass == "dslash_f16" and variants and min(variants.values()) >= N_SITE_VARIANTS_DOT:
         return "k_dslash_march<F16, DOT> (fused MR-smoother dslash, plane-marching)"
     return KERNEL_NAMES[kclass]
@@ -74,15 +85,15 @@ def dslash_flops(kclass, V, launches, total_bytes):
     """Algorithmic flops of `launches` dslash applications whose algorithmic
     bytes sum to total_bytes (the rhs count of each follows from its bytes)."""
     wc = PREC_BYTES[kclass]
-    rhs_total = (total_bytes / V - launches * (36 * wc + 36 * wc)) / (24 * wc)
-    return DSLASH_FLOP * V * rhs_total
+    rhs_total = (total_bytes / V - launches * (36 * wc + 36 * wc)) / (12 * SPINOR_VOLUMES[kclass] * wc)
+    return FLOP_PER_UNIT[kclass] * V * rhs_total
 
 
 def dslash_bytes(kclass, V, nrhs):
     """Algorithmic bytes of one fine dslash (links and clover once, spinors in
     and out), as the library's FineOp::bytes."""
     wc = PREC_BYTES[kclass]
-    return V * (36 * wc + 72 * wc / 2 + 24 * wc * nrhs)
+    return V * (36 * wc + 72 * wc / 2 + 12 * SPINOR_VOLUMES[kclass] * wc * nrhs)
 
 
 def traffic_record(kclass):
@@ -277,19 +288,21 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     kind = "mg_mixed" if mixed else "mg"
     # mixed form: FP16-storage fine smoother, BF16 MFMA coarse operators,
     # autotuned launch shapes and graph-captured coarse-grid corrections
-    # smoothing 6 / 2 (fine / coarser levels) and 3 coarse-solve steps: the
-    # fastest settings measured for both the FP64 and the mixed fine solves
-    sd = m.solve_desc(tol=1e-10, kind=kind, smooth=6, smooth_coarse=2, coarse_iters=3, inner_tol=1e-5,
+    # smoothing 8 (mixed form; 6 for FP64) / 2 (fine / coarser levels) and 3
+    # coarse-solve steps: the fastest settings measured for each form
+    sd = m.solve_desc(tol=1e-10, kind=kind, smooth=args.smooth, smooth_coarse=2, coarse_iters=3, inner_tol=1e-5,
                       maxiter=5000, coarse_bf16=True, smoother_f16=True, graphs=bool(mixed))
-    dot_keys = {n: "dslash_dot/%d/%d/%d" % (m.api.PREC["f16"], op.V, n)
-                for n in rhs_counts(traffic_record("dslash_f16"))}
+    # launch-shape keys of the kernel classes with recorded HBM counters
+    pin_keys = {kc: {n: "%s/%d/%d/%d" % (TUNE_PREFIX[kc], m.api.PREC["f16"], op.V, n)
+                     for n in rhs_counts(traffic_record(kc))} for kc in TUNE_PREFIX}
     if mixed:
-        # the fused smoother dslash keeps the launch shapes its HBM counters
-        # were recorded with (the fastest measured); everything else is tuned
-        rec = traffic_record("dslash_f16")
-        for n, key in dot_keys.items():
-            if "variant_nrhs%d" % n in rec:
-                ctx.tune_set(key, int(rec["variant_nrhs%d" % n]))
+        # the smoother kernels keep the launch shapes their HBM counters were
+        # recorded with (the fastest measured); everything else is tuned
+        for kc, keys in pin_keys.items():
+            rec = traffic_record(kc)
+            for n, key in keys.items():
+                if "variant_nrhs%d" % n in rec:
+                    ctx.tune_set(key, int(rec["variant_nrhs%d" % n]))
         ctx.autotune(True)
     batch = cfg["batch"]
 
@@ -309,16 +322,16 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
         results.append(step((k + 1) * 1000))
     torch.cuda.synchronize()
     dt = time.time() - t0
-    prof = {c: ctx.profile_query(c) for c in ("dslash_f64", "dslash_f32", "dslash_f16", "coarse_f64",
-                                               "coarse_f32", "coarse_bf16", "transfer")}
+    prof = {c: ctx.profile_query(c) for c in ("dslash_f64", "dslash_f32", "dslash_f16", "dslash_step",
+                                               "coarse_f64", "coarse_f32", "coarse_bf16", "transfer")}
     ctx.profile(False)
     nrhs_step = rhs_per_step(cfg["nprobe"])
     value = nrhs_step * args.steps / dt
     # dominant kernel: the dslash precision class with the most time
-    ds = max(("dslash_f64", "dslash_f32", "dslash_f16"), key=lambda k: prof[k]["ms"])
+    ds = max(("dslash_f64", "dslash_f32", "dslash_f16", "dslash_step"), key=lambda k: prof[k]["ms"])
     q = prof[ds]
     rep = ctx.tune_report()
-    variants = {n: rep[k][0] for n, k in dot_keys.items() if k in rep} if ds == "dslash_f16" else {}
+    variants = {n: rep[k][0] for n, k in pin_keys.get(ds, {}).items() if k in rep}
     avg_ms = q["ms"] / max(q["launches"], 1)
     bytes_launch = q["bytes"] / max(q["launches"], 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if q["launches"] else 0.0
@@ -405,13 +418,20 @@ def micro(args):
                 x = torch.randn(shape, generator=g, device="cuda:0",
                                 dtype=torch.complex128 if prec == "f64" else torch.complex64)
             y = torch.empty_like(x)
+            if args.micro == "step":
+                xv = torch.zeros_like(x)
+                wqr = torch.full((nrhs,), 0.01, dtype=torch.complex128, device="cuda:0")
+                wqq = torch.ones(nrhs, dtype=torch.float64, device="cuda:0")
+
             def once():
                 if args.micro == "dslash_dot":
                     op.apply_dot(x, y, prec)
+                elif args.micro == "step":
+                    op.smoother_step(x, xv, wqr, wqq, r_next=y)
                 else:
                     op.apply(x, y, prec)
 
-            key = "%s/%d/%d/%d" % ("dslash_dot" if args.micro == "dslash_dot" else "dslash",
+            key = "%s/%d/%d/%d" % ({"dslash_dot": "dslash_dot", "step": "dslash_step"}.get(args.micro, "dslash"),
                                    m.api.PREC[prec], op.V, nrhs)
             if args.variant is not None:
                 ctx.tune_set(key, args.variant)
@@ -426,7 +446,7 @@ def micro(args):
             for _ in range(args.iters):
                 once()
             torch.cuda.synchronize()
-            q = ctx.profile_query("dslash_" + prec)
+            q = ctx.profile_query("dslash_step" if args.micro == "step" else "dslash_" + prec)
             ctx.profile(False)
             ms = q["ms"] / q["launches"]
             bl = q["bytes"] / q["launches"]
@@ -546,6 +566,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c4", choices=sorted(CONFIGS))
+    ap.add_argument("--smooth", type=int, default=8, help="fine-level smoothing steps of the timed form")
     ap.add_argument("--batch", type=int, nargs="+", default=None,
                     help="right-hand sides per batch on each level (default: the configuration's)")
     ap.add_argument("--form", default="mixed", choices=["mixed", "f64"])
@@ -554,7 +575,7 @@ def main():
     ap.add_argument("--learned", action="store_true", help="also measure the learned-preconditioner form")
     ap.add_argument("--net-widths", type=int, nargs="+", default=[4, 8, 8, 4])
     ap.add_argument("--net-steps", type=int, default=150)
-    ap.add_argument("--micro", choices=["dslash", "dslash_dot", "copy"])
+    ap.add_argument("--micro", choices=["dslash", "dslash_dot", "step", "copy"])
     ap.add_argument("--tune", action="store_true", help="micro: autotune the launch shape first")
     ap.add_argument("--variant", type=int, default=None, help="micro: pin this launch variant")
     ap.add_argument("--prec", default="f32", help="comma list of f64, f32, f16")

@@ -148,6 +148,24 @@ mgm_status mgm_operator_apply_dot(mgm_operator op, mgm_prec prec, const void* x_
                                   int32_t nrhs, void* ws_dev, size_t ws_bytes, void* yx_dev,
                                   void* yy_dev);
 
+/* One fused step of the FP16 minimal-residual smoother with the previous
+ * step's length (the MR smoother of the multigrid solver, Sec. 2.1's solver
+ * setting, as a Richardson step of lagged MR length): with
+ * omega_r = qr_prev_dev[r] / qq_prev_dev[r] (0 where qq_prev_dev[r] is 0) and
+ * q = D r (not stored), writes r_next = r - omega q, updates x += omega r in
+ * place, and yx_dev[r] = q_r^H r_r, yy_dev[r] = |q_r|^2 (FP64; q rounded to
+ * FP16 as if stored), which give the next step's length.  r, r_next and x
+ * are distinct FP16 dof-major (12, V, nrhs) complex-pair arrays; qr_prev /
+ * qq_prev may coincide with yx / yy (they are read first).  Workspace as
+ * mgm_operator_apply_dot with prec F16.  Errors: INVALID_ARG; SHAPE when no
+ * plane-marching tile fits the lattice and nrhs (mgm_operator_step_fusable);
+ * WORKSPACE; HIP. */
+mgm_status mgm_operator_smoother_step(mgm_operator op, const void* r_dev, void* r_next_dev, void* x_dev,
+                                      const void* qr_prev_dev, const void* qq_prev_dev, int32_t nrhs,
+                                      void* ws_dev, size_t ws_bytes, void* yx_dev, void* yy_dev);
+/* 1 when mgm_operator_smoother_step runs for this rhs count, else 0. */
+int32_t mgm_operator_step_fusable(mgm_operator op, int32_t nrhs);
+
 /* Number of lattice sites of the fine operator. */
 int64_t mgm_operator_sites(mgm_operator op);
 void mgm_operator_destroy(mgm_operator op);
@@ -452,7 +470,8 @@ mgm_status mgm_mlmc_allocate(int32_t nterms, const double* var, const double* co
  * stencil, transfers), off by default.  mgm_profile_query returns the number
  * of launches, their summed duration in ms and the summed algorithmic bytes
  * of kernel class `kclass` (0 fine dslash F64, 1 F32, 2 F16, 3 coarse stencil
- * F64, 4 coarse stencil F32, 5 coarse stencil BF16 MFMA, 6 restrict/prolong).
+ * F64, 4 coarse stencil F32, 5 coarse stencil BF16 MFMA, 6 restrict/prolong,
+ * 7 network layers, 8 fused FP16 smoother steps).
  * Synchronises. */
 mgm_status mgm_profile_enable(mgm_context ctx, int32_t on);
 mgm_status mgm_profile_reset(mgm_context ctx);

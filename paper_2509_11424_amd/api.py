@@ -23,7 +23,7 @@ OBS = {"trace": 0, "corr": 1, "loops": 2}
 DEC = {"plain": 0, "oblique": 1, "orthogonal": 2}
 EXPORT = {"agg_map": 0, "P": 1, "coarse": 2, "tv": 3}
 KCLASS = {"dslash_f64": 0, "dslash_f32": 1, "dslash_f16": 2, "coarse_f64": 3, "coarse_f32": 4,
-          "coarse_bf16": 5, "transfer": 6, "net": 7}
+          "coarse_bf16": 5, "transfer": 6, "net": 7, "dslash_step": 8}
 NET_MAX_LAYERS = 8
 STATUS = {0: "MGM_OK", -1: "MGM_ERR_INVALID_ARG", -2: "MGM_ERR_SHAPE", -3: "MGM_ERR_WORKSPACE",
           -4: "MGM_ERR_NOT_CONVERGED", -5: "MGM_ERR_RANK_DEFICIENT", -6: "MGM_ERR_NUMERIC",
@@ -144,6 +144,9 @@ _SIGS = [
     ("mgm_operator_dot_workspace_size", C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.POINTER(C.c_size_t)]),
     ("mgm_operator_apply_dot", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                          C.c_size_t, C.c_void_p, C.c_void_p]),
+    ("mgm_operator_smoother_step", C.c_int, [C.c_void_p] * 6 + [C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                                                C.c_void_p]),
+    ("mgm_operator_step_fusable", C.c_int32, [C.c_void_p, C.c_int32]),
     ("mgm_net_workspace_size", C.c_int, [C.c_void_p, C.POINTER(NetDesc), C.POINTER(C.c_size_t)]),
     ("mgm_net_create", C.c_int, [C.c_void_p, C.POINTER(NetDesc), C.c_void_p, C.c_size_t,
                                  C.POINTER(C.c_void_p)]),
@@ -315,6 +318,28 @@ class Operator:
                                             C.c_void_p(_ptr(ws)), ws.numel(), C.c_void_p(_ptr(yx)),
                                             C.c_void_p(_ptr(yy))))
         return y, yx, yy
+
+    def step_fusable(self, nrhs: int) -> bool:
+        return bool(lib().mgm_operator_step_fusable(self.h, nrhs))
+
+    def smoother_step(self, r, x, qr_prev, qq_prev, r_next=None):
+        """One fused FP16 smoother step (float16 pair tensors (12, V, nrhs, 2);
+        qr_prev complex128 / qq_prev float64 (nrhs,)): returns (r_next, q^H r,
+        |q|^2) and updates x in place."""
+        import torch
+        nrhs = r.shape[2]
+        if r_next is None:
+            r_next = torch.empty_like(r)
+        nb = C.c_size_t()
+        _check(lib().mgm_operator_dot_workspace_size(self.h, PREC["f16"], nrhs, C.byref(nb)))
+        ws = _empty_ws(nb.value, self.ctx.device)
+        yx = torch.empty(nrhs, dtype=torch.complex128, device=r.device)
+        yy = torch.empty(nrhs, dtype=torch.float64, device=r.device)
+        _check(lib().mgm_operator_smoother_step(self.h, *[C.c_void_p(_ptr(t)) for t in (r, r_next, x, qr_prev,
+                                                                                         qq_prev)],
+                                                nrhs, C.c_void_p(_ptr(ws)), ws.numel(), C.c_void_p(_ptr(yx)),
+                                                C.c_void_p(_ptr(yy))))
+        return r_next, yx, yy
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

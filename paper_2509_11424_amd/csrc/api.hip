@@ -303,6 +303,36 @@ mgm_status mgm_operator_apply_dot(mgm_operator op, mgm_prec prec, const void* x,
   API_END
 }
 
+mgm_status mgm_operator_smoother_step(mgm_operator op, const void* r_dev, void* r_next_dev, void* x_dev,
+                                      const void* qr_prev_dev, const void* qq_prev_dev, int32_t nrhs,
+                                      void* ws_dev, size_t ws_bytes, void* yx_dev, void* yy_dev) {
+  API_BEGIN
+  MGM_CHECK(op && r_dev && r_next_dev && x_dev && qr_prev_dev && qq_prev_dev && ws_dev && yx_dev && yy_dev,
+            MGM_ERR_INVALID_ARG, "NULL argument");
+  MGM_CHECK(nrhs >= 1 && nrhs <= 256, MGM_ERR_INVALID_ARG, "nrhs must be 1..256");
+  MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  MGM_CHECK(ws_bytes >= dot_ws_bytes(op->op, MGM_PREC_F16, nrhs), MGM_ERR_WORKSPACE, "workspace too small");
+  MGM_CHECK(op->op.step_fusable(MGM_PREC_F16, nrhs), MGM_ERR_SHAPE, "no plane-marching tile for this lattice and nrhs");
+  const int64_t nb = op->op.nblocks(MGM_PREC_F16, nrhs, true);
+  double2* part = (double2*)ws_dev;
+  Scratch sc;
+  sc.partial = part + (size_t)nb * 2 * nrhs;
+  sc.cap = (size_t)64 * 2 * nrhs;
+  const int64_t nrun = op->op.apply_step(MGM_PREC_F16, r_dev, r_next_dev, x_dev, (const double2*)qr_prev_dev,
+                                         (const double*)qq_prev_dev, nrhs, part);
+  b_finalize_dot_norm(op->ctx, sc, part, nrun, nrhs, (double2*)yx_dev, (double*)yy_dev);
+  API_END
+}
+
+int32_t mgm_operator_step_fusable(mgm_operator op, int32_t nrhs) {
+  if (!op || nrhs < 1 || nrhs > 256) return 0;
+  try {
+    return op->op.step_fusable(MGM_PREC_F16, nrhs) ? 1 : 0;
+  } catch (...) {
+    return 0;
+  }
+}
+
 int64_t mgm_operator_sites(mgm_operator op) { return op ? op->op.g.V : 0; }
 void mgm_operator_destroy(mgm_operator op) { delete op; }
 

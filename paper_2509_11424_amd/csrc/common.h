@@ -251,7 +251,8 @@ enum KClass {
   KC_COARSE_BF16 = 5,
   KC_TRANSFER = 6,
   KC_NET = 7,
-  KC_COUNT = 8
+  KC_DSLASH_STEP = 8,  // fused FP16 minimal-residual smoother step
+  KC_COUNT = 9
 };
 
 struct Profiler {

@@ -739,22 +739,36 @@ __device__ __forceinline__ void buf_clover(Rsrc rc, uint32_t plane_b, uint32_t v
 }
 
 // Launch: blockDim = X * TY * nbr (a multiple of 64, at most MAXT), grid =
-// (nrhs / nbr) * T * (Y / TY) * (Z / zs), dynamic LDS = 12 * (TY + 2) * X *
+// (nrhs / nbr) * T * (Y / TY) * (Z / zs), dynamic LDS = 2 * 12 * (TY + 2) * X *
 // nbr elements of P::S (at least the DOT reduction's 16 * 64 * 24 bytes);
 // nbr divides nrhs and 64; TY is even; 12 * V * nrhs spinor elements, the
 // links and the clover each below 4 GiB.
-template <class P, bool DOT, int TY, int MAXT>
+//
+// MR (with DOT): one step of the minimal-residual smoother with the step
+// length of the previous step (Richardson with lagged MR lengths).  `in`
+// holds r, `wqr`/`wqq` the dots of the previous step, omega = wqr / wqq per
+// rhs (0 where wqq is 0).  q = D r is not stored: the owner of a site
+// writes r - omega q to `out` and updates x += omega r in place in `xio`;
+// the dots are those of (q, r), which give the next step's length.  in, out
+// and xio are distinct arrays.
+template <class P, bool DOT, bool MR, int TY, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict__ out,
                                                        const typename P::S* __restrict__ in,
                                                        const typename P::S* __restrict__ U,
                                                        const typename P::RS* __restrict__ C, Geom g, int nrhs,
                                                        int nbr, int zs, int64_t nblocks,
-                                                       double2* __restrict__ dpart) {
+                                                       double2* __restrict__ dpart,
+                                                       typename P::S* __restrict__ xio,
+                                                       const double2* __restrict__ wqr,
+                                                       const double* __restrict__ wqq) {
   using R = typename P::R;
   using S = typename P::S;
   using IO = BufIO<P>;
+  static_assert(!MR || DOT, "the smoother step also produces the next dots");
   extern __shared__ __align__(16) unsigned char march_smem[];
-  S* pl = reinterpret_cast<S*>(march_smem);  // [12][TY + 2][X * nbr]
+  // two plane buffers [2][12][TY + 2][X * nbr]: step i reads buffer i % 2
+  // and stages the next plane into the other, so one barrier per step
+  S* pl = reinterpret_cast<S*>(march_smem);
   constexpr int kRows = TY + 2;
   const uint32_t V = (uint32_t)g.V, N = V * (uint32_t)nrhs;
   const uint32_t spb = N * IO::SB;   // bytes per spinor dof plane
@@ -786,13 +800,28 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
   const int hy0 = y0 == 0 ? g.Y - 1 : y0 - 1, hy1 = y0 + TY == g.Y ? 0 : y0 + TY;
   const uint32_t rowoff = (uint32_t)y * sy + xs;  // (x, y) part of a site index
   // LDS element of dof k, LDS row lr, column c
+  const int plane_elems = 12 * kRows * rowlen;
   auto lidx = [&](int k, int lr, int c) { return (k * kRows + lr) * rowlen + c; };
   // Halo rows: 12 dof x 2 rows = 24 row-planes; thread (yl, col) stages
   // row-plane q = yl + TY j (all q < 24) at its own column, i.e. dof
   // yl / 2 + (TY / 2) j of halo row yl % 2 (TY is even).
   const int hrow = yl & 1, hk0 = yl >> 1;
   const uint32_t hyoff = (uint32_t)(hrow ? hy1 : hy0) * sy;
-  auto stage_halo = [&](int zz) {
+  // smoother step: lagged step length and the x array (the descriptor
+  // aliases the input when unused)
+  const Rsrc rx = make_rsrc(MR ? (const void*)xio : (const void*)in, 12 * spb);
+  cx<R> om = {0, 0};
+  if (MR) {
+    const double d = wqq[r];
+    if (d > 0.0) om = {(R)(wqr[r].x / d), (R)(wqr[r].y / d)};
+  }
+  // x += omega r at one element of this block's own planes (r as loaded)
+  auto x_update = [&](uint32_t vo, uint32_t so, S rv) {
+    cx<R> xv = IO::cvt(IO::raw(rx, vo, so));
+    fma_(xv, om, IO::cvt(rv));
+    IO::st(rx, vo, so, xv);
+  };
+  auto stage_halo = [&](int zz, S* buf) {
     // the per-thread dof offset goes into the lane offset, the per-j one
     // into the uniform offset
     const uint32_t vo = (((uint32_t)zz * sz + (uint32_t)t * st + hyoff + xs) * nrhs + r) * IO::SB +
@@ -801,7 +830,7 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
     for (int j = 0; j < (24 + TY - 1) / TY; j++) {
       const int k = hk0 + (TY / 2) * j;
       if (24 % TY == 0 || k < 12)
-        pl[lidx(k, hrow ? kRows - 1 : 0, col)] = IO::raw(rin, vo, (uint32_t)((TY / 2) * j) * spb);
+        buf[lidx(k, hrow ? kRows - 1 : 0, col)] = IO::raw(rin, vo, (uint32_t)((TY / 2) * j) * spb);
     }
   };
   // The accumulator of a plane starts as the backward z-hop contribution of
@@ -820,8 +849,12 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
     hop_add<P>(2, false, (R)-0.5, gg, acc);
     const uint32_t s0 = (uint32_t)z0 * sz + (uint32_t)t * st + rowoff;
 #pragma unroll
-    for (int k = 0; k < 12; k++) pl[lidx(k, yl + 1, col)] = IO::raw(rin, (s0 * nrhs + r) * IO::SB, (uint32_t)k * spb);
-    stage_halo(z0);
+    for (int k = 0; k < 12; k++) {
+      const S rv = IO::raw(rin, (s0 * nrhs + r) * IO::SB, (uint32_t)k * spb);
+      pl[lidx(k, yl + 1, col)] = rv;
+      if (MR) x_update((s0 * nrhs + r) * IO::SB, (uint32_t)k * spb, rv);
+    }
+    stage_halo(z0, pl);
   }
   cx<double> dqr = {0, 0};
   double dqq = 0;
@@ -830,7 +863,9 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
     const int z = z0 + i;
     const int zp = z == g.Z - 1 ? 0 : z + 1;
     const uint32_t s = (uint32_t)z * sz + (uint32_t)t * st + rowoff;
-    __syncthreads();  // plane z staged
+    S* const cur = pl + (i & 1) * plane_elems;  // plane z
+    S* const nxt = pl + ((i & 1) ^ 1) * plane_elems;  // plane z + 1, staged during this step
+    __syncthreads();  // plane z staged; every read of the other buffer done
     // x and y hops from LDS
 #pragma unroll 1
     for (int hop = 0; hop < 4; hop++) {
@@ -849,7 +884,7 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
       }
       cx<R> ps[12], Um[3][3], gg[2][3];
 #pragma unroll
-      for (int k = 0; k < 12; k++) ps[k] = IO::cvt(pl[lidx(k, lrow, lcol)]);
+      for (int k = 0; k < 12; k++) ps[k] = IO::cvt(cur[lidx(k, lrow, lcol)]);
       buf_link<P>(ru, upb, mu, ls * IO::SB, Um);
       hop_half<P>(mu, fwd, ps, Um, gg);
       hop_add<P>(mu, fwd, (R)-0.5, gg, acc);
@@ -878,7 +913,7 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
     for (int chi = 0; chi < 2; chi++) {
       cx<R> p6[6], q6[6];
 #pragma unroll
-      for (int k = 0; k < 6; k++) p6[k] = IO::cvt(pl[lidx(6 * chi + k, yl + 1, col)]);
+      for (int k = 0; k < 6; k++) p6[k] = IO::cvt(cur[lidx(6 * chi + k, yl + 1, col)]);
       buf_clover<P>(rc, cpb, s * IO::RB, chi, p6, q6);
 #pragma unroll
       for (int k = 0; k < 6; k++) {
@@ -895,14 +930,25 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
       hop_half<P>(2, true, ps, Um, gg);
       hop_add<P>(2, true, (R)-0.5, gg, acc);
     }
-    // backward z hop of this plane (into the next one's accumulator), then
-    // the store; the fused dots take the rounded stored values
-    {
-      cx<R> pv[12], gg[2][3];
+    // stage the next plane (own rows from the registers, halo rows loaded)
+    if (i + 1 < zs) {
+      const uint32_t vn = (((uint32_t)zp * sz + (uint32_t)t * st + rowoff) * nrhs + r) * IO::SB;
 #pragma unroll
-      for (int k = 0; k < 12; k++) pv[k] = IO::cvt(pl[lidx(k, yl + 1, col)]);
+      for (int k = 0; k < 12; k++) {
+        nxt[lidx(k, yl + 1, col)] = nx[k];
+        if (MR) x_update(vn, (uint32_t)k * spb, nx[k]);
+      }
+      stage_halo(zp, nxt);
+    }
+    // backward z hop of this plane (into the next one's accumulator), then
+    // the store; the fused dots take the values of q rounded to the storage
+    // type
+    {
+      cx<R> gg[2][3];
       {
-        cx<R> Um[3][3];
+        cx<R> pv[12], Um[3][3];
+#pragma unroll
+        for (int k = 0; k < 12; k++) pv[k] = IO::cvt(cur[lidx(k, yl + 1, col)]);
         buf_link<P>(ru, upb, 2, s * IO::SB, Um);
         hop_half<P>(2, false, pv, Um, gg);
       }
@@ -911,12 +957,23 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
       R sqq = 0;           // accumulated over the march in FP64
 #pragma unroll
       for (int k = 0; k < 12; k++) {
-        IO::st(rout, vo, (uint32_t)k * spb, acc[k]);
+        const cx<R> pvk = IO::cvt(cur[lidx(k, yl + 1, col)]);  // centre, re-read from LDS
+        if (MR) {
+          // r - omega q (x + omega r was done when the plane was loaded)
+          cx<R> rn = pvk;
+          rn.re = fmar(-om.re, acc[k].re, rn.re);
+          rn.re = fmar(om.im, acc[k].im, rn.re);
+          rn.im = fmar(-om.re, acc[k].im, rn.im);
+          rn.im = fmar(-om.im, acc[k].re, rn.im);
+          IO::st(rout, vo, (uint32_t)k * spb, rn);
+        } else {
+          IO::st(rout, vo, (uint32_t)k * spb, acc[k]);
+        }
         if (DOT) {
           S st_;
           P::st(&st_, 0, acc[k]);
           const cx<R> os = P::ld(&st_, 0);
-          fmac_(sqr, os, pv[k]);
+          fmac_(sqr, os, pvk);
           sqq += os.re * os.re + os.im * os.im;
         }
       }
@@ -929,17 +986,12 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
       for (int k = 0; k < 12; k++) acc[k] = {0, 0};
       hop_add<P>(2, false, (R)-0.5, gg, acc);
     }
-    __syncthreads();  // every read of plane z done
-    if (i + 1 < zs) {
-#pragma unroll
-      for (int k = 0; k < 12; k++) pl[lidx(k, yl + 1, col)] = nx[k];
-      stage_halo(zp);
-    }
   }
   if (DOT) {
     // per-rhs block sums: lane % nbr is the rhs within the group (nbr divides
-    // 64); the LDS plane is free again after the last barrier.  Columns of
-    // the other groups' rhs get zeros.
+    // 64); the LDS planes are free after this barrier.  Columns of the other
+    // groups' rhs get zeros.
+    __syncthreads();
     for (int off = 32; off >= nbr; off >>= 1) {
       dqr.re += __shfl_xor(dqr.re, off, 64);
       dqr.im += __shfl_xor(dqr.im, off, 64);
@@ -1080,7 +1132,7 @@ static const MarchShape kMarchShapes[] = {
     {4, 8, 4},  {4, 8, 2},  {16, 16, 1}, {16, 8, 1}, {8, 8, 1},  {4, 8, 1},  {2, 8, 8}};
 
 static size_t march_lds(const Geom& g, mgm_prec p, const MarchShape& m, bool dot) {
-  size_t b = (size_t)12 * (m.ty + 2) * g.X * m.nbr * prec_bytes(p);
+  size_t b = (size_t)2 * 12 * (m.ty + 2) * g.X * m.nbr * prec_bytes(p);  // two plane buffers
   if (dot) b = std::max(b, (size_t)16 * 64 * (sizeof(double2) + sizeof(double)));
   return b;
 }
@@ -1097,38 +1149,51 @@ static bool march_ok(const FineOp& op, mgm_prec p, int nrhs, const MarchShape& m
   return march_lds(g, p, m, dot) <= op.ctx->max_lds;
 }
 
-template <class P, bool DOT, int TY>
+// Extra arrays of the smoother-step mode (all null otherwise).
+struct MrArgs {
+  void* x = nullptr;
+  const double2* qr = nullptr;
+  const double* qq = nullptr;
+};
+
+template <class P, bool DOT, bool MR, int TY>
 static void launch_march_p(const FineOp& op, const typename P::S* U, const typename P::RS* C, const void* x,
                            void* y, int nrhs, const MarchShape& m, int64_t nb, int threads, size_t lds,
-                           double2* dpart) {
-  auto* k = k_dslash_march<P, DOT, TY, 1024>;
+                           double2* dpart, const MrArgs& mr) {
+  using S = typename P::S;
+  auto* k = k_dslash_march<P, DOT, MR, TY, 1024>;
   if (lds > 65536)
     MGM_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(threads), lds, op.ctx->stream, (typename P::S*)y,
-                     (const typename P::S*)x, U, C, op.g, nrhs, m.nbr, m.zs, nb, dpart);
+  hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(threads), lds, op.ctx->stream, (S*)y, (const S*)x, U, C, op.g,
+                     nrhs, m.nbr, m.zs, nb, dpart, (S*)mr.x, mr.qr, mr.qq);
   MGM_LAUNCH_CHECK();
 }
 
 // Returns the number of blocks (partial-sum columns of the reducing variant).
-template <bool DOT>
+template <bool DOT, bool MR>
 static int64_t launch_march(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart,
-                            const MarchShape& m) {
+                            const MarchShape& m, const MrArgs& mr = MrArgs()) {
   const Geom& g = op.g;
   const int threads = g.X * m.ty * m.nbr;
   const int64_t nb = (int64_t)(nrhs / m.nbr) * g.T * (g.Y / m.ty) * (g.Z / m.zs);
   const size_t lds = march_lds(g, p, m, DOT);
-#define MGM_MARCH_TY(PT, UU, CC)                                                                  \
-  switch (m.ty) {                                                                                 \
-    case 2: launch_march_p<PT, DOT, 2>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart); break;   \
-    case 4: launch_march_p<PT, DOT, 4>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart); break;   \
-    case 8: launch_march_p<PT, DOT, 8>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart); break;   \
-    case 16: launch_march_p<PT, DOT, 16>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart); break; \
-    default: throw Error(MGM_ERR_SHAPE, "unsupported plane-marching tile");                       \
+#define MGM_MARCH_TY(PT, UU, CC)                                                                           \
+  switch (m.ty) {                                                                                          \
+    case 2: launch_march_p<PT, DOT, MR, 2>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break;   \
+    case 4: launch_march_p<PT, DOT, MR, 4>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break;   \
+    case 8: launch_march_p<PT, DOT, MR, 8>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break;   \
+    case 16: launch_march_p<PT, DOT, MR, 16>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break; \
+    default: throw Error(MGM_ERR_SHAPE, "unsupported plane-marching tile");                                \
   }
-  if (p == MGM_PREC_F32) {
-    MGM_MARCH_TY(F32, op.U32, op.C32)
-  } else {
+  if constexpr (MR) {
+    MGM_CHECK(p == MGM_PREC_F16, MGM_ERR_INVALID_ARG, "the fused smoother step runs in FP16 storage");
     MGM_MARCH_TY(F16, op.U16, op.C16)
+  } else {
+    if (p == MGM_PREC_F32) {
+      MGM_MARCH_TY(F32, op.U32, op.C32)
+    } else {
+      MGM_MARCH_TY(F16, op.U16, op.C16)
+    }
   }
 #undef MGM_MARCH_TY
   return nb;
@@ -1159,7 +1224,7 @@ static int64_t launch_dslash(const FineOp& op, mgm_prec p, const void* x, void* 
     MGM_CHECK(v >= 0 && v < nsite + (int)shapes.size(), MGM_ERR_INVALID_ARG,
               "dslash launch variant out of range for this shape");
     if (v >= nsite) {
-      nb = launch_march<DOT>(op, p, x, y, nrhs, dpart, shapes[v - nsite]);
+      nb = launch_march<DOT, false>(op, p, x, y, nrhs, dpart, shapes[v - nsite]);
       return;
     }
     const int rb = v < 2 ? rb0 : 3 - rb0;
@@ -1188,6 +1253,39 @@ int64_t FineOp::apply_dot(mgm_prec p, const void* x, void* y, int nrhs, double2*
   MGM_CHECK(nrhs >= 1 && nrhs <= 256, MGM_ERR_INVALID_ARG, "fused dslash reduction supports 1..256 rhs");
   ProfScope ps(ctx, kclass_of(p), bytes(p, nrhs));
   return launch_dslash<true>(*this, p, x, y, nrhs, dpart);
+}
+
+bool FineOp::step_fusable(mgm_prec p, int nrhs) const {
+  if (p != MGM_PREC_F16) return false;
+  for (const MarchShape& m : kMarchShapes)
+    if (march_ok(*this, p, nrhs, m, true)) return true;
+  return false;
+}
+
+double FineOp::step_bytes(mgm_prec p, int nrhs) const {
+  // the dslash (r in, r' out in place of q), plus x read and written
+  return bytes(p, nrhs) + 2.0 * 12.0 * (double)g.V * nrhs * (double)prec_bytes(p);
+}
+
+int64_t FineOp::apply_step(mgm_prec p, const void* r, void* r_next, void* x, const double2* qr, const double* qq,
+                           int nrhs, double2* dpart) const {
+  MGM_CHECK(step_fusable(p, nrhs), MGM_ERR_SHAPE, "no plane-marching tile for the fused smoother step");
+  MGM_CHECK(r != r_next && r != x && r_next != x, MGM_ERR_INVALID_ARG, "fused smoother step needs distinct arrays");
+  std::vector<MarchShape> shapes;
+  for (const MarchShape& m : kMarchShapes)
+    if (march_ok(*this, p, nrhs, m, true)) shapes.push_back(m);
+  MrArgs mr;
+  mr.x = x;
+  mr.qr = qr;
+  mr.qq = qq;
+  const std::string key = "dslash_step/" + std::to_string((int)p) + "/" + std::to_string(g.V) + "/" + std::to_string(nrhs);
+  ProfScope ps(ctx, KC_DSLASH_STEP, step_bytes(p, nrhs));
+  int64_t nb = 0;
+  ctx->choose(key, (int)shapes.size(), [&](int v) {
+    MGM_CHECK(v >= 0 && v < (int)shapes.size(), MGM_ERR_INVALID_ARG, "fused smoother launch variant out of range");
+    nb = launch_march<true, true>(*this, p, r, r_next, nrhs, dpart, shapes[v], mr);
+  });
+  return nb;
 }
 
 }  // namespace mgm

@@ -38,6 +38,15 @@ struct FineOp {
   int64_t nblocks(mgm_prec p, int nrhs, bool dot) const;
   // algorithmic bytes of one application (fields once, spinors in and out)
   double bytes(mgm_prec p, int nrhs) const;
+  // One fused minimal-residual smoother step with the previous step's
+  // length (FP16 storage, plane-marching shapes only): with omega = qr / qq
+  // per rhs (0 where qq is 0) and q = D r (not stored), writes
+  // r_next = r - omega q, updates x += omega r in place and writes the block
+  // partials of q^H r and |q|^2 to dpart; returns their block count.
+  bool step_fusable(mgm_prec p, int nrhs) const;
+  int64_t apply_step(mgm_prec p, const void* r, void* r_next, void* x, const double2* qr, const double* qq,
+                     int nrhs, double2* dpart) const;
+  double step_bytes(mgm_prec p, int nrhs) const;
 };
 
 }  // namespace mgm

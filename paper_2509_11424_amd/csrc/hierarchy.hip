@@ -25,6 +25,8 @@ static void carve_smooth16(Arena& a, LevelWS& w, int64_t n, int nmax) {
   w.n2b = a.take_n<double>(nmax);
   w.qr = a.take_n<double2>(nmax);
   w.qq = a.take_n<double>(nmax);
+  w.qr2 = a.take_n<double2>(nmax);
+  w.qq2 = a.take_n<double>(nmax);
   w.mask = a.take_n<double>(nmax);
 }
 

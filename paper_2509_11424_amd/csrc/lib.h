@@ -38,6 +38,8 @@ struct LevelWS {
   double* n2b = nullptr;
   double2* qr = nullptr;   // [nmax]
   double* qq = nullptr;
+  double2* qr2 = nullptr;  // second pair (fused FP16 smoother: previous step's dots)
+  double* qq2 = nullptr;
   double* mask = nullptr;  // [nmax] per-rhs scale factors
 };
 

@@ -12,6 +12,7 @@
 // * Mixed precision: FP64 defect correction r = b - D x around an FP32
 //   FGMRES whose V-cycle runs on FP32 vectors (optionally FP16 fine-level
 //   smoothing and BF16-MFMA coarse stencils).
+#include <utility>
 #include "lib.h"
 #include "net.h"
 
@@ -25,6 +26,30 @@ static void op_apply(Hier& H, int l, mgm_prec p, bool inner, const SolveCfg& cfg
     H.A[l].apply(MGM_PREC_BF16, x, y, nrhs);
   else
     H.apply(l, p, x, y, nrhs);
+}
+
+// FP16 fine-level smoother, fused form: the first step is the exact MR step
+// (dslash with dots, then the update); every later step is one fused kernel
+// that applies D, moves r and x by the previous step's MR length and forms
+// the dots that give the next length (FineOp::apply_step).  r ping-pongs
+// between b (the caller's scratch input, overwritten) and w.rho.
+static void mr_smooth_fused(Hier& H, Vec b, Vec y, int nu) {
+  LevelWS& w = H.ws16[0];
+  Context* c = H.ctx;
+  b_zero(c, y);
+  int64_t nb = H.fine->apply_dot(MGM_PREC_F16, b.p, w.q, b.nrhs, H.dpart);
+  b_finalize_dot_norm(c, H.scratch, H.dpart, nb, b.nrhs, w.qr, w.qq);
+  b_mr_update(c, w.qr, w.qq, b, b.with(w.q), y);
+  void* r = b.p;
+  void* r_next = w.rho;
+  for (int i = 1; i < nu; i++) {
+    double2* qr_prev = (i & 1) ? w.qr : w.qr2;
+    double* qq_prev = (i & 1) ? w.qq : w.qq2;
+    nb = H.fine->apply_step(MGM_PREC_F16, r, r_next, y.p, qr_prev, qq_prev, b.nrhs, H.dpart);
+    if (i + 1 < nu)
+      b_finalize_dot_norm(c, H.scratch, H.dpart, nb, b.nrhs, (i & 1) ? w.qr2 : w.qr, (i & 1) ? w.qq2 : w.qq);
+    std::swap(r, r_next);
+  }
 }
 
 static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const SolveCfg& cfg) {
@@ -61,7 +86,10 @@ static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg
     b_norm2(c, H.scratch, r, w.n2a);
     b_unit_scales(c, w.n2a, (double)r.nsite * r.dof, r.nrhs, w.mask, w.n2b);
     b_copy_scaled(c, r16, r, w.mask);
-    mr_smooth(H, 0, MGM_PREC_F16, r16, y16, cfg.smooth, cfg);
+    if (cfg.smooth >= 2 && w.qr2 != nullptr && H.fine->step_fusable(MGM_PREC_F16, r.nrhs))
+      mr_smooth_fused(H, r16, y16, cfg.smooth);
+    else
+      mr_smooth(H, 0, MGM_PREC_F16, r16, y16, cfg.smooth, cfg);
     b_copy_scaled(c, e, y16, w.n2b);
     return;
   }

@@ -185,3 +185,54 @@ def test_march_full_size_f16_eight_rhs(ctx):
     ctx.tune_set(key, 0)
     del x, xc, ref, y0, y0c
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("lname", ["8x16x8x4", "16x4x16x6"])
+@pytest.mark.parametrize("nrhs", [16, 4])
+def test_fused_smoother_step(ctx, lats, lname, nrhs):
+    """mgm_operator_smoother_step against its definition, built from the
+    reducing dslash: q = D r (variant 0), r' = r - omega q, x' = x + omega r
+    with omega = qr / qq of the previous step (0 where qq = 0), and the dots of
+    (q, r).  r' and x' within one FP16 ulp plus omega times the FP16 rounding of
+    q (the kernel uses q before rounding); dots within 1e-5 of those of the
+    rounded q (the two kernels sum in other orders)."""
+    import torch
+    lat = lats[lname]
+    op = lat.op
+    assert op.step_fusable(nrhs)
+    g = torch.Generator(device="cuda:0").manual_seed(90 + nrhs)
+    shape = (12, lat.V, nrhs, 2)
+    r, x = (torch.randn(shape, generator=g, device="cuda:0").to(torch.float16) for _ in range(2))
+    qr = torch.complex(torch.randn(nrhs, generator=g, device="cuda:0", dtype=torch.float64),
+                       torch.randn(nrhs, generator=g, device="cuda:0", dtype=torch.float64)) * 0.05
+    qq = torch.rand(nrhs, generator=g, device="cuda:0", dtype=torch.float64) + 0.5
+    qq[0] = 0.0  # omega = 0 for the first rhs
+    x0 = x.clone()
+    rn, yx, yy = op.smoother_step(r, x, qr, qq)
+    q, yx_ref, yy_ref = op.apply_dot(r, prec="f16")
+    torch.cuda.synchronize()
+
+    def c(t):
+        return torch.view_as_complex(t.float().contiguous()).to(torch.complex128)
+
+    om = torch.where(qq > 0, qr / qq.clamp_min(1e-300), torch.zeros_like(qr))
+    want_r = c(r) - om * c(q)
+    want_x = c(x0) + om * c(r)
+    slack = om.abs() * c(q).abs() * 2.0 ** -10
+    assert torch.all((c(rn) - want_r).abs() <= 2.0 ** -10 * want_r.abs() + slack + 2.0 ** -14 + 1e-6)
+    assert torch.all((c(x) - want_x).abs() <= 2.0 ** -10 * want_x.abs() + 2.0 ** -14 + 1e-6)
+    assert torch.equal(rn[:, :, 0], r[:, :, 0]) and torch.equal(x[:, :, 0], x0[:, :, 0])
+    assert torch.all((yx - yx_ref).abs() <= 1e-5 * yy_ref.sqrt() * c(r).abs().pow(2).sum(dim=(0, 1)).sqrt())
+    assert torch.all((yy - yy_ref).abs() <= 1e-5 * yy_ref)
+
+
+def test_fused_smoother_step_refuses_lattice_without_tile(ctx):
+    import torch
+    import paper_2509_11424_amd as m
+    U = gauge_field((4, 4, 4, 8), 0.6, 43)
+    op = m.Operator(ctx, U, 0.03, 1.0)
+    assert not op.step_fusable(4)
+    t = torch.zeros((12, op.V, 4, 2), dtype=torch.float16, device="cuda:0")
+    z = torch.zeros(4, dtype=torch.complex128, device="cuda:0")
+    with pytest.raises(RuntimeError, match="SHAPE"):
+        op.smoother_step(t, t.clone(), z, torch.ones(4, dtype=torch.float64, device="cuda:0"))
