@@ -153,8 +153,8 @@ mgm_status mgm_operator_apply_dot(mgm_operator op, mgm_prec prec, const void* x_
  * setting, as a Richardson step of lagged MR length): with
  * omega_r = qr_prev_dev[r] / qq_prev_dev[r] (0 where qq_prev_dev[r] is 0) and
  * q = D r (not stored), writes r_next = r - omega q, updates x += omega r in
- * place, and yx_dev[r] = q_r^H r_r, yy_dev[r] = |q_r|^2 (FP64; q rounded to
- * FP16 as if stored), which give the next step's length.  r, r_next and x
+ * place, and yx_dev[r] = q_r^H r_r, yy_dev[r] = |q_r|^2 (FP64 sums of the
+ * FP32 q), which give the next step's length.  r, r_next and x
  * are distinct FP16 dof-major (12, V, nrhs) complex-pair arrays; qr_prev /
  * qq_prev may coincide with yx / yy (they are read first).  Workspace as
  * mgm_operator_apply_dot with prec F16.  Errors: INVALID_ARG; SHAPE when no

@@ -749,7 +749,8 @@ __device__ __forceinline__ void buf_clover(Rsrc rc, uint32_t plane_b, uint32_t v
 // holds r, `wqr`/`wqq` the dots of the previous step, omega = wqr / wqq per
 // rhs (0 where wqq is 0).  q = D r is not stored: the owner of a site
 // writes r - omega q to `out` and updates x += omega r in place in `xio`;
-// the dots are those of (q, r), which give the next step's length.  in, out
+// the dots are those of (q, r) (q unrounded), which give the next step's
+// length.  in, out
 // and xio are distinct arrays.
 template <class P, bool DOT, bool MR, int TY, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict__ out,
@@ -970,9 +971,14 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
           IO::st(rout, vo, (uint32_t)k * spb, acc[k]);
         }
         if (DOT) {
-          S st_;
-          P::st(&st_, 0, acc[k]);
-          const cx<R> os = P::ld(&st_, 0);
+          // q as stored (rounded to the storage type); in the smoother step q
+          // is not stored and enters unrounded
+          cx<R> os = acc[k];
+          if (!MR) {
+            S st_;
+            P::st(&st_, 0, acc[k]);
+            os = P::ld(&st_, 0);
+          }
           fmac_(sqr, os, pvk);
           sqq += os.re * os.re + os.im * os.im;
         }

@@ -194,8 +194,10 @@ def test_fused_smoother_step(ctx, lats, lname, nrhs):
     reducing dslash: q = D r (variant 0), r' = r - omega q, x' = x + omega r
     with omega = qr / qq of the previous step (0 where qq = 0), and the dots of
     (q, r).  r' and x' within one FP16 ulp plus omega times the FP16 rounding of
-    q (the kernel uses q before rounding); dots within 1e-5 of those of the
-    rounded q (the two kernels sum in other orders)."""
+    q (the kernel uses q before rounding); dots within 1e-4 of those of the
+    rounded q (the kernel sums the unrounded q, in another order: the FP16
+    rounding of q, 2^-11 per element, averages to a few 1e-6 over the
+    lattice)."""
     import torch
     lat = lats[lname]
     op = lat.op
@@ -222,8 +224,8 @@ def test_fused_smoother_step(ctx, lats, lname, nrhs):
     assert torch.all((c(rn) - want_r).abs() <= 2.0 ** -10 * want_r.abs() + slack + 2.0 ** -14 + 1e-6)
     assert torch.all((c(x) - want_x).abs() <= 2.0 ** -10 * want_x.abs() + 2.0 ** -14 + 1e-6)
     assert torch.equal(rn[:, :, 0], r[:, :, 0]) and torch.equal(x[:, :, 0], x0[:, :, 0])
-    assert torch.all((yx - yx_ref).abs() <= 1e-5 * yy_ref.sqrt() * c(r).abs().pow(2).sum(dim=(0, 1)).sqrt())
-    assert torch.all((yy - yy_ref).abs() <= 1e-5 * yy_ref)
+    assert torch.all((yx - yx_ref).abs() <= 1e-4 * yy_ref.sqrt() * c(r).abs().pow(2).sum(dim=(0, 1)).sqrt())
+    assert torch.all((yy - yy_ref).abs() <= 1e-4 * yy_ref)
 
 
 def test_fused_smoother_step_refuses_lattice_without_tile(ctx):
