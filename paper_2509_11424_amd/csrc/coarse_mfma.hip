@@ -197,31 +197,32 @@ __global__ __launch_bounds__(256) void k_coarse_mfma4(const typename M::C2* __re
   }
 }
 
-template <int MT>
+template <int MT, int NT>
 __global__ __launch_bounds__(256) void k_coarse_mfma_bf16(const float2* __restrict__ x, float2* __restrict__ y,
                                                          const uint16_t* __restrict__ Ap, LGeom g, int d,
                                                          int nrhs, int ntr, int wpb) {
   // K chunks of 16 = ceil(d / 16) = MT: the chunk loop unrolls completely so
   // every fragment load of a direction is in flight at once
   constexpr int KC = MT;
-  // one workgroup per site and group of wpb 16-rhs tiles (one wave each):
-  // the tiles of a site stream the same A fragments through the CU's caches
-  // at the same time
+  // one workgroup per site and group of wpb waves, each wave NT consecutive
+  // 16-rhs tiles: a wave loads every A fragment once for its NT tiles, and
+  // the waves of a site stream the same fragments through the CU's caches
   const int64_t s = blockIdx.x;
-  const int nt = blockIdx.y * wpb + (threadIdx.x >> 6);
+  const int nt0 = (blockIdx.y * wpb + (threadIdx.x >> 6)) * NT;
   const int lane = threadIdx.x & 63;
-  if (nt >= ntr) return;
+  if (nt0 >= ntr) return;
   const int n = lane & 15, kq = lane >> 4;
-  const int r = nt * 16 + n;
   const int64_t V = g.V;
   int c[4];
   coords_c(g, s, c);
-  f4_t yr[MT], yi[MT];
+  f4_t yr[NT][MT], yi[NT][MT];
 #pragma unroll
-  for (int mt = 0; mt < MT; mt++) {
-    yr[mt] = (f4_t){0, 0, 0, 0};
-    yi[mt] = (f4_t){0, 0, 0, 0};
-  }
+  for (int t = 0; t < NT; t++)
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++) {
+      yr[t][mt] = (f4_t){0, 0, 0, 0};
+      yi[t][mt] = (f4_t){0, 0, 0, 0};
+    }
   const uint16_t* As = Ap + (int64_t)s * 9 * KC * MT * 512 + lane * 4;
 #pragma unroll 1
   for (int dir = 0; dir < 9; dir++) {
@@ -229,36 +230,48 @@ __global__ __launch_bounds__(256) void k_coarse_mfma_bf16(const float2* __restri
     const uint16_t* Ad = As + (int64_t)dir * KC * MT * 512;
 #pragma unroll
     for (int kc = 0; kc < KC; kc++) {
-      s4_t br, bi;
-#pragma unroll
-      for (int el = 0; el < 4; el++) {
-        const int k = 16 * kc + 4 * kq + el;
-        float2 xv = make_float2(0.f, 0.f);
-        if (k < d && r < nrhs) xv = x[((int64_t)k * V + sn) * nrhs + r];
-        br[el] = (short)bf16_rne(xv.x);
-        bi[el] = (short)bf16_rne(xv.y);
-      }
+      s4_t ar[MT], ai[MT], nai[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; mt++) {
         const uint16_t* f = Ad + (int64_t)(kc * MT + mt) * 512;
-        const s4_t ar = *(const s4_t*)f;
-        const s4_t ai = *(const s4_t*)(f + 256);
-        const s4_t nai = ai ^ (s4_t){(short)0x8000, (short)0x8000, (short)0x8000, (short)0x8000};
-        yr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, br, yr[mt], 0, 0, 0);
-        yr[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nai, bi, yr[mt], 0, 0, 0);
-        yi[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bi, yi[mt], 0, 0, 0);
-        yi[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, br, yi[mt], 0, 0, 0);
+        ar[mt] = *(const s4_t*)f;
+        ai[mt] = *(const s4_t*)(f + 256);
+        nai[mt] = ai[mt] ^ (s4_t){(short)0x8000, (short)0x8000, (short)0x8000, (short)0x8000};
+      }
+#pragma unroll
+      for (int t = 0; t < NT; t++) {
+        const int r = (nt0 + t) * 16 + n;
+        s4_t br, bi;
+#pragma unroll
+        for (int el = 0; el < 4; el++) {
+          const int k = 16 * kc + 4 * kq + el;
+          float2 xv = make_float2(0.f, 0.f);
+          if (k < d && r < nrhs) xv = x[((int64_t)k * V + sn) * nrhs + r];
+          br[el] = (short)bf16_rne(xv.x);
+          bi[el] = (short)bf16_rne(xv.y);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; mt++) {
+          yr[t][mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar[mt], br, yr[t][mt], 0, 0, 0);
+          yr[t][mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nai[mt], bi, yr[t][mt], 0, 0, 0);
+          yi[t][mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar[mt], bi, yi[t][mt], 0, 0, 0);
+          yi[t][mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai[mt], br, yi[t][mt], 0, 0, 0);
+        }
       }
     }
   }
-  if (r < nrhs) {
 #pragma unroll
-    for (int mt = 0; mt < MT; mt++)
+  for (int t = 0; t < NT; t++) {
+    const int r = (nt0 + t) * 16 + n;
+    if (r < nrhs) {
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
-        const int i = 16 * mt + 4 * kq + j;
-        if (i < d) y[((int64_t)i * V + s) * nrhs + r] = make_float2(yr[mt][j], yi[mt][j]);
-      }
+      for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int i = 16 * mt + 4 * kq + j;
+          if (i < d) y[((int64_t)i * V + s) * nrhs + r] = make_float2(yr[t][mt][j], yi[t][mt][j]);
+        }
+    }
   }
 }
 
@@ -331,12 +344,40 @@ void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs) 
   MGeo m = mgeo(A.d);
   const int ntr = (nrhs + 15) / 16;
   ProfScope ps(A.ctx, KC_COARSE_BF16, A.bytes(MGM_PREC_BF16, nrhs));
+  // shapes: one tile per wave with 4 / 2 / 1 waves per workgroup, then two
+  // and four tiles per wave (fewer A fragment loads per rhs)
+  struct Shape {
+    int wpb, nt;
+  };
+  std::vector<Shape> shapes;
+  for (int v = 0; v < wpb_count(ntr); v++) shapes.push_back({wpb_of(ntr, v), 1});
+  if (ntr >= 2) shapes.push_back({1, 2});
+  if (ntr >= 4) shapes.push_back({2, 2});
+  if (ntr >= 4 && m.MT <= 3) shapes.push_back({1, 4});
+  if (ntr >= 8 && m.MT <= 3) shapes.push_back({2, 4});
   A.ctx->choose("coarsebf16/" + std::to_string(A.g.V) + "/" + std::to_string(A.d) + "/" + std::to_string(nrhs),
-                wpb_count(ntr), [&](int v) {
-                  const int wpb = wpb_of(ntr, v);
-                  const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + wpb - 1) / wpb)), tb(64 * wpb);
-                  MT_DISPATCH(m.MT, hipLaunchKernelGGL(k_coarse_mfma_bf16<MTc>, nb, tb, 0, A.ctx->stream, x, y,
-                                                       (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb));
+                (int)shapes.size(), [&](int v) {
+                  MGM_CHECK(v >= 0 && v < (int)shapes.size(), MGM_ERR_INVALID_ARG,
+                            "coarse launch variant out of range");
+                  const int wpb = shapes[v].wpb, tpw = shapes[v].nt;
+                  const int groups = (ntr + tpw - 1) / tpw;
+                  const dim3 nb((unsigned)A.g.V, (unsigned)((groups + wpb - 1) / wpb)), tb(64 * wpb);
+                  if (tpw == 1) {
+                    MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma_bf16<MTc, 1>), nb, tb, 0, A.ctx->stream, x,
+                                                         y, (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb));
+                  } else if (tpw == 2) {
+                    MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma_bf16<MTc, 2>), nb, tb, 0, A.ctx->stream, x,
+                                                         y, (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb));
+                  } else {
+                    switch (m.MT) {
+                      case 1: hipLaunchKernelGGL((k_coarse_mfma_bf16<1, 4>), nb, tb, 0, A.ctx->stream, x, y,
+                                                 (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb); break;
+                      case 2: hipLaunchKernelGGL((k_coarse_mfma_bf16<2, 4>), nb, tb, 0, A.ctx->stream, x, y,
+                                                 (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb); break;
+                      default: hipLaunchKernelGGL((k_coarse_mfma_bf16<3, 4>), nb, tb, 0, A.ctx->stream, x, y,
+                                                  (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb); break;
+                    }
+                  }
                   MGM_LAUNCH_CHECK();
                 });
 }

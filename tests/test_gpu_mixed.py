@@ -28,6 +28,7 @@ def three():
 
     p = P()
     ctx = m.Context(0)
+    p.ctx = ctx
     p.U = gauge_field((4, 4, 4, 8), 0.6, 31)
     p.op = m.Operator(ctx, p.U, 0.05, 1.0)
     p.h = m.Hierarchy(p.op, [(2, 2, 2, 2), (1, 1, 1, 2)], [8, 8], seed=17, max_nrhs=8, restart=20, mixed=2)
@@ -55,6 +56,39 @@ def test_coarse_stencil_precisions(three, prec, bound):
             xg = xg.to(torch.complex64)
         y = p.h.apply_prec(l, xg, prec).to(torch.complex128)
         assert rel(from_gpu(y).reshape(5, -1), want) < bound, (l, prec)
+
+
+def test_coarse_bf16_launch_shapes_agree(three):
+    """Every launch shape of the BF16 MFMA stencil (waves per workgroup, 16-rhs
+    tiles per wave) on a ragged rhs count (70 = 4 x 16 + 6): each tile runs the
+    same MFMA sequence in every shape, so the results are bitwise equal; all
+    within the BF16 bound of the oracle."""
+    import torch
+    p = three
+    nrhs = 70
+    for l in (1, 2):
+        s, d, n = p.h.level_info(l)
+        x = _rand(s, d, nrhs, 10 + l)
+        want = p.oh.ops[l].matvec(x.reshape(nrhs, -1))
+        xg = to_gpu(x).to(torch.complex64)
+        key = "coarsebf16/%d/%d/%d" % (s, d, nrhs)
+        p.ctx.autotune(True)
+        try:
+            p.h.apply_prec(l, xg, "bf16")
+        finally:
+            p.ctx.autotune(False)
+        torch.cuda.synchronize()
+        nvar = len(p.ctx.tune_report()[key][1])
+        assert nvar >= 5  # three workgroup sizes, then two and four tiles per wave
+        p.ctx.tune_set(key, 0)
+        y0 = p.h.apply_prec(l, xg, "bf16")
+        for v in range(1, nvar):
+            p.ctx.tune_set(key, v)
+            y = p.h.apply_prec(l, xg, "bf16")
+            torch.cuda.synchronize()
+            assert torch.equal(y, y0), (l, v)
+        p.ctx.tune_set(key, 0)
+        assert rel(from_gpu(y0.to(torch.complex128)).reshape(nrhs, -1), want) < 2e-2
 
 
 def test_fine_operator_f16_through_hierarchy(three):
