@@ -262,6 +262,15 @@ mgm_status mgm_prolong(mgm_hierarchy h, int32_t level, const void* x_dev, void* 
                        int32_t nrhs);
 mgm_status mgm_project_out(mgm_hierarchy h, int32_t level, const void* x_dev, void* y_dev,
                            int32_t nrhs);
+/* Restriction and prolongation (Sec. 2.2: y_c = P_l^H x, y = P_l x_c) in
+ * precision `prec`: F64 as mgm_restrict / mgm_prolong, or F32 (float complex
+ * dof-major vectors, P_l stored in FP16, FP32 arithmetic; the transfers of
+ * the mixed V-cycle, present only in hierarchies built with mixed != 0).
+ * Other precisions return MGM_ERR_INVALID_ARG. */
+mgm_status mgm_restrict_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const void* x_dev,
+                             void* y_dev, int32_t nrhs);
+mgm_status mgm_prolong_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const void* x_dev,
+                            void* y_dev, int32_t nrhs);
 
 /* ------------------------------------------------------------------ solve */
 

@@ -129,6 +129,8 @@ _SIGS = [
     ("mgm_restrict", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     ("mgm_prolong", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     ("mgm_project_out", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("mgm_restrict_prec", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("mgm_prolong_prec", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_void_p, C.c_void_p, C.c_int32]),
     ("mgm_solve", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(SolveDesc), C.c_void_p, C.c_void_p,
                             C.c_int32, C.POINTER(SolveStats)]),
     ("mgm_estimate_sizes_query", C.c_int, [C.c_void_p, C.POINTER(EstimateDesc),
@@ -432,10 +434,10 @@ class Hierarchy:
                                           out.nbytes))
         return out
 
-    def _vec(self, level: int, nrhs: int):
+    def _vec(self, level: int, nrhs: int, dtype=None):
         import torch
         s, d, _ = self.level_info(level)
-        return torch.empty((d, s, nrhs), dtype=torch.complex128, device="cuda:%d" % self.ctx.device)
+        return torch.empty((d, s, nrhs), dtype=dtype or torch.complex128, device="cuda:%d" % self.ctx.device)
 
     def apply(self, level: int, x):
         y = self._vec(level, x.shape[2])
@@ -451,14 +453,25 @@ class Hierarchy:
                                           C.c_void_p(_ptr(y)), x.shape[2]))
         return y
 
-    def restrict(self, level: int, x):
-        y = self._vec(level + 1, x.shape[2])
-        _check(lib().mgm_restrict(self.h, level, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)), x.shape[2]))
+    def restrict(self, level: int, x, prec: str = "f64"):
+        """y_c = P^H x; f64: complex128 vectors, f32: complex64 vectors with
+        the FP16-stored P of a mixed hierarchy."""
+        y = self._vec(level + 1, x.shape[2], x.dtype)
+        if prec == "f64":
+            _check(lib().mgm_restrict(self.h, level, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)), x.shape[2]))
+        else:
+            _check(lib().mgm_restrict_prec(self.h, level, PREC[prec], C.c_void_p(_ptr(x)),
+                                           C.c_void_p(_ptr(y)), x.shape[2]))
         return y
 
-    def prolong(self, level: int, xc):
-        y = self._vec(level, xc.shape[2])
-        _check(lib().mgm_prolong(self.h, level, C.c_void_p(_ptr(xc)), C.c_void_p(_ptr(y)), xc.shape[2]))
+    def prolong(self, level: int, xc, prec: str = "f64"):
+        """y = P x_c in precision prec (as restrict)."""
+        y = self._vec(level, xc.shape[2], xc.dtype)
+        if prec == "f64":
+            _check(lib().mgm_prolong(self.h, level, C.c_void_p(_ptr(xc)), C.c_void_p(_ptr(y)), xc.shape[2]))
+        else:
+            _check(lib().mgm_prolong_prec(self.h, level, PREC[prec], C.c_void_p(_ptr(xc)),
+                                          C.c_void_p(_ptr(y)), xc.shape[2]))
         return y
 
     def project_out(self, level: int, x):

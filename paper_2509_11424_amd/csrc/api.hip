@@ -529,6 +529,33 @@ mgm_status mgm_prolong(mgm_hierarchy h, int32_t level, const void* x, void* y, i
   API_END
 }
 
+static void check_transfer_prec(mgm_hierarchy h, mgm_prec prec) {
+  MGM_CHECK(prec == MGM_PREC_F64 || prec == MGM_PREC_F32, MGM_ERR_INVALID_ARG,
+            "transfers run in F64 or F32");
+  MGM_CHECK(prec == MGM_PREC_F64 || h->h.desc.mixed, MGM_ERR_INVALID_ARG,
+            "F32 transfers need a hierarchy built with mixed != 0");
+}
+
+mgm_status mgm_restrict_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const void* x, void* y,
+                             int32_t nrhs) {
+  API_BEGIN
+  check_level(h, level, nrhs, true);
+  MGM_CHECK(x && y, MGM_ERR_INVALID_ARG, "bad vectors");
+  check_transfer_prec(h, prec);
+  h->h.T[level].restrict_(prec, x, y, nrhs);
+  API_END
+}
+
+mgm_status mgm_prolong_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const void* x, void* y,
+                            int32_t nrhs) {
+  API_BEGIN
+  check_level(h, level, nrhs, true);
+  MGM_CHECK(x && y, MGM_ERR_INVALID_ARG, "bad vectors");
+  check_transfer_prec(h, prec);
+  h->h.T[level].prolong(prec, x, nullptr, y, nrhs, 0);
+  API_END
+}
+
 mgm_status mgm_project_out(mgm_hierarchy h, int32_t level, const void* x, void* y, int32_t nrhs) {
   API_BEGIN
   check_level(h, level, nrhs, true);

@@ -90,22 +90,57 @@ void mg_agg_map(Context* c, const TGeom& t, int64_t* out) {
 // Transfers run one workgroup per (aggregate, chirality, rhs tile): the
 // aggregate's P block (rows x N_tv) is streamed once through LDS in chunks of
 // rows, so every P entry is read from HBM once per launch and reused by all
-// right-hand sides of the tile.
-constexpr int kTransferRT = 64;  // right-hand sides per workgroup
-constexpr int kTransferLDS = 24576;  // bytes of streamed P rows (and restricted inputs)
+// right-hand sides of the tile.  Each thread owns a 4 x 4 register tile of
+// the block's products (four test vectors or rows by four right-hand sides),
+// so one pair of 32-byte LDS reads feeds sixteen complex FMAs.
+constexpr int kTransferRT = 64;     // right-hand sides per workgroup
+constexpr int kTransferTB = 256;    // threads per workgroup
+constexpr int kRestrictLDS = 24576; // bytes of streamed P rows and restricted inputs
+constexpr int kProlongLDS = 49152;  // bytes of streamed (transposed) P rows
+constexpr int kTransferLDSMax = 65536;
 
-__host__ __device__ inline int transfer_chunk_rows(int rows, int ntv, int rt, int cbytes, bool with_x) {
-  const int per_row = (ntv + (with_x ? rt : 0)) * cbytes;
-  int rc = kTransferLDS / per_row;
-  if (rc > rows) rc = rows;
-  return rc < 1 ? 1 : rc;
+__host__ __device__ inline int round4(int v) { return (v + 3) & ~3; }
+__host__ __device__ inline int sites_bytes(int bvol) { return (bvol * 8 + 15) & ~15; }
+
+// restrict: the rhs tile of width rt splits into T = (Kp/4)(rtp/4) output
+// tiles; G = 256 / T thread groups share the rows of a chunk
+__host__ __device__ inline int restrict_groups(int K, int rt) { return kTransferTB / ((round4(K) / 4) * (round4(rt) / 4)); }
+
+// rows per chunk: the fewest equal chunks that fit the byte budget, rounded
+// up to a multiple of `mult` when that still fits
+inline int balanced_chunk(int rows, int rc_max, int mult) {
+  if (rc_max < 1) rc_max = 1;
+  if (rc_max >= rows) return rows;
+  const int n = (rows + rc_max - 1) / rc_max;
+  int rc = (rows + n - 1) / n;
+  const int up = (rc + mult - 1) / mult * mult;
+  return up <= rc_max ? up : rc;
+}
+
+inline int restrict_chunk_rows(const TGeom& t, int rt, int cbytes) {
+  const int Kp = round4(t.ntv), rtp = round4(rt);
+  return balanced_chunk(t.rows, kRestrictLDS / ((Kp + rtp) * cbytes), restrict_groups(t.ntv, rt));
+}
+inline size_t restrict_lds(const TGeom& t, int rt, int rc, int cbytes) {
+  const size_t chunk = (size_t)rc * (round4(t.ntv) + round4(rt)) * cbytes;
+  const size_t red = (size_t)kTransferTB * 4 * cbytes;
+  return sites_bytes(t.bvol) + (chunk > red ? chunk : red);
+}
+inline int prolong_chunk_rows(const TGeom& t, int rt, int cbytes) {
+  const int avail = kTransferLDSMax - sites_bytes(t.bvol) - t.ntv * round4(rt) * cbytes;
+  const int budget = avail < kProlongLDS ? avail : kProlongLDS;
+  int rc = balanced_chunk(round4(t.rows), (budget / (t.ntv * cbytes)) & ~3, 4);
+  return round4(rc);
+}
+inline size_t prolong_lds(const TGeom& t, int rt, int rc, int cbytes) {
+  return sites_bytes(t.bvol) + ((size_t)t.ntv * round4(rt) + (size_t)rc * t.ntv) * cbytes;
 }
 
 // fine sites of aggregate a, in local (lexicographic) order, into LDS
 __device__ __forceinline__ void aggregate_sites(const TGeom& t, int64_t a, int64_t* sites) {
   int ca[4];
   coords_of(t.c, a, ca);
-  for (int loc = threadIdx.x; loc < t.bvol; loc += blockDim.x) {
+  for (int loc = threadIdx.x; loc < t.bvol; loc += kTransferTB) {
     int rem = loc, f[4];
 #pragma unroll
     for (int m = 0; m < 4; m++) {
@@ -118,140 +153,220 @@ __device__ __forceinline__ void aggregate_sites(const TGeom& t, int64_t a, int64
 }
 
 // P rows [row0, row0 + nr) of one (aggregate, chirality) block into LDS as
-// complex R; FP16 blocks with K % 4 == 0 move 16 bytes (4 entries) per lane
-template <class PM, typename R>
-__device__ __forceinline__ void stage_p_rows(const typename PM::S* __restrict__ pb, int row0, int nr, int K,
+// complex R: entry (row ii, vector k) goes to sP[ii * ld + k] (row-major,
+// columns K..ld-1 zeroed) or, transposed, to sP[k * ld + ii].  FP16 blocks
+// with K % 4 == 0 move 16 bytes (4 entries) per lane.
+template <class PM, typename R, bool TRANS>
+__device__ __forceinline__ void stage_p_rows(const typename PM::S* __restrict__ pb, int row0, int nr, int K, int ld,
                                              cx<R>* sP) {
-  const int n = nr * K;
   if constexpr (std::is_same<PM, F16>::value) {
     if ((K & 3) == 0) {
+      const int K4 = K >> 2;
       const uint4* src = reinterpret_cast<const uint4*>(pb + (int64_t)row0 * K);
-      for (int i = threadIdx.x; i < n / 4; i += blockDim.x) {
+      for (int i = threadIdx.x; i < nr * K4; i += kTransferTB) {
         const uint4 v = src[i];
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        const int ii = i / K4, k0 = (i - ii * K4) * 4;
 #pragma unroll
         for (int e = 0; e < 4; e++) {
           __half2 h;
           __builtin_memcpy(&h, &w[e], 4);
           const float2 f = __half22float2(h);
-          sP[4 * i + e] = {(R)f.x, (R)f.y};
+          if (TRANS)
+            sP[(k0 + e) * ld + ii] = {(R)f.x, (R)f.y};
+          else
+            sP[ii * ld + k0 + e] = {(R)f.x, (R)f.y};  // ld == K here
         }
       }
       return;
     }
   }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const cx<typename PM::R> v = PM::ld(pb, (int64_t)row0 * K + i);
-    sP[i] = {(R)v.re, (R)v.im};
+  if (TRANS) {
+    for (int i = threadIdx.x; i < nr * K; i += kTransferTB) {
+      const int ii = i / K, k = i - ii * K;
+      const cx<typename PM::R> v = PM::ld(pb, (int64_t)row0 * K + i);
+      sP[k * ld + ii] = {(R)v.re, (R)v.im};
+    }
+  } else {
+    for (int i = threadIdx.x; i < nr * ld; i += kTransferTB) {
+      const int ii = i / ld, k = i - ii * ld;
+      cx<R> v = {0, 0};
+      if (k < K) {
+        const cx<typename PM::R> u = PM::ld(pb, (int64_t)(row0 + ii) * K + k);
+        v = {(R)u.re, (R)u.im};
+      }
+      sP[i] = v;
+    }
+  }
+}
+
+// four consecutive complex entries from 16-byte aligned LDS
+template <typename R>
+__device__ __forceinline__ void lds_ld4(const cx<R>* p, cx<R> (&v)[4]) {
+  if constexpr (std::is_same<R, float>::value) {
+    const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+    v[0] = {a.x, a.y};
+    v[1] = {a.z, a.w};
+    v[2] = {b.x, b.y};
+    v[3] = {b.z, b.w};
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const double2 a = reinterpret_cast<const double2*>(p)[j];
+      v[j] = {a.x, a.y};
+    }
   }
 }
 
 // y_c[chi k][a][r] = sum_rows conj(P[a][chi][row][k]) x[chi half + j][site(loc)][r]
+// Thread (g, u) accumulates the output tile u = (k/4, r/4) over the rows
+// g, g + G, ... of every chunk; the G partial tiles are then summed in group
+// order through LDS.
 template <class P, class PM>
 __global__ __launch_bounds__(256) void k_restrict(const typename P::S* __restrict__ x, typename P::S* __restrict__ yc,
                                                   const typename PM::S* __restrict__ Pm, TGeom t, int nrhs, int rc) {
   using R = typename P::R;
-  extern __shared__ char smem[];
+  extern __shared__ __align__(16) char smem[];
   const int64_t a = blockIdx.x >> 1;
   const int chi = blockIdx.x & 1;
   const int r0 = blockIdx.y * kTransferRT;
   const int rt = nrhs - r0 < kTransferRT ? nrhs - r0 : kTransferRT;
   const int K = t.ntv, half = t.half, rows = t.rows;
+  const int Kp = round4(K), rtp = round4(rt), ntr = rtp >> 2;
+  const int T = (Kp >> 2) * ntr, G = kTransferTB / T;
   const int64_t Vc = t.c.V, Vf = t.f.V;
-  int64_t* sS = reinterpret_cast<int64_t*>(smem);                      // [bvol] fine sites
-  cx<R>* sP = reinterpret_cast<cx<R>*>(smem + (size_t)t.bvol * 8);     // [rc][K]
-  cx<R>* sX = sP + (size_t)rc * K;                                      // [rc][rt]
-  const int O = K * rt;                          // outputs of this workgroup, r fastest
+  const int tid = threadIdx.x;
+  const bool active = tid < G * T;
+  const int g = tid / T, u = tid - g * T;
+  const int kt = u / ntr, rtt = u - kt * ntr;
+  int64_t* sS = reinterpret_cast<int64_t*>(smem);                        // [bvol] fine sites
+  cx<R>* sP = reinterpret_cast<cx<R>*>(smem + sites_bytes(t.bvol));      // [rc][Kp]
+  cx<R>* sX = sP + (size_t)rc * Kp;                                       // [rc][rtp]
   aggregate_sites(t, a, sS);
   __syncthreads();
-  constexpr int MAXO = (32 * kTransferRT + 255) / 256;
-  cx<R> acc[MAXO];
+  cx<R> acc[4][4];
 #pragma unroll
-  for (int m = 0; m < MAXO; m++) acc[m] = {0, 0};
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[i][j] = {0, 0};
   const typename PM::S* pb = Pm + ((a * 2 + chi) * rows) * (int64_t)K;
   for (int row0 = 0; row0 < rows; row0 += rc) {
     const int nr = rows - row0 < rc ? rows - row0 : rc;
-    stage_p_rows<PM, R>(pb, row0, nr, K, sP);
-    for (int i = threadIdx.x; i < nr * rt; i += blockDim.x) {
-      const int ii = i / rt, r = i - ii * rt;
-      const int row = row0 + ii, loc = row / half, j = row - loc * half;
-      sX[i] = P::ld(x, ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + r);
+    stage_p_rows<PM, R, false>(pb, row0, nr, K, Kp, sP);
+    for (int i = tid; i < nr * rtp; i += kTransferTB) {
+      const int ii = i / rtp, r = i - ii * rtp;
+      cx<R> v = {0, 0};
+      if (r < rt) {
+        const int row = row0 + ii, loc = row / half, j = row - loc * half;
+        v = P::ld(x, ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + r);
+      }
+      sX[i] = v;
     }
     __syncthreads();
+    if (active) {
+      for (int i = g; i < nr; i += G) {
+        cx<R> pv[4], xv[4];
+        lds_ld4(sP + i * Kp + 4 * kt, pv);
+        lds_ld4(sX + i * rtp + 4 * rtt, xv);
 #pragma unroll
-    for (int m = 0; m < MAXO; m++) {
-      const int o = threadIdx.x + m * 256;
-      if (o < O) {
-        const int k = o / rt, r = o - k * rt;
-        // four independent partial sums keep several LDS reads in flight
-        cx<R> s0 = acc[m], s1 = {0, 0}, s2 = {0, 0}, s3 = {0, 0};
-        int i = 0;
-        for (; i + 4 <= nr; i += 4) {
-          fmac_(s0, sP[i * K + k], sX[i * rt + r]);
-          fmac_(s1, sP[(i + 1) * K + k], sX[(i + 1) * rt + r]);
-          fmac_(s2, sP[(i + 2) * K + k], sX[(i + 2) * rt + r]);
-          fmac_(s3, sP[(i + 3) * K + k], sX[(i + 3) * rt + r]);
-        }
-        for (; i < nr; i++) fmac_(s0, sP[i * K + k], sX[i * rt + r]);
-        acc[m] = (s0 + s1) + (s2 + s3);
+        for (int kk = 0; kk < 4; kk++)
+#pragma unroll
+          for (int rr = 0; rr < 4; rr++) fmac_(acc[kk][rr], pv[kk], xv[rr]);
       }
     }
     __syncthreads();
   }
+  // group reduction, one k row of the tiles at a time: sR[(g T + u) 4 + rr]
+  cx<R>* sR = sP;
 #pragma unroll
-  for (int m = 0; m < MAXO; m++) {
-    const int o = threadIdx.x + m * 256;
-    if (o < O) {
-      const int k = o / rt, r = o - k * rt;
-      P::st(yc, ((int64_t)(chi * K + k) * Vc + a) * nrhs + r0 + r, acc[m]);
+  for (int kk = 0; kk < 4; kk++) {
+    if (active) {
+#pragma unroll
+      for (int rr = 0; rr < 4; rr++) sR[tid * 4 + rr] = acc[kk][rr];
     }
+    __syncthreads();
+    for (int o = tid; o < T * 4; o += kTransferTB) {
+      const int uo = o >> 2, rr = o & 3;
+      const int k = 4 * (uo / ntr) + kk, r = 4 * (uo % ntr) + rr;
+      if (k < K && r < rt) {
+        cx<R> s = sR[o];
+        for (int g2 = 1; g2 < G; g2++) s = s + sR[g2 * T * 4 + o];
+        P::st(yc, ((int64_t)(chi * K + k) * Vc + a) * nrhs + r0 + r, s);
+      }
+    }
+    __syncthreads();
   }
 }
 
 // y = P x_c (mode 0), x - P x_c (mode 1), y + P x_c (mode 2)
+// P rows of a chunk sit transposed in LDS; thread u = (q, r/4) owns rows
+// q, q + Q, q + 2Q, q + 3Q of the chunk (Q = rc / 4) by four right-hand sides.
 template <class P, class PM>
 __global__ __launch_bounds__(256) void k_prolong(const typename P::S* __restrict__ xc, const typename P::S* __restrict__ x,
                                                  typename P::S* __restrict__ y, const typename PM::S* __restrict__ Pm,
                                                  TGeom t, int nrhs, int mode, int rc) {
   using R = typename P::R;
-  extern __shared__ char smem[];
+  extern __shared__ __align__(16) char smem[];
   const int64_t a = blockIdx.x >> 1;
   const int chi = blockIdx.x & 1;
   const int r0 = blockIdx.y * kTransferRT;
   const int rt = nrhs - r0 < kTransferRT ? nrhs - r0 : kTransferRT;
   const int K = t.ntv, half = t.half, rows = t.rows;
+  const int rtp = round4(rt), ntr = rtp >> 2;
+  const int Q = rc >> 2, NT = Q * ntr;
   const int64_t Vc = t.c.V, Vf = t.f.V;
-  int64_t* sS = reinterpret_cast<int64_t*>(smem);                      // [bvol] fine sites
-  cx<R>* sC = reinterpret_cast<cx<R>*>(smem + (size_t)t.bvol * 8);     // [K][rt] coarse values
-  cx<R>* sP = sC + (size_t)K * rt;                                      // [rc][K]
+  const int tid = threadIdx.x;
+  int64_t* sS = reinterpret_cast<int64_t*>(smem);                        // [bvol] fine sites
+  cx<R>* sC = reinterpret_cast<cx<R>*>(smem + sites_bytes(t.bvol));      // [K][rtp] coarse values
+  cx<R>* sPT = sC + (size_t)K * rtp;                                      // [K][rc] P^T of the chunk
   aggregate_sites(t, a, sS);
-  for (int i = threadIdx.x; i < K * rt; i += blockDim.x) {
-    const int k = i / rt, r = i - k * rt;
-    sC[i] = P::ld(xc, ((int64_t)(chi * K + k) * Vc + a) * nrhs + r0 + r);
+  for (int i = tid; i < K * rtp; i += kTransferTB) {
+    const int k = i / rtp, r = i - k * rtp;
+    cx<R> v = {0, 0};
+    if (r < rt) v = P::ld(xc, ((int64_t)(chi * K + k) * Vc + a) * nrhs + r0 + r);
+    sC[i] = v;
   }
   const typename PM::S* pb = Pm + ((a * 2 + chi) * rows) * (int64_t)K;
   for (int row0 = 0; row0 < rows; row0 += rc) {
     const int nr = rows - row0 < rc ? rows - row0 : rc;
-    __syncthreads();  // previous chunk consumed (and sC written on the first pass)
-    stage_p_rows<PM, R>(pb, row0, nr, K, sP);
+    __syncthreads();  // previous chunk consumed (and sC, sS written on the first pass)
+    stage_p_rows<PM, R, true>(pb, row0, nr, K, rc, sPT);
     __syncthreads();
-    for (int o = threadIdx.x; o < nr * rt; o += blockDim.x) {
-      const int ii = o / rt, r = o - ii * rt;
-      cx<R> a0 = {0, 0}, a1 = {0, 0}, a2 = {0, 0}, a3 = {0, 0};
-      int k = 0;
-      for (; k + 4 <= K; k += 4) {
-        fma_(a0, sP[ii * K + k], sC[k * rt + r]);
-        fma_(a1, sP[ii * K + k + 1], sC[(k + 1) * rt + r]);
-        fma_(a2, sP[ii * K + k + 2], sC[(k + 2) * rt + r]);
-        fma_(a3, sP[ii * K + k + 3], sC[(k + 3) * rt + r]);
+    for (int uo = tid; uo < NT; uo += kTransferTB) {
+      const int q = uo / ntr, rtt = uo - q * ntr;
+      if (q >= nr) continue;
+      cx<R> acc[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = {0, 0};
+      for (int k = 0; k < K; k++) {
+        cx<R> cv[4], pv[4];
+        lds_ld4(sC + k * rtp + 4 * rtt, cv);
+#pragma unroll
+        for (int i = 0; i < 4; i++) pv[i] = sPT[k * rc + q + Q * i];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+          for (int rr = 0; rr < 4; rr++) fma_(acc[i][rr], pv[i], cv[rr]);
       }
-      for (; k < K; k++) fma_(a0, sP[ii * K + k], sC[k * rt + r]);
-      cx<R> acc = (a0 + a1) + (a2 + a3);
-      const int row = row0 + ii, loc = row / half, j = row - loc * half;
-      const int64_t e = ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + r;
-      if (mode == 1) acc = P::ld(x, e) - acc;
-      else if (mode == 2) acc = P::ld(y, e) + acc;
-      P::st(y, e, acc);
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int ii = q + Q * i;
+        if (ii < nr) {
+          const int row = row0 + ii, loc = row / half, j = row - loc * half;
+          const int64_t base = ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + 4 * rtt;
+#pragma unroll
+          for (int rr = 0; rr < 4; rr++) {
+            if (4 * rtt + rr < rt) {
+              cx<R> v = acc[i][rr];
+              if (mode == 1) v = P::ld(x, base + rr) - v;
+              else if (mode == 2) v = P::ld(y, base + rr) + v;
+              P::st(y, base + rr, v);
+            }
+          }
+        }
+      }
     }
   }
 }
@@ -264,17 +379,17 @@ double Transfer::bytes(mgm_prec p, int nrhs) const {
 
 void Transfer::restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const {
   ProfScope ps(ctx, KC_TRANSFER, bytes(p, nrhs));
-  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(256);
+  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(kTransferTB);
   const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
   MGM_CHECK(t.ntv <= 32 && t.bvol <= 1024, MGM_ERR_SHAPE,
             "transfers support at most 32 test vectors and 1024 sites per aggregate");
   if (p == MGM_PREC_F64) {
-    const int rc = transfer_chunk_rows(t.rows, t.ntv, rt, 16, true);
-    hipLaunchKernelGGL((k_restrict<F64, F64>), nb, tb, (size_t)t.bvol * 8 + (size_t)rc * (t.ntv + rt) * 16, ctx->stream,
+    const int rc = restrict_chunk_rows(t, rt, 16);
+    hipLaunchKernelGGL((k_restrict<F64, F64>), nb, tb, restrict_lds(t, rt, rc, 16), ctx->stream,
                        (const double2*)x, (double2*)yc, P64, t, nrhs, rc);
   } else if (p == MGM_PREC_F32) {
-    const int rc = transfer_chunk_rows(t.rows, t.ntv, rt, 8, true);
-    hipLaunchKernelGGL((k_restrict<F32, F16>), nb, tb, (size_t)t.bvol * 8 + (size_t)rc * (t.ntv + rt) * 8, ctx->stream,
+    const int rc = restrict_chunk_rows(t, rt, 8);
+    hipLaunchKernelGGL((k_restrict<F32, F16>), nb, tb, restrict_lds(t, rt, rc, 8), ctx->stream,
                        (const float2*)x, (float2*)yc, P16, t, nrhs, rc);
   } else {
     throw Error(MGM_ERR_INVALID_ARG, "restrict: precision must be F64 or F32");
@@ -284,17 +399,17 @@ void Transfer::restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const {
 
 void Transfer::prolong(mgm_prec p, const void* xc, const void* x, void* y, int nrhs, int mode) const {
   ProfScope ps(ctx, KC_TRANSFER, bytes(p, nrhs));
-  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(256);
+  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(kTransferTB);
   const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
   MGM_CHECK(t.ntv <= 32 && t.bvol <= 1024, MGM_ERR_SHAPE,
             "transfers support at most 32 test vectors and 1024 sites per aggregate");
   if (p == MGM_PREC_F64) {
-    const int rc = transfer_chunk_rows(t.rows, t.ntv, rt, 16, false);
-    hipLaunchKernelGGL((k_prolong<F64, F64>), nb, tb, (size_t)t.bvol * 8 + ((size_t)t.ntv * rt + (size_t)rc * t.ntv) * 16, ctx->stream,
+    const int rc = prolong_chunk_rows(t, rt, 16);
+    hipLaunchKernelGGL((k_prolong<F64, F64>), nb, tb, prolong_lds(t, rt, rc, 16), ctx->stream,
                        (const double2*)xc, (const double2*)x, (double2*)y, P64, t, nrhs, mode, rc);
   } else if (p == MGM_PREC_F32) {
-    const int rc = transfer_chunk_rows(t.rows, t.ntv, rt, 8, false);
-    hipLaunchKernelGGL((k_prolong<F32, F16>), nb, tb, (size_t)t.bvol * 8 + ((size_t)t.ntv * rt + (size_t)rc * t.ntv) * 8, ctx->stream,
+    const int rc = prolong_chunk_rows(t, rt, 8);
+    hipLaunchKernelGGL((k_prolong<F32, F16>), nb, tb, prolong_lds(t, rt, rc, 8), ctx->stream,
                        (const float2*)xc, (const float2*)x, (float2*)y, P16, t, nrhs, mode, rc);
   } else {
     throw Error(MGM_ERR_INVALID_ARG, "prolong: precision must be F64 or F32");

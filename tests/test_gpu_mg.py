@@ -93,6 +93,69 @@ def test_transfers_and_level_apply(three):
         assert rel(y, p.oh.ops[l].matvec(x.reshape(2, -1))) < 1e-10
 
 
+@pytest.fixture(scope="module")
+def wide(ctx):
+    """24 and 32 test vectors, aggregates of 32 and 2 sites: transfer blocks of
+    192 and 48 rows that span several LDS chunks, in a mixed hierarchy."""
+    return Pair(ctx, (4, 4, 4, 16), 0.5, 33, 0.1, 1.0, [(2, 2, 2, 4), (1, 1, 1, 2)], [24, 32], 41,
+                max_nrhs=72, mixed=1)
+
+
+@pytest.mark.parametrize("nrhs", [1, 5, 70])
+def test_transfers_many_vectors_f64(wide, nrhs):
+    p = wide
+    for l in range(p.oh.L - 1):
+        s, d, n = p.h.level_info(l)
+        cs, cd, cn = p.h.level_info(l + 1)
+        x = _rand(s, d, nrhs, 100 + l)
+        xc = _rand(cs, cd, nrhs, 200 + l)
+        tr = p.oh.transfers[l]
+        xf, xcf = x.reshape(nrhs, -1), xc.reshape(nrhs, -1)
+        assert rel(from_gpu(p.h.restrict(l, to_gpu(x))).reshape(nrhs, -1), tr.restrict(xf)) < 1e-10
+        assert rel(from_gpu(p.h.prolong(l, to_gpu(xc))).reshape(nrhs, -1), tr.prolong(xcf)) < 1e-10
+        assert rel(from_gpu(p.h.project_out(l, to_gpu(x))).reshape(nrhs, -1), tr.project_out(xf)) < 1e-10
+
+
+def _fp16_rounded(P):
+    """P as the mixed transfers hold it: FP64 -> FP32 -> FP16, per component."""
+    re = P.real.astype(np.float32).astype(np.float16).astype(np.float64)
+    im = P.imag.astype(np.float32).astype(np.float16).astype(np.float64)
+    return re + 1j * im
+
+
+@pytest.mark.parametrize("nrhs", [3, 16, 70])
+def test_transfers_f32_fp16_P(wide, nrhs):
+    """FP32 transfers with FP16-stored P against the oracle's P rounded the
+    same way, applied in FP64 to the same FP32 inputs: only FP32 accumulation
+    (at most 192 terms) separates the two."""
+    import torch
+    from oracle.multigrid import Transfer
+    p = wide
+    for l in range(p.oh.L - 1):
+        s, d, n = p.h.level_info(l)
+        cs, cd, cn = p.h.level_info(l + 1)
+        x = _rand(s, d, nrhs, 300 + l).astype(np.complex64)
+        xc = _rand(cs, cd, nrhs, 400 + l).astype(np.complex64)
+        tr = p.oh.transfers[l]
+        t16 = Transfer(tr.agg, _fp16_rounded(tr.P))
+        yc = p.h.restrict(l, to_gpu(x).to(torch.complex64), prec="f32")
+        y = p.h.prolong(l, to_gpu(xc).to(torch.complex64), prec="f32")
+        assert yc.dtype == torch.complex64 and y.dtype == torch.complex64
+        want_c = t16.restrict(x.astype(np.complex128).reshape(nrhs, -1))
+        want = t16.prolong(xc.astype(np.complex128).reshape(nrhs, -1))
+        assert rel(from_gpu(yc).reshape(nrhs, -1), want_c) < 1e-5
+        assert rel(from_gpu(y).reshape(nrhs, -1), want) < 1e-5
+
+
+def test_transfer_prec_rejects_f16(wide):
+    import torch
+    import paper_2509_11424_amd as m
+    s, d, n = wide.h.level_info(0)
+    x = torch.zeros((d, s, 2), dtype=torch.complex64, device="cuda:0")
+    with pytest.raises(m.MgmError):
+        wide.h.restrict(0, x, prec="f16")
+
+
 @pytest.mark.parametrize("kind", ["mg", "gmres"])
 def test_solves_every_level(three, kind):
     import paper_2509_11424_amd as m
