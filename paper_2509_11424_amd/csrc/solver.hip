@@ -32,8 +32,9 @@ static void op_apply(Hier& H, int l, mgm_prec p, bool inner, const SolveCfg& cfg
 // (dslash with dots, then the update); every later step is one fused kernel
 // that applies D, moves r and x by the previous step's MR length and forms
 // the dots that give the next length (FineOp::apply_step).  r ping-pongs
-// between b (the caller's scratch input, overwritten) and w.rho.
-static void mr_smooth_fused(Hier& H, Vec b, Vec y, int nu) {
+// between b (the caller's scratch input, overwritten) and w.rho; the return
+// value is the buffer that holds the final residual b - D y.
+static void* mr_smooth_fused(Hier& H, Vec b, Vec y, int nu) {
   LevelWS& w = H.ws16[0];
   Context* c = H.ctx;
   b_zero(c, y);
@@ -50,12 +51,15 @@ static void mr_smooth_fused(Hier& H, Vec b, Vec y, int nu) {
       b_finalize_dot_norm(c, H.scratch, H.dpart, nb, b.nrhs, (i & 1) ? w.qr2 : w.qr, (i & 1) ? w.qq2 : w.qq);
     std::swap(r, r_next);
   }
+  return r;
 }
 
-static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const SolveCfg& cfg) {
+// MR smoothing y = S b from y = 0; the residual b - D y is carried in rho,
+// which is `res` when the caller wants it.
+static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const SolveCfg& cfg, Vec* res = nullptr) {
   LevelWS& w = H.ws(l, p);
   Context* c = H.ctx;
-  Vec rho = b.with(w.rho), q = b.with(w.q);
+  Vec rho = res ? *res : b.with(w.rho), q = b.with(w.q);
   b_zero(c, y);
   b_copy(c, rho, b);
   for (int i = 0; i < nu; i++) {
@@ -77,7 +81,9 @@ static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool p
 // scaled per rhs to unit RMS entries (MR is homogeneous of degree one, and
 // FP16 keeps its full precision away from the subnormal range), smoothed with
 // FP16 vectors and FP32 arithmetic, and scaled back into FP32.
-static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
+// With res != nullptr the residual r - D e that the smoother carries is also
+// written to *res (in the precision of r).
+static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, Vec* res = nullptr) {
   if (l == 0 && p == MGM_PREC_F32 && cfg.smooth_f16 && cfg.smooth > 0 && H.ws16.size() > 0 &&
       H.ws16[0].rho != nullptr) {
     LevelWS& w = H.ws16[0];
@@ -86,15 +92,17 @@ static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg
     b_norm2(c, H.scratch, r, w.n2a);
     b_unit_scales(c, w.n2a, (double)r.nsite * r.dof, r.nrhs, w.mask, w.n2b);
     b_copy_scaled(c, r16, r, w.mask);
+    void* rf = w.rho;
     if (cfg.smooth >= 2 && w.qr2 != nullptr && H.fine->step_fusable(MGM_PREC_F16, r.nrhs))
-      mr_smooth_fused(H, r16, y16, cfg.smooth);
+      rf = mr_smooth_fused(H, r16, y16, cfg.smooth);
     else
       mr_smooth(H, 0, MGM_PREC_F16, r16, y16, cfg.smooth, cfg);
     b_copy_scaled(c, e, y16, w.n2b);
+    if (res) b_copy_scaled(c, *res, r16.with(rf), w.n2b);
     return;
   }
   const int nu = (l > 0 && cfg.smooth_coarse > 0) ? cfg.smooth_coarse : cfg.smooth;
-  mr_smooth(H, l, p, r, e, nu, cfg);
+  mr_smooth(H, l, p, r, e, nu, cfg, res);
 }
 
 // e_c = (cfg.coarse_iters FGMRES steps on level lc) r_c, between the level's
@@ -165,9 +173,8 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
     b_axpy(c, nullptr, 1.0, y, e);
     return;
   }
-  smooth(H, l, p, r, e, cfg);
-  op_apply(H, l, p, true, cfg, e.p, t.p, nrhs);
-  b_xpay(c, r, nullptr, -1.0, t);  // t = r - D e
+  // pre-smoothing; the smoother's own recursion leaves t = r - D e
+  smooth(H, l, p, r, e, cfg, &t);
   LevelWS& wc = H.ws(l + 1, p);
   Vec rc = H.vec(l + 1, p, wc.bc, nrhs), ec = H.vec(l + 1, p, wc.xc, nrhs);
   H.T[l].restrict_(p, t.p, rc.p, nrhs);
