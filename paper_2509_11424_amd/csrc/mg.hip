@@ -96,8 +96,7 @@ void mg_agg_map(Context* c, const TGeom& t, int64_t* out) {
 constexpr int kTransferRT = 64;     // right-hand sides per workgroup
 constexpr int kTransferTB = 256;    // threads per workgroup
 constexpr int kRestrictLDS = 24576; // bytes of streamed P rows and restricted inputs
-constexpr int kProlongLDS = 49152;  // bytes of streamed (transposed) P rows
-constexpr int kTransferLDSMax = 65536;
+constexpr int kProlongLDS = 24576;  // bytes of streamed (transposed) P rows
 
 __host__ __device__ inline int round4(int v) { return (v + 3) & ~3; }
 __host__ __device__ inline int sites_bytes(int bvol) { return (bvol * 8 + 15) & ~15; }
@@ -126,11 +125,17 @@ inline size_t restrict_lds(const TGeom& t, int rt, int rc, int cbytes) {
   const size_t red = (size_t)kTransferTB * 4 * cbytes;
   return sites_bytes(t.bvol) + (chunk > red ? chunk : red);
 }
-inline int prolong_chunk_rows(const TGeom& t, int rt, int cbytes) {
-  const int avail = kTransferLDSMax - sites_bytes(t.bvol) - t.ntv * round4(rt) * cbytes;
-  const int budget = avail < kProlongLDS ? avail : kProlongLDS;
-  int rc = balanced_chunk(round4(t.rows), (budget / (t.ntv * cbytes)) & ~3, 4);
-  return round4(rc);
+// prolong: TI rows per thread, chunks of about one tile per thread (at
+// most kProlongLDS bytes of P), rows a multiple of TI
+inline int prolong_chunk_rows(const TGeom& t, int rt, int cbytes, int TI) {
+  const int ntr = round4(rt) / 4;
+  const int want = TI * ((kTransferTB + ntr - 1) / ntr);
+  int cap = kProlongLDS / (t.ntv * cbytes);
+  cap = (cap < want ? cap : want) / TI * TI;
+  if (cap < TI) cap = TI;
+  const int rows = (t.rows + TI - 1) / TI * TI;
+  const int rc = balanced_chunk(rows, cap, TI);
+  return (rc + TI - 1) / TI * TI;
 }
 inline size_t prolong_lds(const TGeom& t, int rt, int rc, int cbytes) {
   return sites_bytes(t.bvol) + ((size_t)t.ntv * round4(rt) + (size_t)rc * t.ntv) * cbytes;
@@ -300,8 +305,9 @@ __global__ __launch_bounds__(256) void k_restrict(const typename P::S* __restric
 
 // y = P x_c (mode 0), x - P x_c (mode 1), y + P x_c (mode 2)
 // P rows of a chunk sit transposed in LDS; thread u = (q, r/4) owns rows
-// q, q + Q, q + 2Q, q + 3Q of the chunk (Q = rc / 4) by four right-hand sides.
-template <class P, class PM>
+// q, q + Q, ..., q + (TI-1) Q of the chunk (Q = rc / TI) by four right-hand
+// sides, and loads the destination entries it updates before its products.
+template <class P, class PM, int TI>
 __global__ __launch_bounds__(256) void k_prolong(const typename P::S* __restrict__ xc, const typename P::S* __restrict__ x,
                                                  typename P::S* __restrict__ y, const typename PM::S* __restrict__ Pm,
                                                  TGeom t, int nrhs, int mode, int rc) {
@@ -313,7 +319,7 @@ __global__ __launch_bounds__(256) void k_prolong(const typename P::S* __restrict
   const int rt = nrhs - r0 < kTransferRT ? nrhs - r0 : kTransferRT;
   const int K = t.ntv, half = t.half, rows = t.rows;
   const int rtp = round4(rt), ntr = rtp >> 2;
-  const int Q = rc >> 2, NT = Q * ntr;
+  const int Q = rc / TI, NT = Q * ntr;
   const int64_t Vc = t.c.V, Vf = t.f.V;
   const int tid = threadIdx.x;
   int64_t* sS = reinterpret_cast<int64_t*>(smem);                        // [bvol] fine sites
@@ -327,6 +333,7 @@ __global__ __launch_bounds__(256) void k_prolong(const typename P::S* __restrict
     sC[i] = v;
   }
   const typename PM::S* pb = Pm + ((a * 2 + chi) * rows) * (int64_t)K;
+  const typename P::S* src = mode == 1 ? x : y;
   for (int row0 = 0; row0 < rows; row0 += rc) {
     const int nr = rows - row0 < rc ? rows - row0 : rc;
     __syncthreads();  // previous chunk consumed (and sC, sS written on the first pass)
@@ -335,35 +342,49 @@ __global__ __launch_bounds__(256) void k_prolong(const typename P::S* __restrict
     for (int uo = tid; uo < NT; uo += kTransferTB) {
       const int q = uo / ntr, rtt = uo - q * ntr;
       if (q >= nr) continue;
-      cx<R> acc[4][4];
+      int64_t base[TI];
+      cx<R> acc[TI][4];
 #pragma unroll
-      for (int i = 0; i < 4; i++)
+      for (int i = 0; i < TI; i++) {
+        const int ii = q + Q * i;
+        base[i] = -1;
+        if (ii < nr) {
+          const int row = row0 + ii, loc = row / half, j = row - loc * half;
+          base[i] = ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + 4 * rtt;
+        }
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = {0, 0};
+        for (int rr = 0; rr < 4; rr++) {
+          acc[i][rr] = {0, 0};
+          if (mode != 0 && base[i] >= 0 && 4 * rtt + rr < rt) acc[i][rr] = P::ld(src, base[i] + rr);
+        }
+      }
+      if (mode == 1) {
+#pragma unroll
+        for (int i = 0; i < TI; i++)
+#pragma unroll
+          for (int rr = 0; rr < 4; rr++) acc[i][rr] = {-acc[i][rr].re, -acc[i][rr].im};
+      }
+      // acc holds -x (mode 1), y (mode 2) or 0; the sum over k is added on
+      // top and the sign restored for mode 1
       for (int k = 0; k < K; k++) {
-        cx<R> cv[4], pv[4];
+        cx<R> cv[4], pv[TI];
         lds_ld4(sC + k * rtp + 4 * rtt, cv);
 #pragma unroll
-        for (int i = 0; i < 4; i++) pv[i] = sPT[k * rc + q + Q * i];
+        for (int i = 0; i < TI; i++) pv[i] = sPT[k * rc + q + Q * i];
 #pragma unroll
-        for (int i = 0; i < 4; i++)
+        for (int i = 0; i < TI; i++)
 #pragma unroll
           for (int rr = 0; rr < 4; rr++) fma_(acc[i][rr], pv[i], cv[rr]);
       }
 #pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const int ii = q + Q * i;
-        if (ii < nr) {
-          const int row = row0 + ii, loc = row / half, j = row - loc * half;
-          const int64_t base = ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + 4 * rtt;
+      for (int i = 0; i < TI; i++) {
+        if (base[i] < 0) continue;
 #pragma unroll
-          for (int rr = 0; rr < 4; rr++) {
-            if (4 * rtt + rr < rt) {
-              cx<R> v = acc[i][rr];
-              if (mode == 1) v = P::ld(x, base + rr) - v;
-              else if (mode == 2) v = P::ld(y, base + rr) + v;
-              P::st(y, base + rr, v);
-            }
+        for (int rr = 0; rr < 4; rr++) {
+          if (4 * rtt + rr < rt) {
+            cx<R> v = acc[i][rr];
+            if (mode == 1) v = {-v.re, -v.im};
+            P::st(y, base[i] + rr, v);
           }
         }
       }
@@ -404,12 +425,12 @@ void Transfer::prolong(mgm_prec p, const void* xc, const void* x, void* y, int n
   MGM_CHECK(t.ntv <= 32 && t.bvol <= 1024, MGM_ERR_SHAPE,
             "transfers support at most 32 test vectors and 1024 sites per aggregate");
   if (p == MGM_PREC_F64) {
-    const int rc = prolong_chunk_rows(t, rt, 16);
-    hipLaunchKernelGGL((k_prolong<F64, F64>), nb, tb, prolong_lds(t, rt, rc, 16), ctx->stream,
+    const int rc = prolong_chunk_rows(t, rt, 16, 1);
+    hipLaunchKernelGGL((k_prolong<F64, F64, 1>), nb, tb, prolong_lds(t, rt, rc, 16), ctx->stream,
                        (const double2*)xc, (const double2*)x, (double2*)y, P64, t, nrhs, mode, rc);
   } else if (p == MGM_PREC_F32) {
-    const int rc = prolong_chunk_rows(t, rt, 8);
-    hipLaunchKernelGGL((k_prolong<F32, F16>), nb, tb, prolong_lds(t, rt, rc, 8), ctx->stream,
+    const int rc = prolong_chunk_rows(t, rt, 8, 2);
+    hipLaunchKernelGGL((k_prolong<F32, F16, 2>), nb, tb, prolong_lds(t, rt, rc, 8), ctx->stream,
                        (const float2*)xc, (const float2*)x, (float2*)y, P16, t, nrhs, mode, rc);
   } else {
     throw Error(MGM_ERR_INVALID_ARG, "prolong: precision must be F64 or F32");
