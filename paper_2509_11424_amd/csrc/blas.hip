@@ -90,7 +90,7 @@ void b_copy_scaled(Context* c, Vec dst, Vec src, const double* s) {
 __global__ void k_unit_scales(const double* n2, double target2, int nrhs, double* s, double* inv) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs) return;
-  const double d = n2[r];
+  const double d = n2 ? n2[r] : 1.0;  // no norms given: unit columns
   const double f = d > 0.0 ? sqrt(target2 / d) : 0.0;
   s[r] = f;
   inv[r] = f > 0.0 ? 1.0 / f : 0.0;

@@ -148,7 +148,8 @@ struct SolveOut {
 void solve(Hier& H, int l, const SolveCfg& cfg, const double2* b, double2* x, int nrhs, SolveOut* out);
 
 // e = M r: one V-cycle of level l in precision p (e overwritten)
-void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg);
+// unit: every column of r has norm 1 or 0 (a normalised Arnoldi vector)
+void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, bool unit = false);
 
 // ------------------------------------------------------------ estimator
 

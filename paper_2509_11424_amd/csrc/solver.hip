@@ -82,15 +82,17 @@ static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool p
 // FP16 keeps its full precision away from the subnormal range), smoothed with
 // FP16 vectors and FP32 arithmetic, and scaled back into FP32.
 // With res != nullptr the residual r - D e that the smoother carries is also
-// written to *res (in the precision of r).
-static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, Vec* res = nullptr) {
+// written to *res (in the precision of r); unit says that every column of r
+// has norm 1 or 0 (a normalised Arnoldi vector), so no norms are taken.
+static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, Vec* res = nullptr,
+                   bool unit = false) {
   if (l == 0 && p == MGM_PREC_F32 && cfg.smooth_f16 && cfg.smooth > 0 && H.ws16.size() > 0 &&
       H.ws16[0].rho != nullptr) {
     LevelWS& w = H.ws16[0];
     Context* c = H.ctx;
     Vec r16 = r.as(MGM_PREC_F16, w.r), y16 = r.as(MGM_PREC_F16, w.t);
-    b_norm2(c, H.scratch, r, w.n2a);
-    b_unit_scales(c, w.n2a, (double)r.nsite * r.dof, r.nrhs, w.mask, w.n2b);
+    if (!unit) b_norm2(c, H.scratch, r, w.n2a);
+    b_unit_scales(c, unit ? nullptr : w.n2a, (double)r.nsite * r.dof, r.nrhs, w.mask, w.n2b);
     b_copy_scaled(c, r16, r, w.mask);
     void* rf = w.rho;
     if (cfg.smooth >= 2 && w.qr2 != nullptr && H.fine->step_fusable(MGM_PREC_F16, r.nrhs))
@@ -149,7 +151,7 @@ static void coarse_correction(Hier& H, int lc, mgm_prec p, Vec rc, Vec ec, const
   MGM_HIP(hipGraphLaunch(g.exec, c->stream));
 }
 
-void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
+void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, bool unit) {
   Context* c = H.ctx;
   if (l == H.L - 1) {
     fgmres_fixed(H, l, p, r, e, cfg.coarse_iters, false, cfg);
@@ -174,7 +176,7 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg) {
     return;
   }
   // pre-smoothing; the smoother's own recursion leaves t = r - D e
-  smooth(H, l, p, r, e, cfg, &t);
+  smooth(H, l, p, r, e, cfg, &t, unit);
   LevelWS& wc = H.ws(l + 1, p);
   Vec rc = H.vec(l + 1, p, wc.bc, nrhs), ec = H.vec(l + 1, p, wc.xc, nrhs);
   H.T[l].restrict_(p, t.p, rc.p, nrhs);
@@ -208,7 +210,7 @@ static int arnoldi(Hier& H, int l, mgm_prec p, int nrhs, int kmax, bool precond,
     char* Vj = (char*)w.V + (size_t)j * stride * eb;
     char* Zj = precond ? (char*)w.Z + (size_t)j * stride * eb : Vj;
     char* W = (char*)w.V + (size_t)(j + 1) * stride * eb;
-    if (precond) vcycle(H, l, p, base.with(Vj), base.with(Zj), cfg);
+    if (precond) vcycle(H, l, p, base.with(Vj), base.with(Zj), cfg, true);
     op_apply(H, l, p, inner, cfg, Zj, W, nrhs);
     Vec Wv = base.with(W);
     // classical Gram-Schmidt with one re-orthogonalisation: the first
