@@ -288,9 +288,10 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     kind = "mg_mixed" if mixed else "mg"
     # mixed form: FP16-storage fine smoother, BF16 MFMA coarse operators,
     # autotuned launch shapes and graph-captured coarse-grid corrections
-    # smoothing 8 (mixed form; 6 for FP64) / 2 (fine / coarser levels) and 3
-    # coarse-solve steps: the fastest settings measured for each form
-    sd = m.solve_desc(tol=1e-10, kind=kind, smooth=args.smooth, smooth_coarse=2, coarse_iters=3, inner_tol=1e-5,
+    # smoothing 8 (mixed form; 6 for FP64) / 2 (fine / coarser levels) and one
+    # coarse-solve step: the fastest settings measured for each form
+    sd = m.solve_desc(tol=1e-10, kind=kind, smooth=args.smooth, smooth_coarse=args.smooth_coarse,
+                      coarse_iters=args.coarse_iters, inner_tol=1e-5,
                       maxiter=5000, coarse_bf16=True, smoother_f16=True, graphs=bool(mixed))
     # launch-shape keys of the kernel classes with recorded HBM counters
     pin_keys = {kc: {n: "%s/%d/%d/%d" % (TUNE_PREFIX[kc], m.api.PREC["f16"], op.V, n)
@@ -342,7 +343,8 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
         "dtype": "f32+bf16 (f64 defect correction)" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "lattice": "x".join(map(str, cfg["dims"])), "levels": L,
-                   "probes": cfg["nprobe"], "batch": batch, "tol": 1e-10, "form": args.form},
+                   "probes": cfg["nprobe"], "batch": batch, "tol": 1e-10, "form": args.form,
+                   "smoothing": [sd.smooth, sd.smooth_coarse], "coarse_iters": sd.coarse_iters},
         "roofline": roofline(ds, op.V, q, achieved, avg_ms, bytes_launch, variants,
                              measured_traffic(ds, op.V, q["launches"], q["bytes"], variants)
                              if args.config == "c4" else None),
@@ -543,7 +545,7 @@ def time_to_target(m, ctx, op, cfg, make_mixed, sd_mixed, args):
     b64 = cfg.get("batch_f64", cfg["batch"])
     h64 = m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=b64[0],
                       max_nrhs_level=b64, restart=cfg["restart"], mixed=0)
-    sd64 = m.solve_desc(tol=1e-10, kind="mg", smooth=6, smooth_coarse=2, coarse_iters=3, maxiter=5000)
+    sd64 = m.solve_desc(tol=1e-10, kind="mg", smooth=6, smooth_coarse=2, coarse_iters=1, maxiter=5000)
     p64 = pilot(h64, sd64, b64)
     eps2 = p64["total_var"]
     out = {"eps2": eps2, "f64": final(h64, sd64, p64, eps2, b64)}
@@ -567,6 +569,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c4", choices=sorted(CONFIGS))
     ap.add_argument("--smooth", type=int, default=8, help="fine-level smoothing steps of the timed form")
+    ap.add_argument("--smooth-coarse", type=int, default=2, help="smoothing steps on the coarser levels")
+    ap.add_argument("--coarse-iters", type=int, default=1, help="FGMRES steps of a coarse-grid solve")
     ap.add_argument("--batch", type=int, nargs="+", default=None,
                     help="right-hand sides per batch on each level (default: the configuration's)")
     ap.add_argument("--form", default="mixed", choices=["mixed", "f64"])

@@ -147,6 +147,47 @@ def test_transfers_f32_fp16_P(wide, nrhs):
         assert rel(from_gpu(y).reshape(nrhs, -1), want) < 1e-5
 
 
+def _bf16(a):
+    """round to nearest even BF16 after rounding to FP32 (as the device does)"""
+    b = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _bf16c(z):
+    return _bf16(z.real) + 1j * _bf16(z.imag)
+
+
+@pytest.mark.parametrize("nrhs", [4, 37])
+def test_coarse_bf16_backward_blocks(wide, nrhs):
+    """BF16 coarse stencil against an FP64 stencil built from the oracle's
+    self and forward blocks rounded to BF16, with every backward block the
+    chirality-signed conjugate transpose of the neighbour's rounded forward
+    block (gamma5-hermiticity; round-to-nearest-even commutes with sign
+    changes, so this equals the rounded backward block), on BF16-rounded
+    inputs: only the FP32 accumulation separates the two.  d = 48 and 64
+    (three and four 16-row tiles, chirality boundary inside and at the edge
+    of a tile)."""
+    import torch
+    p = wide
+    for l in (1, 2):
+        op = p.oh.ops[l]
+        B, nbr = op.stencil()
+        d, V = op.d, op.V
+        g = np.where(np.arange(d) < d // 2, 1.0, -1.0)
+        Bf = _bf16c(B[:, :5])
+        blocks = np.concatenate([Bf] + [
+            (g[None, :, None] * np.conj(np.transpose(Bf[nbr[5 + mu], 1 + mu], (0, 2, 1))) * g[None, None, :])[:, None]
+            for mu in range(4)], axis=1)
+        x = _rand(V, d, nrhs, 500 + l).astype(np.complex64)
+        xr = _bf16c(x.astype(np.complex128))
+        want = np.zeros((nrhs, V, d), dtype=np.complex128)
+        for k in range(9):
+            want += np.einsum("sij,nsj->nsi", blocks[:, k], xr[:, nbr[k], :])
+        got = p.h.apply_prec(l, to_gpu(x), "bf16")
+        assert rel(from_gpu(got).astype(np.complex128).reshape(nrhs, -1), want.reshape(nrhs, -1)) < 5e-5
+
+
 def test_transfer_prec_rejects_f16(wide):
     import torch
     import paper_2509_11424_amd as m

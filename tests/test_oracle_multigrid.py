@@ -122,6 +122,24 @@ def test_coarse_operator_gamma5_hermitian(hier44):
     np.testing.assert_allclose(g[:, None] * Dc * g[None, :], Dc.conj().T, atol=1e-14)
 
 
+def test_coarse_backward_blocks_from_forward(hier44):
+    """The stencil form of gamma5-hermiticity that the BF16 coarse layout
+    relies on: the backward block at x is the chirality-signed conjugate
+    transpose of the forward block at x - mu (Gamma5_c = diag(+1, -1) over
+    the two chirality halves of a coarse site)."""
+    _, h = hier44
+    op = h.ops[1]
+    B, nbr = op.stencil()
+    d = op.d
+    g = np.where(np.arange(d) < d // 2, 1.0, -1.0)
+    for mu in range(4):
+        xm = nbr[5 + mu]
+        want = g[None, :, None] * np.conj(np.transpose(B[xm, 1 + mu], (0, 2, 1))) * g[None, None, :]
+        np.testing.assert_allclose(B[:, 5 + mu], want, atol=1e-14)
+        # and the forward neighbour of x - mu is x
+        assert np.array_equal(nbr[1 + mu][xm], np.arange(op.V))
+
+
 def test_three_level_odd_shape():
     """4x4x4x8 -> (2,2,2,2) blocks -> 2x2x2x4 -> (1,1,1,2) -> 2x2x2x2."""
     U = gauge_field((4, 4, 4, 8), 0.5, 21)
