@@ -87,6 +87,23 @@ void b_copy_scaled(Context* c, Vec dst, Vec src, const double* s) {
   MGM_LAUNCH_CHECK();
 }
 
+template <class PD, class PS>
+__global__ void k_add_scaled(void* dst, const void* src, int64_t n, int nrhs, const double* s) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next())
+    std_<PD>(dst, i, ldd<PD>(dst, i) + s[it.r] * ldd<PS>(src, i));
+}
+void b_add_scaled(Context* c, Vec dst, Vec src, const double* s) {
+  int64_t n = src.n();
+  MGM_CHECK(dst.n() == n && dst.nrhs == src.nrhs, MGM_ERR_INVALID_ARG, "add: shape mismatch");
+  if (n == 0) return;
+  DISPATCH_PREC(dst.prec, PD, DISPATCH_PREC(src.prec, PS,
+      hipLaunchKernelGGL((k_add_scaled<PD, PS>), dim3(ew_blocks(n)), dim3(256), 0, c->stream, dst.p, src.p, n,
+                         src.nrhs, s)));
+  MGM_LAUNCH_CHECK();
+}
+
 __global__ void k_unit_scales(const double* n2, double target2, int nrhs, double* s, double* inv) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs) return;

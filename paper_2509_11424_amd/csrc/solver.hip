@@ -54,13 +54,14 @@ static void* mr_smooth_fused(Hier& H, Vec b, Vec y, int nu) {
   return r;
 }
 
-// MR smoothing y = S b from y = 0; the residual b - D y is carried in rho,
-// which is `res` when the caller wants it.
-static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const SolveCfg& cfg, Vec* res = nullptr) {
+// MR smoothing y = S b from y = 0 (add: y += S b); the residual b - D S b
+// is carried in rho, which is `res` when the caller wants it.
+static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const SolveCfg& cfg, Vec* res = nullptr,
+                      bool add = false) {
   LevelWS& w = H.ws(l, p);
   Context* c = H.ctx;
   Vec rho = res ? *res : b.with(w.rho), q = b.with(w.q);
-  b_zero(c, y);
+  if (!add) b_zero(c, y);
   b_copy(c, rho, b);
   for (int i = 0; i < nu; i++) {
     if (l == 0) {
@@ -83,9 +84,10 @@ static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool p
 // FP16 vectors and FP32 arithmetic, and scaled back into FP32.
 // With res != nullptr the residual r - D e that the smoother carries is also
 // written to *res (in the precision of r); unit says that every column of r
-// has norm 1 or 0 (a normalised Arnoldi vector), so no norms are taken.
+// has norm 1 or 0 (a normalised Arnoldi vector), so no norms are taken; add
+// accumulates the smoothed correction into e instead of overwriting it.
 static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, Vec* res = nullptr,
-                   bool unit = false) {
+                   bool unit = false, bool add = false) {
   if (l == 0 && p == MGM_PREC_F32 && cfg.smooth_f16 && cfg.smooth > 0 && H.ws16.size() > 0 &&
       H.ws16[0].rho != nullptr) {
     LevelWS& w = H.ws16[0];
@@ -99,12 +101,15 @@ static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg
       rf = mr_smooth_fused(H, r16, y16, cfg.smooth);
     else
       mr_smooth(H, 0, MGM_PREC_F16, r16, y16, cfg.smooth, cfg);
-    b_copy_scaled(c, e, y16, w.n2b);
+    if (add)
+      b_add_scaled(c, e, y16, w.n2b);
+    else
+      b_copy_scaled(c, e, y16, w.n2b);
     if (res) b_copy_scaled(c, *res, r16.with(rf), w.n2b);
     return;
   }
   const int nu = (l > 0 && cfg.smooth_coarse > 0) ? cfg.smooth_coarse : cfg.smooth;
-  mr_smooth(H, l, p, r, e, nu, cfg, res);
+  mr_smooth(H, l, p, r, e, nu, cfg, res, add);
 }
 
 // e_c = (cfg.coarse_iters FGMRES steps on level lc) r_c, between the level's
@@ -184,9 +189,7 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, bool 
   H.T[l].prolong(p, ec.p, nullptr, e.p, nrhs, 2);  // e += P e_c
   op_apply(H, l, p, true, cfg, e.p, t.p, nrhs);
   b_xpay(c, r, nullptr, -1.0, t);
-  Vec y = r.with(w.y);
-  smooth(H, l, p, t, y, cfg);
-  b_axpy(c, nullptr, 1.0, y, e);
+  smooth(H, l, p, t, e, cfg, nullptr, false, true);  // e += S t
 }
 
 // Arnoldi steps from a normalised V_0 and started Givens state.  stop (host,
