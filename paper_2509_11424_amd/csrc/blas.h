@@ -42,6 +42,8 @@ void b_axpy(Context* c, const double2* a, double sgn, Vec x, Vec y);
 void b_xpay(Context* c, Vec x, const double2* a, double sgn, Vec y);
 // dst[e] = s[r] * src[e] (converting copy with a per-rhs real scale)
 void b_copy_scaled(Context* c, Vec dst, Vec src, const double* s);
+// dst[e] = s[r] * (a[e] - b[e]) (converting, per-rhs real scale)
+void b_sub_scaled(Context* c, Vec dst, Vec a, Vec b, const double* s);
 // dst[e] += s[r] * src[e] (converting, per-rhs real scale)
 void b_add_scaled(Context* c, Vec dst, Vec src, const double* s);
 // s[r] = sqrt(target2 / n2[r]) and inv[r] = 1 / s[r] (both 0 where n2[r] = 0;

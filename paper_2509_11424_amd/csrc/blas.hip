@@ -88,6 +88,24 @@ void b_copy_scaled(Context* c, Vec dst, Vec src, const double* s) {
 }
 
 template <class PD, class PS>
+__global__ void k_sub_scaled(void* dst, const void* a, const void* b, int64_t n, int nrhs, const double* s) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next())
+    std_<PD>(dst, i, s[it.r] * (ldd<PS>(a, i) - ldd<PS>(b, i)));
+}
+void b_sub_scaled(Context* c, Vec dst, Vec a, Vec b, const double* s) {
+  int64_t n = a.n();
+  MGM_CHECK(dst.n() == n && b.n() == n && dst.nrhs == a.nrhs && b.prec == a.prec, MGM_ERR_INVALID_ARG,
+            "sub: shape mismatch");
+  if (n == 0) return;
+  DISPATCH_PREC(dst.prec, PD, DISPATCH_PREC(a.prec, PS,
+      hipLaunchKernelGGL((k_sub_scaled<PD, PS>), dim3(ew_blocks(n)), dim3(256), 0, c->stream, dst.p, a.p, b.p,
+                         n, a.nrhs, s)));
+  MGM_LAUNCH_CHECK();
+}
+
+template <class PD, class PS>
 __global__ void k_add_scaled(void* dst, const void* src, int64_t n, int nrhs, const double* s) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -86,16 +86,25 @@ static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool p
 // written to *res (in the precision of r); unit says that every column of r
 // has norm 1 or 0 (a normalised Arnoldi vector), so no norms are taken; add
 // accumulates the smoothed correction into e instead of overwriting it.
+static bool smooth_f16(Hier& H, int l, mgm_prec p, const SolveCfg& cfg) {
+  return l == 0 && p == MGM_PREC_F32 && cfg.smooth_f16 && cfg.smooth > 0 && H.ws16.size() > 0 &&
+         H.ws16[0].rho != nullptr;
+}
+// sub != nullptr (FP16 smoother only): the smoother's input is r - *sub,
+// scaled by the norms of r.
 static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, Vec* res = nullptr,
-                   bool unit = false, bool add = false) {
-  if (l == 0 && p == MGM_PREC_F32 && cfg.smooth_f16 && cfg.smooth > 0 && H.ws16.size() > 0 &&
-      H.ws16[0].rho != nullptr) {
+                   bool unit = false, bool add = false, const Vec* sub = nullptr) {
+  MGM_CHECK(sub == nullptr || smooth_f16(H, l, p, cfg), MGM_ERR_INVALID_ARG, "smoother input r - q needs the FP16 smoother");
+  if (smooth_f16(H, l, p, cfg)) {
     LevelWS& w = H.ws16[0];
     Context* c = H.ctx;
     Vec r16 = r.as(MGM_PREC_F16, w.r), y16 = r.as(MGM_PREC_F16, w.t);
     if (!unit) b_norm2(c, H.scratch, r, w.n2a);
     b_unit_scales(c, unit ? nullptr : w.n2a, (double)r.nsite * r.dof, r.nrhs, w.mask, w.n2b);
-    b_copy_scaled(c, r16, r, w.mask);
+    if (sub)
+      b_sub_scaled(c, r16, r, *sub, w.mask);
+    else
+      b_copy_scaled(c, r16, r, w.mask);
     void* rf = w.rho;
     if (cfg.smooth >= 2 && w.qr2 != nullptr && H.fine->step_fusable(MGM_PREC_F16, r.nrhs))
       rf = mr_smooth_fused(H, r16, y16, cfg.smooth);
@@ -188,8 +197,14 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, bool 
   coarse_correction(H, l + 1, p, rc, ec, cfg);
   H.T[l].prolong(p, ec.p, nullptr, e.p, nrhs, 2);  // e += P e_c
   op_apply(H, l, p, true, cfg, e.p, t.p, nrhs);
-  b_xpay(c, r, nullptr, -1.0, t);
-  smooth(H, l, p, t, e, cfg, nullptr, false, true);  // e += S t
+  if (unit && smooth_f16(H, l, p, cfg)) {
+    // e += S (r - D e): the FP16 smoother's input formed in its conversion,
+    // scaled by the (unit) norms of r, as MR is homogeneous of degree one
+    smooth(H, l, p, r, e, cfg, nullptr, true, true, &t);
+  } else {
+    b_xpay(c, r, nullptr, -1.0, t);
+    smooth(H, l, p, t, e, cfg, nullptr, false, true);  // e += S t
+  }
 }
 
 // Arnoldi steps from a normalised V_0 and started Givens state.  stop (host,
