@@ -30,6 +30,10 @@ struct Transfer {
   // restrict: y_c = P^H x ; prolong: mode 0 y = P x_c, 1 y = x - P x_c, 2 y += P x_c
   void restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const;
   void prolong(mgm_prec p, const void* xc, const void* x, void* y, int nrhs, int mode) const;
+  // FP32 transfers whose fine input is FP16 scaled per rhs by xs:
+  // y_c = P^H (xs x16) and y = xs x16 + P x_c
+  void restrict16(const __half2* x16, const double* xs, float2* yc, int nrhs) const;
+  void prolong16(const float2* xc, const __half2* x16, const double* xs, float2* y, int nrhs) const;
   double bytes(mgm_prec p, int nrhs) const;
 };
 

@@ -227,9 +227,11 @@ __device__ __forceinline__ void lds_ld4(const cx<R>* p, cx<R> (&v)[4]) {
 // Thread (g, u) accumulates the output tile u = (k/4, r/4) over the rows
 // g, g + G, ... of every chunk; the G partial tiles are then summed in group
 // order through LDS.
-template <class P, class PM>
-__global__ __launch_bounds__(256) void k_restrict(const typename P::S* __restrict__ x, typename P::S* __restrict__ yc,
-                                                  const typename PM::S* __restrict__ Pm, TGeom t, int nrhs, int rc) {
+// The input x may be stored in another format PX, scaled per rhs by xs.
+template <class P, class PM, class PX = P>
+__global__ __launch_bounds__(256) void k_restrict(const typename PX::S* __restrict__ x, typename P::S* __restrict__ yc,
+                                                  const typename PM::S* __restrict__ Pm, TGeom t, int nrhs, int rc,
+                                                  const double* __restrict__ xs) {
   using R = typename P::R;
   extern __shared__ __align__(16) char smem[];
   const int64_t a = blockIdx.x >> 1;
@@ -263,7 +265,9 @@ __global__ __launch_bounds__(256) void k_restrict(const typename P::S* __restric
       cx<R> v = {0, 0};
       if (r < rt) {
         const int row = row0 + ii, loc = row / half, j = row - loc * half;
-        v = P::ld(x, ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + r);
+        const cx<typename PX::R> u = PX::ld(x, ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + r);
+        v = {(R)u.re, (R)u.im};
+        if (xs) v = (R)xs[r0 + r] * v;
       }
       sX[i] = v;
     }
@@ -303,14 +307,16 @@ __global__ __launch_bounds__(256) void k_restrict(const typename P::S* __restric
   }
 }
 
-// y = P x_c (mode 0), x - P x_c (mode 1), y + P x_c (mode 2)
+// y = P x_c (mode 0), x - P x_c (mode 1), y + P x_c (mode 2), or
+// xs * x + P x_c (mode 3, x stored as PX and scaled per rhs by xs)
 // P rows of a chunk sit transposed in LDS; thread u = (q, r/4) owns rows
 // q, q + Q, ..., q + (TI-1) Q of the chunk (Q = rc / TI) by four right-hand
 // sides, and loads the destination entries it updates before its products.
-template <class P, class PM, int TI>
+template <class P, class PM, int TI, class PX = P>
 __global__ __launch_bounds__(256) void k_prolong(const typename P::S* __restrict__ xc, const typename P::S* __restrict__ x,
                                                  typename P::S* __restrict__ y, const typename PM::S* __restrict__ Pm,
-                                                 TGeom t, int nrhs, int mode, int rc) {
+                                                 TGeom t, int nrhs, int mode, int rc,
+                                                 const typename PX::S* __restrict__ xq, const double* __restrict__ xs) {
   using R = typename P::R;
   extern __shared__ __align__(16) char smem[];
   const int64_t a = blockIdx.x >> 1;
@@ -355,7 +361,14 @@ __global__ __launch_bounds__(256) void k_prolong(const typename P::S* __restrict
 #pragma unroll
         for (int rr = 0; rr < 4; rr++) {
           acc[i][rr] = {0, 0};
-          if (mode != 0 && base[i] >= 0 && 4 * rtt + rr < rt) acc[i][rr] = P::ld(src, base[i] + rr);
+          if (mode != 0 && base[i] >= 0 && 4 * rtt + rr < rt) {
+            if (mode == 3) {
+              const cx<typename PX::R> u = PX::ld(xq, base[i] + rr);
+              acc[i][rr] = (R)xs[r0 + 4 * rtt + rr] * cx<R>{(R)u.re, (R)u.im};
+            } else {
+              acc[i][rr] = P::ld(src, base[i] + rr);
+            }
+          }
         }
       }
       if (mode == 1) {
@@ -407,11 +420,11 @@ void Transfer::restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const {
   if (p == MGM_PREC_F64) {
     const int rc = restrict_chunk_rows(t, rt, 16);
     hipLaunchKernelGGL((k_restrict<F64, F64>), nb, tb, restrict_lds(t, rt, rc, 16), ctx->stream,
-                       (const double2*)x, (double2*)yc, P64, t, nrhs, rc);
+                       (const double2*)x, (double2*)yc, P64, t, nrhs, rc, nullptr);
   } else if (p == MGM_PREC_F32) {
     const int rc = restrict_chunk_rows(t, rt, 8);
     hipLaunchKernelGGL((k_restrict<F32, F16>), nb, tb, restrict_lds(t, rt, rc, 8), ctx->stream,
-                       (const float2*)x, (float2*)yc, P16, t, nrhs, rc);
+                       (const float2*)x, (float2*)yc, P16, t, nrhs, rc, nullptr);
   } else {
     throw Error(MGM_ERR_INVALID_ARG, "restrict: precision must be F64 or F32");
   }
@@ -427,14 +440,40 @@ void Transfer::prolong(mgm_prec p, const void* xc, const void* x, void* y, int n
   if (p == MGM_PREC_F64) {
     const int rc = prolong_chunk_rows(t, rt, 16, 1);
     hipLaunchKernelGGL((k_prolong<F64, F64, 1>), nb, tb, prolong_lds(t, rt, rc, 16), ctx->stream,
-                       (const double2*)xc, (const double2*)x, (double2*)y, P64, t, nrhs, mode, rc);
+                       (const double2*)xc, (const double2*)x, (double2*)y, P64, t, nrhs, mode, rc, nullptr, nullptr);
   } else if (p == MGM_PREC_F32) {
     const int rc = prolong_chunk_rows(t, rt, 8, 2);
     hipLaunchKernelGGL((k_prolong<F32, F16, 2>), nb, tb, prolong_lds(t, rt, rc, 8), ctx->stream,
-                       (const float2*)xc, (const float2*)x, (float2*)y, P16, t, nrhs, mode, rc);
+                       (const float2*)xc, (const float2*)x, (float2*)y, P16, t, nrhs, mode, rc, nullptr, nullptr);
   } else {
     throw Error(MGM_ERR_INVALID_ARG, "prolong: precision must be F64 or F32");
   }
+  MGM_LAUNCH_CHECK();
+}
+
+void Transfer::restrict16(const __half2* x16, const double* xs, float2* yc, int nrhs) const {
+  ProfScope ps(ctx, KC_TRANSFER, bytes(MGM_PREC_F32, nrhs));
+  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(kTransferTB);
+  const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
+  MGM_CHECK(t.ntv <= 32 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 32 test vectors and 1024 sites per aggregate");
+  MGM_CHECK(P16 != nullptr && xs != nullptr, MGM_ERR_INVALID_ARG, "FP16 transfer input needs P16 and scales");
+  const int rc = restrict_chunk_rows(t, rt, 8);
+  hipLaunchKernelGGL((k_restrict<F32, F16, F16>), nb, tb, restrict_lds(t, rt, rc, 8), ctx->stream, x16, yc, P16, t,
+                     nrhs, rc, xs);
+  MGM_LAUNCH_CHECK();
+}
+
+void Transfer::prolong16(const float2* xc, const __half2* x16, const double* xs, float2* y, int nrhs) const {
+  ProfScope ps(ctx, KC_TRANSFER, bytes(MGM_PREC_F32, nrhs));
+  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(kTransferTB);
+  const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
+  MGM_CHECK(t.ntv <= 32 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 32 test vectors and 1024 sites per aggregate");
+  MGM_CHECK(P16 != nullptr && xs != nullptr, MGM_ERR_INVALID_ARG, "FP16 transfer input needs P16 and scales");
+  const int rc = prolong_chunk_rows(t, rt, 8, 2);
+  hipLaunchKernelGGL((k_prolong<F32, F16, 2, F16>), nb, tb, prolong_lds(t, rt, rc, 8), ctx->stream, xc,
+                     (const float2*)nullptr, y, P16, t, nrhs, 3, rc, x16, xs);
   MGM_LAUNCH_CHECK();
 }
 

@@ -91,10 +91,18 @@ static bool smooth_f16(Hier& H, int l, mgm_prec p, const SolveCfg& cfg) {
          H.ws16[0].rho != nullptr;
 }
 // sub != nullptr (FP16 smoother only): the smoother's input is r - *sub,
-// scaled by the norms of r.
+// scaled by the norms of r.  o16 != nullptr (FP16 smoother only): e and the
+// residual are not converted; o16 receives the FP16 correction, the FP16
+// residual and the per-rhs factors that scale both back.
+struct Smooth16 {
+  const __half2* y = nullptr;
+  const __half2* r = nullptr;
+  const double* inv = nullptr;
+};
 static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, Vec* res = nullptr,
-                   bool unit = false, bool add = false, const Vec* sub = nullptr) {
-  MGM_CHECK(sub == nullptr || smooth_f16(H, l, p, cfg), MGM_ERR_INVALID_ARG, "smoother input r - q needs the FP16 smoother");
+                   bool unit = false, bool add = false, const Vec* sub = nullptr, Smooth16* o16 = nullptr) {
+  MGM_CHECK((sub == nullptr && o16 == nullptr) || smooth_f16(H, l, p, cfg), MGM_ERR_INVALID_ARG,
+            "FP16 smoother options without the FP16 smoother");
   if (smooth_f16(H, l, p, cfg)) {
     LevelWS& w = H.ws16[0];
     Context* c = H.ctx;
@@ -110,6 +118,12 @@ static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg
       rf = mr_smooth_fused(H, r16, y16, cfg.smooth);
     else
       mr_smooth(H, 0, MGM_PREC_F16, r16, y16, cfg.smooth, cfg);
+    if (o16) {
+      o16->y = (const __half2*)y16.p;
+      o16->r = (const __half2*)rf;
+      o16->inv = w.n2b;
+      return;
+    }
     if (add)
       b_add_scaled(c, e, y16, w.n2b);
     else
@@ -189,13 +203,22 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, bool 
     b_axpy(c, nullptr, 1.0, y, e);
     return;
   }
-  // pre-smoothing; the smoother's own recursion leaves t = r - D e
-  smooth(H, l, p, r, e, cfg, &t, unit);
+  // pre-smoothing; the smoother's own recursion leaves t = r - D e.  With
+  // the FP16 smoother, e and t stay in FP16 and the transfers read them
+  // scaled: rc = P^H t, e = e + P e_c
+  Smooth16 o16;
+  smooth(H, l, p, r, e, cfg, &t, unit, false, nullptr, smooth_f16(H, l, p, cfg) ? &o16 : nullptr);
   LevelWS& wc = H.ws(l + 1, p);
   Vec rc = H.vec(l + 1, p, wc.bc, nrhs), ec = H.vec(l + 1, p, wc.xc, nrhs);
-  H.T[l].restrict_(p, t.p, rc.p, nrhs);
+  if (o16.y)
+    H.T[l].restrict16(o16.r, o16.inv, (float2*)rc.p, nrhs);
+  else
+    H.T[l].restrict_(p, t.p, rc.p, nrhs);
   coarse_correction(H, l + 1, p, rc, ec, cfg);
-  H.T[l].prolong(p, ec.p, nullptr, e.p, nrhs, 2);  // e += P e_c
+  if (o16.y)
+    H.T[l].prolong16((const float2*)ec.p, o16.y, o16.inv, (float2*)e.p, nrhs);
+  else
+    H.T[l].prolong(p, ec.p, nullptr, e.p, nrhs, 2);  // e += P e_c
   op_apply(H, l, p, true, cfg, e.p, t.p, nrhs);
   if (unit && smooth_f16(H, l, p, cfg)) {
     // e += S (r - D e): the FP16 smoother's input formed in its conversion,
