@@ -392,7 +392,7 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
   LevelWS& w64 = H.ws64[l];
   LevelWS& w32 = H.ws32[l];
   MGM_CHECK(w32.V != nullptr, MGM_ERR_INVALID_ARG, "mixed solve needs a hierarchy built with mixed != 0");
-  Vec r = b.with(w64.r), t = b.with(w64.t);
+  Vec r = b.with(w64.r);
   Vec r32 = H.vec(l, MGM_PREC_F32, w32.bc, nrhs), e32 = H.vec(l, MGM_PREC_F32, w32.xc, nrhs);
   double* pin = H.pinned;
   b_norm2(c, H.scratch, b, w64.n2b);
@@ -446,8 +446,7 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
     }
     if (all) break;
     MGM_HIP(hipMemcpyAsync(w64.mask, mask.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-    b_scale_rhs(c, r, w64.mask);
-    b_copy(c, r32, r);
+    b_copy_scaled(c, r32, r, w64.mask);  // converged right-hand sides get a zero residual
     SolveOut inner;
     try {
       fgmres_tol(H, l, MGM_PREC_F32, r32, e32, cur.inner_tol, 4, cfg.maxiter - steps, precond, cur, &inner);
@@ -459,8 +458,7 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
     steps += inner.iterations;
     out->iterations += inner.iterations;
     out->restarts += inner.restarts;
-    b_copy(c, t, e32);
-    b_axpy(c, nullptr, 1.0, t, x);
+    b_add_scaled(c, x, e32, w64.mask);  // x += e (zero for converged right-hand sides)
     H.apply(l, MGM_PREC_F64, x.p, r.p, nrhs);
     b_xpay(c, b, nullptr, -1.0, r);  // r = b - D x in FP64
     c->sync();  // mask staging
