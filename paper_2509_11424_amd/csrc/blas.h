@@ -67,9 +67,10 @@ void b_finalize_dot_norm(Context* c, Scratch& s, const double2* part, int64_t nb
                          double* qq);
 // out[i*nrhs + r] = V_i^H w for i < k; basis V_i = base + i * stride (elements)
 void b_multidot(Context* c, Scratch& s, Vec base, int64_t stride, int k, Vec w, double2* out);
-// w += sgn * sum_i h[i*nrhs + r] V_i ; if n2 != nullptr also n2[r] = |w|^2 after the update
+// w += sgn * sum_i h[i*nrhs + r] V_i (overwrite: w = sgn * sum ..., w not read);
+// if n2 != nullptr also n2[r] = |w|^2 after the update
 void b_multiaxpy(Context* c, Scratch& s, Vec base, int64_t stride, int k, const double2* h, double sgn,
-                 Vec w, double* n2);
+                 Vec w, double* n2, bool overwrite = false);
 // w -= sum_i h_i V_i and out[i*nrhs + r] = V_i^H w (updated), one sweep, k <= kFusedGS
 constexpr int kFusedGS = 16;
 void b_multiaxpy_dot(Context* c, Scratch& s, Vec base, int64_t stride, int k, const double2* h, Vec w,

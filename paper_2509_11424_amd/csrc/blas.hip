@@ -484,7 +484,7 @@ void b_multidot(Context* c, Scratch& s, Vec base, int64_t stride, int k, Vec w, 
 
 template <class P>
 __global__ void k_multiaxpy(const void* base, int64_t stride, int k, const double2* h, double sgn, void* w,
-                            int nrhs, RedPlan pl, double2* partial, int want_norm) {
+                            int nrhs, RedPlan pl, double2* partial, int want_norm, int overwrite) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double2 v[1] = {make_double2(0, 0)};
   if (g < pl.J * nrhs) {
@@ -494,7 +494,7 @@ __global__ void k_multiaxpy(const void* base, int64_t stride, int k, const doubl
     double nn = 0;
     for (int64_t m = j; m < pl.m; m += pl.J) {
       int64_t e = m * nrhs + r;
-      cx<double> wv = ldd<P>(w, e);
+      cx<double> wv = overwrite ? cx<double>{0, 0} : ldd<P>(w, e);
       for (int i = 0; i < k; i++) {
         double2 hh = h[(int64_t)i * nrhs + r];
         cx<double> hc = {sgn * hh.x, sgn * hh.y};
@@ -511,12 +511,12 @@ __global__ void k_multiaxpy(const void* base, int64_t stride, int k, const doubl
   if (want_norm) block_store<1>(v, partial, nrhs);
 }
 void b_multiaxpy(Context* c, Scratch& s, Vec base, int64_t stride, int k, const double2* h, double sgn, Vec w,
-                 double* n2) {
+                 double* n2, bool overwrite) {
   RedPlan pl = red_plan(w.n(), w.nrhs);
   need(s, (size_t)pl.blocks * w.nrhs);
   DISPATCH_PREC(w.prec, P, hipLaunchKernelGGL(k_multiaxpy<P>, dim3(pl.blocks), dim3(256), 0, c->stream,
                                               (const void*)base.p, stride, k, h, sgn, w.p, w.nrhs, pl,
-                                              s.partial, n2 ? 1 : 0));
+                                              s.partial, n2 ? 1 : 0, overwrite ? 1 : 0));
   if (n2)
     hipLaunchKernelGGL(k_finalize_r, dim3(w.nrhs), dim3(64), 0, c->stream, s.partial,
                        (int)pl.blocks, 1, w.nrhs, n2);

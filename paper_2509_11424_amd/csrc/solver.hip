@@ -78,6 +78,12 @@ static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const So
 
 static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool precond, const SolveCfg& cfg);
 
+// the fine-level smoother of the mixed V-cycle runs in FP16 storage
+static bool smooth_f16(Hier& H, int l, mgm_prec p, const SolveCfg& cfg) {
+  return l == 0 && p == MGM_PREC_F32 && cfg.smooth_f16 && cfg.smooth > 0 && H.ws16.size() > 0 &&
+         H.ws16[0].rho != nullptr;
+}
+
 // Fine-level smoothing of the mixed V-cycle in FP16 storage: the input is
 // scaled per rhs to unit RMS entries (MR is homogeneous of degree one, and
 // FP16 keeps its full precision away from the subnormal range), smoothed with
@@ -86,10 +92,6 @@ static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool p
 // written to *res (in the precision of r); unit says that every column of r
 // has norm 1 or 0 (a normalised Arnoldi vector), so no norms are taken; add
 // accumulates the smoothed correction into e instead of overwriting it.
-static bool smooth_f16(Hier& H, int l, mgm_prec p, const SolveCfg& cfg) {
-  return l == 0 && p == MGM_PREC_F32 && cfg.smooth_f16 && cfg.smooth > 0 && H.ws16.size() > 0 &&
-         H.ws16[0].rho != nullptr;
-}
 // sub != nullptr (FP16 smoother only): the smoother's input is r - *sub,
 // scaled by the norms of r.  o16 != nullptr (FP16 smoother only): e and the
 // residual are not converted; o16 receives the FP16 correction, the FP16
@@ -300,8 +302,7 @@ static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool p
   b_normalize(c, V0, w.n2a, nullptr);
   k_gmres_start(c, w.G, w.n2a, nrhs);
   int kk = arnoldi(H, l, p, nrhs, std::min(k, w.m), precond, cfg, nullptr, true);
-  b_zero(c, x);
-  b_multiaxpy(c, H.scratch, b.with(precond ? w.Z : w.V), H.n(l) * nrhs, kk, w.G.y, 1.0, x, nullptr);
+  b_multiaxpy(c, H.scratch, b.with(precond ? w.Z : w.V), H.n(l) * nrhs, kk, w.G.y, 1.0, x, nullptr, true);
 }
 
 // Restarted FGMRES to |r_i| <= tol_rel |b_i| for every rhs.  x0 = 0.
@@ -318,12 +319,11 @@ static void fgmres_tol(Hier& H, int l, mgm_prec p, Vec b, Vec x, double tol_rel,
   MGM_HIP(hipMemcpyAsync(pin, w.n2a, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
   c->sync();
   for (int i = 0; i < nrhs; i++) b2[i] = pin[i];
-  b_zero(c, x);
+  bool xset = false;  // x is written by the first solution update (zeroed if there is none)
   int steps = 0;
   for (int cyc = 0; cyc < maxcycles && steps < maxsteps; cyc++) {
     if (cyc == 0) {
-      b_copy(c, r, b);
-      r2 = b2;
+      r2 = b2;  // r = b, read from b below
     } else {
       H.apply(l, p, x.p, r.p, nrhs);
       b_xpay(c, b, nullptr, -1.0, r);
@@ -349,18 +349,19 @@ static void fgmres_tol(Hier& H, int l, mgm_prec p, Vec b, Vec x, double tol_rel,
     }
     MGM_HIP(hipMemcpyAsync(w.n2b, pin, sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
     MGM_HIP(hipMemcpyAsync(w.mask, pin + nrhs, sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-    b_copy(c, V0, r);
-    b_scale_rhs(c, V0, w.mask);
+    b_copy_scaled(c, V0, cyc == 0 ? b : r, w.mask);
     k_gmres_start(c, w.G, w.n2b, nrhs);
     c->sync();  // the staging buffer is reused by arnoldi
     int k = arnoldi(H, l, p, nrhs, std::min(w.m, maxsteps - steps), precond, cfg, stop.data(), false);
-    b_multiaxpy(c, H.scratch, b.with(precond ? w.Z : w.V), H.n(l) * nrhs, k, w.G.y, 1.0, x, nullptr);
+    b_multiaxpy(c, H.scratch, b.with(precond ? w.Z : w.V), H.n(l) * nrhs, k, w.G.y, 1.0, x, nullptr, !xset);
+    xset = true;
     steps += k;
     if (out) {
       out->iterations += k;
       out->restarts += 1;
     }
   }
+  if (!xset) b_zero(c, x);
 }
 
 static void true_residual(Hier& H, int l, Vec b, Vec x, SolveOut* out, double tol) {
