@@ -60,7 +60,9 @@ void b_mr_update(Context* c, const double2* qr, const double* qq, Vec rho, Vec q
 
 // ---- reductions (out in device memory, FP64) ----
 void b_dot(Context* c, Scratch& s, Vec x, Vec y, double2* out);          // out[r] = x^H y
-void b_norm2(Context* c, Scratch& s, Vec x, double* out);                // out[r] = |x|^2
+void b_norm2(Context* c, Scratch& s, Vec x, double* out);                 // out[r] = |x|^2
+// r = b - r and out[r] = |r|^2 (of the stored values) in one sweep
+void b_rsub_norm2(Context* c, Scratch& s, Vec b, Vec r, double* out);
 void b_dot_norm(Context* c, Scratch& s, Vec q, Vec rho, double2* qr, double* qq);  // q^H rho, |q|^2
 // sums per-block partials [2][nrhs][nblk] (q^H rho, then |q|^2) written by a fused kernel
 void b_finalize_dot_norm(Context* c, Scratch& s, const double2* part, int64_t nblk, int nrhs, double2* qr,

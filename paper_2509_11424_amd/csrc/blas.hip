@@ -394,6 +394,35 @@ void b_norm2(Context* c, Scratch& s, Vec x, double* out) {
   MGM_LAUNCH_CHECK();
 }
 
+// r = b - r with the norms of the stored r
+template <class P>
+__global__ void k_rsub_norm2(const void* b, void* r, int nrhs, RedPlan pl, double2* partial) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 v[1] = {make_double2(0, 0)};
+  if (g < pl.J * nrhs) {
+    int rr = (int)(g % nrhs);
+    int64_t j = g / nrhs;
+    double a = 0;
+    for (int64_t m = j; m < pl.m; m += pl.J) {
+      const int64_t e = m * nrhs + rr;
+      std_<P>(r, e, ldd<P>(b, e) - ldd<P>(r, e));
+      a += norm2(ldd<P>(r, e));
+    }
+    v[0] = make_double2(a, 0);
+  }
+  block_store<1>(v, partial, nrhs);
+}
+void b_rsub_norm2(Context* c, Scratch& s, Vec b, Vec r, double* out) {
+  MGM_CHECK(b.n() == r.n() && b.nrhs == r.nrhs && b.prec == r.prec, MGM_ERR_INVALID_ARG, "rsub: shape mismatch");
+  RedPlan pl = red_plan(r.n(), r.nrhs);
+  need(s, (size_t)pl.blocks * r.nrhs);
+  DISPATCH_PREC(r.prec, P, hipLaunchKernelGGL(k_rsub_norm2<P>, dim3(pl.blocks), dim3(256), 0, c->stream, b.p,
+                                              r.p, r.nrhs, pl, s.partial));
+  hipLaunchKernelGGL(k_finalize_r, dim3(r.nrhs), dim3(64), 0, c->stream, s.partial,
+                     (int)pl.blocks, 1, r.nrhs, out);
+  MGM_LAUNCH_CHECK();
+}
+
 template <class P>
 __global__ void k_dot_norm(const void* q, const void* rho, int nrhs, RedPlan pl, double2* partial) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -400,8 +400,10 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
   MGM_HIP(hipMemcpyAsync(pin, w64.n2b, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
   c->sync();
   std::vector<double> b2(pin, pin + nrhs), mask(nrhs);
-  b_zero(c, x);
-  b_copy(c, r, b);
+  // x = 0 and r = b are not materialised: the first cycle reads b and
+  // overwrites x (zeroed at the end if no cycle ran); w64.n2a holds |r|^2
+  // from the fused residual update of the previous cycle
+  bool x_zero = true, r_is_b = true;
   const bool precond = l < H.L - 1;
   // the learned smoother falls back to plain MG for the rest of the solve
   // when an inner solve produces non-finite values or fails to halve the
@@ -413,15 +415,21 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
     cur.kind = MGM_SOLVE_MG_MIXED;
     out->fallbacks += 1;
     if (restart) {
-      b_zero(c, x);
-      b_copy(c, r, b);
+      x_zero = true;
+      r_is_b = true;
     }
+  };
+  auto residual_norms = [&]() {
+    if (r_is_b) {
+      for (int i = 0; i < nrhs; i++) pin[i] = b2[i];
+      return;
+    }
+    MGM_HIP(hipMemcpyAsync(pin, w64.n2a, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
   };
   int steps = 0;
   for (int outer = 0; outer < 64 && steps < cfg.maxiter; outer++) {
-    b_norm2(c, H.scratch, r, w64.n2a);
-    MGM_HIP(hipMemcpyAsync(pin, w64.n2a, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
-    c->sync();
+    residual_norms();
     if (cur.net) {
       bool bad = false, nonfinite = false;
       for (int i = 0; i < nrhs; i++) {
@@ -430,11 +438,7 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
       }
       if (nonfinite || bad) {
         fall_back(nonfinite);
-        if (nonfinite) {
-          b_norm2(c, H.scratch, r, w64.n2a);
-          MGM_HIP(hipMemcpyAsync(pin, w64.n2a, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
-          c->sync();
-        }
+        if (nonfinite) residual_norms();
       }
     }
     bool all = true;
@@ -447,7 +451,7 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
     }
     if (all) break;
     MGM_HIP(hipMemcpyAsync(w64.mask, mask.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-    b_copy_scaled(c, r32, r, w64.mask);  // converged right-hand sides get a zero residual
+    b_copy_scaled(c, r32, r_is_b ? b : r, w64.mask);  // converged right-hand sides get a zero residual
     SolveOut inner;
     try {
       fgmres_tol(H, l, MGM_PREC_F32, r32, e32, cur.inner_tol, 4, cfg.maxiter - steps, precond, cur, &inner);
@@ -459,11 +463,18 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
     steps += inner.iterations;
     out->iterations += inner.iterations;
     out->restarts += inner.restarts;
-    b_add_scaled(c, x, e32, w64.mask);  // x += e (zero for converged right-hand sides)
+    // x += e (zero for converged right-hand sides)
+    if (x_zero)
+      b_copy_scaled(c, x, e32, w64.mask);
+    else
+      b_add_scaled(c, x, e32, w64.mask);
+    x_zero = false;
     H.apply(l, MGM_PREC_F64, x.p, r.p, nrhs);
-    b_xpay(c, b, nullptr, -1.0, r);  // r = b - D x in FP64
+    b_rsub_norm2(c, H.scratch, b, r, w64.n2a);  // r = b - D x in FP64, and |r|^2
+    r_is_b = false;
     c->sync();  // mask staging
   }
+  if (x_zero) b_zero(c, x);
 }
 
 void solve(Hier& H, int l, const SolveCfg& cfg, const double2* b, double2* x, int nrhs, SolveOut* out) {
