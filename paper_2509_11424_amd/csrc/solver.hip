@@ -326,8 +326,7 @@ static void fgmres_tol(Hier& H, int l, mgm_prec p, Vec b, Vec x, double tol_rel,
       r2 = b2;  // r = b, read from b below
     } else {
       H.apply(l, p, x.p, r.p, nrhs);
-      b_xpay(c, b, nullptr, -1.0, r);
-      b_norm2(c, H.scratch, r, w.n2a);
+      b_rsub_norm2(c, H.scratch, b, r, w.n2a);  // r = b - D x and |r|^2
       MGM_HIP(hipMemcpyAsync(pin, w.n2a, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
       c->sync();
       for (int i = 0; i < nrhs; i++) r2[i] = pin[i];
@@ -454,7 +453,10 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
     b_copy_scaled(c, r32, r_is_b ? b : r, w64.mask);  // converged right-hand sides get a zero residual
     SolveOut inner;
     try {
-      fgmres_tol(H, l, MGM_PREC_F32, r32, e32, cur.inner_tol, 4, cfg.maxiter - steps, precond, cur, &inner);
+      // one Arnoldi cycle, stopped by its residual estimate: the true
+      // residual of the next defect-correction cycle checks it, so no FP32
+      // restart is spent on confirming convergence
+      fgmres_tol(H, l, MGM_PREC_F32, r32, e32, cur.inner_tol, 1, cfg.maxiter - steps, precond, cur, &inner);
     } catch (const Error& e) {
       if (cur.net == nullptr || e.code != MGM_ERR_NUMERIC) throw;
       fall_back(true);
