@@ -56,7 +56,9 @@ void b_normalize(Context* c, Vec x, const double* n2, double* beta);
 // x[r] *= m[r] (device real, per rhs)
 void b_scale_rhs(Context* c, Vec x, const double* m);
 // minimal-residual update: alpha = qr[r] / qq[r]; y += alpha rho; rho -= alpha q
-void b_mr_update(Context* c, const double2* qr, const double* qq, Vec rho, Vec q, Vec y);
+// (rho_in: read the old rho from there instead; y_zero: y = alpha rho, y not read)
+void b_mr_update(Context* c, const double2* qr, const double* qq, Vec rho, Vec q, Vec y,
+                 const Vec* rho_in = nullptr, bool y_zero = false);
 
 // ---- reductions (out in device memory, FP64) ----
 void b_dot(Context* c, Scratch& s, Vec x, Vec y, double2* out);          // out[r] = x^H y

@@ -226,8 +226,9 @@ void b_scale_rhs(Context* c, Vec x, const double* m) {
 }
 
 template <class P>
-__global__ __launch_bounds__(256) void k_mr_update(const double2* qr, const double* qq, void* rho, const void* q,
-                                                   void* y, int64_t n, int nrhs) {
+__global__ __launch_bounds__(256) void k_mr_update(const double2* qr, const double* qq, const void* rho_in,
+                                                   void* rho, const void* q, void* y, int64_t n, int nrhs,
+                                                   int y_zero) {
   __shared__ double2 sa[256];  // alpha = qr / qq per rhs (nrhs <= 256)
   for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
     const double d = qq[r];
@@ -238,8 +239,8 @@ __global__ __launch_bounds__(256) void k_mr_update(const double2* qr, const doub
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next()) {
     const cx<double> al = {sa[it.r].x, sa[it.r].y};
-    cx<double> rv = ldd<P>(rho, i);
-    cx<double> yv = ldd<P>(y, i);
+    cx<double> rv = ldd<P>(rho_in, i);
+    cx<double> yv = y_zero ? cx<double>{0, 0} : ldd<P>(y, i);
     fma_(yv, al, rv);
     cx<double> qv = ldd<P>(q, i);
     rv = rv - al * qv;
@@ -247,12 +248,16 @@ __global__ __launch_bounds__(256) void k_mr_update(const double2* qr, const doub
     std_<P>(rho, i, rv);
   }
 }
-void b_mr_update(Context* c, const double2* qr, const double* qq, Vec rho, Vec q, Vec y) {
+void b_mr_update(Context* c, const double2* qr, const double* qq, Vec rho, Vec q, Vec y, const Vec* rho_in,
+                 bool y_zero) {
   int64_t n = rho.n();
   if (n == 0) return;
   MGM_CHECK(rho.nrhs >= 1 && rho.nrhs <= 256, MGM_ERR_INVALID_ARG, "at most 256 right-hand sides");
+  MGM_CHECK(rho_in == nullptr || (rho_in->n() == n && rho_in->prec == rho.prec), MGM_ERR_INVALID_ARG,
+            "mr update: shape mismatch");
+  const void* src = rho_in ? rho_in->p : rho.p;
   DISPATCH_PREC(rho.prec, P, hipLaunchKernelGGL(k_mr_update<P>, dim3(ew_blocks(n)), dim3(256), 0, c->stream,
-                                                qr, qq, rho.p, q.p, y.p, n, rho.nrhs));
+                                                qr, qq, src, rho.p, q.p, y.p, n, rho.nrhs, y_zero ? 1 : 0));
   MGM_LAUNCH_CHECK();
 }
 

@@ -37,10 +37,9 @@ static void op_apply(Hier& H, int l, mgm_prec p, bool inner, const SolveCfg& cfg
 static void* mr_smooth_fused(Hier& H, Vec b, Vec y, int nu) {
   LevelWS& w = H.ws16[0];
   Context* c = H.ctx;
-  b_zero(c, y);
   int64_t nb = H.fine->apply_dot(MGM_PREC_F16, b.p, w.q, b.nrhs, H.dpart);
   b_finalize_dot_norm(c, H.scratch, H.dpart, nb, b.nrhs, w.qr, w.qq);
-  b_mr_update(c, w.qr, w.qq, b, b.with(w.q), y);
+  b_mr_update(c, w.qr, w.qq, b, b.with(w.q), y, nullptr, true);  // y = alpha b
   void* r = b.p;
   void* r_next = w.rho;
   for (int i = 1; i < nu; i++) {
@@ -61,18 +60,22 @@ static void mr_smooth(Hier& H, int l, mgm_prec p, Vec b, Vec y, int nu, const So
   LevelWS& w = H.ws(l, p);
   Context* c = H.ctx;
   Vec rho = res ? *res : b.with(w.rho), q = b.with(w.q);
-  if (!add) b_zero(c, y);
-  b_copy(c, rho, b);
+  // the first step reads b in place of rho = b, and sets y unless adding
+  if (nu <= 0) {
+    if (!add) b_zero(c, y);
+    b_copy(c, rho, b);
+  }
   for (int i = 0; i < nu; i++) {
+    const Vec cur = i == 0 ? b : rho;
     if (l == 0) {
       // fine level: q^H rho and |q|^2 come out of the dslash itself
-      const int64_t nb = H.fine->apply_dot(p, rho.p, q.p, b.nrhs, H.dpart);
+      const int64_t nb = H.fine->apply_dot(p, cur.p, q.p, b.nrhs, H.dpart);
       b_finalize_dot_norm(c, H.scratch, H.dpart, nb, b.nrhs, w.qr, w.qq);
     } else {
-      op_apply(H, l, p, true, cfg, rho.p, q.p, b.nrhs);
-      b_dot_norm(c, H.scratch, q, rho, w.qr, w.qq);
+      op_apply(H, l, p, true, cfg, cur.p, q.p, b.nrhs);
+      b_dot_norm(c, H.scratch, q, cur, w.qr, w.qq);
     }
-    b_mr_update(c, w.qr, w.qq, rho, q, y);
+    b_mr_update(c, w.qr, w.qq, rho, q, y, i == 0 ? &b : nullptr, i == 0 && !add);
   }
 }
 
