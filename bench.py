@@ -288,7 +288,7 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     kind = "mg_mixed" if mixed else "mg"
     # mixed form: FP16-storage fine smoother, BF16 MFMA coarse operators,
     # autotuned launch shapes and graph-captured coarse-grid corrections
-    # smoothing 8 / 3 (mixed form; 6 / 2 for FP64) on the fine / coarser levels, one
+    # smoothing 9 / 3 (mixed form; 6 / 2 for FP64) on the fine / coarser levels, one
     # coarse-solve step and (mixed form) FP32 inner solves that reduce the
     # residual by 4e-3 per FP64 defect-correction cycle: the fastest settings
     # measured for each form
@@ -571,7 +571,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c4", choices=sorted(CONFIGS))
-    ap.add_argument("--smooth", type=int, default=8, help="fine-level smoothing steps of the timed form")
+    ap.add_argument("--smooth", type=int, default=9, help="fine-level smoothing steps of the timed form")
     ap.add_argument("--smooth-coarse", type=int, default=3, help="smoothing steps on the coarser levels")
     ap.add_argument("--coarse-iters", type=int, default=1, help="FGMRES steps of a coarse-grid solve")
     ap.add_argument("--inner-tol", type=float, default=4e-3,
