@@ -87,18 +87,20 @@ static bool smooth_f16(Hier& H, int l, mgm_prec p, const SolveCfg& cfg) {
          H.ws16[0].rho != nullptr;
 }
 
-// Fine-level smoothing of the mixed V-cycle in FP16 storage: the input is
-// scaled per rhs to unit RMS entries (MR is homogeneous of degree one, and
-// FP16 keeps its full precision away from the subnormal range), smoothed with
-// FP16 vectors and FP32 arithmetic, and scaled back into FP32.
-// With res != nullptr the residual r - D e that the smoother carries is also
-// written to *res (in the precision of r); unit says that every column of r
-// has norm 1 or 0 (a normalised Arnoldi vector), so no norms are taken; add
-// accumulates the smoothed correction into e instead of overwriting it.
-// sub != nullptr (FP16 smoother only): the smoother's input is r - *sub,
-// scaled by the norms of r.  o16 != nullptr (FP16 smoother only): e and the
-// residual are not converted; o16 receives the FP16 correction, the FP16
-// residual and the per-rhs factors that scale both back.
+// Smoothing e = S r on level l.  On the fine level of the mixed V-cycle the
+// smoother runs in FP16 storage: the input is scaled per rhs to unit RMS
+// entries (MR is homogeneous of degree one, and FP16 keeps its full
+// precision away from the subnormal range), smoothed with FP16 vectors and
+// FP32 arithmetic, and scaled back into FP32.  Options:
+//   res   write the residual r - D e that the smoother carries to *res (in
+//         the precision of r)
+//   unit  every column of r has norm 1 or 0 (a normalised Arnoldi vector):
+//         no norm pass
+//   add   e += S r instead of e = S r
+//   sub   (FP16 smoother only) the input is r - *sub, scaled by the norms of r
+//   o16   (FP16 smoother only) e and the residual stay in FP16: o16 receives
+//         the FP16 correction, the FP16 residual and the per-rhs factors that
+//         scale both back (e and *res are not written)
 struct Smooth16 {
   const __half2* y = nullptr;
   const __half2* r = nullptr;
