@@ -303,8 +303,9 @@ static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool p
   const int nrhs = b.nrhs;
   Vec V0 = b.with(w.V);
   b_norm2(c, H.scratch, b, w.n2a);
-  b_copy(c, V0, b);
-  b_normalize(c, V0, w.n2a, nullptr);
+  // V_0 = b / |b| in one scaled copy (zero columns stay zero)
+  b_unit_scales(c, w.n2a, 1.0, nrhs, w.mask, w.n2b);
+  b_copy_scaled(c, V0, b, w.mask);
   k_gmres_start(c, w.G, w.n2a, nrhs);
   int kk = arnoldi(H, l, p, nrhs, std::min(k, w.m), precond, cfg, nullptr, true);
   b_multiaxpy(c, H.scratch, b.with(precond ? w.Z : w.V), H.n(l) * nrhs, kk, w.G.y, 1.0, x, nullptr, true);
