@@ -11,7 +11,9 @@
 //   (recursively preconditioned), prolongation, post-smoothing.
 // * Mixed precision: FP64 defect correction r = b - D x around an FP32
 //   FGMRES whose V-cycle runs on FP32 vectors (optionally FP16 fine-level
-//   smoothing and BF16-MFMA coarse stencils).
+//   smoothing and BF16-MFMA coarse stencils); each inner solve is one
+//   Arnoldi cycle stopped by its residual estimate, which the next FP64
+//   residual checks.
 #include <utility>
 #include "lib.h"
 #include "net.h"
