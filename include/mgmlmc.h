@@ -271,6 +271,16 @@ mgm_status mgm_restrict_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, cons
                              void* y_dev, int32_t nrhs);
 mgm_status mgm_prolong_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const void* x_dev,
                             void* y_dev, int32_t nrhs);
+/* The transfers of the mixed V-cycle whose fine-side vector is stored in FP16
+ * (half complex, dof-major) and scaled per right-hand side by scale_dev
+ * (device, nrhs doubles), with FP16-stored P_l and FP32 arithmetic (Sec. 2.2):
+ *   mgm_restrict_f16:    y_c = P_l^H (scale x16)          (y_c float complex)
+ *   mgm_prolong_add_f16: y = scale x16 + P_l x_c          (x_c, y float complex)
+ * Hierarchies built with mixed != 0 only; y and the inputs must not overlap. */
+mgm_status mgm_restrict_f16(mgm_hierarchy h, int32_t level, const void* x16_dev, const double* scale_dev,
+                            void* y_dev, int32_t nrhs);
+mgm_status mgm_prolong_add_f16(mgm_hierarchy h, int32_t level, const void* xc_dev, const void* x16_dev,
+                               const double* scale_dev, void* y_dev, int32_t nrhs);
 
 /* ------------------------------------------------------------------ solve */
 

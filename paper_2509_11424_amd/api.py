@@ -131,6 +131,9 @@ _SIGS = [
     ("mgm_project_out", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     ("mgm_restrict_prec", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_void_p, C.c_void_p, C.c_int32]),
     ("mgm_prolong_prec", C.c_int, [C.c_void_p, C.c_int32, C.c_int, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("mgm_restrict_f16", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("mgm_prolong_add_f16", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_int32]),
     ("mgm_solve", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(SolveDesc), C.c_void_p, C.c_void_p,
                             C.c_int32, C.POINTER(SolveStats)]),
     ("mgm_estimate_sizes_query", C.c_int, [C.c_void_p, C.POINTER(EstimateDesc),
@@ -472,6 +475,24 @@ class Hierarchy:
         else:
             _check(lib().mgm_prolong_prec(self.h, level, PREC[prec], C.c_void_p(_ptr(xc)),
                                           C.c_void_p(_ptr(y)), xc.shape[2]))
+        return y
+
+    def restrict_f16(self, level: int, x16, scale):
+        """y_c = P^H (scale x16): x16 float16 pairs (dof, site, nrhs, 2) on the
+        fine side, scale float64 (nrhs,); complex64 result (mixed hierarchies)."""
+        import torch
+        y = self._vec(level + 1, x16.shape[2], torch.complex64)
+        _check(lib().mgm_restrict_f16(self.h, level, C.c_void_p(_ptr(x16)), C.c_void_p(_ptr(scale)),
+                                      C.c_void_p(_ptr(y)), x16.shape[2]))
+        return y
+
+    def prolong_add_f16(self, level: int, xc, x16, scale):
+        """y = scale x16 + P x_c: xc complex64 on the coarse side, x16 and scale
+        as for restrict_f16; complex64 result."""
+        import torch
+        y = self._vec(level, xc.shape[2], torch.complex64)
+        _check(lib().mgm_prolong_add_f16(self.h, level, C.c_void_p(_ptr(xc)), C.c_void_p(_ptr(x16)),
+                                         C.c_void_p(_ptr(scale)), C.c_void_p(_ptr(y)), xc.shape[2]))
         return y
 
     def project_out(self, level: int, x):

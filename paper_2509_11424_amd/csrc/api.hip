@@ -556,6 +556,26 @@ mgm_status mgm_prolong_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const
   API_END
 }
 
+mgm_status mgm_restrict_f16(mgm_hierarchy h, int32_t level, const void* x16, const double* scale, void* y,
+                            int32_t nrhs) {
+  API_BEGIN
+  check_level(h, level, nrhs, true);
+  MGM_CHECK(x16 && scale && y && x16 != y, MGM_ERR_INVALID_ARG, "bad vectors");
+  check_transfer_prec(h, MGM_PREC_F32);
+  h->h.T[level].restrict16((const __half2*)x16, scale, (float2*)y, nrhs);
+  API_END
+}
+
+mgm_status mgm_prolong_add_f16(mgm_hierarchy h, int32_t level, const void* xc, const void* x16,
+                               const double* scale, void* y, int32_t nrhs) {
+  API_BEGIN
+  check_level(h, level, nrhs, true);
+  MGM_CHECK(xc && x16 && scale && y && y != x16 && y != xc, MGM_ERR_INVALID_ARG, "bad vectors");
+  check_transfer_prec(h, MGM_PREC_F32);
+  h->h.T[level].prolong16((const float2*)xc, (const __half2*)x16, scale, (float2*)y, nrhs);
+  API_END
+}
+
 mgm_status mgm_project_out(mgm_hierarchy h, int32_t level, const void* x, void* y, int32_t nrhs) {
   API_BEGIN
   check_level(h, level, nrhs, true);

@@ -188,6 +188,43 @@ def test_coarse_bf16_backward_blocks(wide, nrhs):
         assert rel(from_gpu(got).astype(np.complex128).reshape(nrhs, -1), want.reshape(nrhs, -1)) < 5e-5
 
 
+def _f16_pairs(x):
+    """numpy (nrhs, sites, dof) complex -> device float16 pairs (dof, sites, nrhs, 2)
+    and the values they hold as complex128 (nrhs, sites, dof)"""
+    import torch
+    from paper_2509_11424_amd import to_dofmajor
+    xd = to_dofmajor(x)
+    pairs = np.stack([xd.real, xd.imag], axis=-1).astype(np.float16)
+    held = pairs[..., 0].astype(np.float64) + 1j * pairs[..., 1].astype(np.float64)
+    return torch.from_numpy(np.ascontiguousarray(pairs)).to("cuda:0"), np.transpose(held, (2, 1, 0))
+
+
+@pytest.mark.parametrize("nrhs", [3, 16, 70])
+def test_transfers_fp16_input(wide, nrhs):
+    """Transfers of the mixed V-cycle that read the FP16 smoother vectors
+    with per-rhs scales: y_c = P^H (s x16) and y = s x16 + P x_c, against the
+    oracle's P rounded to FP16 applied in FP64 to the values the FP16 input
+    holds (FP32 accumulation only)."""
+    import torch
+    from oracle.multigrid import Transfer
+    p = wide
+    rng = np.random.default_rng(900 + nrhs)
+    scale = rng.uniform(0.1, 10.0, nrhs)
+    sg = torch.from_numpy(scale).to("cuda:0")
+    for l in range(p.oh.L - 1):
+        s, d, n = p.h.level_info(l)
+        cs, cd, cn = p.h.level_info(l + 1)
+        x16, held = _f16_pairs(_rand(s, d, nrhs, 600 + l))
+        xc = _rand(cs, cd, nrhs, 700 + l).astype(np.complex64)
+        t16 = Transfer(p.oh.transfers[l].agg, _fp16_rounded(p.oh.transfers[l].P))
+        xs = (scale[:, None, None] * held).reshape(nrhs, -1)
+        yc = p.h.restrict_f16(l, x16, sg)
+        assert rel(from_gpu(yc).reshape(nrhs, -1), t16.restrict(xs)) < 1e-5
+        y = p.h.prolong_add_f16(l, to_gpu(xc), x16, sg)
+        want = xs + t16.prolong(xc.astype(np.complex128).reshape(nrhs, -1))
+        assert rel(from_gpu(y).reshape(nrhs, -1), want) < 1e-5
+
+
 def test_transfer_prec_rejects_f16(wide):
     import torch
     import paper_2509_11424_amd as m
