@@ -96,7 +96,8 @@ struct Givens {
 // g = (beta0, 0, ...); beta0 given as |r|^2 per rhs
 void k_gmres_start(Context* c, Givens& G, const double* r2, int nrhs);
 // column j: combine h + h2, apply old rotations, new rotation with beta (|w|^2 given)
-void k_gmres_column(Context* c, Givens& G, int j, const double* w2, int nrhs);
+// (reorth: the column is h + h2, the projections of both Gram-Schmidt passes; else h)
+void k_gmres_column(Context* c, Givens& G, int j, const double* w2, int nrhs, bool reorth = true);
 // back substitution R y = g for k columns
 void k_gmres_solve(Context* c, Givens& G, int k, int nrhs);
 

@@ -679,13 +679,13 @@ void k_gmres_start(Context* c, Givens& G, const double* r2, int nrhs) {
 // Complex Givens rotation with real cosine: for the pair (x, y),
 // x' = c x + conj(s) y, y' = -s x + c y.  Chosen to zero y for (a, b):
 // c = |a| / rho, s = b conj(a) / (|a| rho), rho = sqrt(|a|^2 + |b|^2).
-__global__ void kk_gmres_column(Givens G, int j, const double* w2, int nrhs) {
+__global__ void kk_gmres_column(Givens G, int j, const double* w2, int nrhs, int reorth) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs) return;
   const int m = G.m;
   cx<double> hcol[64];
   for (int i = 0; i <= j; i++) {
-    double2 a = G.h[(int64_t)i * nrhs + r], b = G.h2[(int64_t)i * nrhs + r];
+    double2 a = G.h[(int64_t)i * nrhs + r], b = reorth ? G.h2[(int64_t)i * nrhs + r] : make_double2(0, 0);
     hcol[i] = {a.x + b.x, a.y + b.y};
   }
   double beta = sqrt(w2[r]);
@@ -728,9 +728,10 @@ __global__ void kk_gmres_column(Givens G, int j, const double* w2, int nrhs) {
   G.g[(int64_t)(j + 1) * nrhs + r] = make_double2(g1.re, g1.im);
   G.est[r] = sqrt(norm2(g1));
 }
-void k_gmres_column(Context* c, Givens& G, int j, const double* w2, int nrhs) {
+void k_gmres_column(Context* c, Givens& G, int j, const double* w2, int nrhs, bool reorth) {
   MGM_CHECK(G.m <= 63, MGM_ERR_INVALID_ARG, "restart too long");
-  hipLaunchKernelGGL(kk_gmres_column, dim3(nblocks_for(nrhs, 64)), dim3(64), 0, c->stream, G, j, w2, nrhs);
+  hipLaunchKernelGGL(kk_gmres_column, dim3(nblocks_for(nrhs, 64)), dim3(64), 0, c->stream, G, j, w2, nrhs,
+                     reorth ? 1 : 0);
   MGM_LAUNCH_CHECK();
 }
 

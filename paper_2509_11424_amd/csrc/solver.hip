@@ -242,7 +242,7 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, bool 
 // Arnoldi steps from a normalised V_0 and started Givens state.  stop (host,
 // per rhs) enables the lagged early exit when every estimate falls below it.
 static int arnoldi(Hier& H, int l, mgm_prec p, int nrhs, int kmax, bool precond, const SolveCfg& cfg,
-                   const double* stop, bool inner) {
+                   const double* stop, bool inner, bool reorth = true) {
   Context* c = H.ctx;
   LevelWS& w = H.ws(l, p);
   Givens& G = w.G;
@@ -264,17 +264,24 @@ static int arnoldi(Hier& H, int l, mgm_prec p, int nrhs, int kmax, bool precond,
     op_apply(H, l, p, inner, cfg, Zj, W, nrhs);
     Vec Wv = base.with(W);
     // classical Gram-Schmidt with one re-orthogonalisation: the first
-    // subtraction and the second projection share one sweep over the basis
+    // subtraction and the second projection share one sweep over the basis.
+    // Without reorth one pass: the Arnoldi relation still holds exactly, and
+    // the orthogonality lost (about the FP32 rounding over the cancellation
+    // of one step) only matters far below a loose inner tolerance.
     b_multidot(c, H.scratch, base, stride, j + 1, Wv, G.h);
-    if (j + 1 <= kFusedGS) {
-      b_multiaxpy_dot(c, H.scratch, base, stride, j + 1, G.h, Wv, G.h2);
+    if (!reorth) {
+      b_multiaxpy(c, H.scratch, base, stride, j + 1, G.h, -1.0, Wv, w.n2a);
     } else {
-      b_multiaxpy(c, H.scratch, base, stride, j + 1, G.h, -1.0, Wv, nullptr);
-      b_multidot(c, H.scratch, base, stride, j + 1, Wv, G.h2);
+      if (j + 1 <= kFusedGS) {
+        b_multiaxpy_dot(c, H.scratch, base, stride, j + 1, G.h, Wv, G.h2);
+      } else {
+        b_multiaxpy(c, H.scratch, base, stride, j + 1, G.h, -1.0, Wv, nullptr);
+        b_multidot(c, H.scratch, base, stride, j + 1, Wv, G.h2);
+      }
+      b_multiaxpy(c, H.scratch, base, stride, j + 1, G.h2, -1.0, Wv, w.n2a);
     }
-    b_multiaxpy(c, H.scratch, base, stride, j + 1, G.h2, -1.0, Wv, w.n2a);
     b_normalize(c, Wv, w.n2a, nullptr);
-    k_gmres_column(c, G, j, w.n2a, nrhs);
+    k_gmres_column(c, G, j, w.n2a, nrhs, reorth);
     k = j + 1;
     if (stop) {
       MGM_HIP(hipMemcpyAsync(pin + (j & 1) * nrhs, G.est, sizeof(double) * nrhs, hipMemcpyDeviceToHost,
@@ -316,7 +323,7 @@ static void fgmres_fixed(Hier& H, int l, mgm_prec p, Vec b, Vec x, int k, bool p
 // Restarted FGMRES to |r_i| <= tol_rel |b_i| for every rhs.  x0 = 0.
 // The residual at each restart is recomputed as b - D x in precision p.
 static void fgmres_tol(Hier& H, int l, mgm_prec p, Vec b, Vec x, double tol_rel, int maxcycles, int maxsteps,
-                       bool precond, const SolveCfg& cfg, SolveOut* out) {
+                       bool precond, const SolveCfg& cfg, SolveOut* out, bool reorth = true) {
   Context* c = H.ctx;
   LevelWS& w = H.ws(l, p);
   const int nrhs = b.nrhs;
@@ -359,7 +366,7 @@ static void fgmres_tol(Hier& H, int l, mgm_prec p, Vec b, Vec x, double tol_rel,
     b_copy_scaled(c, V0, cyc == 0 ? b : r, w.mask);
     k_gmres_start(c, w.G, w.n2b, nrhs);
     c->sync();  // the staging buffer is reused by arnoldi
-    int k = arnoldi(H, l, p, nrhs, std::min(w.m, maxsteps - steps), precond, cfg, stop.data(), false);
+    int k = arnoldi(H, l, p, nrhs, std::min(w.m, maxsteps - steps), precond, cfg, stop.data(), false, reorth);
     b_multiaxpy(c, H.scratch, b.with(precond ? w.Z : w.V), H.n(l) * nrhs, k, w.G.y, 1.0, x, nullptr, !xset);
     xset = true;
     steps += k;
@@ -464,7 +471,9 @@ static void solve_mixed(Hier& H, int l, const SolveCfg& cfg, Vec b, Vec x, Solve
       // one Arnoldi cycle, stopped by its residual estimate: the true
       // residual of the next defect-correction cycle checks it, so no FP32
       // restart is spent on confirming convergence
-      fgmres_tol(H, l, MGM_PREC_F32, r32, e32, cur.inner_tol, 1, cfg.maxiter - steps, precond, cur, &inner);
+      // (one Gram-Schmidt pass when the inner tolerance is loose: 1e-4 or more)
+      fgmres_tol(H, l, MGM_PREC_F32, r32, e32, cur.inner_tol, 1, cfg.maxiter - steps, precond, cur, &inner,
+                 cur.inner_tol < 1e-4);
     } catch (const Error& e) {
       if (cur.net == nullptr || e.code != MGM_ERR_NUMERIC) throw;
       fall_back(true);
