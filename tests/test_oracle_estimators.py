@@ -167,3 +167,55 @@ def test_mlmc_allocation_closed_form():
     N = E.mlmc_allocation(V, C, eps2)
     assert abs(np.sum(V / N) - eps2) < 1e-15
     assert abs(np.sum(N * C) - np.sum(np.sqrt(V * C)) ** 2 / eps2) < 1e-8
+
+
+def _slice_index(dims):
+    return np.repeat(np.arange(dims[3]), dims[0] * dims[1] * dims[2] * 12)
+
+
+def test_plain_correlator_is_frobenius_norm_of_slice_blocks(setup):
+    """Sec. 1.1, eq. connected-G with Gamma5-hermiticity D^-1(t',t1) =
+    G5 D^-1(t1,t')^H G5: G(t) = (1/T) sum_t' ||D^-1(t+t', t')||_F^2, computed
+    here straight from the dense inverse (no Gamma5 algebra).  A slip in the
+    Gamma5 placement or in the slice pairing of exact_correlator breaks it."""
+    h, _, ex = setup
+    Dinv = ex["Dinv"][0]
+    dims = h.ops[0].dims
+    T = dims[3]
+    sl = _slice_index(dims)
+    want = np.zeros(T)
+    for t in range(T):
+        for tp in range(T):
+            blk = Dinv[np.ix_(sl == (t + tp) % T, sl == tp)]
+            want[t] += np.sum(np.abs(blk) ** 2) / T
+    G, _ = E.exact_correlator(h, "plain")
+    np.testing.assert_allclose(G[0, 0].real, want, rtol=1e-12)
+    assert np.abs(G[0, 0].imag).max() < 1e-12 * want.max()
+    # ||D^-1(a, b)||_F = ||D^-1(b, a)||_F by Gamma5-hermiticity, so G(t) = G(-t)
+    np.testing.assert_allclose(want, np.roll(want[::-1], 1), rtol=1e-12)
+    # and the pairing of slices is not the trivial one: G(0) differs from G(1)
+    assert abs(want[0] - want[1]) > 1e-3 * want[0]
+
+
+def test_plain_correlator_samples_unbiased_with_exact_variance(setup):
+    """The plain one-end estimator of one probe is the real quadratic form
+    X(t) = eta^H A_t eta with A_t = (1/T) blockdiag_t'(D^-1(t+t',t')^H
+    D^-1(t+t',t')): its mean is G(t) above and its Z4 variance is
+    ||offdiag(A_t)||_F^2 (eq. variance-Frobenius-Relation).  The sample mean of
+    N probes lies within 5 sigma of the Frobenius-norm value."""
+    h, solvers, ex = setup
+    Dinv = ex["Dinv"][0]
+    dims = h.ops[0].dims
+    T = dims[3]
+    sl = _slice_index(dims)
+    N = 24
+    _, X = E.correlator_samples(h, solvers, "plain", 0, seed=31, nprobe=N)
+    assert np.abs(X.imag).max() < 1e-12 * np.abs(X.real).max()
+    for t in range(T):
+        A = np.zeros_like(Dinv)
+        for tp in range(T):
+            m1, m0 = sl == (t + tp) % T, sl == tp
+            blk = Dinv[np.ix_(m1, m0)]
+            A[np.ix_(m0, m0)] += blk.conj().T @ blk / T
+        sigma = np.sqrt(E.offdiag_fro2(A) / N)
+        assert abs(X[:, 0, t].mean() - np.trace(A)) < 5 * sigma, t

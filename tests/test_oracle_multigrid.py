@@ -164,3 +164,38 @@ def test_gmres_matches_dense_lu(hier44):
     s = level_solver(h.ops[1])
     bc = rng.standard_normal(h.ops[1].n) + 0j
     assert relative_residual(h.ops[1].matvec, s(bc), bc) < 1e-13
+
+
+def test_mr4_on_a_diagonal_operator_by_hand():
+    """Four minimal-residual steps from y = 0 on D = diag(1, 2), worked out by
+    hand with exact fractions: from v = (1, 1) the lengths are 3/5, 3/4, 3/5,
+    3/4 and y = (99/100, 99/200); from v = (2, 1) they are 3/4, 3/5, 3/4, 3/5
+    and y = (198/100, 99/200)."""
+    d = np.array([1.0, 2.0])
+    y = mr_steps(lambda v: d * v, np.array([1.0, 1.0], dtype=complex), 4)
+    np.testing.assert_allclose(y, [0.99, 0.495], rtol=0, atol=1e-15)
+    y = mr_steps(lambda v: d * v, np.array([2.0, 1.0], dtype=complex), 4)
+    np.testing.assert_allclose(y, [1.98, 0.495], rtol=0, atol=1e-15)
+    # three steps stop at y = (0.96, 0.51): the step count matters
+    y3 = mr_steps(lambda v: d * v, np.array([1.0, 1.0], dtype=complex), 3)
+    np.testing.assert_allclose(y3, [0.96, 0.51], rtol=0, atol=1e-15)
+
+
+def test_test_vectors_round_count_and_stream_by_hand():
+    """Test vectors of D = diag(1, 2) from a Z4 start s(1, 1) (seed 8 gives
+    s = -1 on the test-vector stream of level 0, and no other stream or probe
+    gives that start): MR_4 is homogeneous of degree one, so by the hand values
+    above one round gives s(2, 1)/sqrt(5) and two rounds s(4, 1)/sqrt(17).  A
+    wrong round count, MR step count, stream kind, level or probe index gives
+    another vector."""
+    from oracle.philox import z4_vector, stream_id, KIND_TV
+    d = np.array([1.0, 2.0])
+    seed = 8
+    start = z4_vector(2, seed, stream_id(0, KIND_TV), 0)
+    assert start[0] == start[1] == -1.0
+    s = start[0]
+    v1 = tv_fn(lambda v: d * v, 2, 1, seed, 0, setup_steps=1, mr=4)
+    np.testing.assert_allclose(v1[0], s * np.array([2.0, 1.0]) / np.sqrt(5.0), atol=1e-15)
+    v2 = tv_fn(lambda v: d * v, 2, 1, seed, 0, setup_steps=2, mr=4)
+    np.testing.assert_allclose(v2[0], s * np.array([4.0, 1.0]) / np.sqrt(17.0), atol=1e-15)
+    assert np.linalg.norm(tv_fn(lambda v: d * v, 2, 1, seed, 0, setup_steps=2, mr=3)[0] - v2[0]) > 1e-3
