@@ -12,7 +12,8 @@ Convention (shared with the GPU library, written independently there):
   x_i     = (1, i, -1, -i)[word0 >> 30]
 where i is the dof index within the level vector and
 stream = 256 * level + kind, kind in {0 plain, 1 O_l, 2 F_l, 3 M_l,
-4 coarsest, 5 correlator source, 6 loop source, 7 test vector}.
+4 coarsest, 5 correlator source, 6 loop source, 7 test vector, 8 network
+training input, 9 deflation basis start, 10 deflated-estimator probe}.
 
 Parity status: pinned by the generator's published known-answer vectors
 (tests/golden/philox4x32_10_kat.txt) and by frequency tests of the Z4 map.
