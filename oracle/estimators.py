@@ -28,6 +28,10 @@ A term's probe count is that of the finest level it touches (Sec. 4.1).
 Disconnected loops (Sec. 4.3 eq. trace_equality_disconnected): for a full
 volume Z4 eta, X(t, Gamma) = sum_{x in t} eta(x)^H Gamma (B eta)(x).
 
+Probe entries are Z4 by default; every sample function also takes the other
+distributions of noise.py (Z2, U(1), real Gaussian), and the loops take
+probing (coloured) sources.
+
 Variance estimator (Sec. 4): V = sum |X_i - mean|^2 / (N - 1).
 MLMC sample sizes (Sec. 2.2 eq. MLMC-Nl):
   N_l = eps^-2 sqrt(V_l / C_l) sum_i sqrt(V_i C_i).
@@ -39,62 +43,63 @@ from __future__ import annotations
 
 import numpy as np
 
-from .philox import (z4_vector, stream_id, KIND_PLAIN, KIND_O, KIND_F,
+from .philox import (stream_id, KIND_PLAIN, KIND_O, KIND_F,
                      KIND_M, KIND_COARSEST, KIND_CORR, KIND_LOOP)
+from .noise import noise_vector, colour_masks, NOISE_Z4
 from .dirac import gammas, gamma5
 from .multigrid import gamma5_level
 
 
 # ----------------------------------------------------------------- tr(D^-1)
 
-def plain_samples(h, solvers, seed: int, nprobe: int, first: int = 0):
+def plain_samples(h, solvers, seed: int, nprobe: int, first: int = 0, noise: int = NOISE_Z4):
     n = h.ops[0].n
     out = np.zeros(nprobe, dtype=np.complex128)
     for k in range(nprobe):
-        x = z4_vector(n, seed, stream_id(0, KIND_PLAIN), first + k)
+        x = noise_vector(n, seed, stream_id(0, KIND_PLAIN), first + k, noise)
         out[k] = np.vdot(x, solvers[0](x))
     return out
 
 
-def O_samples(h, solvers, l: int, seed: int, nprobe: int, first: int = 0):
+def O_samples(h, solvers, l: int, seed: int, nprobe: int, first: int = 0, noise: int = NOISE_Z4):
     tr = h.transfers[l]
     n = h.ops[l].n
     out = np.zeros(nprobe, dtype=np.complex128)
     for k in range(nprobe):
-        x = z4_vector(n, seed, stream_id(l, KIND_O), first + k)
+        x = noise_vector(n, seed, stream_id(l, KIND_O), first + k, noise)
         y = tr.project_out(x)
         out[k] = np.vdot(y, solvers[l](y))
     return out
 
 
-def F_samples(h, solvers, l: int, seed: int, nprobe: int, first: int = 0):
+def F_samples(h, solvers, l: int, seed: int, nprobe: int, first: int = 0, noise: int = NOISE_Z4):
     tr = h.transfers[l]
     nc = h.ops[l + 1].n
     out = np.zeros(nprobe, dtype=np.complex128)
     for k in range(nprobe):
-        x = z4_vector(nc, seed, stream_id(l, KIND_F), first + k)
+        x = noise_vector(nc, seed, stream_id(l, KIND_F), first + k, noise)
         px = tr.prolong(x)
         out[k] = np.vdot(px, solvers[l](px)) - np.vdot(x, solvers[l + 1](x))
     return out
 
 
-def M_samples(h, solvers, l: int, seed: int, nprobe: int, first: int = 0):
+def M_samples(h, solvers, l: int, seed: int, nprobe: int, first: int = 0, noise: int = NOISE_Z4):
     tr = h.transfers[l]
     n = h.ops[l].n
     out = np.zeros(nprobe, dtype=np.complex128)
     for k in range(nprobe):
-        x = z4_vector(n, seed, stream_id(l, KIND_M), first + k)
+        x = noise_vector(n, seed, stream_id(l, KIND_M), first + k, noise)
         xc = tr.restrict(x)
         out[k] = np.vdot(x, solvers[l](x)) - np.vdot(xc, solvers[l + 1](xc))
     return out
 
 
-def coarsest_samples(h, solvers, seed: int, nprobe: int, first: int = 0):
+def coarsest_samples(h, solvers, seed: int, nprobe: int, first: int = 0, noise: int = NOISE_Z4):
     L = h.L
     n = h.ops[L - 1].n
     out = np.zeros(nprobe, dtype=np.complex128)
     for k in range(nprobe):
-        x = z4_vector(n, seed, stream_id(L - 1, KIND_COARSEST), first + k)
+        x = noise_vector(n, seed, stream_id(L - 1, KIND_COARSEST), first + k, noise)
         out[k] = np.vdot(x, solvers[L - 1](x))
     return out
 
@@ -203,7 +208,7 @@ class TermOperators:
 
 
 def correlator_samples(h, solvers, decomposition: str, group: int, seed: int,
-                       nprobe: int, first: int = 0):
+                       nprobe: int, first: int = 0, noise: int = NOISE_Z4):
     """Per-probe X_rs(t) for the pairs whose finest level is `group`.
 
     Returns (pairs, X) with pairs a list of (r, s) and X of shape
@@ -219,7 +224,7 @@ def correlator_samples(h, solvers, decomposition: str, group: int, seed: int,
     sl = _slice_of_sites(dims)
     X = np.zeros((nprobe, len(pairs), T), dtype=np.complex128)
     for k in range(nprobe):
-        eta = z4_vector(n, seed, stream_id(group, KIND_CORR), first + k)
+        eta = noise_vector(n, seed, stream_id(group, KIND_CORR), first + k, noise)
         for tp in range(T):
             e = np.where(_slice_mask(dims, tp), eta, 0)
             Bv = {r: ops.apply(r, e, False) for r in needed}
@@ -292,9 +297,11 @@ def gamma_list() -> np.ndarray:
 
 
 def loop_samples(h, solvers, decomposition: str, group: int, seed: int,
-                 nprobe: int, first: int = 0):
+                 nprobe: int, first: int = 0, noise: int = NOISE_Z4, probing: int = 1):
     """X[k, term, Gamma, t] = sum_{x in t} eta(x)^H Gamma (B eta)(x) for the
-    terms whose finest level is `group`.  Returns (terms, X)."""
+    terms whose finest level is `group`.  With probing p > 1 the source is
+    split into the p^4 colours of noise.py and X sums the colours' values
+    (one application of B per colour).  Returns (terms, X)."""
     ops = TermOperators(h, solvers, decomposition)
     terms = [r for r, lv in enumerate(ops.levels) if lv == group]
     dims = h.ops[0].dims
@@ -303,16 +310,19 @@ def loop_samples(h, solvers, decomposition: str, group: int, seed: int,
     sl = _slice_of_sites(dims)
     Gs = gamma_list()
     X = np.zeros((nprobe, len(terms), 6, T), dtype=np.complex128)
+    masks = colour_masks(dims, probing) if probing > 1 else [np.ones(n, dtype=bool)]
     for k in range(nprobe):
-        eta = z4_vector(n, seed, stream_id(group, KIND_LOOP), first + k)
-        e4 = eta.reshape(-1, 4, 3)
-        for it, r in enumerate(terms):
-            b4 = ops.apply(r, eta, False).reshape(-1, 4, 3)
-            for ig in range(6):
-                gb = np.einsum("st,vtc->vsc", Gs[ig], b4)
-                prod = np.sum(np.conj(e4) * gb, axis=(1, 2))
-                X[k, it, ig] = np.bincount(sl, weights=prod.real, minlength=T) + \
-                    1j * np.bincount(sl, weights=prod.imag, minlength=T)
+        eta_full = noise_vector(n, seed, stream_id(group, KIND_LOOP), first + k, noise)
+        for mask in masks:
+            eta = np.where(mask, eta_full, 0)
+            e4 = eta.reshape(-1, 4, 3)
+            for it, r in enumerate(terms):
+                b4 = ops.apply(r, eta, False).reshape(-1, 4, 3)
+                for ig in range(6):
+                    gb = np.einsum("st,vtc->vsc", Gs[ig], b4)
+                    prod = np.sum(np.conj(e4) * gb, axis=(1, 2))
+                    X[k, it, ig] += np.bincount(sl, weights=prod.real, minlength=T) + \
+                        1j * np.bincount(sl, weights=prod.imag, minlength=T)
     return terms, X
 
 

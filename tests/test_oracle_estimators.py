@@ -219,3 +219,32 @@ def test_plain_correlator_samples_unbiased_with_exact_variance(setup):
             A[np.ix_(m0, m0)] += blk.conj().T @ blk / T
         sigma = np.sqrt(E.offdiag_fro2(A) / N)
         assert abs(X[:, 0, t].mean() - np.trace(A)) < 5 * sigma, t
+
+
+def test_loop_probing_unbiased_with_exact_coloured_variance(setup):
+    """Probing sources (2^4 colours, oracle/noise.py) for the loop
+    tr(Gamma5 D^-1(t, t)): the coloured estimator is unbiased, its Z4 variance
+    is the sum of |A_ij|^2 over i != j of equal colour, and on this field it
+    is below the plain Z4 variance ||offdiag A||_F^2 (Sec. 5, probing)."""
+    from oracle.noise import site_colours
+    h, solvers, ex = setup
+    Dinv = ex["Dinv"][0]
+    dims = h.ops[0].dims
+    per = dims[0] * dims[1] * dims[2] * 12
+    G = E.gamma_list()
+    t, ig = 1, 1
+    idx = slice(t * per, (t + 1) * per)
+    A = np.zeros_like(Dinv)
+    A[idx, :] = np.kron(np.eye(per // 12), np.kron(G[ig], np.eye(3))) @ Dinv[idx, :]
+    col = np.repeat(site_colours(dims, 2), 12)
+    same = col[:, None] == col[None, :]
+    v_col = float(np.sum(np.abs(A[same]) ** 2) - np.sum(np.abs(np.diag(A)) ** 2))
+    v_plain = E.offdiag_fro2(A)
+    assert v_col < 0.5 * v_plain
+    N = 12
+    _, X = E.loop_samples(h, solvers, "plain", 0, seed=8, nprobe=N, probing=2)
+    assert abs(X[:, 0, ig, t].mean() - np.trace(A)) < 5 * np.sqrt(v_col / N)
+    # probing distance 1 is plain
+    _, X1 = E.loop_samples(h, solvers, "plain", 0, seed=8, nprobe=2, probing=1)
+    _, X0 = E.loop_samples(h, solvers, "plain", 0, seed=8, nprobe=2)
+    np.testing.assert_allclose(X1, X0, rtol=0, atol=0)
