@@ -148,6 +148,25 @@ mgm_status mgm_operator_apply_dot(mgm_operator op, mgm_prec prec, const void* x_
                                   int32_t nrhs, void* ws_dev, size_t ws_bytes, void* yx_dev,
                                   void* yy_dev);
 
+/* Allocation-free form of mgm_operator_apply_dot, for callers that cannot
+ * allocate device memory or hand over a workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and results as mgm_operator_apply_dot without ws_dev / ws_bytes:
+ * the reduction partials live in one fixed device array of the library,
+ * MGM_NOALLOC_SCRATCH_BYTES per GPU, held from the first mgm_context_create
+ * on that GPU until the process ends.  A call needs
+ * mgm_operator_dot_workspace_size(op, prec, nrhs) <= MGM_NOALLOC_SCRATCH_BYTES
+ * (for example up to 32 rhs on a 16^4 lattice, up to 4 on 32^3 x 64);
+ * larger shapes return MGM_ERR_WORKSPACE without launching anything.  The
+ * call allocates no device or host memory.  Every call on one GPU shares the
+ * array: calls that overlap on one GPU (other streams, other threads) race;
+ * calls ordered on one stream do not.  Nothing in the array needs clearing
+ * (each call writes every partial it reads).
+ * Errors: INVALID_ARG, WORKSPACE, HIP. */
+#define MGM_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+mgm_status mgm_operator_apply_dot_noalloc(mgm_operator op, mgm_prec prec, const void* x_dev, void* y_dev,
+                                          int32_t nrhs, void* yx_dev, void* yy_dev);
+
 /* One fused step of the FP16 minimal-residual smoother with the previous
  * step's length (the MR smoother of the multigrid solver, Sec. 2.1's solver
  * setting, as a Richardson step of lagged MR length): with

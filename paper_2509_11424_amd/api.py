@@ -25,6 +25,7 @@ EXPORT = {"agg_map": 0, "P": 1, "coarse": 2, "tv": 3}
 KCLASS = {"dslash_f64": 0, "dslash_f32": 1, "dslash_f16": 2, "coarse_f64": 3, "coarse_f32": 4,
           "coarse_bf16": 5, "transfer": 6, "net": 7, "dslash_step": 8}
 NET_MAX_LAYERS = 8
+NOALLOC_SCRATCH_BYTES = 16 << 20  # MGM_NOALLOC_SCRATCH_BYTES
 STATUS = {0: "MGM_OK", -1: "MGM_ERR_INVALID_ARG", -2: "MGM_ERR_SHAPE", -3: "MGM_ERR_WORKSPACE",
           -4: "MGM_ERR_NOT_CONVERGED", -5: "MGM_ERR_RANK_DEFICIENT", -6: "MGM_ERR_NUMERIC",
           -7: "MGM_ERR_HIP"}
@@ -149,6 +150,8 @@ _SIGS = [
     ("mgm_operator_dot_workspace_size", C.c_int, [C.c_void_p, C.c_int, C.c_int32, C.POINTER(C.c_size_t)]),
     ("mgm_operator_apply_dot", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                          C.c_size_t, C.c_void_p, C.c_void_p]),
+    ("mgm_operator_apply_dot_noalloc", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int32,
+                                                 C.c_void_p, C.c_void_p]),
     ("mgm_operator_smoother_step", C.c_int, [C.c_void_p] * 6 + [C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                                                 C.c_void_p]),
     ("mgm_operator_step_fusable", C.c_int32, [C.c_void_p, C.c_int32]),
@@ -323,6 +326,18 @@ class Operator:
                                             C.c_void_p(_ptr(ws)), ws.numel(), C.c_void_p(_ptr(yx)),
                                             C.c_void_p(_ptr(yy))))
         return y, yx, yy
+
+    def apply_dot_noalloc(self, x, y, yx, yy, prec: str = "f64"):
+        """mgm_operator_apply_dot_noalloc into caller tensors y (like x),
+        yx (complex128 (nrhs,)) and yy (float64 (nrhs,)); allocates nothing."""
+        _check(lib().mgm_operator_apply_dot_noalloc(self.h, PREC[prec], C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y)),
+                                                    x.shape[2], C.c_void_p(_ptr(yx)), C.c_void_p(_ptr(yy))))
+        return y, yx, yy
+
+    def dot_workspace_size(self, nrhs: int, prec: str = "f64") -> int:
+        nb = C.c_size_t()
+        _check(lib().mgm_operator_dot_workspace_size(self.h, PREC[prec], nrhs, C.byref(nb)))
+        return nb.value
 
     def step_fusable(self, nrhs: int) -> bool:
         return bool(lib().mgm_operator_step_fusable(self.h, nrhs))

@@ -151,6 +151,12 @@ mgm_status mgm_context_create(int device, void* hip_stream, mgm_context* out) {
   MGM_HIP(hipGetDeviceProperties(&prop, device));
   c->c.cu_count = prop.multiProcessorCount;
   c->c.max_lds = prop.sharedMemPerBlock;
+  try {
+    noalloc_bind_device(device);  // device address of the allocation-free entry point's scratch
+  } catch (...) {
+    delete c;
+    throw;
+  }
   *out = c;
   API_END
 }

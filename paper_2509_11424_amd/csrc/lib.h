@@ -151,6 +151,12 @@ void solve(Hier& H, int l, const SolveCfg& cfg, const double2* b, double2* x, in
 // unit: every column of r has norm 1 or 0 (a normalised Arnoldi vector)
 void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, bool unit = false);
 
+// ------------------------------------------------------------ no-alloc
+
+// Looks up, once per device (with that device current), the device address of
+// the fixed scratch array used by mgm_operator_apply_dot_noalloc.
+void noalloc_bind_device(int device);
+
 // ------------------------------------------------------------ estimator
 
 void estimate(Hier& H, const mgm_estimate_desc& d, mgm_estimate_result* out);
