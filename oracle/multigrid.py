@@ -15,6 +15,8 @@ open, and the readings used here (also recorded in the design notes):
   Hence Gamma5 P = P Gamma5_c (Gamma5_c = +1 on chi = 0, -1 on chi = 1).
 * Test vectors: v = Z4 probe (kind 7); 20 times: v <- MR_4(D_l, v),
   v <- v / |v|, where MR_4 runs 4 minimal-residual steps on D_l y = v from 0.
+  Optionally (Sec. 5, more accurate test vectors) the fine level's vectors
+  are refined to a target eigen-residual (refine_test_vectors).
 * Orthonormalisation: modified Gram-Schmidt with one re-orthogonalisation
   pass per (aggregate, chirality) block, columns in order; diag(R) > 0 so the
   result is unique.  A column whose norm falls below 1e-12 of its original
@@ -111,6 +113,43 @@ def test_vectors(apply, n: int, ntv: int, seed: int, level: int,
             v = y / np.linalg.norm(y)
         out[k] = v
     return out
+
+
+def refine_test_vectors(apply, solve, V0: np.ndarray, max_iters: int, eig_tol: float):
+    """Higher-accuracy test vectors of the fine operator (Sec. 5: test vectors
+    with eigen-residuals down to 1e-4 give a stronger coarse space).
+
+    Reading: inverse block power on the Hermitian Q = Gamma5 D with a
+    Rayleigh-Ritz step after every QR.  V0 (n x k) are the rough test vectors;
+    V = QR(V0); then, until every Ritz pair has
+    rho_i = |Q v_i - theta_i v_i| / |theta_i| <= eig_tol or max_iters power
+    steps are done: Rayleigh-Ritz (H = V^H Q V = S diag(theta) S^H, Ritz values
+    ordered by |theta| ascending, V <- V S, each column's phase fixed so that
+    the sum of its entries is real and positive), then a power step
+    V <- QR(D^-1 Gamma5 V).  QR is modified Gram-Schmidt with one
+    re-orthogonalisation pass and positive diag(R).  Returns (V, rho, steps)."""
+    from .deflation import mgs2, gamma5_fine
+
+    V = mgs2(V0)
+    steps = 0
+    while True:
+        DV = np.stack([apply(V[:, j]) for j in range(V.shape[1])], axis=1)
+        G5V = np.stack([gamma5_fine(V[:, j]) for j in range(V.shape[1])], axis=1)
+        H = G5V.conj().T @ DV
+        H = 0.5 * (H + H.conj().T)
+        theta, S = np.linalg.eigh(H)
+        order = np.argsort(np.abs(theta), kind="stable")
+        theta, S = theta[order], S[:, order]
+        V = V @ S
+        QV = np.stack([gamma5_fine(c) for c in (DV @ S).T], axis=1)
+        rho = np.linalg.norm(QV - V * theta[None, :], axis=0) / np.abs(theta)
+        s = V.sum(axis=0)
+        V = V * (np.conj(s) / np.abs(s))[None, :]
+        if rho.max() <= eig_tol or steps >= max_iters:
+            return V, rho, steps
+        W = np.stack([solve(gamma5_fine(V[:, j])) for j in range(V.shape[1])], axis=1)
+        V = mgs2(W)
+        steps += 1
 
 
 def block_mgs2(Vb: np.ndarray) -> np.ndarray:
@@ -239,7 +278,10 @@ class Hierarchy:
     """Levels D_0 (fine) .. D_{L-1} and transfers P_0 .. P_{L-2}."""
 
     def __init__(self, fine, blocks, ntvs, seed: int, setup_steps: int = 20,
-                 mr: int = 4):
+                 mr: int = 4, refine=None):
+        """refine: None, or (solve, max_iters, eig_tol) to replace the level-0
+        test vectors by refine_test_vectors(fine.matvec, solve, ...) of the
+        rough ones (the coarser levels keep the rough recipe)."""
         self.ops = [fine]
         self.transfers = []
         self.tvs = []
@@ -249,6 +291,11 @@ class Hierarchy:
             op = self.ops[-1]
             agg = Aggregation(dims, b, dof)
             tv = test_vectors(op.matvec, op.n, ntv, seed, l, setup_steps, mr)
+            if l == 0 and refine is not None:
+                solve, iters, tol = refine
+                Vr, self.refine_rho, self.refine_steps = refine_test_vectors(op.matvec, solve, tv.T.copy(),
+                                                                             iters, tol)
+                tv = Vr.T.copy()
             self.tvs.append(tv)
             Vb = tv.T[agg.block_index()]       # (Vc, 2, rows, ntv)
             P = block_mgs2(Vb)

@@ -4,7 +4,7 @@ import pytest
 
 from lattice_inputs import gauge_field
 from oracle.dirac import WilsonClover
-from oracle.multigrid import (Aggregation, Hierarchy, block_mgs2, mr_steps,
+from oracle.multigrid import (Aggregation, Hierarchy, block_mgs2, mr_steps, refine_test_vectors,
                               gamma5_level, RankDeficient, test_vectors as tv_fn)
 from oracle.solve import gmres, DenseSolver, level_solver, relative_residual
 
@@ -199,3 +199,48 @@ def test_test_vectors_round_count_and_stream_by_hand():
     v2 = tv_fn(lambda v: d * v, 2, 1, seed, 0, setup_steps=2, mr=4)
     np.testing.assert_allclose(v2[0], s * np.array([4.0, 1.0]) / np.sqrt(17.0), atol=1e-15)
     assert np.linalg.norm(tv_fn(lambda v: d * v, 2, 1, seed, 0, setup_steps=2, mr=3)[0] - v2[0]) > 1e-3
+
+
+def _known_spectrum(n=48, k=4, seed=3):
+    from oracle.deflation import gamma5_fine
+    rng = np.random.default_rng(seed)
+    W, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    mags = np.concatenate([[0.5, 0.6, 0.7, 0.8], np.linspace(1.6, 24.0, n - 4)])
+    lam = mags * np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    Q = W @ np.diag(lam) @ W.conj().T
+    Dm = np.stack([gamma5_fine(Q[:, j]) for j in range(n)], axis=1)
+    return W, lam, Dm
+
+
+def test_refined_test_vectors_converge_to_eigenpairs():
+    """Known spectrum of Q = Gamma5 D (n = 48): from random starts the refined
+    block reaches eigen-residual 1e-10 with Ritz values equal to the four
+    eigenvalues of smallest modulus (in that order) and vectors equal to the
+    eigenvectors up to the fixed phase (sum of entries real, positive)."""
+    W, lam, Dm = _known_spectrum()
+    Dinv = np.linalg.inv(Dm)
+    rng = np.random.default_rng(4)
+    V0 = rng.standard_normal((48, 4)) + 1j * rng.standard_normal((48, 4))
+    V, rho, steps = refine_test_vectors(lambda v: Dm @ v, lambda b: Dinv @ b, V0, 200, 1e-10)
+    assert rho.max() <= 1e-10 and 0 < steps < 200
+    for i in range(4):
+        w = W[:, i] * np.conj(W[:, i].sum()) / abs(W[:, i].sum())
+        assert np.linalg.norm(V[:, i] - w) < 1e-9, i
+        assert abs(np.sum(V[:, i]).imag) < 1e-12 and np.sum(V[:, i]).real > 0
+
+
+def test_refine_eigen_residual_by_hand():
+    """One column v = (w1 + eps w2)/sqrt(1 + eps^2) of two eigenvectors: no
+    power step (max_iters 0) returns theta = (l1 + eps^2 l2)/(1 + eps^2) and
+    rho = sqrt((l1 - theta)^2 + eps^2 (l2 - theta)^2) / (sqrt(1 + eps^2) |theta|)."""
+    W, lam, Dm = _known_spectrum()
+    eps = 0.1
+    v = (W[:, 0] + eps * W[:, 5]) / np.sqrt(1 + eps ** 2)
+    V, rho, steps = refine_test_vectors(lambda x: Dm @ x, None, v[:, None], 0, 0.0)
+    l1, l2 = lam[0], lam[5]
+    th = (l1 + eps ** 2 * l2) / (1 + eps ** 2)
+    want = np.sqrt((l1 - th) ** 2 + eps ** 2 * (l2 - th) ** 2) / (np.sqrt(1 + eps ** 2) * abs(th))
+    assert steps == 0 and abs(rho[0] - want) < 1e-13 * want
+    # exact eigenvectors have zero residual
+    V, rho, steps = refine_test_vectors(lambda x: Dm @ x, None, W[:, :3].copy(), 0, 0.0)
+    assert rho.max() < 1e-12
