@@ -9,13 +9,17 @@ block QR, Galerkin operators) runs once before the timed region and is
 reported separately.
 
 value = right-hand sides solved to 1e-10 per second (every level's solves
-counted), whole job.  The JSON line also carries the dslash roofline (HIP
-events around every dslash launch in the timed region) and the CPU-oracle
-baseline (fine-level solve rate of the FP64 oracle, extrapolated from one
-operator application and an iteration count measured on a small lattice).
+counted), whole job.  The JSON line also carries the rate of each level alone
+(`per_level`: one batch of the level's size solved to 1e-10), the dslash
+roofline (HIP events around every dslash launch in the timed region), the
+time to reach the target variance of tr(D^-1) in plain FP64 MG and in the
+mixed batched form (`time_to_target`, MLMC-optimal probe counts), and the
+CPU-oracle baseline (fine-level solve rate of the FP64 oracle on the host's
+cores, extrapolated from one operator application per core and the
+iteration count of a measured 16^4 solve).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4|c3|c2]
-                  [--form mixed|f64] [--cpu 0|1] [--ttt] [--learned [--net-widths 4 8 8 4]]
+                  [--form mixed|f64] [--cpu 0|1] [--ttt 0|1] [--learned [--net-widths 4 8 8 4]]
 
 Kernel micro-benchmarks (used for the profiler runs of single kernels):
 
@@ -179,45 +183,97 @@ def rhs_per_step(nprobe):
 
 # ------------------------------------------------------------ CPU baseline
 
-def cpu_baseline(cfg, out_path):
-    """Oracle on the host: one fine Wilson-clover application on the
-    workload's lattice, times the number of GMRES(50) iterations the oracle
-    needs for one right-hand side to 1e-10 on the 8^4 lattice with the same
-    operator parameters (the full-size solve does not fit in a bounded
-    sample).  Writes a JSON dict to out_path."""
+CPU_WORKERS_MAX = 16  # host cores of one GPU's share on the GPU machine
+
+
+def _cpu_apply_worker(D, seed, conn):
+    """One FP64 oracle application in a forked worker (single-threaded BLAS)."""
     import numpy as np
-    from lattice_inputs import gauge_field
-    from oracle.dirac import WilsonClover
-    from oracle.solve import gmres
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        x = np.random.default_rng(seed).standard_normal(D.n) + 0j
+        conn.send(time.time())
+        D.matvec(x)
+        conn.send(time.time())
+    conn.close()
+
+
+def cpu_baseline(cfg, U, out_path):
+    """The FP64 numpy oracle on the host, on a bounded sample of the workload.
+
+    * single thread (BLAS limited to one thread with threadpoolctl): one
+      Wilson-clover application on the workload's lattice, and one GMRES(50)
+      solve of a Z4 right-hand side to a true relative residual of 1e-10 on
+      the 16^4 lattice of the same ensemble family (m0 0.01, roughness 0.6),
+      whose iteration count extrapolates the fine-level solve rate of the
+      workload (labelled extrapolated);
+    * all cores: the same application in W forked single-threaded workers at
+      once (W = min(16, cores)), i.e. independent probes run side by side.
+    Writes a JSON dict to out_path."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
     res = {}
     try:
-        t0 = time.time()
-        U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])
-        D = WilsonClover(U, cfg["m0"], cfg["csw"])
-        t_build = time.time() - t0
-        x = np.random.default_rng(0).standard_normal(D.n) + 0j
-        t0 = time.time()
-        D.matvec(x)
-        t_apply = time.time() - t0
-        del D, U
-        Up = gauge_field((8, 8, 8, 8), cfg["eps"], cfg["gseed"])
-        Dp = WilsonClover(Up, cfg["m0"], cfg["csw"])
-        count = [0]
+        from oracle.dirac import WilsonClover
+        from oracle.solve import gmres
+        from oracle.philox import z4_vector
+        ncpu = os.cpu_count() or 1
+        workers = max(1, min(CPU_WORKERS_MAX, ncpu))
+        with threadpool_limits(1):
+            t0 = time.time()
+            D = WilsonClover(U, cfg["m0"], cfg["csw"])
+            t_build = time.time() - t0
+            x = np.random.default_rng(0).standard_normal(D.n) + 0j
+            t0 = time.time()
+            D.matvec(x)
+            t_apply = time.time() - t0
+            del x
+        # all cores: W workers, one application each, started together
+        import multiprocessing as mp
+        ctxm = mp.get_context("fork")
+        pipes, procs = [], []
+        for w in range(workers):
+            a, b = ctxm.Pipe(duplex=False)
+            pr = ctxm.Process(target=_cpu_apply_worker, args=(D, 10 + w, b))
+            pr.start()
+            pipes.append(a)
+            procs.append(pr)
+        starts = [p.recv() for p in pipes]
+        ends = [p.recv() for p in pipes]
+        for pr in procs:
+            pr.join()
+        t_all = max(ends) - min(starts)
+        del D
+        # measured solve at 16^4 (single thread)
+        from lattice_inputs import gauge_field
+        with threadpool_limits(1):
+            U3 = gauge_field((16, 16, 16, 16), 0.6, 13)
+            D3 = WilsonClover(U3, 0.01, 1.0)
+            count = [0]
 
-        def mv(v):
-            count[0] += 1
-            return Dp.matvec(v)
+            def mv(v):
+                count[0] += 1
+                return D3.matvec(v)
 
-        b = np.random.default_rng(1).standard_normal(Dp.n) + 0j
-        gmres(mv, b, tol=1e-10, restart=50)
+            b = z4_vector(D3.n, 103, 0, 0)
+            t0 = time.time()
+            gmres(mv, b, tol=1e-10, restart=50)
+            t_solve3 = time.time() - t0
         iters = count[0]
-        t_solve = t_apply * iters
-        res = {"value": 1.0 / t_solve, "unit": "RHS/s", "cores": 1, "kind": "oracle",
-               "sample": "numpy FP64 oracle, 1 thread: one Wilson-clover application on %s (%.2f s, after a "
-                         "%.0f s operator build) x %d GMRES(50) applications per RHS to 1e-10 measured by the "
-                         "oracle on the 8^4 lattice with the same parameters; fine-level RHS/s, extrapolated"
-                         % ("x".join(map(str, cfg["dims"])), t_apply, t_build, iters),
-               "t_apply_s": t_apply, "iters_proxy": iters}
+        lat = "x".join(map(str, cfg["dims"]))
+        single = 1.0 / (t_apply * iters)
+        allcore = workers / (t_all * iters)
+        res = {"value": allcore, "unit": "RHS/s", "cores": workers, "kind": "oracle",
+               "sample": "numpy FP64 oracle, fine-level RHS/s on %s, extrapolated: %d single-threaded workers "
+                         "each apply D once side by side (%.2f s wall), times the %d GMRES(50) applications the "
+                         "oracle needed for one Z4 right-hand side to 1e-10 on 16^4 (measured, %.1f s); host "
+                         "reports %d cores" % (lat, workers, t_all, iters, t_solve3, ncpu),
+               "extrapolated": True, "nproc": ncpu,
+               "single_thread": {"value": single, "unit": "RHS/s", "cores": 1, "t_apply_s": t_apply,
+                                 "t_build_s": t_build},
+               "all_cores": {"value": allcore, "workers": workers, "t_apply_wall_s": t_all},
+               "solve_16x16x16x16": {"seconds": t_solve3, "applications": iters, "tol": 1e-10,
+                                     "rhs_per_s": 1.0 / t_solve3, "cores": 1}}
     except Exception as e:  # reported, never fatal for the GPU leg
         res = {"error": repr(e)}
     with open(out_path, "w") as f:
@@ -238,12 +294,12 @@ def run(args):
     cpu_pid = None
     cpu_out = os.path.join("/tmp", "mgm_cpu_baseline_%d.json" % os.getpid())
     if args.cpu:
-        # fork before any GPU call: the child only runs numpy
+        # fork before any GPU call: the child only runs numpy (BLAS threads
+        # limited inside it with threadpoolctl)
         cpu_pid = os.fork()
         if cpu_pid == 0:
             try:
-                os.environ["OMP_NUM_THREADS"] = "1"
-                cpu_baseline(cfg, cpu_out)
+                cpu_baseline(cfg, U, cpu_out)
             finally:
                 os._exit(0)
     import torch
@@ -362,6 +418,7 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
                         "coarse-grid-correction graphs are not timed per class",
         "tuned_shapes": len(ctx.tune_report()) if mixed else 0,
     }
+    line["per_level"] = per_level_rates(m, ctx, h, cfg, sd, batch, torch)
     if args.learned:
         line["learned"] = learned_form(m, ctx, op, cfg, h, sd, args, torch)
     if args.ttt:
@@ -382,6 +439,27 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
         except Exception as e:
             line["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(line), flush=True)
+
+
+def per_level_rates(m, ctx, h, cfg, sd, batch, torch):
+    """RHS solved per second on each level alone: one batch of the level's
+    size of Z4 right-hand sides solved to 1e-10 with the timed form's
+    settings (after one untimed solve of the same batch)."""
+    out = []
+    for l in range(h.L):
+        s_, d_, n_ = h.level_info(l)
+        b = m.draw_z4(ctx, cfg["pseed"] + 900 + l, 256 * l, 0, batch[l], s_, d_, "f64")
+        h.solve(l, b, sd)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        x, st = h.solve(l, b, sd)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        out.append({"level": l, "lattice_sites": s_, "dof": d_, "nrhs": batch[l], "seconds": dt,
+                    "rhs_per_s": batch[l] / dt, "iterations": st["iterations"],
+                    "max_rel_residual": st["max_rel_residual"]})
+        del b, x
+    return out
 
 
 def micro(args):
@@ -580,7 +658,7 @@ def main():
                     help="right-hand sides per batch on each level (default: the configuration's)")
     ap.add_argument("--form", default="mixed", choices=["mixed", "f64"])
     ap.add_argument("--cpu", type=int, default=1)
-    ap.add_argument("--ttt", action="store_true")
+    ap.add_argument("--ttt", type=int, default=1, help="time to target variance, FP64 against the mixed form")
     ap.add_argument("--learned", action="store_true", help="also measure the learned-preconditioner form")
     ap.add_argument("--net-widths", type=int, nargs="+", default=[4, 8, 8, 4])
     ap.add_argument("--net-steps", type=int, default=150)

@@ -204,6 +204,22 @@ mgm_status mgm_draw_z4(mgm_context ctx, uint64_t seed, uint32_t stream, uint64_t
                        int32_t nprobe, int64_t n_site, int32_t dof, mgm_prec prec,
                        void* out_dev);
 
+/* Probe distributions (Sec. 1: entries i.i.d. with E[x] = 0 and
+ * E[conj(x_i) x_j] = delta_ij; Z4 is eq. z4, the others are the alternatives
+ * named after eq. variance-Frobenius-Relation), all from the Philox4x32-10
+ * words w of the entry's counter as in mgm_draw_z4:
+ *   Z4: (1, i, -1, -i)[w0 >> 30]        Z2: 1 - 2 (w0 >> 31)
+ *   U1: exp(2 pi i (w0 + 1/2) 2^-32)    (uniform on the unit circle)
+ *   GAUSS: real standard normal by the Box-Muller transform of
+ *          u1 = (w0 + 1) 2^-32, u2 = w1 2^-32: sqrt(-2 ln u1) cos(2 pi u2). */
+typedef enum { MGM_NOISE_Z4 = 0, MGM_NOISE_Z2 = 1, MGM_NOISE_U1 = 2, MGM_NOISE_GAUSS = 3 } mgm_noise_kind;
+
+/* mgm_draw_z4 for any distribution of mgm_noise_kind (Z4 and Z2 bit-exact
+ * functions of the counter; U1 and GAUSS through FP64 cos / sin / log / sqrt).
+ * Errors: INVALID_ARG, HIP. */
+mgm_status mgm_draw_noise(mgm_context ctx, int32_t kind, uint64_t seed, uint32_t stream, uint64_t first_probe,
+                          int32_t nprobe, int64_t n_site, int32_t dof, mgm_prec prec, void* out_dev);
+
 /* -------------------------------------------------------------- hierarchy */
 
 #define MGM_MAX_LEVELS 4
@@ -349,6 +365,45 @@ typedef struct {
 mgm_status mgm_solve(mgm_hierarchy h, int32_t level, const mgm_solve_desc* desc,
                      const void* b_dev, void* x_dev, int32_t nrhs, mgm_solve_stats* stats);
 
+/* ------------------------------------------------- hierarchy refinement */
+
+/* More accurate fine test vectors (Sec. 5: test vectors computed to smaller
+ * eigen-residuals strengthen the coarse space).  Starting from the rough
+ * vectors of the hierarchy's recipe (orthonormalised), alternates a
+ * Rayleigh-Ritz step on the Hermitian Q = Gamma5 D over span(V) (Ritz pairs
+ * ordered by |theta| ascending, each vector's phase fixed so that the sum of
+ * its entries is real and positive) with inverse block power steps
+ * V <- QR(D^-1 Gamma5 V) (solves with `solve` at tolerance power_tol, batch
+ * columns at a time), until every Ritz pair has the eigen-residual
+ * rho = |Q v - theta v| / |theta| <= eig_tol or max_iters steps are done.  The
+ * Ritz vectors then replace the test vectors of transfer 0: P_0, D_1 and every
+ * coarser level (rough recipe) are rebuilt in place.  N_tv stays ntv[0]. */
+typedef struct {
+  int32_t max_iters;    /* inverse block power steps, at most */
+  double eig_tol;       /* target eigen-residual of every Ritz pair (the paper: 1e-4) */
+  double power_tol;     /* relative residual of the power-step solves */
+  int32_t batch;        /* columns per solver launch, 1..fine-level capacity */
+  mgm_solve_desc solve; /* solver of the power steps (tolerance replaced by power_tol) */
+} mgm_refine_desc;
+
+typedef struct {
+  int32_t steps;         /* power steps taken */
+  int32_t converged;     /* 1 if every power-step solve reached power_tol */
+  double max_rho_start;  /* largest eigen-residual of the rough vectors */
+  double max_rho;        /* largest eigen-residual of the final vectors */
+  double seconds;        /* wall time including the rebuild */
+} mgm_refine_stats;
+
+/* Device bytes of the refinement's temporary workspace (three blocks of
+ * ntv[0] fine vectors, FP64). */
+mgm_status mgm_hierarchy_refine_workspace_size(mgm_hierarchy h, size_t* bytes);
+/* Runs the refinement in the caller's temporary workspace (free afterwards).
+ * rho_host / theta_host (host, ntv[0] doubles each, may be NULL) receive the
+ * final eigen-residuals and Ritz values.  Errors: INVALID_ARG, WORKSPACE,
+ * RANK_DEFICIENT, NUMERIC, HIP. */
+mgm_status mgm_hierarchy_refine(mgm_hierarchy h, const mgm_refine_desc* desc, void* ws_dev, size_t ws_bytes,
+                                mgm_refine_stats* stats, double* rho_host, double* theta_host);
+
 /* ------------------------------------------------ learned preconditioner */
 
 /*
@@ -440,7 +495,7 @@ void mgm_net_destroy(mgm_net net);
 /* --------------------------------------------------------------- estimate */
 
 typedef enum { MGM_OBS_TRACE = 0, MGM_OBS_CORR_PS = 1, MGM_OBS_LOOPS = 2 } mgm_observable;
-typedef enum { MGM_DEC_PLAIN = 0, MGM_DEC_OBLIQUE = 1, MGM_DEC_ORTHOGONAL = 2 } mgm_decomposition;
+typedef enum { MGM_DEC_PLAIN = 0, MGM_DEC_OBLIQUE = 1, MGM_DEC_ORTHOGONAL = 2, MGM_DEC_DEFLATED = 3 } mgm_decomposition;
 
 /*
  * Term numbering (L = nlevels):
@@ -451,9 +506,14 @@ typedef enum { MGM_DEC_PLAIN = 0, MGM_DEC_OBLIQUE = 1, MGM_DEC_ORTHOGONAL = 2 } 
  *         plain [0] D^-1; oblique [l] B_l (l <= L-1); orthogonal
  *         [l] J_l, [L-1+l] K_l, [2L-2] coarsest.  Correlator results are
  *         per pair (r, s) in row-major order r*R + s.
+ *  TRACE  deflated (Sec. 2.1, eq. deflated-estimator; needs `deflation`):
+ *         [0] x^H (I - V V^H) D^-1 x with nprobe[0] Z4 probes (stream kind 10),
+ *         [1] tr(V^H D^-1 V), computed once when the basis was built: one
+ *         sample, variance 0, cost_s = the seconds of its k solves.
  * Probe groups: nprobe[g] probes for every term (TRACE, LOOPS) or pair
  * (CORR_PS) whose finest level is g; plain uses nprobe[0].
  */
+typedef struct mgm_deflation_s* mgm_deflation;
 typedef struct {
   int32_t observable;       /* mgm_observable */
   int32_t decomposition;    /* mgm_decomposition */
@@ -464,6 +524,15 @@ typedef struct {
   mgm_solve_desc solve;
   int32_t batch_level[MGM_MAX_LEVELS]; /* optional batch per probe group g (0: batch);
                                           must not exceed the capacity of level g */
+  mgm_deflation deflation;  /* MGM_DEC_DEFLATED: a basis built on this hierarchy, else NULL */
+  int32_t noise;            /* probe distribution (mgm_noise_kind; 0 = Z4) of every term */
+  int32_t probing;          /* LOOPS: probing distance p >= 1 (0 or 1: none).  Every source is
+                               split into the p^4 colours of the block pattern
+                               colour(x) = (x mod p) + p((y mod p) + p((z mod p) + p(t mod p)))
+                               (p must divide every fine extent); a probe's value is the
+                               sum over colours of the coloured sources' values, one
+                               application of every term per colour (Sec. 5: probing
+                               combined with the multilevel decomposition) */
 } mgm_estimate_desc;
 
 typedef struct {
@@ -493,6 +562,47 @@ typedef struct {
 mgm_status mgm_estimate_sizes_query(mgm_hierarchy h, const mgm_estimate_desc* desc,
                                     mgm_estimate_sizes* sizes);
 mgm_status mgm_estimate(mgm_hierarchy h, const mgm_estimate_desc* desc, mgm_estimate_result* out);
+
+/* -------------------------------------------------------------- deflation */
+
+/* Inexact deflation basis of the fine operator (Sec. 2.1, "Deflation for the
+ * Dirac operator"; setup of Sec. 4.2): V (n x k, orthonormal columns)
+ * approximates the eigenvectors of the Hermitian Gamma5 D belonging to its
+ * smallest |eigenvalues|.  Start: k Z4 columns (stream kind 9 of level 0,
+ * probe index = column), orthonormalised; then power_iters inverse block
+ * power steps V <- QR(D^-1 Gamma5 V), the solves to power_tol.  QR: the
+ * unique factor with positive real diag(R) (CholeskyQR applied twice; a
+ * column whose component outside the earlier ones falls below 1e-12 of its
+ * norm: MGM_ERR_RANK_DEFICIENT).  After the power steps the exact term
+ * tr(V^H D^-1 V) is computed with `solve` (its tolerance).  Solves run in
+ * batches of `batch` columns on the hierarchy's fine level. */
+typedef struct {
+  int32_t k;            /* basis columns, 1..1024 */
+  int32_t power_iters;  /* inverse block power steps (the paper: 5) */
+  double power_tol;     /* relative residual of the power-step solves (the paper: 1e-6) */
+  uint64_t seed;        /* start block */
+  int32_t batch;        /* columns per solver launch, 1..fine-level capacity */
+  mgm_solve_desc solve; /* solver of the power steps (tolerance replaced by power_tol)
+                           and of the exact term */
+} mgm_deflation_desc;
+
+/* Device bytes of the basis workspace: V (n x k complex FP64) plus the
+ * partial sums of its tall-skinny products. */
+mgm_status mgm_deflation_workspace_size(mgm_hierarchy h, const mgm_deflation_desc* desc, size_t* bytes);
+/* Builds the basis in the caller's workspace (256-byte aligned, kept until
+ * mgm_deflation_destroy; h must outlive it).  Errors: INVALID_ARG,
+ * WORKSPACE, RANK_DEFICIENT, NOT_CONVERGED (a solve missed its tolerance; the
+ * basis is still returned), NUMERIC, HIP. */
+mgm_status mgm_deflation_create(mgm_hierarchy h, const mgm_deflation_desc* desc, void* ws_dev, size_t ws_bytes,
+                                mgm_deflation* out);
+/* Copies V to host memory as one dof-major block of k vectors: element
+ * (dof, site, column) at (dof * V + site) * k + column, complex FP64;
+ * host_buf must hold n * k * 16 bytes.  Synchronises. */
+mgm_status mgm_deflation_export(mgm_deflation f, double* host_buf, size_t bytes);
+/* tr(V^H D^-1 V) (complex, 2 doubles), and the seconds of the basis setup and
+ * of the exact term. */
+mgm_status mgm_deflation_info(mgm_deflation f, double* exact_trace, double* setup_s, double* exact_s);
+void mgm_deflation_destroy(mgm_deflation f);
 
 /* ------------------------------------------------------------------- MLMC */
 

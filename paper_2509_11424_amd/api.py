@@ -20,8 +20,9 @@ MAX_LEVELS = 4
 PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 SOLVE = {"mg": 0, "mg_mixed": 1, "gmres": 2, "net": 3}
 OBS = {"trace": 0, "corr": 1, "loops": 2}
-DEC = {"plain": 0, "oblique": 1, "orthogonal": 2}
+DEC = {"plain": 0, "oblique": 1, "orthogonal": 2, "deflated": 3}
 EXPORT = {"agg_map": 0, "P": 1, "coarse": 2, "tv": 3}
+NOISE = {"z4": 0, "z2": 1, "u1": 2, "gauss": 3}
 KCLASS = {"dslash_f64": 0, "dslash_f32": 1, "dslash_f16": 2, "coarse_f64": 3, "coarse_f32": 4,
           "coarse_bf16": 5, "transfer": 6, "net": 7, "dslash_step": 8}
 NET_MAX_LAYERS = 8
@@ -57,6 +58,16 @@ class SolveDesc(C.Structure):
                 ("smooth_coarse", C.c_int32), ("graphs", C.c_int32)]
 
 
+class RefineDesc(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("eig_tol", C.c_double), ("power_tol", C.c_double),
+                ("batch", C.c_int32), ("solve", SolveDesc)]
+
+
+class RefineStats(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("converged", C.c_int32), ("max_rho_start", C.c_double),
+                ("max_rho", C.c_double), ("seconds", C.c_double)]
+
+
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("fallbacks", C.c_int32),
                 ("max_rel_residual", C.c_double), ("seconds", C.c_double)]
@@ -66,7 +77,13 @@ class EstimateDesc(C.Structure):
     _fields_ = [("observable", C.c_int32), ("decomposition", C.c_int32),
                 ("nprobe", C.c_int32 * MAX_LEVELS), ("seed", C.c_uint64),
                 ("first_probe", C.c_uint64), ("batch", C.c_int32), ("solve", SolveDesc),
-                ("batch_level", C.c_int32 * MAX_LEVELS)]
+                ("batch_level", C.c_int32 * MAX_LEVELS), ("deflation", C.c_void_p), ("noise", C.c_int32),
+                ("probing", C.c_int32)]
+
+
+class DeflationDesc(C.Structure):
+    _fields_ = [("k", C.c_int32), ("power_iters", C.c_int32), ("power_tol", C.c_double), ("seed", C.c_uint64),
+                ("batch", C.c_int32), ("solve", SolveDesc)]
 
 
 class EstimateSizes(C.Structure):
@@ -117,6 +134,8 @@ _SIGS = [
     ("mgm_operator_destroy", None, [C.c_void_p]),
     ("mgm_draw_z4", C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int32, C.c_int64,
                               C.c_int32, C.c_int, C.c_void_p]),
+    ("mgm_draw_noise", C.c_int, [C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int32, C.c_int64,
+                                 C.c_int32, C.c_int, C.c_void_p]),
     ("mgm_hierarchy_workspace_size", C.c_int, [C.c_void_p, C.POINTER(HierarchyDesc),
                                                C.POINTER(C.c_size_t)]),
     ("mgm_hierarchy_create", C.c_int, [C.c_void_p, C.POINTER(HierarchyDesc), C.c_void_p, C.c_size_t,
@@ -155,6 +174,16 @@ _SIGS = [
     ("mgm_operator_smoother_step", C.c_int, [C.c_void_p] * 6 + [C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                                                 C.c_void_p]),
     ("mgm_operator_step_fusable", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("mgm_hierarchy_refine_workspace_size", C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    ("mgm_hierarchy_refine", C.c_int, [C.c_void_p, C.POINTER(RefineDesc), C.c_void_p, C.c_size_t,
+                                       C.POINTER(RefineStats), C.c_void_p, C.c_void_p]),
+    ("mgm_deflation_workspace_size", C.c_int, [C.c_void_p, C.POINTER(DeflationDesc), C.POINTER(C.c_size_t)]),
+    ("mgm_deflation_create", C.c_int, [C.c_void_p, C.POINTER(DeflationDesc), C.c_void_p, C.c_size_t,
+                                       C.POINTER(C.c_void_p)]),
+    ("mgm_deflation_export", C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    ("mgm_deflation_info", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]),
+    ("mgm_deflation_destroy", None, [C.c_void_p]),
     ("mgm_net_workspace_size", C.c_int, [C.c_void_p, C.POINTER(NetDesc), C.POINTER(C.c_size_t)]),
     ("mgm_net_create", C.c_int, [C.c_void_p, C.POINTER(NetDesc), C.c_void_p, C.c_size_t,
                                  C.POINTER(C.c_void_p)]),
@@ -377,6 +406,18 @@ def draw_z4(ctx: Context, seed: int, stream: int, first_probe: int, nprobe: int,
     return out
 
 
+def draw_noise(ctx: Context, kind, seed: int, stream: int, first_probe: int, nprobe: int, nsite: int, dof: int,
+               prec: str = "f64"):
+    """Probe entries of distribution kind ("z4", "z2", "u1", "gauss")."""
+    import torch
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    out = torch.empty((dof, nsite, nprobe), dtype=dt, device="cuda:%d" % ctx.device)
+    k = NOISE[kind] if isinstance(kind, str) else int(kind)
+    _check(lib().mgm_draw_noise(ctx.h, k, seed, stream, first_probe, nprobe, nsite, dof, PREC[prec],
+                                C.c_void_p(_ptr(out))))
+    return out
+
+
 def solve_desc(tol=1e-12, maxiter=2000, kind="mg", smooth=2, coarse_iters=8, inner_tol=1e-5,
                net=None, coarse_bf16=True, smoother_f16=True, graphs=False, smooth_coarse=0) -> SolveDesc:
     d = SolveDesc()
@@ -425,6 +466,28 @@ class Hierarchy:
         _check(lib().mgm_hierarchy_create(op.h, C.byref(d), C.c_void_p(_ptr(self.ws)), self.ws.numel(),
                                           C.byref(h)))
         self.h = h
+
+    def refine(self, max_iters: int = 20, eig_tol: float = 1e-4, power_tol: float = 1e-6, batch: int | None = None,
+               solve: SolveDesc | None = None) -> dict:
+        """Replaces the fine test vectors by Ritz vectors of Gamma5 D refined
+        to eigen-residual eig_tol and rebuilds the hierarchy in place."""
+        d = RefineDesc()
+        d.max_iters, d.eig_tol, d.power_tol = max_iters, eig_tol, power_tol
+        cap = self.desc.max_nrhs_level[0] or self.desc.max_nrhs
+        d.batch = batch if batch is not None else min(cap, self.desc.ntv[0])
+        d.solve = solve or solve_desc()
+        nb = C.c_size_t()
+        _check(lib().mgm_hierarchy_refine_workspace_size(self.h, C.byref(nb)))
+        ws = _empty_ws(nb.value, self.ctx.device)
+        st = RefineStats()
+        k = self.desc.ntv[0]
+        rho = np.zeros(k)
+        theta = np.zeros(k)
+        _check(lib().mgm_hierarchy_refine(self.h, C.byref(d), C.c_void_p(_ptr(ws)), ws.numel(), C.byref(st),
+                                          rho.ctypes.data_as(C.c_void_p), theta.ctypes.data_as(C.c_void_p)))
+        del ws
+        return {"steps": st.steps, "converged": bool(st.converged), "max_rho_start": st.max_rho_start,
+                "max_rho": st.max_rho, "seconds": st.seconds, "rho": rho, "theta": theta}
 
     def level_info(self, level: int):
         s = C.c_int64()
@@ -530,9 +593,14 @@ class Hierarchy:
 
     def estimate(self, observable: str, decomposition: str, nprobe, seed: int, batch=8,
                  first_probe: int = 0, solve: SolveDesc | None = None, samples: bool = True,
-                 check: bool = True):
-        """batch: an int, or a per-probe-group list (finest group first)."""
+                 check: bool = True, deflation=None, noise="z4", probing: int = 0):
+        """batch: an int, or a per-probe-group list (finest group first);
+        deflation: a Deflation built on this hierarchy (decomposition
+        "deflated")."""
         d = EstimateDesc()
+        d.deflation = deflation.h if deflation is not None else None
+        d.noise = NOISE[noise] if isinstance(noise, str) else int(noise)
+        d.probing = int(probing)
         if not isinstance(batch, int):
             bl = list(batch) + [0] * (MAX_LEVELS - len(batch))
             d.batch_level[:] = bl[:MAX_LEVELS]
@@ -588,6 +656,50 @@ class Hierarchy:
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.mgm_hierarchy_destroy(self.h)
+            self.h = None
+
+
+class Deflation:
+    """Inexact deflation basis V of the hierarchy's fine operator (inverse
+    block power on Gamma5 D) and its exact term tr(V^H D^-1 V)."""
+
+    def __init__(self, hierarchy: Hierarchy, k: int, power_iters: int = 5, power_tol: float = 1e-6,
+                 seed: int = 1, batch: int | None = None, solve: SolveDesc | None = None, check: bool = True):
+        self.hier = hierarchy
+        d = DeflationDesc()
+        d.k, d.power_iters, d.power_tol, d.seed = k, power_iters, power_tol, seed
+        d.batch = batch if batch is not None else min(k, hierarchy.desc.max_nrhs_level[0] or hierarchy.desc.max_nrhs)
+        d.solve = solve or solve_desc()
+        self.desc = d
+        self.k = k
+        nb = C.c_size_t()
+        _check(lib().mgm_deflation_workspace_size(hierarchy.h, C.byref(d), C.byref(nb)))
+        self.ws = _empty_ws(nb.value, hierarchy.ctx.device)
+        h = C.c_void_p()
+        rc = lib().mgm_deflation_create(hierarchy.h, C.byref(d), C.c_void_p(_ptr(self.ws)), self.ws.numel(),
+                                        C.byref(h))
+        self.status = rc
+        if rc == 0 or rc == -4:
+            self.h = h
+        if check:
+            _check(rc)
+
+    def info(self) -> dict:
+        tr = (C.c_double * 2)()
+        a, b = C.c_double(), C.c_double()
+        _check(lib().mgm_deflation_info(self.h, tr, C.byref(a), C.byref(b)))
+        return {"exact_trace": complex(tr[0], tr[1]), "setup_s": a.value, "exact_s": b.value}
+
+    def export(self) -> np.ndarray:
+        """V as (k, sites, 12) complex128 (column j = basis vector j)."""
+        s, d, n = self.hier.level_info(0)
+        out = np.zeros((d, s, self.k), dtype=np.complex128)
+        _check(lib().mgm_deflation_export(self.h, out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return from_dofmajor(out)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mgm_deflation_destroy(self.h)
             self.h = None
 
 

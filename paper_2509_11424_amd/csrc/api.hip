@@ -344,6 +344,17 @@ void mgm_operator_destroy(mgm_operator op) { delete op; }
 
 // --------------------------------------------------------------- probes
 
+mgm_status mgm_draw_noise(mgm_context ctx, int32_t kind, uint64_t seed, uint32_t stream, uint64_t first_probe,
+                          int32_t nprobe, int64_t n_site, int32_t dof, mgm_prec prec, void* out_dev) {
+  API_BEGIN
+  MGM_CHECK(ctx && out_dev && nprobe >= 1 && n_site >= 1 && dof >= 1, MGM_ERR_INVALID_ARG, "bad arguments");
+  MGM_CHECK(first_probe + (uint64_t)nprobe <= (1ull << 32), MGM_ERR_INVALID_ARG,
+            "probe indices must be below 2^32 (32-bit counter word)");
+  NoiseMask mk;
+  draw_noise(&ctx->c, kind, seed, stream, first_probe, nprobe, n_site, dof, prec, out_dev, mk);
+  API_END
+}
+
 mgm_status mgm_draw_z4(mgm_context ctx, uint64_t seed, uint32_t stream, uint64_t first_probe, int32_t nprobe,
                        int64_t n_site, int32_t dof, mgm_prec prec, void* out) {
   API_BEGIN
@@ -663,6 +674,121 @@ mgm_status mgm_estimate(mgm_hierarchy h, const mgm_estimate_desc* desc, mgm_esti
   API_END
 }
 
+// ----------------------------------------------------------- refinement
+
+mgm_status mgm_hierarchy_refine_workspace_size(mgm_hierarchy h, size_t* bytes) {
+  API_BEGIN
+  MGM_CHECK(h && bytes, MGM_ERR_INVALID_ARG, "NULL argument");
+  *bytes = refine_workspace_bytes(h->h);
+  API_END
+}
+
+mgm_status mgm_hierarchy_refine(mgm_hierarchy h, const mgm_refine_desc* desc, void* ws_dev, size_t ws_bytes,
+                                mgm_refine_stats* stats, double* rho_host, double* theta_host) {
+  API_BEGIN
+  MGM_CHECK(h && desc && ws_dev, MGM_ERR_INVALID_ARG, "NULL argument");
+  MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  MGM_CHECK(ws_bytes >= refine_workspace_bytes(h->h), MGM_ERR_WORKSPACE, "refinement workspace too small");
+  MGM_CHECK(desc->max_iters >= 0 && desc->eig_tol >= 0 && desc->power_tol > 0, MGM_ERR_INVALID_ARG,
+            "bad refinement settings");
+  MGM_CHECK(desc->batch >= 1 && desc->batch <= h->h.cap(0), MGM_ERR_INVALID_ARG,
+            "refinement batch must be 1..the fine-level capacity");
+  MGM_CHECK(h->h.L >= 2, MGM_ERR_INVALID_ARG, "the hierarchy has no transfer to refine");
+  SolveCfg power = cfg_of(&desc->solve);
+  power.tol = desc->power_tol;
+  refine_hierarchy(h->h, *desc, power, ws_dev, ws_bytes, stats, rho_host, theta_host);
+  API_END
+}
+
+// ------------------------------------------------------------ deflation
+
+static void check_defl_desc(mgm_hierarchy h, const mgm_deflation_desc* d) {
+  MGM_CHECK(h && d, MGM_ERR_INVALID_ARG, "NULL argument");
+  MGM_CHECK(d->k >= 1 && d->k <= 1024, MGM_ERR_INVALID_ARG, "deflation basis size must be 1..1024");
+  MGM_CHECK(d->k <= h->h.n(0), MGM_ERR_INVALID_ARG, "deflation basis larger than the fine dimension");
+  MGM_CHECK(d->power_iters >= 0 && d->power_tol > 0, MGM_ERR_INVALID_ARG, "bad power-step settings");
+  MGM_CHECK(d->batch >= 1 && d->batch <= h->h.cap(0), MGM_ERR_INVALID_ARG,
+            "deflation batch must be 1..the fine-level capacity");
+}
+
+mgm_status mgm_deflation_workspace_size(mgm_hierarchy h, const mgm_deflation_desc* desc, size_t* bytes) {
+  API_BEGIN
+  check_defl_desc(h, desc);
+  MGM_CHECK(bytes != nullptr, MGM_ERR_INVALID_ARG, "bytes is NULL");
+  Defl f;
+  f.H = &h->h;
+  f.k = desc->k;
+  Arena a;
+  f.layout(a);
+  *bytes = a.off;
+  API_END
+}
+
+mgm_status mgm_deflation_create(mgm_hierarchy h, const mgm_deflation_desc* desc, void* ws_dev, size_t ws_bytes,
+                                mgm_deflation* out) {
+  mgm_status st = MGM_OK;
+  try {
+    check_defl_desc(h, desc);
+    MGM_CHECK(ws_dev && out, MGM_ERR_INVALID_ARG, "NULL argument");
+    MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    SolveCfg power = cfg_of(&desc->solve);
+    SolveCfg exact = power;
+    power.tol = desc->power_tol;
+    auto* f = new mgm_deflation_s();
+    try {
+      f->owner = h;
+      f->f.H = &h->h;
+      f->f.k = desc->k;
+      f->f.batch = desc->batch;
+      Arena a;
+      a.base = (char*)ws_dev;
+      a.cap = ws_bytes;
+      f->f.layout(a);
+      f->f.build(*desc, power, exact);
+    } catch (...) {
+      delete f;
+      throw;
+    }
+    *out = f;
+    if (!f->f.so.converged) {
+      set_last_error("a deflation solve did not reach its tolerance");
+      st = MGM_ERR_NOT_CONVERGED;
+    }
+  } catch (const mgm::Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return MGM_ERR_INVALID_ARG;
+  }
+  return st;
+}
+
+mgm_status mgm_deflation_export(mgm_deflation f, double* host_buf, size_t bytes) {
+  API_BEGIN
+  MGM_CHECK(f && host_buf, MGM_ERR_INVALID_ARG, "NULL argument");
+  const size_t need = (size_t)f->f.H->n(0) * f->f.k * sizeof(double2);
+  MGM_CHECK(bytes >= need, MGM_ERR_INVALID_ARG, "host buffer too small");
+  Context* c = f->f.H->ctx;
+  MGM_HIP(hipMemcpyAsync(host_buf, f->f.V, need, hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  API_END
+}
+
+mgm_status mgm_deflation_info(mgm_deflation f, double* exact_trace, double* setup_s, double* exact_s) {
+  API_BEGIN
+  MGM_CHECK(f != nullptr, MGM_ERR_INVALID_ARG, "NULL argument");
+  if (exact_trace) {
+    exact_trace[0] = f->f.exact.real();
+    exact_trace[1] = f->f.exact.imag();
+  }
+  if (setup_s) *setup_s = f->f.setup_seconds;
+  if (exact_s) *exact_s = f->f.exact_seconds;
+  API_END
+}
+
+void mgm_deflation_destroy(mgm_deflation f) { delete f; }
+
 mgm_status mgm_mlmc_allocate(int32_t nterms, const double* var, const double* cost, double eps2, int64_t* n_out) {
   API_BEGIN
   MGM_CHECK(nterms >= 1 && var && cost && n_out && eps2 > 0, MGM_ERR_INVALID_ARG, "bad arguments");
@@ -879,3 +1005,7 @@ void mgm_net_destroy(mgm_net net) {
 }
 
 }  // extern "C"
+
+namespace mgm {
+SolveCfg solve_cfg_of(const mgm_solve_desc* d) { return cfg_of(d); }
+}  // namespace mgm

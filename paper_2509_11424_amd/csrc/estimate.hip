@@ -57,12 +57,23 @@ struct Run {
     return b;
   }
   void solve(int l, const double2* b, double2* x, int nb) { mgm::solve(H, l, cfg, b, x, nb, &so); }
-  // Z4 probes of stream (ls, kind) on the lattice of level `lat`
-  void z4(int ls, int kind, int lat, uint64_t first, int nb, double2* out, int slice = -1) {
+  // probes of stream (ls, kind) on the lattice of level `lat`, from the
+  // estimate's distribution; slice >= 0: one time slice (fine lattice),
+  // colour >= 0: one colour of the probing pattern (fine lattice)
+  void z4(int ls, int kind, int lat, uint64_t first, int nb, double2* out, int slice = -1, int colour = -1) {
     MGM_CHECK(first + (uint64_t)nb <= (1ull << 32), MGM_ERR_INVALID_ARG, "probe indices must be below 2^32");
-    int64_t sps = (int64_t)H.g[0].dims[0] * H.g[0].dims[1] * H.g[0].dims[2];
-    draw_z4(c, d.seed, (uint32_t)(256 * ls + kind), first, nb, H.g[lat].V, H.g[lat].dof, MGM_PREC_F64, out, slice,
-            sps);
+    NoiseMask mk;
+    mk.slice = slice;
+    mk.sites_per_slice = (int64_t)H.g[0].dims[0] * H.g[0].dims[1] * H.g[0].dims[2];
+    if (colour >= 0) {
+      mk.colour = colour;
+      mk.p = d.probing;
+      mk.X = H.g[0].dims[0];
+      mk.Y = H.g[0].dims[1];
+      mk.Z = H.g[0].dims[2];
+    }
+    draw_noise(c, d.noise, d.seed, (uint32_t)(256 * ls + kind), first, nb, H.g[lat].V, H.g[lat].dof, MGM_PREC_F64,
+               out, mk);
   }
   // out = a^H b per rhs (device), then fetched with the other values
   void dot(int l, const double2* a, const double2* b, int nb, double2* out) {
@@ -126,6 +137,14 @@ static int term_level(int dec, int L, int r) {
 mgm_estimate_sizes estimate_sizes(const Hier& H, const mgm_estimate_desc& d) {
   mgm_estimate_sizes s{};
   const int L = H.L;
+  if (d.decomposition == MGM_DEC_DEFLATED) {
+    // the stochastic term and the exact tr(V^H D^-1 V) (one value)
+    s.nterms = 2;
+    s.T = 1;
+    s.ngamma = 1;
+    s.nsamples = (int64_t)d.nprobe[0] + 1;
+    return s;
+  }
   int R = nterms_for(d.observable, d.decomposition, L);
   s.nterms = d.observable == MGM_OBS_CORR_PS ? R * R : R;
   s.T = d.observable == MGM_OBS_TRACE ? 1 : H.g[0].dims[3];
@@ -206,6 +225,41 @@ static void trace_terms(Run& R, std::vector<TermAcc>& acc) {
     A.seconds = now_s() - t0;
     A.n = N;
   }
+}
+
+// ------------------------------------------------------- deflated trace
+
+// Sec. 2.1, eq. deflated-estimator: X = x^H (I - V V^H) D^-1 x
+//   = x^H y - (V^H x)^H (V^H y), y = D^-1 x, plus tr(V^H D^-1 V).
+static void deflated_terms(Run& R, Defl& F, std::vector<TermAcc>& acc) {
+  Hier& H = R.H;
+  EstWS& E = H.est;
+  const int N = R.d.nprobe[0];
+  const int B = R.batch(0, 0);
+  const int k = F.k;
+  TermAcc& A = acc[0];
+  double t0 = now_s();
+  for (int b0 = 0; b0 < N; b0 += B) {
+    const int nb = std::min(B, N - b0);
+    R.z4(0, kStreamDeflProbe, 0, R.d.first_probe + b0, nb, E.x[0]);
+    R.solve(0, E.x[0], E.z[0], nb);
+    R.dot(0, E.x[0], E.z[0], nb, E.qf);
+    F.vh_times(E.x[0], nb, F.C);
+    F.vh_times(E.z[0], nb, F.C2);
+    auto X = R.fetch(E.qf, nb);
+    auto a = R.fetch(F.C, k * nb);
+    auto c = R.fetch(F.C2, k * nb);
+    for (int j = 0; j < nb; j++) {
+      std::complex<double> s = 0.0;
+      for (int i = 0; i < k; i++) s += std::conj(a[(size_t)i * nb + j]) * c[(size_t)i * nb + j];
+      A.s.push_back(X[j] - s);
+    }
+  }
+  A.seconds = now_s() - t0;
+  A.n = N;
+  acc[1].s.push_back(F.exact);
+  acc[1].seconds = F.exact_seconds;
+  acc[1].n = 1;
 }
 
 // ---------------------------------------------------- fine term vectors
@@ -387,26 +441,30 @@ static void loop_terms(Run& R, std::vector<TermAcc>& acc) {
     const int N = R.d.nprobe[g];
     const int B = R.batch(g, 0);  // sources live on the fine lattice
     double t0 = now_s();
+    // probing: one source per colour of the p^4 pattern, values summed
+    const int p = R.d.probing > 1 ? R.d.probing : 1;
+    const int ncol = p > 1 ? p * p * p * p : 1;
     for (int b0 = 0; b0 < N; b0 += B) {
       const int nb = std::min(B, N - b0);
-      R.z4(g, 6, 0, R.d.first_probe + b0, nb, E.eta);
-      term_vectors(R, g, E.eta, nb, Bv, Bv, false);
-      LoopArgs la{};
-      la.eta = E.eta;
-      la.nvec = (int)terms.size();
-      for (size_t i = 0; i < terms.size(); i++) la.psi[i] = Bv[terms[i]];
-      loop_gamma(R.c, la, Vs, T, nb, E.slice_partial, E.slice_out);
-      std::vector<double2> h((size_t)terms.size() * 6 * nb * T);
-      MGM_HIP(hipMemcpyAsync(h.data(), E.slice_out, sizeof(double2) * h.size(), hipMemcpyDeviceToHost,
-                             R.c->stream));
-      R.c->sync();
+      std::vector<std::complex<double>> X((size_t)terms.size() * 6 * nb * T, 0.0);
+      for (int col = 0; col < ncol; col++) {
+        R.z4(g, 6, 0, R.d.first_probe + b0, nb, E.eta, -1, p > 1 ? col : -1);
+        term_vectors(R, g, E.eta, nb, Bv, Bv, false);
+        LoopArgs la{};
+        la.eta = E.eta;
+        la.nvec = (int)terms.size();
+        for (size_t i = 0; i < terms.size(); i++) la.psi[i] = Bv[terms[i]];
+        loop_gamma(R.c, la, Vs, T, nb, E.slice_partial, E.slice_out);
+        std::vector<double2> h((size_t)terms.size() * 6 * nb * T);
+        MGM_HIP(hipMemcpyAsync(h.data(), E.slice_out, sizeof(double2) * h.size(), hipMemcpyDeviceToHost,
+                               R.c->stream));
+        R.c->sync();
+        for (size_t e = 0; e < h.size(); e++) X[e] += std::complex<double>(h[e].x, h[e].y);
+      }
       for (size_t i = 0; i < terms.size(); i++)
         for (int k = 0; k < nb; k++)
           for (int gm = 0; gm < 6; gm++)
-            for (int t = 0; t < T; t++) {
-              double2 v = h[(((size_t)i * 6 + gm) * nb + k) * T + t];
-              acc[terms[i]].s.push_back({v.x, v.y});
-            }
+            for (int t = 0; t < T; t++) acc[terms[i]].s.push_back(X[(((size_t)i * 6 + gm) * nb + k) * T + t]);
     }
     double dt = now_s() - t0;
     for (int q : terms) {
@@ -420,13 +478,29 @@ static void loop_terms(Run& R, std::vector<TermAcc>& acc) {
 
 void estimate(Hier& H, const mgm_estimate_desc& d, mgm_estimate_result* out) {
   MGM_CHECK(d.batch >= 1, MGM_ERR_INVALID_ARG, "batch must be >= 1");
-  MGM_CHECK(d.decomposition >= 0 && d.decomposition <= 2 && d.observable >= 0 && d.observable <= 2,
+  MGM_CHECK(d.decomposition >= 0 && d.decomposition <= 3 && d.observable >= 0 && d.observable <= 2,
             MGM_ERR_INVALID_ARG, "bad observable or decomposition");
+  MGM_CHECK(d.noise >= MGM_NOISE_Z4 && d.noise <= MGM_NOISE_GAUSS, MGM_ERR_INVALID_ARG, "unknown probe distribution");
+  MGM_CHECK(d.probing >= 0 && d.probing <= 8, MGM_ERR_INVALID_ARG, "probing distance must be 0..8");
+  if (d.probing > 1) {
+    MGM_CHECK(d.observable == MGM_OBS_LOOPS, MGM_ERR_INVALID_ARG, "probing sources are for loops");
+    for (int m = 0; m < 4; m++)
+      MGM_CHECK(H.g[0].dims[m] % d.probing == 0, MGM_ERR_SHAPE, "probing distance must divide the fine lattice");
+  }
+  Defl* defl = nullptr;
+  if (d.decomposition == MGM_DEC_DEFLATED) {
+    MGM_CHECK(d.observable == MGM_OBS_TRACE, MGM_ERR_INVALID_ARG, "the deflated decomposition estimates the trace");
+    MGM_CHECK(d.deflation != nullptr && d.deflation->f.H == &H, MGM_ERR_INVALID_ARG,
+              "the deflated decomposition needs a basis built on this hierarchy");
+    defl = &d.deflation->f;
+  }
   for (int l = 0; l < H.L; l++) MGM_CHECK(d.nprobe[l] >= 0, MGM_ERR_INVALID_ARG, "negative probe count");
   mgm_estimate_sizes sz = estimate_sizes(H, d);
   Run R(H, d);
   std::vector<TermAcc> acc(sz.nterms);
-  if (d.observable == MGM_OBS_TRACE)
+  if (defl != nullptr)
+    deflated_terms(R, *defl, acc);
+  else if (d.observable == MGM_OBS_TRACE)
     trace_terms(R, acc);
   else if (d.observable == MGM_OBS_CORR_PS)
     corr_terms(R, acc);

@@ -165,9 +165,27 @@ void Hier::layout(Arena& a) {
 }
 
 void Hier::build() {
+  for (int l = 0; l + 1 < L; l++) build_level(l, nullptr);
+  ctx->sync();
+}
+
+// Transfer l and the coarse operator D_{l+1}: from the rough test-vector
+// recipe, or (tvsrc != nullptr) from the given block of ntv[l] vectors of
+// level l (dof-major, ntv[l] columns).
+void Hier::build_level(int l, const double2* tvsrc) {
+  const double2* src = tvsrc;
+  if (src == nullptr) {
+    rough_tv(l);
+    src = tv[l];
+  }
+  finish_level(l, src);
+}
+
+// The rough test vectors of level l into tv[l].
+void Hier::rough_tv(int l) {
   Context* c = ctx;
-  for (int l = 0; l + 1 < L; l++) {
-    const int ntv = desc.ntv[l];
+  const int ntv = desc.ntv[l];
+  {
     Vec v = vec(l, MGM_PREC_F64, tv[l], ntv);
     Vec y = v.with(setup_y), rho = v.with(setup_rho), q = v.with(setup_q);
     // Z4 starts (kind 7), then setup_steps rounds of MR_k smoothing and
@@ -185,25 +203,33 @@ void Hier::build() {
       b_copy(c, v, y);
       b_normalize(c, v, setup_n2, nullptr);
     }
-    MGM_HIP(hipMemsetAsync(d_flag, 0, sizeof(int), c->stream));
-    mg_block_mgs2(c, T[l].t, tv[l], T[l].P64, d_flag);
-    int flag = 0;
-    MGM_HIP(hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    c->sync();
-    MGM_CHECK(flag == 0, MGM_ERR_RANK_DEFICIENT,
-              "test vectors of level " + std::to_string(l) + " are rank deficient on some aggregate");
-    if (l == 0)
-      mg_galerkin_fine(c, *fine, T[0], A[1]);
-    else
-      mg_galerkin_coarse(c, A[l], T[l], A[l + 1]);
-    mg_mfma64_pack(c, A[l + 1]);
-    if (desc.mixed) {
-      mg_convert_P(c, T[l]);
-      mg_convert_A(c, A[l + 1]);
-      mg_mfma_pack(c, A[l + 1]);
-    }
   }
+}
+
+// P_l from a block of test vectors (block MGS2), the Galerkin D_{l+1} and
+// the precision copies.
+void Hier::finish_level(int l, const double2* src) {
+  Context* c = ctx;
+  MGM_HIP(hipMemsetAsync(d_flag, 0, sizeof(int), c->stream));
+  mg_block_mgs2(c, T[l].t, src, T[l].P64, d_flag);
+  int flag = 0;
+  MGM_HIP(hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   c->sync();
+  MGM_CHECK(flag == 0, MGM_ERR_RANK_DEFICIENT,
+            "test vectors of level " + std::to_string(l) + " are rank deficient on some aggregate");
+  if (l == 0)
+    mg_galerkin_fine(c, *fine, T[0], A[1]);
+  else
+    mg_galerkin_coarse(c, A[l], T[l], A[l + 1]);
+  mg_mfma64_pack(c, A[l + 1]);
+  if (desc.mixed) {
+    mg_convert_P(c, T[l]);
+    mg_convert_A(c, A[l + 1]);
+    mg_mfma_pack(c, A[l + 1]);
+  }
+  // captured coarse-grid corrections hold the old operators' launch
+  // arguments only through buffer addresses, which do not move; nothing to
+  // invalidate
 }
 
 }  // namespace mgm

@@ -118,6 +118,9 @@ struct Hier {
 
   void layout(Arena& a);  // carve (or size) every buffer
   void build();           // test vectors, QR, Galerkin, precision copies
+  void build_level(int l, const double2* tvsrc);  // transfer l and D_{l+1}
+  void rough_tv(int l);                              // rough test vectors of level l into tv[l]
+  void finish_level(int l, const double2* src);      // P_l, D_{l+1}, copies from a block of tvs
 };
 
 // ------------------------------------------------------------ solver
@@ -157,6 +160,43 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, bool 
 // the fixed scratch array used by mgm_operator_apply_dot_noalloc.
 void noalloc_bind_device(int device);
 
+// ------------------------------------------------------------ deflation
+
+constexpr int kStreamDeflBasis = 9;   // Z4 start block of the deflation basis (level 0)
+constexpr int kStreamDeflProbe = 10;  // probes of the deflated estimator (level 0)
+
+SolveCfg solve_cfg_of(const mgm_solve_desc* d);
+
+// Inexact deflation basis V (fine level, n x k, orthonormal columns) of a
+// hierarchy's fine operator, and tr(V^H D^-1 V).
+struct Defl {
+  Hier* H = nullptr;
+  int k = 0;
+  int batch = 0;
+  double2* V = nullptr;     // [n][k] dof-major block
+  double2* part = nullptr;  // chunk partials of the tall-skinny products
+  size_t part_cap = 0;
+  double2* C = nullptr;     // [k][max(k, cap0)] product results
+  double2* C2 = nullptr;
+  double2* M = nullptr;     // [k][k] triangular factor inverse
+  std::complex<double> exact = 0.0;
+  double setup_seconds = 0, exact_seconds = 0;
+  SolveOut so;
+  static size_t part_entries(int k, int kb_max);
+  void layout(Arena& a);
+  void build(const mgm_deflation_desc& d, const SolveCfg& power, const SolveCfg& exact_cfg);
+  void cholqr();
+  void gather(int c0, int b, bool g5, double2* out);
+  void scatter(int c0, int b, const double2* in);
+  void vh_times(const double2* X, int nb, double2* out);  // out = V^H X (k x nb)
+};
+
+// ------------------------------------------------------------ refinement
+
+size_t refine_workspace_bytes(const Hier& H);
+void refine_hierarchy(Hier& H, const mgm_refine_desc& d, const SolveCfg& power, void* ws, size_t ws_bytes,
+                      mgm_refine_stats* st, double* rho_out, double* theta_out);
+
 // ------------------------------------------------------------ estimator
 
 void estimate(Hier& H, const mgm_estimate_desc& d, mgm_estimate_result* out);
@@ -166,4 +206,9 @@ mgm_estimate_sizes estimate_sizes(const Hier& H, const mgm_estimate_desc& d);
 
 struct mgm_hierarchy_s {
   mgm::Hier h;
+};
+
+struct mgm_deflation_s {
+  mgm_hierarchy_s* owner = nullptr;
+  mgm::Defl f;
 };

@@ -1,4 +1,6 @@
-// Z4 probe vectors (Sec. 1, eq. z4) from the counter-based Philox4x32-10
+// Probe vectors (Sec. 1: Z4, eq. z4, and the Z2, U(1) and Gaussian
+// distributions named after eq. variance-Frobenius-Relation) from the
+// counter-based Philox4x32-10
 // generator (Salmon, Moraes, Dror, Shaw, SC'11): every entry is an
 // independent function of (seed, stream, probe, index), so any probe range can
 // be drawn in any batch and reproduced bit for bit.
@@ -24,10 +26,14 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 
 // element e = (dof * nsite + site) * nprobe + rhs, entry index i = site*dof + dof.
 // slice >= 0 keeps only sites of that time slice (sites_per_slice consecutive
-// sites per slice), others are zero.
+// sites per slice), colour >= 0 only sites of that colour of the p^4 block
+// pattern (x mod p) + p((y mod p) + p((z mod p) + p(t mod p))); others are zero.
+// Distributions from the Philox words w: Z4 (1, i, -1, -i)[w0 >> 30]; Z2
+// 1 - 2 (w0 >> 31); U(1) exp(2 pi i (w0 + 1/2) 2^-32); real N(0, 1) by Box and
+// Muller (1958) from u1 = (w0 + 1) 2^-32, u2 = w1 2^-32.
 template <class P>
-__global__ void k_z4(typename P::S* out, uint2 key, uint32_t stream, uint64_t first, int nprobe, int64_t nsite,
-                     int dof, int slice, int64_t sites_per_slice) {
+__global__ void k_noise(typename P::S* out, uint2 key, uint32_t stream, uint64_t first, int nprobe, int64_t nsite,
+                        int dof, int kind, NoiseMask mk) {
   using R = typename P::R;
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t n = nsite * dof * nprobe;
@@ -36,39 +42,69 @@ __global__ void k_z4(typename P::S* out, uint2 key, uint32_t stream, uint64_t fi
   int64_t q = e / nprobe;
   int64_t site = q % nsite;
   int d = (int)(q / nsite);
-  if (slice >= 0 && site / sites_per_slice != slice) {
+  if (mk.slice >= 0 && site / mk.sites_per_slice != mk.slice) {
     P::st(out, e, cx<R>{0, 0});
     return;
   }
+  if (mk.colour >= 0) {
+    const int p = mk.p;
+    const int64_t x = site % mk.X, y = (site / mk.X) % mk.Y, z = (site / ((int64_t)mk.X * mk.Y)) % mk.Z,
+                  t = site / ((int64_t)mk.X * mk.Y * mk.Z);
+    const int64_t col = x % p + p * (y % p + p * (z % p + p * (t % p)));
+    if (col != mk.colour) {
+      P::st(out, e, cx<R>{0, 0});
+      return;
+    }
+  }
   uint64_t i = (uint64_t)site * dof + d;
-  uint64_t p = first + r;
-  uint4 w = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)(i >> 32), (uint32_t)p, stream), key);
-  uint32_t code = w.x >> 30;
+  uint64_t pr = first + r;
+  uint4 w = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)(i >> 32), (uint32_t)pr, stream), key);
   cx<R> v;
-  switch (code) {
-    case 0: v = {1, 0}; break;
-    case 1: v = {0, 1}; break;
-    case 2: v = {-1, 0}; break;
-    default: v = {0, -1}; break;
+  if (kind == MGM_NOISE_Z2) {
+    v = {(R)((w.x >> 31) ? -1 : 1), 0};
+  } else if (kind == MGM_NOISE_U1) {
+    const double th = 6.283185307179586476925287 * ((double)w.x + 0.5) * 0x1p-32;
+    v = {(R)cos(th), (R)sin(th)};
+  } else if (kind == MGM_NOISE_GAUSS) {
+    const double u1 = ((double)w.x + 1.0) * 0x1p-32, u2 = (double)w.y * 0x1p-32;
+    v = {(R)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925287 * u2)), 0};
+  } else {
+    switch (w.x >> 30) {
+      case 0: v = {1, 0}; break;
+      case 1: v = {0, 1}; break;
+      case 2: v = {-1, 0}; break;
+      default: v = {0, -1}; break;
+    }
   }
   P::st(out, e, v);
 }
 
-void draw_z4(Context* c, uint64_t seed, uint32_t stream, uint64_t first, int nprobe, int64_t nsite, int dof,
-             mgm_prec prec, void* out, int slice, int64_t sites_per_slice) {
+void draw_noise(Context* c, int kind, uint64_t seed, uint32_t stream, uint64_t first, int nprobe, int64_t nsite,
+                int dof, mgm_prec prec, void* out, const NoiseMask& mk) {
+  MGM_CHECK(kind >= MGM_NOISE_Z4 && kind <= MGM_NOISE_GAUSS, MGM_ERR_INVALID_ARG, "unknown probe distribution");
+  MGM_CHECK(mk.colour < 0 || (mk.p >= 1 && mk.X % mk.p == 0 && mk.Y % mk.p == 0 && mk.Z % mk.p == 0),
+            MGM_ERR_INVALID_ARG, "probing distance must divide the lattice");
   int64_t n = nsite * dof * nprobe;
   if (n == 0) return;
   uint2 key = make_uint2((uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
   unsigned nb = nblocks_for(n, 256);
   if (prec == MGM_PREC_F64)
-    hipLaunchKernelGGL(k_z4<F64>, dim3(nb), dim3(256), 0, c->stream, (double2*)out, key, stream, first, nprobe,
-                       nsite, dof, slice, sites_per_slice);
+    hipLaunchKernelGGL(k_noise<F64>, dim3(nb), dim3(256), 0, c->stream, (double2*)out, key, stream, first, nprobe,
+                       nsite, dof, kind, mk);
   else if (prec == MGM_PREC_F32)
-    hipLaunchKernelGGL(k_z4<F32>, dim3(nb), dim3(256), 0, c->stream, (float2*)out, key, stream, first, nprobe,
-                       nsite, dof, slice, sites_per_slice);
+    hipLaunchKernelGGL(k_noise<F32>, dim3(nb), dim3(256), 0, c->stream, (float2*)out, key, stream, first, nprobe,
+                       nsite, dof, kind, mk);
   else
-    throw Error(MGM_ERR_INVALID_ARG, "z4: precision must be F64 or F32");
+    throw Error(MGM_ERR_INVALID_ARG, "probe draws: precision must be F64 or F32");
   MGM_LAUNCH_CHECK();
+}
+
+void draw_z4(Context* c, uint64_t seed, uint32_t stream, uint64_t first, int nprobe, int64_t nsite, int dof,
+             mgm_prec prec, void* out, int slice, int64_t sites_per_slice) {
+  NoiseMask mk;
+  mk.slice = slice;
+  mk.sites_per_slice = sites_per_slice;
+  draw_noise(c, MGM_NOISE_Z4, seed, stream, first, nprobe, nsite, dof, prec, out, mk);
 }
 
 // ------------------------------------------------------ slice reductions

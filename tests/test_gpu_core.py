@@ -9,7 +9,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import to_gpu, from_gpu, rel, flat_to_sites  # noqa: E402
+from gpu_common import LocalStencil, to_gpu, from_gpu, rel, flat_to_sites  # noqa: E402
 from lattice_inputs import gauge_field, random_spinor  # noqa: E402
 
 
@@ -114,55 +114,10 @@ def test_dslash_sampled_sites_full_size(ctx):
     # oracle on a small periodic-in-space window is not the same operator, so
     # evaluate D at sampled sites from the definition with the full field
     sites = rng.integers(0, V, 16)
-    D = _LocalStencil(U, 0.02, 1.0)
+    D = LocalStencil(U, 0.02, 1.0)
     for s in sites:
         want = D.at(s, x[:, :, 0].T)
         assert np.linalg.norm(y[:, s, 0] - want) < 1e-13 * np.linalg.norm(want)
-
-
-class _LocalStencil:
-    """Evaluates (D x)(s) at one site from the oracle's building blocks."""
-
-    def __init__(self, U, m0, csw):
-        from oracle import dirac
-        self.U, self.m0, self.csw = U, m0, csw
-        self.dirac = dirac
-        self.T, self.Z, self.Y, self.X = U.shape[:4]
-
-    def _idx(self, c):
-        x, y, z, t = c
-        return x % self.X + self.X * (y % self.Y + self.Y * (z % self.Z + self.Z * (t % self.T)))
-
-    def at(self, s, x):
-        d = self.dirac
-        X, Y, Z, T = self.X, self.Y, self.Z, self.T
-        c = [s % X, (s // X) % Y, (s // (X * Y)) % Z, s // (X * Y * Z)]
-        # clover from a 3^4 patch around the site (periodic copy of the field)
-        patch = np.zeros((3, 3, 3, 3, 4, 3, 3), dtype=complex)
-        for dt in range(3):
-            for dz in range(3):
-                for dy in range(3):
-                    for dx in range(3):
-                        cc = (c[0] + dx - 1, c[1] + dy - 1, c[2] + dz - 1, c[3] + dt - 1)
-                        patch[dt, dz, dy, dx] = self.U[cc[3] % T, cc[2] % Z, cc[1] % Y, cc[0] % X]
-        Cl = d.clover_matrix(patch, self.csw)[1, 1, 1, 1]
-        out = (4 + self.m0) * x[s] + Cl @ x[s]
-        g = d.gammas()
-        I4 = np.eye(4)
-        for mu in range(4):
-            e = [0, 0, 0, 0]
-            e[mu] = 1
-            cf = [c[i] + e[i] for i in range(4)]
-            cb = [c[i] - e[i] for i in range(4)]
-            ph_f = -1.0 if (mu == 3 and c[3] == T - 1) else 1.0
-            ph_b = -1.0 if (mu == 3 and c[3] == 0) else 1.0
-            Uf = self.U[c[3], c[2], c[1], c[0], mu]
-            Ub = self.U[cb[3] % T, cb[2] % Z, cb[1] % Y, cb[0] % X, mu].conj().T
-            pf = x[self._idx(cf)].reshape(4, 3)
-            pb = x[self._idx(cb)].reshape(4, 3)
-            out = out - 0.5 * ph_f * ((I4 - g[mu]) @ (pf @ Uf.T)).reshape(12)
-            out = out - 0.5 * ph_b * ((I4 + g[mu]) @ (pb @ Ub.T)).reshape(12)
-        return out
 
 
 @pytest.mark.parametrize("prec,nrhs", [("f64", 3), ("f32", 4), ("f32", 5), ("f16", 8)])

@@ -22,7 +22,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import to_gpu, from_gpu, rel  # noqa: E402
+from gpu_common import LocalStencil, to_gpu, from_gpu, rel  # noqa: E402
 from lattice_inputs import gauge_field, random_spinor  # noqa: E402
 
 BOUND = {"f32": 2e-6, "f16": 4e-3}
@@ -183,6 +183,17 @@ def test_march_full_size_f16_eight_rhs(ctx):
         assert torch.all((yx - a).abs() <= 1e-6 * b.sqrt() * nx), v
         assert torch.all((yy - b).abs() <= 1e-6 * b), v
     ctx.tune_set(key, 0)
+    # variant 0 against the oracle's stencil at sampled sites (FP64, from the
+    # definition, on the stored FP16 input): FP16 links, clover and output
+    # give at most 4e-3 of the site's norm
+    xs_np = xc[:, :, :2].cpu().numpy()  # (12, V, 2)
+    y0_np = y0c[:, :, :2].cpu().numpy()
+    st = LocalStencil(U, 0.02, 1.0)
+    rng = np.random.default_rng(7)
+    for s_ in rng.integers(0, V, 12):
+        for r in range(2):
+            want = st.at(s_, xs_np[:, :, r].T)
+            assert np.linalg.norm(y0_np[:, s_, r] - want) <= 4e-3 * np.linalg.norm(want), (s_, r)
     del x, xc, ref, y0, y0c
     torch.cuda.empty_cache()
 
@@ -226,6 +237,20 @@ def test_fused_smoother_step(ctx, lats, lname, nrhs):
     assert torch.equal(rn[:, :, 0], r[:, :, 0]) and torch.equal(x[:, :, 0], x0[:, :, 0])
     assert torch.all((yx - yx_ref).abs() <= 1e-4 * yy_ref.sqrt() * c(r).abs().pow(2).sum(dim=(0, 1)).sqrt())
     assert torch.all((yy - yy_ref).abs() <= 1e-4 * yy_ref)
+    # against the oracle: q = D r from the FP64 operator on the stored FP16 r,
+    # r' = r - omega q and the dots of (q, r) within the FP16 operator's bound
+    # (links and clover stored in FP16: 4e-3 of |q| per rhs)
+    rr = from_gpu(c(r)).reshape(nrhs, -1)
+    qo = lat.D.matvec(rr)
+    omn = om.cpu().numpy()
+    rn_np = from_gpu(c(rn)).reshape(nrhs, -1)
+    yxn, yyn = yx.cpu().numpy(), yy.cpu().numpy()
+    for j in range(nrhs):
+        want_rj = rr[j] - omn[j] * qo[j]
+        nq = np.linalg.norm(qo[j])
+        assert np.linalg.norm(rn_np[j] - want_rj) <= 2.0 ** -10 * np.linalg.norm(want_rj) + abs(omn[j]) * 4e-3 * nq, j
+        assert abs(yxn[j] - np.vdot(qo[j], rr[j])) <= 4e-3 * nq * np.linalg.norm(rr[j]), j
+        assert abs(yyn[j] - nq ** 2) <= 8e-3 * nq ** 2, j
 
 
 def test_fused_smoother_step_refuses_lattice_without_tile(ctx):

@@ -300,19 +300,21 @@ def test_correlator_per_probe(two, three, dec):
 
 
 @pytest.mark.parametrize("dec", ["plain", "oblique", "orthogonal"])
-def test_loops_per_probe(two, dec):
+def test_loops_per_probe(two, three, dec):
+    """Loop slices tr(Gamma B(t,t)) per probe, term, Gamma and t (Sec. 4.3)
+    on two- and three-level hierarchies against the oracle."""
     import paper_2509_11424_amd as m
     from oracle import estimators as E
-    p = two
-    L = p.oh.L
-    res = p.h.estimate("loops", dec, [3] * L, seed=5, batch=3, solve=m.solve_desc(tol=1e-12))
-    groups = [0] if dec == "plain" else range(L)
-    for g in groups:
-        terms, X = E.loop_samples(p.oh, p.solvers, dec, g, seed=5, nprobe=3)
-        for it, r in enumerate(terms):
-            got = res["samples"][r]
-            scale = np.abs(X[:, it]).max()
-            assert np.abs(got - X[:, it]).max() <= 1e-8 * scale, (dec, g, r)
+    for p in (two, three):
+        L = p.oh.L
+        res = p.h.estimate("loops", dec, [3] * L, seed=5, batch=3, solve=m.solve_desc(tol=1e-12))
+        groups = [0] if dec == "plain" else range(L)
+        for g in groups:
+            terms, X = E.loop_samples(p.oh, p.solvers, dec, g, seed=5, nprobe=3)
+            for it, r in enumerate(terms):
+                got = res["samples"][r]
+                scale = np.abs(X[:, it]).max()
+                assert np.abs(got - X[:, it]).max() <= 1e-8 * scale, (L, dec, g, r)
 
 
 def test_estimate_first_probe_offset_reproduces(two):
