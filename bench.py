@@ -163,6 +163,16 @@ CONFIGS = {
                restart=12,
                name="32^3x64 Wilson-clover (csw 1, roughness 0.6, m0 0.02), 3-level orthogonal MG-MLMC "
                     "tr(D^-1), aggregates 4^4/2^4, N_tv 24/32, probes 20/100/400"),
+    # one GPU's share of the paper's J501 lattice (192 x 64^3 split four ways
+    # in time) with its four-level aggregation 4^4 / 2^4 / 2^4 (coarse
+    # lattices 16^3 x 12, 8^3 x 6, 4^3 x 3); synthetic field of the same
+    # family as the 32^3 x 64 workload
+    "j501q": dict(dims=(64, 64, 64, 48), eps=0.6, m0=0.02, csw=1.0, gseed=15,
+                  blocks=[(4, 4, 4, 4), (2, 2, 2, 2), (2, 2, 2, 2)], ntv=[24, 32, 32], nprobe=[4, 8, 16, 64],
+                  pseed=105, batch=[2, 8, 16, 32], batch_f64=[2, 8, 16, 32], restart=8,
+                  name="64^3x48 Wilson-clover (csw 1, roughness 0.6, m0 0.02; one quarter of J501's 192x64^3 in "
+                       "time), 4-level orthogonal MG-MLMC tr(D^-1), aggregates 4^4/2^4/2^4, N_tv 24/32/32, "
+                       "probes 4/8/16/64"),
     "c3": dict(dims=(16, 16, 16, 16), eps=0.6, m0=0.01, csw=1.0, gseed=13, blocks=[(2, 2, 2, 2)], ntv=[12],
                nprobe=[64, 256], pseed=103, batch=[32, 64], restart=16,
                name="16^4 Wilson-clover (csw 1, roughness 0.6, m0 0.01), 2-level orthogonal MG-MLMC tr(D^-1), "
@@ -419,17 +429,19 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
         "tuned_shapes": len(ctx.tune_report()) if mixed else 0,
     }
     line["per_level"] = per_level_rates(m, ctx, h, cfg, sd, batch, torch)
-    if args.learned:
-        line["learned"] = learned_form(m, ctx, op, cfg, h, sd, args, torch)
-    if args.ttt:
+    weights = None
+    if args.learned or args.ttt:
         del h, results
         torch.cuda.empty_cache()
+    if args.learned:
+        line["learned"], weights = learned_form(m, ctx, args, torch)
+    if args.ttt:
 
         def make_mixed():
             return m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=cfg["batch"][0],
                                max_nrhs_level=cfg["batch"], restart=cfg["restart"], mixed=1)
 
-        line["time_to_target"] = time_to_target(m, ctx, op, cfg, make_mixed, sd, args)
+        line["time_to_target"] = time_to_target(m, ctx, op, cfg, make_mixed, sd, args, weights)
     if cpu_pid:
         os.waitpid(cpu_pid, 0)
         try:
@@ -543,57 +555,114 @@ def micro(args):
             del x, y
 
 
-def learned_form(m, ctx, op, cfg, h, sd_mixed, args, torch):
-    """Learned preconditioner at the workload's size: a PTC network trained on
-    a small lattice of the same ensemble parameters (the weights are
-    volume-independent), then used as the fine smoother of the mixed solver
-    on the full lattice; compared with the MR-smoothed mixed solve on the same
-    right-hand sides, and one full estimate step with it."""
+LEARNED = dict(widths=(4, 16, 16, 16, 4), train_seeds=list(range(1001, 1009)), eval_seeds=list(range(2001, 2009)),
+               eps=0.6, m0=0.01, csw=1.0, dims=(16, 16, 16, 16), blocks=[(2, 2, 2, 2)], ntv=[12],
+               big_dims=(24, 24, 24, 48), big_blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], big_ntv=[24, 32],
+               big_eval_seeds=list(range(2001, 2003)), pairs=16, epochs=4, steps_per_visit=15, lr=3e-3)
+
+
+def learned_form(m, ctx, args, torch):
+    """The learned-preconditioner form on its own workloads: a PTC network of
+    four layers, 4 -> 16 -> 16 -> 16 -> 4 colour-triplet channels (one spinor's
+    12 complex components in and out), BF16 weights with FP32 accumulation,
+    trained with the library's kernels (full-batch Adam) on residual / error
+    pairs from FP64 MG solves on 8 seeded 16^4 training fields (roughness 0.6,
+    m0 0.01, c_sw 1; seeds 1001-1008), visiting the fields in turn for a few
+    Adam steps each.  Then used as the fine smoother inside the mixed FGMRES
+    on 8 held-out 16^4 fields (seeds 2001-2008) and on 24^3 x 48 fields, the
+    weights carried over unchanged (the layers do not depend on the volume),
+    against MR smoothing in the same solver and against plain FP64 MG, every
+    solve to a true FP64 residual of 1e-10.  Returns the weights as a list."""
+    import numpy as np
     from lattice_inputs import gauge_field
-    small = (8, 8, 8, 8)
-    Us = gauge_field(small, cfg["eps"], cfg["gseed"] + 500)
-    ops = m.Operator(ctx, Us, cfg["m0"], cfg["csw"])
-    hs = m.Hierarchy(ops, [(4, 4, 4, 4)], [cfg["ntv"][0]], seed=cfg["pseed"] + 2000, max_nrhs=16, restart=16,
-                     mixed=2)
-    widths = tuple(args.net_widths)
-    ns = m.Net(ops, widths=widths, seed=cfg["pseed"] + 3000, max_nrhs=16, train_nrhs=16)
-    t0 = time.time()
-    tr = ns.train(hs, steps=args.net_steps, lr=3e-3, seed=cfg["pseed"] + 4000, target_tol=1e-8)
-    torch.cuda.synchronize()
-    t_train = time.time() - t0
-    net = m.Net(op, widths=widths, seed=1, max_nrhs=cfg["batch"][0])
-    net.set_weights(ns.get_weights())
-    del ns, hs, ops
-    sd_net = m.solve_desc(tol=1e-10, kind="net", net=net, smooth=sd_mixed.smooth, smooth_coarse=sd_mixed.smooth_coarse,
-                          coarse_iters=sd_mixed.coarse_iters, inner_tol=sd_mixed.inner_tol, maxiter=5000, coarse_bf16=True,
-                          smoother_f16=True, graphs=True)
-    s_, d_, _ = h.level_info(0)
-    b = m.draw_z4(ctx, cfg["pseed"] + 5000, 0, 0, cfg["batch"][0], s_, d_, "f64")
-    out = {"widths": list(widths), "train_lattice": "x".join(map(str, small)), "train_steps": args.net_steps,
-           "train_pairs": 16, "train_s": t_train, "loss_first": tr["loss_first"], "loss_last": tr["loss_last"]}
-    for name, desc in (("mr_smoother", sd_mixed), ("network", sd_net)):
-        h.solve(0, b, desc)  # warm-up (tuning, graph capture)
-        torch.cuda.synchronize()
-        t0 = time.time()
-        x, st = h.solve(0, b, desc)
-        torch.cuda.synchronize()
-        out[name] = {"seconds": time.time() - t0, "iterations": st["iterations"], "fallbacks": st["fallbacks"],
-                     "max_rel_residual": st["max_rel_residual"]}
+    L5 = LEARNED
+    out = {"widths": list(L5["widths"]), "bf16_weights": True, "train_lattice": "x".join(map(str, L5["dims"])),
+           "train_fields": L5["train_seeds"], "pairs_per_field": L5["pairs"], "epochs": L5["epochs"],
+           "adam_steps_per_visit": L5["steps_per_visit"]}
+    hs = []
+    for sd_ in L5["train_seeds"]:
+        U = gauge_field(L5["dims"], L5["eps"], sd_)
+        op = m.Operator(ctx, U, L5["m0"], L5["csw"])
+        h = m.Hierarchy(op, L5["blocks"], L5["ntv"], seed=sd_ + 100, max_nrhs=L5["pairs"], restart=16, mixed=2)
+        hs.append((op, h))
+    net0 = m.Net(hs[0][0], widths=L5["widths"], seed=3001, max_nrhs=L5["pairs"], train_nrhs=L5["pairs"],
+                 bf16_weights=True)
     torch.cuda.synchronize()
     t0 = time.time()
-    r = h.estimate("trace", "orthogonal", cfg["nprobe"], seed=cfg["pseed"] + 6000, batch=cfg["batch"],
-                   solve=sd_net, samples=False)
+    hist = []
+    for ep in range(L5["epochs"]):
+        for i, (op, h) in enumerate(hs):
+            # the weights are field independent: each visit moves the network
+            # to the field's links and trains on that field's pairs (Adam
+            # state kept across visits)
+            net0.bind(op)
+            tr = net0.train(h, steps=L5["steps_per_visit"], lr=L5["lr"], seed=4000 + 100 * ep + i,
+                            target_tol=1e-8)
+            hist.append([tr["loss_first"], tr["loss_last"]])
     torch.cuda.synchronize()
-    dt = time.time() - t0
-    out["estimate_step"] = {"seconds": dt, "rhs_per_s": rhs_per_step(cfg["nprobe"]) / dt,
-                            "fallbacks": r["stats"]["fallbacks"]}
-    return out
+    out["train_s"] = time.time() - t0
+    out["loss_first"] = hist[0][0]
+    out["loss_last"] = hist[-1][1]
+    weights = net0.get_weights()
+    del net0, hs
+    torch.cuda.empty_cache()
+
+    def settings(kind, net=None):
+        if kind == "f64":
+            return m.solve_desc(tol=1e-10, kind="mg", smooth=6, smooth_coarse=2, coarse_iters=1, maxiter=5000)
+        return m.solve_desc(tol=1e-10, kind=kind, net=net, smooth=args.smooth, smooth_coarse=args.smooth_coarse,
+                            coarse_iters=args.coarse_iters, inner_tol=args.inner_tol, maxiter=5000,
+                            coarse_bf16=True, smoother_f16=True, graphs=True)
+
+    def evaluate(dims, blocks, ntv, seeds, nrhs):
+        rows = []
+        for sd_ in seeds:
+            U = gauge_field(dims, L5["eps"], sd_)
+            op = m.Operator(ctx, U, L5["m0"], L5["csw"])
+            h = m.Hierarchy(op, blocks, ntv, seed=sd_ + 100, max_nrhs=nrhs, restart=12, mixed=2)
+            net = m.Net(op, widths=L5["widths"], seed=1, max_nrhs=nrhs, bf16_weights=True)
+            net.set_weights(weights)
+            s_, d_, _ = h.level_info(0)
+            b = m.draw_z4(ctx, sd_ + 5000, 0, 0, nrhs, s_, d_, "f64")
+            row = {"seed": sd_}
+            for name, sd in (("mr", settings("mg_mixed")), ("net", settings("net", net)), ("f64", settings("f64"))):
+                h.solve(0, b, sd)  # warm-up: autotuning, graph capture
+                torch.cuda.synchronize()
+                t1 = time.time()
+                x, st = h.solve(0, b, sd)
+                torch.cuda.synchronize()
+                row[name] = {"seconds": time.time() - t1, "iterations": st["iterations"],
+                             "fallbacks": st["fallbacks"], "max_rel_residual": st["max_rel_residual"]}
+            # traces: the same probes through both smoothers
+            npr = [4] * h.L
+            a = h.estimate("trace", "orthogonal", npr, seed=sd_ + 6000, batch=nrhs, solve=settings("net", net))
+            c = h.estimate("trace", "orthogonal", npr, seed=sd_ + 6000, batch=nrhs, solve=settings("mg_mixed"))
+            d = max(float(np.max(np.abs(sa - sc)) / max(np.max(np.abs(sc)), 1e-300))
+                    for sa, sc in zip(a["samples"], c["samples"]))
+            row["trace_max_rel_diff"] = d
+            row["trace_net"] = [a["total_mean"][0, 0].real, a["total_mean"][0, 0].imag]
+            rows.append(row)
+            del h, net, op, b
+            torch.cuda.empty_cache()
+        return rows
+
+    out["eval_16x16x16x16"] = evaluate(L5["dims"], L5["blocks"], L5["ntv"], L5["eval_seeds"], L5["pairs"])
+    out["eval_24x24x24x48"] = evaluate(L5["big_dims"], L5["big_blocks"], L5["big_ntv"], L5["big_eval_seeds"],
+                                       L5["pairs"])
+    for key in ("eval_16x16x16x16", "eval_24x24x24x48"):
+        rows = out[key]
+        out[key + "_mean"] = {n: {"seconds": float(np.mean([r[n]["seconds"] for r in rows])),
+                                  "iterations": float(np.mean([r[n]["iterations"] for r in rows]))}
+                              for n in ("mr", "net", "f64")}
+    return out, weights
 
 
-def time_to_target(m, ctx, op, cfg, make_mixed, sd_mixed, args):
+def time_to_target(m, ctx, op, cfg, make_mixed, sd_mixed, args, weights=None):
     """Time to reach the variance of the plain FP64 orthogonal estimate at the
     configured probe counts (target eps^2), for plain FP64 MG and for the
-    mixed form with MLMC-optimal sample sizes (Sec. 2.2, eq. MLMC-Nl)."""
+    mixed form with MLMC-optimal sample sizes (Sec. 2.2, eq. MLMC-Nl); with
+    trained network weights also for the learned form (the mixed form with
+    the network as the fine smoother)."""
     import numpy as np
     import torch
     L = len(cfg["nprobe"])
@@ -637,6 +706,18 @@ def time_to_target(m, ctx, op, cfg, make_mixed, sd_mixed, args):
     pm = pilot(h_mixed, sd_mixed, cfg["batch"])
     out["mixed"] = final(h_mixed, sd_mixed, pm, eps2, cfg["batch"])
     out["mixed"]["batch"] = cfg["batch"]
+    if weights is not None:
+        net = m.Net(op, widths=LEARNED["widths"], seed=1, max_nrhs=cfg["batch"][0], bf16_weights=True)
+        net.set_weights(weights)
+        sd_net = m.solve_desc(tol=1e-10, kind="net", net=net, smooth=sd_mixed.smooth,
+                              smooth_coarse=sd_mixed.smooth_coarse, coarse_iters=sd_mixed.coarse_iters,
+                              inner_tol=sd_mixed.inner_tol, maxiter=5000, coarse_bf16=True, smoother_f16=True,
+                              graphs=True)
+        pn = pilot(h_mixed, sd_net, cfg["batch"])
+        out["learned"] = final(h_mixed, sd_net, pn, eps2, cfg["batch"])
+        out["learned"]["batch"] = cfg["batch"]
+        out["ratio_f64_over_learned"] = out["f64"]["seconds"] / out["learned"]["seconds"]
+        del net
     del h_mixed
     torch.cuda.empty_cache()
     out["ratio_f64_over_mixed"] = out["f64"]["seconds"] / out["mixed"]["seconds"]
@@ -660,8 +741,6 @@ def main():
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--ttt", type=int, default=1, help="time to target variance, FP64 against the mixed form")
     ap.add_argument("--learned", action="store_true", help="also measure the learned-preconditioner form")
-    ap.add_argument("--net-widths", type=int, nargs="+", default=[4, 8, 8, 4])
-    ap.add_argument("--net-steps", type=int, default=150)
     ap.add_argument("--micro", choices=["dslash", "dslash_dot", "step", "copy"])
     ap.add_argument("--tune", action="store_true", help="micro: autotune the launch shape first")
     ap.add_argument("--variant", type=int, default=None, help="micro: pin this launch variant")

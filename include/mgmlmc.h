@@ -168,8 +168,10 @@ mgm_status mgm_operator_apply_dot_noalloc(mgm_operator op, mgm_prec prec, const 
                                           int32_t nrhs, void* yx_dev, void* yy_dev);
 
 /* One fused step of the FP16 minimal-residual smoother with the previous
- * step's length (the MR smoother of the multigrid solver, Sec. 2.1's solver
- * setting, as a Richardson step of lagged MR length): with
+ * step's length (the minimal-residual smoother of this library's multigrid
+ * solver as a Richardson step of lagged MR length; the paper fixes only that
+ * the levels are solved by multigrid, Sec. 4, so this smoother is a reading
+ * of this library, not a passage of the paper): with
  * omega_r = qr_prev_dev[r] / qq_prev_dev[r] (0 where qq_prev_dev[r] is 0) and
  * q = D r (not stored), writes r_next = r - omega q, updates x += omega r in
  * place, and yx_dev[r] = q_r^H r_r, yy_dev[r] = |q_r|^2 (FP64 sums of the
@@ -438,6 +440,10 @@ typedef struct {
   uint64_t seed;                            /* initial weights (identity path plus small noise) */
   int32_t max_nrhs;                         /* right-hand sides per application, 1..256 */
   int32_t train_nrhs;                       /* training pairs (= batch), 0..256; 0: no training */
+  int32_t bf16_weights;                     /* 1: the layers use the weights rounded to BF16
+                                               (nearest, ties to even) with FP32 accumulation;
+                                               the FP64 master weights and Adam stay unrounded
+                                               and the gradient is taken at the rounded weights */
 } mgm_net_desc;
 
 typedef struct {
@@ -463,6 +469,11 @@ mgm_status mgm_net_workspace_size(mgm_operator op, const mgm_net_desc* desc, siz
  * MGM_ERR_INVALID_ARG; small workspace: MGM_ERR_WORKSPACE. */
 mgm_status mgm_net_create(mgm_operator op, const mgm_net_desc* desc, void* ws_dev, size_t ws_bytes,
                           mgm_net* out);
+/* Moves the network to another operator of the same lattice (another gauge
+ * field): later applications and training use that operator's links; the
+ * weights and the Adam state are kept (the layers are gauge covariant, their
+ * weights do not depend on the field).  Errors: INVALID_ARG, SHAPE. */
+mgm_status mgm_net_bind(mgm_net net, mgm_operator op);
 mgm_status mgm_net_num_weights(mgm_net net, int64_t* count);  /* complex weights */
 /* Host FP64 weights (2 * count doubles); set also resets the Adam state. */
 mgm_status mgm_net_set_weights(mgm_net net, const double* w_host);

@@ -100,7 +100,7 @@ class EstimateResult(C.Structure):
 
 class NetDesc(C.Structure):
     _fields_ = [("nlayers", C.c_int32), ("width", C.c_int32 * (NET_MAX_LAYERS + 1)), ("seed", C.c_uint64),
-                ("max_nrhs", C.c_int32), ("train_nrhs", C.c_int32)]
+                ("max_nrhs", C.c_int32), ("train_nrhs", C.c_int32), ("bf16_weights", C.c_int32)]
 
 
 class TrainDesc(C.Structure):
@@ -187,6 +187,7 @@ _SIGS = [
     ("mgm_net_workspace_size", C.c_int, [C.c_void_p, C.POINTER(NetDesc), C.POINTER(C.c_size_t)]),
     ("mgm_net_create", C.c_int, [C.c_void_p, C.POINTER(NetDesc), C.c_void_p, C.c_size_t,
                                  C.POINTER(C.c_void_p)]),
+    ("mgm_net_bind", C.c_int, [C.c_void_p, C.c_void_p]),
     ("mgm_net_num_weights", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("mgm_net_save", C.c_int, [C.c_void_p, C.c_char_p]),
     ("mgm_net_load", C.c_int, [C.c_void_p, C.c_char_p]),
@@ -718,7 +719,7 @@ class Net:
     lattice of operator `op`.  widths = [4, c1, ..., 4]."""
 
     def __init__(self, op: Operator, widths=(4, 16, 16, 16, 4), seed: int = 1, max_nrhs: int = 8,
-                 train_nrhs: int = 0):
+                 train_nrhs: int = 0, bf16_weights: bool = False):
         self.op = op
         self.ctx = op.ctx
         d = NetDesc()
@@ -728,6 +729,7 @@ class Net:
         d.seed = seed
         d.max_nrhs = max_nrhs
         d.train_nrhs = train_nrhs
+        d.bf16_weights = 1 if bf16_weights else 0
         self.desc = d
         self.widths = list(widths)
         nb = C.c_size_t()
@@ -748,6 +750,11 @@ class Net:
             out.append(flat[off:off + k].reshape(9, co, ci))
             off += k
         return out
+
+    def bind(self, op: Operator):
+        """Moves the network (weights and Adam state) to another operator of the same lattice."""
+        _check(lib().mgm_net_bind(self.h, op.h))
+        self.op = op
 
     def get_weights(self) -> list:
         w = np.empty(2 * self.nweights, dtype=np.float64)

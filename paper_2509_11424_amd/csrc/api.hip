@@ -892,6 +892,19 @@ mgm_status mgm_net_create(mgm_operator op, const mgm_net_desc* desc, void* ws_de
   API_END
 }
 
+mgm_status mgm_net_bind(mgm_net net, mgm_operator op) {
+  API_BEGIN
+  MGM_CHECK(net && op, MGM_ERR_INVALID_ARG, "NULL argument");
+  const Geom& a = net->n.op->g;
+  const Geom& b = op->op.g;
+  MGM_CHECK(a.X == b.X && a.Y == b.Y && a.Z == b.Z && a.T == b.T && a.antiperiodic == b.antiperiodic,
+            MGM_ERR_SHAPE, "the network can only move to an operator of the same lattice");
+  MGM_CHECK(op->ctx == net->n.ctx, MGM_ERR_INVALID_ARG, "the operator belongs to another context");
+  net->op = op;
+  net->n.op = &op->op;
+  API_END
+}
+
 mgm_status mgm_net_num_weights(mgm_net net, int64_t* count) {
   API_BEGIN
   MGM_CHECK(net && count, MGM_ERR_INVALID_ARG, "NULL argument");

@@ -188,15 +188,29 @@ __global__ void k_ptc_wsum(const double2* __restrict__ part, int64_t nblk, int c
 }
 
 // FP32 forward weights and backward weights W'_q = W_{opposite(q)}^H
+// FP32 value rounded to the nearest BF16 value (ties to even), kept in FP32
+__device__ __forceinline__ float round_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+  return __uint_as_float(u);
+}
+
+// kernel weights from the master weights: FP32, or BF16-rounded when bf16
+// (the layers then multiply BF16 weights and accumulate in FP32)
 __global__ void k_ptc_wcopy(const double2* __restrict__ w64, float2* __restrict__ w32, float2* __restrict__ wadj,
-                            int co, int ci) {
+                            int co, int ci, int bf16) {
   const int n = kNetPaths * co * ci;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int p = i / (co * ci), rem = i % (co * ci), a = rem / ci, b = rem % ci;
     const double2 w = w64[i];
-    w32[i] = make_float2((float)w.x, (float)w.y);
+    float wr = (float)w.x, wi = (float)w.y;
+    if (bf16) {
+      wr = round_bf16(wr);
+      wi = round_bf16(wi);
+    }
+    w32[i] = make_float2(wr, wi);
     const int q = p == 0 ? 0 : (p <= 4 ? p + 4 : p - 4);
-    wadj[(q * ci + b) * co + a] = make_float2((float)w.x, (float)-w.y);
+    wadj[(q * ci + b) * co + a] = make_float2(wr, -wi);
   }
 }
 
@@ -298,7 +312,7 @@ void Net::refresh() {
   for (int l = 0; l < L; l++) {
     const int co = width[l + 1], ci = width[l];
     hipLaunchKernelGGL(k_ptc_wcopy, dim3(nblocks_for((int64_t)kNetPaths * co * ci, 256)), dim3(256), 0,
-                       ctx->stream, w64 + woff[l], w32 + woff[l], wadj + woff[l], co, ci);
+                       ctx->stream, w64 + woff[l], w32 + woff[l], wadj + woff[l], co, ci, desc.bf16_weights ? 1 : 0);
   }
   MGM_LAUNCH_CHECK();
 }

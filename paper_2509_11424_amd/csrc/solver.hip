@@ -2,7 +2,9 @@
 // residual of 1e-12 with a multigrid solver, Sec. 4).
 //
 // * FGMRES(m): Arnoldi with classical Gram-Schmidt plus one
-//   re-orthogonalisation pass, Givens rotations and the small triangular
+//   re-orthogonalisation pass (a single pass in the FP32 inner solves of the
+//   mixed form when their tolerance is 1e-4 or looser: the orthogonality they
+//   lose stays far below that tolerance), Givens rotations and the small triangular
 //   solve on the GPU; the host only reads the per-rhs residual estimate of the
 //   previous step (so the GPU always has the next step queued) and the true
 //   residual once per restart.

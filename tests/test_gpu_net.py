@@ -190,3 +190,78 @@ def test_non_finite_network_falls_back_to_mg(lat, trained):
     x, st = h.solve(0, to_gpu(b), sd)
     assert st["fallbacks"] >= 1
     assert st["max_rel_residual"] <= 1e-10
+
+
+def _bf16(w):
+    """Nearest BF16 value (ties to even) of the FP32 rounding of w, as complex128."""
+    def r(x):
+        u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+        u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+        return u.view(np.float32).astype(np.float64)
+    return r(w.real) + 1j * r(w.imag)
+
+
+def test_bf16_weights_forward_and_gradient_match_oracle(lat):
+    """bf16_weights: the layers use the weights rounded to BF16 with FP32
+    accumulation; forward and gradient equal the oracle's at the rounded
+    weights (FP32 bounds), and differ from the unrounded forward by about the
+    BF16 rounding (2^-9)."""
+    import paper_2509_11424_amd as m
+    from oracle.ptc import PTC, random_weights
+    p = lat
+    widths = (4, 16, 4)
+    W = random_weights(widths, 71)
+    net = m.Net(p.op, widths=widths, max_nrhs=3, train_nrhs=3, bf16_weights=True)
+    net.set_weights(W)
+    x = _to_f32_gpu(_rand(p.V, 3, 72))
+    got = from_gpu(net.apply(x))
+    Wb = [_bf16(w) for w in W]
+    want = PTC(p.U).apply(Wb, _oracle_field(from_gpu(x))).reshape(3, p.V, 12)
+    assert rel(got, want) < 2e-6
+    W32 = [w.astype(np.complex64).astype(np.complex128) for w in W]
+    full = PTC(p.U).apply(W32, _oracle_field(from_gpu(x))).reshape(3, p.V, 12)
+    assert 1e-5 < rel(got, full) < 1e-2
+    e = _to_f32_gpu(_rand(p.V, 3, 73))
+    loss, grads = net.loss_grad(x, e)
+    ol, og = PTC(p.U).loss_grad(Wb, _oracle_field(from_gpu(x)), _oracle_field(from_gpu(e)))
+    assert abs(loss - ol) < 1e-5 * ol
+    for g, o in zip(grads, og):
+        assert rel(g, o) < 1e-4
+
+
+def test_trained_network_gains_over_the_method_without_it(lat, trained):
+    """What training buys, on fresh pairs of the training field's kind
+    (r = z - D P D_c^-1 P^H z, e = D^-1 r for new Z4 z): the trained network's
+    loss |N(r) - e|^2 / |e|^2 is below half the untrained one's; and inside
+    FGMRES (same right-hand sides, 1e-10) the trained network converges
+    without falling back to MG and in fewer outer iterations than the same
+    V-cycle without fine smoothing (coarse-grid correction only).  The
+    MR-smoothed V-cycle is run beside it."""
+    import torch
+    import paper_2509_11424_amd as m
+    p = lat
+    h, net, _ = trained
+    B = 8
+    z = m.draw_z4(p.ctx, 75, 8, 100, B, p.V, 12, "f64")
+    sd = m.solve_desc(tol=1e-12, maxiter=4000)
+    ec, _ = h.solve(1, h.restrict(0, z), sd)
+    r = z - p.op.apply(h.prolong(0, ec))
+    e, _ = h.solve(0, r, sd)
+    torch.cuda.synchronize()
+    r32, e32 = r.to(torch.complex64), e.to(torch.complex64)
+    untrained = m.Net(p.op, widths=(4, 8, 8, 4), seed=65, max_nrhs=8, train_nrhs=8)
+    l_tr, _ = net.loss_grad(r32, e32)
+    l_un, _ = untrained.loss_grad(r32, e32)
+    assert l_tr < 0.5 * l_un, (l_tr, l_un)
+    b = to_gpu(_rand(p.V, 8, 74))
+    its = {}
+    for name, sdx in (("net", m.solve_desc(tol=1e-10, kind="net", net=net, maxiter=4000)),
+                      ("no_smoothing", m.solve_desc(tol=1e-10, kind="mg_mixed", smooth=0, maxiter=1000)),
+                      ("mr", m.solve_desc(tol=1e-10, kind="mg_mixed", maxiter=4000))):
+        x, st = h.solve(0, b, sdx, check=False)
+        # a solve that misses the tolerance within maxiter counts as unbounded
+        its[name] = st["iterations"] if st["max_rel_residual"] <= 1e-10 else float("inf")
+        if name == "net":
+            assert st["fallbacks"] == 0
+    assert its["net"] < float("inf") and its["mr"] < float("inf"), its
+    assert its["net"] < its["no_smoothing"], its
