@@ -26,6 +26,7 @@ Kernel micro-benchmarks (used for the profiler runs of single kernels):
   python bench.py --micro dslash|dslash_dot|step --prec f32[,f64,f16] --nrhs 8[,1,...] [--iters 50]
                   [--tune | --variant V]   # autotune the launch shape, or pin variant V
   python bench.py --micro copy [--iters 50]      # plain 1 GiB device copy
+  python bench.py --micro coarse --prec bf16 --nrhs 16,100 [--level 1]   # coarse stencil
 """
 from __future__ import annotations
 
@@ -453,6 +454,42 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     print(json.dumps(line), flush=True)
 
 
+def micro_coarse(args, cfg, m, ctx, op, g, torch):
+    """Times the coarse stencil of level `--level` (default 1) of the
+    workload's mixed hierarchy in precision bf16 / f32 / f64 (HIP events on
+    the library's stream, autotuned tiles), for each rhs count."""
+    nmax = max(int(v) for v in args.nrhs.split(","))
+    caps = [1] + [nmax] * (len(cfg["blocks"]))
+    h = m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=1, max_nrhs_level=caps,
+                    restart=2, mixed=2)
+    lvl = args.level
+    s_, d_, _ = h.level_info(lvl)
+    kc = {"bf16": "coarse_bf16", "f32": "coarse_f32", "f64": "coarse_f64"}
+    for prec in args.prec.split(","):
+        for nrhs in [int(v) for v in args.nrhs.split(",")]:
+            dt = torch.complex128 if prec == "f64" else torch.complex64
+            x = torch.randn((d_, s_, nrhs), generator=g, device="cuda:0", dtype=dt)
+            ctx.autotune(True)
+            for _ in range(3):
+                h.apply_prec(lvl, x, prec)
+            ctx.autotune(False)
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            ctx.profile_reset()
+            for _ in range(args.iters):
+                h.apply_prec(lvl, x, prec)
+            torch.cuda.synchronize()
+            q = ctx.profile_query(kc[prec])
+            ctx.profile(False)
+            ms = q["ms"] / q["launches"]
+            bl = q["bytes"] / q["launches"]
+            flop = 8.0 * 9 * d_ * d_ * nrhs * s_  # complex multiply-adds of the nine blocks
+            print(json.dumps({"micro": "coarse", "prec": prec, "level": lvl, "sites": s_, "dof": d_, "nrhs": nrhs,
+                              "launches": q["launches"], "avg_ms": ms, "bytes_per_launch": bl,
+                              "GBps": bl / ms / 1e6, "TFLOPs": flop / ms / 1e9}), flush=True)
+            del x
+
+
 def per_level_rates(m, ctx, h, cfg, sd, batch, torch):
     """RHS solved per second on each level alone: one batch of the level's
     size of Z4 right-hand sides solved to 1e-10 with the timed form's
@@ -504,6 +541,9 @@ def micro(args):
     ctx = m.Context(0)
     op = m.Operator(ctx, U, cfg["m0"], cfg["csw"])
     g = torch.Generator(device="cuda:0").manual_seed(5)
+    if args.micro == "coarse":
+        micro_coarse(args, cfg, m, ctx, op, g, torch)
+        return
     for prec in args.prec.split(","):
         for nrhs in [int(v) for v in args.nrhs.split(",")]:
             shape = (12, op.V, nrhs)
@@ -741,7 +781,8 @@ def main():
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--ttt", type=int, default=1, help="time to target variance, FP64 against the mixed form")
     ap.add_argument("--learned", action="store_true", help="also measure the learned-preconditioner form")
-    ap.add_argument("--micro", choices=["dslash", "dslash_dot", "step", "copy"])
+    ap.add_argument("--micro", choices=["dslash", "dslash_dot", "step", "copy", "coarse"])
+    ap.add_argument("--level", type=int, default=1, help="micro coarse: hierarchy level of the stencil")
     ap.add_argument("--tune", action="store_true", help="micro: autotune the launch shape first")
     ap.add_argument("--variant", type=int, default=None, help="micro: pin this launch variant")
     ap.add_argument("--prec", default="f32", help="comma list of f64, f32, f16")

@@ -675,23 +675,26 @@ template <>
 struct BufIO<F32> {
   using S = float2;
   static constexpr uint32_t SB = 8, RB = 4;  // bytes of a complex / real element
+  template <int AUX = 0>
   __device__ __forceinline__ static S raw(Rsrc r, uint32_t vo, uint32_t so) {
-    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, AUX));
   }
   __device__ __forceinline__ static cx<float> cvt(S v) { return {v.x, v.y}; }
   __device__ __forceinline__ static float re(Rsrc r, uint32_t vo, uint32_t so) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
   }
+  template <int AUX = 0>
   __device__ __forceinline__ static void st(Rsrc r, uint32_t vo, uint32_t so, cx<float> v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), make_float2(v.re, v.im)), r, (int)vo, (int)so, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), make_float2(v.re, v.im)), r, (int)vo, (int)so, AUX);
   }
 };
 template <>
 struct BufIO<F16> {
   using S = __half2;
   static constexpr uint32_t SB = 4, RB = 2;
+  template <int AUX = 0>
   __device__ __forceinline__ static S raw(Rsrc r, uint32_t vo, uint32_t so) {
-    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, AUX));
   }
   __device__ __forceinline__ static cx<float> cvt(S v) {
     const float2 f = __half22float2(v);
@@ -700,9 +703,10 @@ struct BufIO<F16> {
   __device__ __forceinline__ static float re(Rsrc r, uint32_t vo, uint32_t so) {
     return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0)));
   }
+  template <int AUX = 0>
   __device__ __forceinline__ static void st(Rsrc r, uint32_t vo, uint32_t so, cx<float> v) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, __floats2half2_rn(v.re, v.im)), r, (int)vo,
-                                          (int)so, 0);
+                                          (int)so, AUX);
   }
 };
 
@@ -738,6 +742,147 @@ __device__ __forceinline__ void buf_clover(Rsrc rc, uint32_t plane_b, uint32_t v
     }
 }
 
+// ------------------------------------------------ packed FP16 arithmetic
+//
+// The FP16 marching kernel can keep the spinors and links in their storage
+// format: the half spinor h = u -/+ A_mu l is formed with FP16 adds (one
+// rounding to FP16, like the stored input), and every complex product with a
+// link or clover entry is a pair of v_dot2_f32_f16 (two FP16 products, exact
+// in FP32, added to an FP32 accumulator): re(U h) = dot2(U, (h.re, -h.im)),
+// im(U h) = dot2(U, (h.im, h.re)); re(conj(U) h) = dot2(U, h),
+// im(conj(U) h) = dot2(U, (h.im, -h.re)).  No conversion of links, clover
+// entries or neighbour spinors, half the multiply instructions of the FP32
+// form, and half the registers for the neighbour spinor.
+typedef _Float16 hv2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ hv2 hv(__half2 v) { return __builtin_bit_cast(hv2, v); }
+__device__ __forceinline__ float dot2(hv2 a, hv2 b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+__device__ __forceinline__ hv2 hmul_i(hv2 z) { return hv2{(_Float16)-z.y, z.x}; }
+__device__ __forceinline__ hv2 hmul_mi(hv2 z) { return hv2{z.y, (_Float16)-z.x}; }
+
+// h = u -/+ A_mu l (fwd: minus) in FP16
+__device__ __forceinline__ void half_spinor_pk(int mu, bool fwd, const hv2 (&ps)[12], hv2 (&h)[2][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    const hv2 l0 = ps[6 + a], l1 = ps[9 + a];
+    hv2 o0, o1;
+    switch (mu) {
+      case 0: o0 = hmul_mi(l1); o1 = hmul_mi(l0); break;  // -i s1
+      case 1: o0 = -l1; o1 = l0; break;                   // -i s2
+      case 2: o0 = hmul_mi(l0); o1 = hmul_i(l1); break;   // -i s3
+      default: o0 = l0; o1 = l1; break;                   // 1
+    }
+    h[0][a] = fwd ? ps[a] - o0 : ps[a] + o0;
+    h[1][a] = fwd ? ps[3 + a] - o1 : ps[3 + a] + o1;
+  }
+}
+
+// gg = U h (fwd) or U^H h (bwd) with FP32 sums of FP16 products
+__device__ __forceinline__ void link_mul_pk(bool fwd, const hv2 (&U)[3][3], const hv2 (&h)[2][3],
+                                            cx<float> (&gg)[2][3]) {
+  if (fwd) {
+    hv2 hn[2][3], hs[2][3];
+#pragma unroll
+    for (int s = 0; s < 2; s++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) {
+        hn[s][b] = hv2{h[s][b].x, (_Float16)-h[s][b].y};
+        hs[s][b] = hv2{h[s][b].y, h[s][b].x};
+      }
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+      for (int s = 0; s < 2; s++) {
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+          re = dot2(U[a][b], hn[s][b], re);
+          im = dot2(U[a][b], hs[s][b], im);
+        }
+        gg[s][a] = {re, im};
+      }
+  } else {
+    hv2 hm[2][3];
+#pragma unroll
+    for (int s = 0; s < 2; s++)
+#pragma unroll
+      for (int b = 0; b < 3; b++) hm[s][b] = hv2{h[s][b].y, (_Float16)-h[s][b].x};
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+      for (int s = 0; s < 2; s++) {
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+          re = dot2(U[b][a], h[s][b], re);
+          im = dot2(U[b][a], hm[s][b], im);
+        }
+        gg[s][a] = {re, im};
+      }
+  }
+}
+
+// the nine links U_mu at byte offset vo, in their FP16 storage
+__device__ __forceinline__ void buf_link_pk(Rsrc ru, uint32_t plane_b, int mu, uint32_t vo, hv2 (&U)[3][3]) {
+#pragma unroll
+  for (int k = 0; k < 9; k++)
+    U[k / 3][k % 3] = __builtin_bit_cast(hv2, __builtin_amdgcn_raw_buffer_load_b32(ru, (int)vo,
+                                                                                 (int)((uint32_t)(mu * 9 + k) * plane_b), 0));
+}
+
+// Hermitian 6x6 clover block (FP16 planes: 6 diagonal reals, then the 15
+// entries below the diagonal as (re, im) plane pairs) times x: diagonal in
+// FP32, off-diagonal products by dot2
+__device__ __forceinline__ void buf_clover_pk(Rsrc rc, uint32_t plane_b, uint32_t vo, int chi, const hv2 (&x)[6],
+                                              cx<float> (&y)[6]) {
+  const uint32_t b0 = (uint32_t)(36 * chi) * plane_b;
+  auto ld16 = [&](uint32_t so) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rc, (int)vo, (int)so, 0));
+  };
+  hv2 xn[6], xs[6], xm[6];
+#pragma unroll
+  for (int i = 0; i < 6; i++) {
+    const float d = (float)ld16(b0 + (uint32_t)i * plane_b);
+    y[i] = {d * (float)x[i].x, d * (float)x[i].y};
+    xn[i] = hv2{x[i].x, (_Float16)-x[i].y};
+    xs[i] = hv2{x[i].y, x[i].x};
+    xm[i] = hv2{x[i].y, (_Float16)-x[i].x};
+  }
+  int q = 0;
+#pragma unroll
+  for (int i = 1; i < 6; i++)
+#pragma unroll
+    for (int j = 0; j < i; j++, q++) {
+      const hv2 c = hv2{ld16(b0 + (uint32_t)(6 + 2 * q) * plane_b), ld16(b0 + (uint32_t)(7 + 2 * q) * plane_b)};
+      y[i].re = dot2(c, xn[j], y[i].re);  // c x_j
+      y[i].im = dot2(c, xs[j], y[i].im);
+      y[j].re = dot2(c, x[i], y[j].re);   // conj(c) x_i
+      y[j].im = dot2(c, xm[i], y[j].im);
+    }
+}
+
+// gg of one hop from the twelve stored components of the neighbour spinor
+// and the link at byte offset lvo: FP32 arithmetic on converted values, or
+// (PK, FP16 storage only) the packed FP16 form above
+template <class P, bool PK>
+__device__ __forceinline__ void hop_raw(const typename P::S (&raw)[12], int mu, bool fwd, Rsrc ru, uint32_t upb,
+                                        uint32_t lvo, cx<typename P::R> (&gg)[2][3]) {
+  if constexpr (PK) {
+    hv2 ps[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) ps[k] = hv(raw[k]);
+    hv2 U[3][3], h[2][3];
+    buf_link_pk(ru, upb, mu, lvo, U);
+    half_spinor_pk(mu, fwd, ps, h);
+    link_mul_pk(fwd, U, h, gg);
+  } else {
+    cx<typename P::R> ps[12], Um[3][3];
+#pragma unroll
+    for (int k = 0; k < 12; k++) ps[k] = BufIO<P>::cvt(raw[k]);
+    buf_link<P>(ru, upb, mu, lvo, Um);
+    hop_half<P>(mu, fwd, ps, Um, gg);
+  }
+}
+
 // Launch: blockDim = X * TY * nbr (a multiple of 64, at most MAXT), grid =
 // (nrhs / nbr) * T * (Y / TY) * (Z / zs), dynamic LDS = 2 * 12 * (TY + 2) * X *
 // nbr elements of P::S (at least the DOT reduction's 16 * 64 * 24 bytes);
@@ -752,7 +897,7 @@ __device__ __forceinline__ void buf_clover(Rsrc rc, uint32_t plane_b, uint32_t v
 // the dots are those of (q, r) (q unrounded), which give the next step's
 // length.  in, out
 // and xio are distinct arrays.
-template <class P, bool DOT, bool MR, int TY, int MAXT>
+template <class P, bool DOT, bool MR, int TY, int MAXT, bool PK = false>
 __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict__ out,
                                                        const typename P::S* __restrict__ in,
                                                        const typename P::S* __restrict__ U,
@@ -766,6 +911,7 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
   using S = typename P::S;
   using IO = BufIO<P>;
   static_assert(!MR || DOT, "the smoother step also produces the next dots");
+  static_assert(!PK || std::is_same<P, F16>::value, "packed arithmetic needs FP16 storage");
   extern __shared__ __align__(16) unsigned char march_smem[];
   // two plane buffers [2][12][TY + 2][X * nbr]: step i reads buffer i % 2
   // and stages the next plane into the other, so one barrier per step
@@ -840,11 +986,11 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
   {
     const int zm = z0 == 0 ? g.Z - 1 : z0 - 1;
     const uint32_t sm = (uint32_t)zm * sz + (uint32_t)t * st + rowoff;
-    cx<R> pm[12], Um[3][3], gg[2][3];
+    S pm[12];
+    cx<R> gg[2][3];
 #pragma unroll
-    for (int k = 0; k < 12; k++) pm[k] = IO::cvt(IO::raw(rin, (sm * nrhs + r) * IO::SB, (uint32_t)k * spb));
-    buf_link<P>(ru, upb, 2, sm * IO::SB, Um);
-    hop_half<P>(2, false, pm, Um, gg);
+    for (int k = 0; k < 12; k++) pm[k] = IO::raw(rin, (sm * nrhs + r) * IO::SB, (uint32_t)k * spb);
+    hop_raw<P, PK>(pm, 2, false, ru, upb, sm * IO::SB, gg);
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k] = {0, 0};
     hop_add<P>(2, false, (R)-0.5, gg, acc);
@@ -883,11 +1029,11 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
         lcol = col;
         ls = fwd ? s : s + (uint32_t)(ym - y) * sy;
       }
-      cx<R> ps[12], Um[3][3], gg[2][3];
+      S ps[12];
+      cx<R> gg[2][3];
 #pragma unroll
-      for (int k = 0; k < 12; k++) ps[k] = IO::cvt(cur[lidx(k, lrow, lcol)]);
-      buf_link<P>(ru, upb, mu, ls * IO::SB, Um);
-      hop_half<P>(mu, fwd, ps, Um, gg);
+      for (int k = 0; k < 12; k++) ps[k] = cur[lidx(k, lrow, lcol)];
+      hop_raw<P, PK>(ps, mu, fwd, ru, upb, ls * IO::SB, gg);
       hop_add<P>(mu, fwd, (R)-0.5, gg, acc);
     }
     // t hops from the adjacent slices
@@ -895,11 +1041,11 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
     for (int hop = 0; hop < 2; hop++) {
       const bool fwd = hop == 0;
       const uint32_t sn = (uint32_t)z * sz + (uint32_t)(fwd ? tp : tm) * st + rowoff;
-      cx<R> ps[12], Um[3][3], gg[2][3];
+      S ps[12];
+      cx<R> gg[2][3];
 #pragma unroll
-      for (int k = 0; k < 12; k++) ps[k] = IO::cvt(IO::raw(rin, (sn * nrhs + r) * IO::SB, (uint32_t)k * spb));
-      buf_link<P>(ru, upb, 3, (fwd ? s : sn) * IO::SB, Um);
-      hop_half<P>(3, fwd, ps, Um, gg);
+      for (int k = 0; k < 12; k++) ps[k] = IO::raw(rin, (sn * nrhs + r) * IO::SB, (uint32_t)k * spb);
+      hop_raw<P, PK>(ps, 3, fwd, ru, upb, (fwd ? s : sn) * IO::SB, gg);
       hop_add<P>(3, fwd, fwd ? ftp : ftm, gg, acc);
     }
     // next plane (kept raw for staging); its loads overlap the clover term
@@ -912,10 +1058,18 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
     // site-local term with the centre from LDS
 #pragma unroll 1
     for (int chi = 0; chi < 2; chi++) {
-      cx<R> p6[6], q6[6];
+      cx<R> q6[6];
+      if constexpr (PK) {
+        hv2 x6[6];
 #pragma unroll
-      for (int k = 0; k < 6; k++) p6[k] = IO::cvt(cur[lidx(6 * chi + k, yl + 1, col)]);
-      buf_clover<P>(rc, cpb, s * IO::RB, chi, p6, q6);
+        for (int k = 0; k < 6; k++) x6[k] = hv(cur[lidx(6 * chi + k, yl + 1, col)]);
+        buf_clover_pk(rc, cpb, s * IO::RB, chi, x6, q6);
+      } else {
+        cx<R> p6[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) p6[k] = IO::cvt(cur[lidx(6 * chi + k, yl + 1, col)]);
+        buf_clover<P>(rc, cpb, s * IO::RB, chi, p6, q6);
+      }
 #pragma unroll
       for (int k = 0; k < 6; k++) {
         if (chi == 0) acc[k] = acc[k] + q6[k];
@@ -924,11 +1078,8 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
     }
     // forward z hop from the next plane
     {
-      cx<R> ps[12], Um[3][3], gg[2][3];
-#pragma unroll
-      for (int k = 0; k < 12; k++) ps[k] = IO::cvt(nx[k]);
-      buf_link<P>(ru, upb, 2, s * IO::SB, Um);
-      hop_half<P>(2, true, ps, Um, gg);
+      cx<R> gg[2][3];
+      hop_raw<P, PK>(nx, 2, true, ru, upb, s * IO::SB, gg);
       hop_add<P>(2, true, (R)-0.5, gg, acc);
     }
     // stage the next plane (own rows from the registers, halo rows loaded)
@@ -947,11 +1098,10 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
     {
       cx<R> gg[2][3];
       {
-        cx<R> pv[12], Um[3][3];
+        S pv[12];
 #pragma unroll
-        for (int k = 0; k < 12; k++) pv[k] = IO::cvt(cur[lidx(k, yl + 1, col)]);
-        buf_link<P>(ru, upb, 2, s * IO::SB, Um);
-        hop_half<P>(2, false, pv, Um, gg);
+        for (int k = 0; k < 12; k++) pv[k] = cur[lidx(k, yl + 1, col)];
+        hop_raw<P, PK>(pv, 2, false, ru, upb, s * IO::SB, gg);
       }
       const uint32_t vo = (s * nrhs + r) * IO::SB;
       cx<R> sqr = {0, 0};  // this site's dots in the working precision,
@@ -1162,12 +1312,12 @@ struct MrArgs {
   const double* qq = nullptr;
 };
 
-template <class P, bool DOT, bool MR, int TY>
+template <class P, bool DOT, bool MR, int TY, bool PK = false>
 static void launch_march_p(const FineOp& op, const typename P::S* U, const typename P::RS* C, const void* x,
                            void* y, int nrhs, const MarchShape& m, int64_t nb, int threads, size_t lds,
                            double2* dpart, const MrArgs& mr) {
   using S = typename P::S;
-  auto* k = k_dslash_march<P, DOT, MR, TY, 1024>;
+  auto* k = k_dslash_march<P, DOT, MR, TY, 1024, PK>;
   if (lds > 65536)
     MGM_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(threads), lds, op.ctx->stream, (S*)y, (const S*)x, U, C, op.g,
@@ -1178,27 +1328,31 @@ static void launch_march_p(const FineOp& op, const typename P::S* U, const typen
 // Returns the number of blocks (partial-sum columns of the reducing variant).
 template <bool DOT, bool MR>
 static int64_t launch_march(const FineOp& op, mgm_prec p, const void* x, void* y, int nrhs, double2* dpart,
-                            const MarchShape& m, const MrArgs& mr = MrArgs()) {
+                            const MarchShape& m, const MrArgs& mr = MrArgs(), bool pk = false) {
   const Geom& g = op.g;
   const int threads = g.X * m.ty * m.nbr;
   const int64_t nb = (int64_t)(nrhs / m.nbr) * g.T * (g.Y / m.ty) * (g.Z / m.zs);
   const size_t lds = march_lds(g, p, m, DOT);
-#define MGM_MARCH_TY(PT, UU, CC)                                                                           \
-  switch (m.ty) {                                                                                          \
-    case 2: launch_march_p<PT, DOT, MR, 2>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break;   \
-    case 4: launch_march_p<PT, DOT, MR, 4>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break;   \
-    case 8: launch_march_p<PT, DOT, MR, 8>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break;   \
-    case 16: launch_march_p<PT, DOT, MR, 16>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break; \
-    default: throw Error(MGM_ERR_SHAPE, "unsupported plane-marching tile");                                \
+#define MGM_MARCH_TY(PT, UU, CC, PKV)                                                                           \
+  switch (m.ty) {                                                                                               \
+    case 2: launch_march_p<PT, DOT, MR, 2, PKV>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break;   \
+    case 4: launch_march_p<PT, DOT, MR, 4, PKV>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break;   \
+    case 8: launch_march_p<PT, DOT, MR, 8, PKV>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break;   \
+    case 16: launch_march_p<PT, DOT, MR, 16, PKV>(op, UU, CC, x, y, nrhs, m, nb, threads, lds, dpart, mr); break; \
+    default: throw Error(MGM_ERR_SHAPE, "unsupported plane-marching tile");                                     \
   }
   if constexpr (MR) {
     MGM_CHECK(p == MGM_PREC_F16, MGM_ERR_INVALID_ARG, "the fused smoother step runs in FP16 storage");
-    MGM_MARCH_TY(F16, op.U16, op.C16)
+    if (pk) {
+      MGM_MARCH_TY(F16, op.U16, op.C16, true)
+    } else {
+      MGM_MARCH_TY(F16, op.U16, op.C16, false)
+    }
   } else {
     if (p == MGM_PREC_F32) {
-      MGM_MARCH_TY(F32, op.U32, op.C32)
+      MGM_MARCH_TY(F32, op.U32, op.C32, false)
     } else {
-      MGM_MARCH_TY(F16, op.U16, op.C16)
+      MGM_MARCH_TY(F16, op.U16, op.C16, false)
     }
   }
 #undef MGM_MARCH_TY
@@ -1287,9 +1441,12 @@ int64_t FineOp::apply_step(mgm_prec p, const void* r, void* r_next, void* x, con
   const std::string key = "dslash_step/" + std::to_string((int)p) + "/" + std::to_string(g.V) + "/" + std::to_string(nrhs);
   ProfScope ps(ctx, KC_DSLASH_STEP, step_bytes(p, nrhs));
   int64_t nb = 0;
-  ctx->choose(key, (int)shapes.size(), [&](int v) {
-    MGM_CHECK(v >= 0 && v < (int)shapes.size(), MGM_ERR_INVALID_ARG, "fused smoother launch variant out of range");
-    nb = launch_march<true, true>(*this, p, r, r_next, nrhs, dpart, shapes[v], mr);
+  // variants: every shape with FP32 arithmetic on converted values, then
+  // every shape with packed FP16 arithmetic
+  const int ns = (int)shapes.size();
+  ctx->choose(key, 2 * ns, [&](int v) {
+    MGM_CHECK(v >= 0 && v < 2 * ns, MGM_ERR_INVALID_ARG, "fused smoother launch variant out of range");
+    nb = launch_march<true, true>(*this, p, r, r_next, nrhs, dpart, shapes[v % ns], mr, v >= ns);
   });
   return nb;
 }

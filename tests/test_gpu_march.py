@@ -201,27 +201,39 @@ def test_march_full_size_f16_eight_rhs(ctx):
 @pytest.mark.parametrize("lname", ["8x16x8x4", "16x4x16x6"])
 @pytest.mark.parametrize("nrhs", [16, 4])
 def test_fused_smoother_step(ctx, lats, lname, nrhs):
-    """mgm_operator_smoother_step against its definition, built from the
-    reducing dslash: q = D r (variant 0), r' = r - omega q, x' = x + omega r
-    with omega = qr / qq of the previous step (0 where qq = 0), and the dots of
-    (q, r).  r' and x' within one FP16 ulp plus omega times the FP16 rounding of
-    q (the kernel uses q before rounding); dots within 1e-4 of those of the
-    rounded q (the kernel sums the unrounded q, in another order: the FP16
-    rounding of q, 2^-11 per element, averages to a few 1e-6 over the
-    lattice)."""
+    """mgm_operator_smoother_step in both arithmetic forms (the launch
+    variants are the marching shapes with FP32 arithmetic on converted
+    values, then the same shapes with packed FP16 arithmetic).
+
+    FP32 form against its definition built from the reducing dslash: q = D r,
+    r' = r - omega q, x' = x + omega r with omega = qr / qq of the previous
+    step (0 where qq = 0), and the dots of (q, r); r' and x' within one FP16
+    ulp plus omega times the FP16 rounding of q (the kernel uses q before
+    rounding); dots within 1e-4 of those of the rounded q.
+
+    Packed form: x' as above (the same FP32 update); q differs from the FP32
+    form's by the FP16 rounding of the half spinors (2^-11 of each hop), so r'
+    is checked norm-wise, within 2^-10 |r'| + 2e-3 |omega| |q| of the FP32
+    form's, and the dots within 2e-3.
+
+    Both against the oracle: q = D r from the FP64 operator on the stored FP16
+    r, r' and the dots within the FP16 operator's bound (4e-3 of |q|)."""
     import torch
+    import paper_2509_11424_amd as m
     lat = lats[lname]
     op = lat.op
     assert op.step_fusable(nrhs)
     g = torch.Generator(device="cuda:0").manual_seed(90 + nrhs)
     shape = (12, lat.V, nrhs, 2)
-    r, x = (torch.randn(shape, generator=g, device="cuda:0").to(torch.float16) for _ in range(2))
+    r, x0 = (torch.randn(shape, generator=g, device="cuda:0").to(torch.float16) for _ in range(2))
     qr = torch.complex(torch.randn(nrhs, generator=g, device="cuda:0", dtype=torch.float64),
                        torch.randn(nrhs, generator=g, device="cuda:0", dtype=torch.float64)) * 0.05
     qq = torch.rand(nrhs, generator=g, device="cuda:0", dtype=torch.float64) + 0.5
     qq[0] = 0.0  # omega = 0 for the first rhs
-    x0 = x.clone()
-    rn, yx, yy = op.smoother_step(r, x, qr, qq)
+    key = "dslash_step/%d/%d/%d" % (m.api.PREC["f16"], lat.V, nrhs)
+    nvar = _variants(ctx, key, lambda: op.smoother_step(r, x0.clone(), qr, qq))
+    assert nvar % 2 == 0 and nvar >= 2
+    ns = nvar // 2
     q, yx_ref, yy_ref = op.apply_dot(r, prec="f16")
     torch.cuda.synchronize()
 
@@ -229,28 +241,44 @@ def test_fused_smoother_step(ctx, lats, lname, nrhs):
         return torch.view_as_complex(t.float().contiguous()).to(torch.complex128)
 
     om = torch.where(qq > 0, qr / qq.clamp_min(1e-300), torch.zeros_like(qr))
-    want_r = c(r) - om * c(q)
     want_x = c(x0) + om * c(r)
-    slack = om.abs() * c(q).abs() * 2.0 ** -10
-    assert torch.all((c(rn) - want_r).abs() <= 2.0 ** -10 * want_r.abs() + slack + 2.0 ** -14 + 1e-6)
-    assert torch.all((c(x) - want_x).abs() <= 2.0 ** -10 * want_x.abs() + 2.0 ** -14 + 1e-6)
-    assert torch.equal(rn[:, :, 0], r[:, :, 0]) and torch.equal(x[:, :, 0], x0[:, :, 0])
-    assert torch.all((yx - yx_ref).abs() <= 1e-4 * yy_ref.sqrt() * c(r).abs().pow(2).sum(dim=(0, 1)).sqrt())
-    assert torch.all((yy - yy_ref).abs() <= 1e-4 * yy_ref)
-    # against the oracle: q = D r from the FP64 operator on the stored FP16 r,
-    # r' = r - omega q and the dots of (q, r) within the FP16 operator's bound
-    # (links and clover stored in FP16: 4e-3 of |q| per rhs)
+    nr = c(r).abs().pow(2).sum(dim=(0, 1)).sqrt()
     rr = from_gpu(c(r)).reshape(nrhs, -1)
     qo = lat.D.matvec(rr)
     omn = om.cpu().numpy()
-    rn_np = from_gpu(c(rn)).reshape(nrhs, -1)
-    yxn, yyn = yx.cpu().numpy(), yy.cpu().numpy()
-    for j in range(nrhs):
-        want_rj = rr[j] - omn[j] * qo[j]
-        nq = np.linalg.norm(qo[j])
-        assert np.linalg.norm(rn_np[j] - want_rj) <= 2.0 ** -10 * np.linalg.norm(want_rj) + abs(omn[j]) * 4e-3 * nq, j
-        assert abs(yxn[j] - np.vdot(qo[j], rr[j])) <= 4e-3 * nq * np.linalg.norm(rr[j]), j
-        assert abs(yyn[j] - nq ** 2) <= 8e-3 * nq ** 2, j
+    out = {}
+    for v, packed in ((0, False), (ns, True)):
+        ctx.tune_set(key, v)
+        x = x0.clone()
+        rn, yx, yy = op.smoother_step(r, x, qr, qq)
+        torch.cuda.synchronize()
+        out[packed] = (rn, yx, yy)
+        assert torch.all((c(x) - want_x).abs() <= 2.0 ** -10 * want_x.abs() + 2.0 ** -14 + 1e-6), packed
+        assert torch.equal(rn[:, :, 0], r[:, :, 0]) and torch.equal(x[:, :, 0], x0[:, :, 0])
+        if not packed:
+            want_r = c(r) - om * c(q)
+            slack = om.abs() * c(q).abs() * 2.0 ** -10
+            assert torch.all((c(rn) - want_r).abs() <= 2.0 ** -10 * want_r.abs() + slack + 2.0 ** -14 + 1e-6)
+            assert torch.all((yx - yx_ref).abs() <= 1e-4 * yy_ref.sqrt() * nr)
+            assert torch.all((yy - yy_ref).abs() <= 1e-4 * yy_ref)
+        else:
+            rn32, yx32, yy32 = out[False]
+            d = (c(rn) - c(rn32)).abs().pow(2).sum(dim=(0, 1)).sqrt()
+            nq = c(q).abs().pow(2).sum(dim=(0, 1)).sqrt()
+            nrn = c(rn32).abs().pow(2).sum(dim=(0, 1)).sqrt()
+            assert torch.all(d <= 2.0 ** -10 * nrn + 2e-3 * om.abs() * nq + 1e-6)
+            assert torch.all((yx - yx32).abs() <= 2e-3 * yy32.sqrt() * nr)
+            assert torch.all((yy - yy32).abs() <= 4e-3 * yy32)
+        rn_np = from_gpu(c(rn)).reshape(nrhs, -1)
+        yxn, yyn = yx.cpu().numpy(), yy.cpu().numpy()
+        for j in range(nrhs):
+            want_rj = rr[j] - omn[j] * qo[j]
+            nqj = np.linalg.norm(qo[j])
+            assert np.linalg.norm(rn_np[j] - want_rj) <= 2.0 ** -10 * np.linalg.norm(want_rj) + \
+                abs(omn[j]) * 4e-3 * nqj, (packed, j)
+            assert abs(yxn[j] - np.vdot(qo[j], rr[j])) <= 4e-3 * nqj * np.linalg.norm(rr[j]), (packed, j)
+            assert abs(yyn[j] - nqj ** 2) <= 8e-3 * nqj ** 2, (packed, j)
+    ctx.tune_set(key, 0)
 
 
 def test_fused_smoother_step_refuses_lattice_without_tile(ctx):
