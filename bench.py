@@ -422,7 +422,9 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
         "setup_s": t_setup, "gauge_gen_s": t_gauge, "rhs_per_step": nrhs_step,
         "solver_iterations_per_step": results[-1]["stats"]["iterations"],
         "estimate": {"tr_Dinv": [results[-1]["total_mean"][0, 0].real, results[-1]["total_mean"][0, 0].imag],
-                     "var_of_mean": float(results[-1]["total_var"][0, 0])},
+                     "var_of_mean": float(results[-1]["total_var"][0, 0]),
+                     "term_var": [float(v) for v in results[-1]["var"][:, 0, 0]],
+                     "term_cost_s": [float(c) for c in results[-1]["cost_s"]]},
         "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
                         "GBps": (v["bytes"] / v["ms"] / 1e6) if v["ms"] > 0 else 0.0} for k, v in prof.items()},
         "kernels_note": "HIP-event statistics of eagerly launched kernels; launches replayed from the captured "
@@ -488,6 +490,129 @@ def micro_coarse(args, cfg, m, ctx, op, g, torch):
                               "launches": q["launches"], "avg_ms": ms, "bytes_per_launch": bl,
                               "GBps": bl / ms / 1e6, "TFLOPs": flop / ms / 1e9}), flush=True)
             del x
+
+
+def observables(args):
+    """The configuration's observables with the timed form's solver (mixed,
+    FP16 smoother, BF16 coarse stencils, graphs): the connected
+    pseudoscalar correlator C(t) for every t with the orthogonal, oblique and
+    plain decompositions (Sec. 1.1, eq. connected-G; Sec. 4.1), and the
+    disconnected loops tr(Gamma D^-1) per time slice for the six Gamma with
+    the orthogonal and plain decompositions (Sec. 4.3).  One JSON line per
+    (observable, decomposition): per-t means and variances of the mean, the
+    per-term variance summed over t, solver seconds per term and wall time.
+    Plain runs as many fine-level probes as the finest difference level."""
+    import numpy as np
+    cfg = dict(CONFIGS[args.config])
+    if args.batch:
+        cfg["batch"] = list(args.batch)
+    from lattice_inputs import gauge_field
+    U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])
+    import torch
+    import paper_2509_11424_amd as m
+    stream = torch.cuda.Stream(device=0)
+    with torch.cuda.stream(stream):
+        ctx = m.Context(0)
+        op = m.Operator(ctx, U, cfg["m0"], cfg["csw"])
+        L = len(cfg["blocks"]) + 1
+        # the fine batch is halved against the trace bench: the fine-level
+        # term vectors of correlators and loops take (4L - 3) fine vectors per rhs
+        batch = [max(1, cfg["batch"][0] // 2)] + list(cfg["batch"][1:])
+        h = m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=batch[0],
+                        max_nrhs_level=batch, restart=cfg["restart"], mixed=1, with_corr=True)
+        sd = m.solve_desc(tol=1e-10, kind="mg_mixed", smooth=args.smooth, smooth_coarse=args.smooth_coarse,
+                          coarse_iters=args.coarse_iters, inner_tol=args.inner_tol, maxiter=5000,
+                          coarse_bf16=True, smoother_f16=True, graphs=True)
+        ctx.autotune(True)
+        T = cfg["dims"][3]
+        for obs, decs in (("corr", ("orthogonal", "oblique", "plain")), ("loops", ("orthogonal", "plain"))):
+            for dec in decs:
+                npr = list(cfg["nprobe"]) if dec != "plain" else [cfg["nprobe"][0]] + [0] * (L - 1)
+                torch.cuda.synchronize()
+                t0 = time.time()
+                # the sources of every probe group of correlators and loops
+                # live on the fine lattice: batches of the fine level's size
+                r = h.estimate(obs, dec, npr, seed=cfg["pseed"] + 21, batch=batch[0], solve=sd, samples=False)
+                torch.cuda.synchronize()
+                dt = time.time() - t0
+                mean, var = r["total_mean"], r["total_var"]
+                line = {"observable": obs, "decomposition": dec, "workload": cfg["name"], "T": T,
+                        "nprobe": npr, "batch": batch, "seconds": dt,
+                        "max_rel_residual": r["stats"]["max_rel_residual"],
+                        "term_var_sum_t": [[float(v) for v in r["var"][q].sum(axis=1)] for q in range(len(r["n"]))],
+                        "term_cost_s": [float(c) for c in r["cost_s"]], "term_n": [int(n) for n in r["n"]]}
+                if obs == "corr":
+                    line["C_t"] = [float(v) for v in mean[0].real]
+                    line["var_of_mean_t"] = [float(v) for v in var[0]]
+                else:
+                    line["gammas"] = ["1", "gamma5", "gamma1", "gamma2", "gamma3", "gamma4"]
+                    line["loop_t_re"] = [[float(v) for v in mean[g].real] for g in range(mean.shape[0])]
+                    line["loop_t_im"] = [[float(v) for v in mean[g].imag] for g in range(mean.shape[0])]
+                    line["var_of_mean_t"] = [[float(v) for v in var[g]] for g in range(var.shape[0])]
+                print(json.dumps(line), flush=True)
+        del h
+        torch.cuda.empty_cache()
+
+
+def hierarchy_study(args):
+    """Variance per term against setup cost for richer hierarchies (Sec. 5:
+    more test vectors, test vectors with small eigen-residuals).  For each
+    variant -- the configuration's N_tv, N_tv 64 on the first transfer, and
+    the configuration's N_tv with the fine test vectors refined to
+    eigen-residual 1e-4 -- one JSON line: setup and refinement seconds, the
+    orthogonal estimate's per-term variance and solver cost at the
+    configured probe counts with the timed form's solver, and the
+    figure of merit (sum_q sqrt(var_q cost_q))^2, the MLMC cost of any fixed
+    target variance up to a common factor (Sec. 2.2, eq. MLMC-Nl)."""
+    import numpy as np
+    cfg = dict(CONFIGS[args.config])
+    from lattice_inputs import gauge_field
+    U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])
+    import torch
+    import paper_2509_11424_amd as m
+    stream = torch.cuda.Stream(device=0)
+    with torch.cuda.stream(stream):
+        ctx = m.Context(0)
+        op = m.Operator(ctx, U, cfg["m0"], cfg["csw"])
+        # half the fine batch of the trace bench: room for 64 test vectors
+        # and for the refinement's block vectors
+        batch = [max(1, cfg["batch"][0] // 2)] + list(cfg["batch"][1:])
+        sd = m.solve_desc(tol=1e-10, kind="mg_mixed", smooth=args.smooth, smooth_coarse=args.smooth_coarse,
+                          coarse_iters=args.coarse_iters, inner_tol=args.inner_tol, maxiter=5000,
+                          coarse_bf16=True, smoother_f16=True, graphs=True)
+        ctx.autotune(True)
+        variants = [("default", list(cfg["ntv"]), False), ("ntv64", [64] + list(cfg["ntv"][1:]), False),
+                    ("refined", list(cfg["ntv"]), True)]
+        for name, ntv, refine in variants:
+            torch.cuda.synchronize()
+            t0 = time.time()
+            h = m.Hierarchy(op, cfg["blocks"], ntv, seed=cfg["pseed"] + 1000, max_nrhs=batch[0],
+                            max_nrhs_level=batch, restart=cfg["restart"], mixed=1)
+            torch.cuda.synchronize()
+            line = {"study": "hierarchy", "variant": name, "workload": cfg["name"], "ntv": ntv,
+                    "setup_s": time.time() - t0, "hierarchy_workspace_gb": h.ws.numel() / 1e9}
+            if refine:
+                rsd = m.solve_desc(tol=1e-6, kind="mg_mixed", smooth=args.smooth, smooth_coarse=args.smooth_coarse,
+                                   coarse_iters=args.coarse_iters, inner_tol=args.inner_tol, maxiter=5000,
+                                   coarse_bf16=True, smoother_f16=True, graphs=True)
+                st = h.refine(max_iters=12, eig_tol=1e-4, power_tol=1e-6, batch=batch[0], solve=rsd)
+                line["refine"] = {k: st[k] for k in ("steps", "converged", "max_rho_start", "max_rho", "seconds")}
+            r = h.estimate("trace", "orthogonal", cfg["nprobe"], seed=cfg["pseed"] + 7, batch=batch, solve=sd,
+                           samples=False)
+            torch.cuda.synchronize()
+            t1 = time.time()
+            r = h.estimate("trace", "orthogonal", cfg["nprobe"], seed=cfg["pseed"] + 7, batch=batch, solve=sd,
+                           samples=False)
+            torch.cuda.synchronize()
+            var, cost = r["var"][:, 0, 0], r["cost_s"]
+            line.update({"estimate_s": time.time() - t1, "term_var": [float(v) for v in var],
+                         "term_cost_s": [float(c) for c in cost], "term_n": [int(n) for n in r["n"]],
+                         "total_var_of_mean": float(r["total_var"][0, 0]),
+                         "mlmc_merit": float(np.sum(np.sqrt(np.maximum(var, 0) * cost)) ** 2),
+                         "iterations": r["stats"]["iterations"]})
+            print(json.dumps(line), flush=True)
+            del h, r
+            torch.cuda.empty_cache()
 
 
 def per_level_rates(m, ctx, h, cfg, sd, batch, torch):
@@ -781,6 +906,10 @@ def main():
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--ttt", type=int, default=1, help="time to target variance, FP64 against the mixed form")
     ap.add_argument("--learned", action="store_true", help="also measure the learned-preconditioner form")
+    ap.add_argument("--hierarchy-study", action="store_true",
+                    help="per-term variance against setup cost for N_tv 64 and refined test vectors")
+    ap.add_argument("--observables", action="store_true",
+                    help="estimate C(t) three ways and the loops two ways with the timed form, one line each")
     ap.add_argument("--micro", choices=["dslash", "dslash_dot", "step", "copy", "coarse"])
     ap.add_argument("--level", type=int, default=1, help="micro coarse: hierarchy level of the stencil")
     ap.add_argument("--tune", action="store_true", help="micro: autotune the launch shape first")
@@ -796,6 +925,10 @@ def main():
         sys.exit(2)
     if args.micro:
         micro(args)
+    elif args.observables:
+        observables(args)
+    elif args.hierarchy_study:
+        hierarchy_study(args)
     else:
         run(args)
 

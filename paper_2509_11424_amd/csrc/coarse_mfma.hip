@@ -140,8 +140,8 @@ struct M32 {
   __device__ static int row(int q, int j) { return 4 * q + j; }
 };
 
-template <class M, int MT>
-__global__ __launch_bounds__(256) void k_coarse_mfma4(const typename M::C2* __restrict__ x,
+template <class M, int MT, int MAXT = 256>
+__global__ __launch_bounds__(MAXT) void k_coarse_mfma4(const typename M::C2* __restrict__ x,
                                                      typename M::C2* __restrict__ y,
                                                      const typename M::C2* __restrict__ Ap, LGeom g, int d, int KC,
                                                      int nrhs, int ntr, int wpb) {
@@ -197,8 +197,8 @@ __global__ __launch_bounds__(256) void k_coarse_mfma4(const typename M::C2* __re
   }
 }
 
-template <int MT, int NT>
-__global__ __launch_bounds__(256) void k_coarse_mfma_bf16(const float2* __restrict__ x, float2* __restrict__ y,
+template <int MT, int NT, int MAXT = 256>
+__global__ __launch_bounds__(MAXT) void k_coarse_mfma_bf16(const float2* __restrict__ x, float2* __restrict__ y,
                                                          const uint16_t* __restrict__ Ap, LGeom g, int d,
                                                          int nrhs, int ntr, int wpb) {
   // K chunks of 16 = ceil(d / 16) = MT: the chunk loop unrolls completely so
@@ -281,11 +281,16 @@ __global__ __launch_bounds__(256) void k_coarse_mfma_bf16(const float2* __restri
     case 2: { constexpr int MTc = 2; __VA_ARGS__; } break; \
     case 3: { constexpr int MTc = 3; __VA_ARGS__; } break; \
     case 4: { constexpr int MTc = 4; __VA_ARGS__; } break; \
-    default: throw Error(MGM_ERR_SHAPE, "coarse dof must be <= 64"); \
+    case 5: { constexpr int MTc = 5; __VA_ARGS__; } break; \
+    case 6: { constexpr int MTc = 6; __VA_ARGS__; } break; \
+    case 7: { constexpr int MTc = 7; __VA_ARGS__; } break; \
+    case 8: { constexpr int MTc = 8; __VA_ARGS__; } break; \
+    default: throw Error(MGM_ERR_SHAPE, "coarse dof must be <= 128"); \
   }
 
-// Waves (16-rhs tiles) per workgroup: 4 by default (the autotuner also tries
-// 2 and 1); v indexes the distinct candidates for ntr tiles.
+// Waves (16-rhs tiles) per workgroup of at most 256 threads: 4 by default
+// (the autotuner also tries 2 and 1); v indexes the distinct candidates for
+// ntr tiles.
 static int wpb_of(int ntr, int v) {
   int cand[3] = {std::min(ntr, 4), std::min(ntr, 2), 1}, n = 0, out[3];
   for (int c : cand) {
@@ -296,17 +301,29 @@ static int wpb_of(int ntr, int v) {
   return out[v < n ? v : 0];
 }
 static int wpb_count(int ntr) { return ntr >= 4 ? 3 : ntr >= 2 ? 2 : 1; }
+// FP64 / FP32 shapes: the wpb_of candidates, then (5 to 8 tiles) every tile
+// of a site in one workgroup of up to 512 threads, so that the site's A
+// fragments are read from HBM once and shared through the CU's cache
+static int shapes4_count(int ntr) { return wpb_count(ntr) + (ntr > 4 && ntr <= 8 ? 1 : 0); }
+static int wpb4_of(int ntr, int v) { return v < wpb_count(ntr) ? wpb_of(ntr, v) : ntr; }
 
 void coarse_apply_mfma64(const CoarseOp& A, const double2* x, double2* y, int nrhs) {
   MGeo m = mgeo(A.d);
   const int ntr = (nrhs + 15) / 16;
   ProfScope ps(A.ctx, KC_COARSE_F64, A.bytes(MGM_PREC_F64, nrhs));
   A.ctx->choose("coarse64/" + std::to_string(A.g.V) + "/" + std::to_string(A.d) + "/" + std::to_string(nrhs),
-                wpb_count(ntr), [&](int v) {
-                  const int wpb = wpb_of(ntr, v);
+                shapes4_count(ntr), [&](int v) {
+                  MGM_CHECK(v >= 0 && v < shapes4_count(ntr), MGM_ERR_INVALID_ARG,
+                            "coarse launch variant out of range");
+                  const int wpb = wpb4_of(ntr, v);
                   const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + wpb - 1) / wpb)), tb(64 * wpb);
-                  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M64, MTc>), nb, tb, 0, A.ctx->stream, x,
-                                                       y, A.Ap64, A.g, A.d, m.KC64, nrhs, ntr, wpb));
+                  if (wpb > 4) {
+                    MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M64, MTc, 512>), nb, tb, 0, A.ctx->stream,
+                                                         x, y, A.Ap64, A.g, A.d, m.KC64, nrhs, ntr, wpb));
+                  } else {
+                    MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M64, MTc>), nb, tb, 0, A.ctx->stream, x,
+                                                         y, A.Ap64, A.g, A.d, m.KC64, nrhs, ntr, wpb));
+                  }
                   MGM_LAUNCH_CHECK();
                 });
 }
@@ -316,11 +333,18 @@ void coarse_apply_mfma32(const CoarseOp& A, const float2* x, float2* y, int nrhs
   const int ntr = (nrhs + 15) / 16;
   ProfScope ps(A.ctx, KC_COARSE_F32, A.bytes(MGM_PREC_F32, nrhs));
   A.ctx->choose("coarse32/" + std::to_string(A.g.V) + "/" + std::to_string(A.d) + "/" + std::to_string(nrhs),
-                wpb_count(ntr), [&](int v) {
-                  const int wpb = wpb_of(ntr, v);
+                shapes4_count(ntr), [&](int v) {
+                  MGM_CHECK(v >= 0 && v < shapes4_count(ntr), MGM_ERR_INVALID_ARG,
+                            "coarse launch variant out of range");
+                  const int wpb = wpb4_of(ntr, v);
                   const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + wpb - 1) / wpb)), tb(64 * wpb);
-                  MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M32, MTc>), nb, tb, 0, A.ctx->stream, x,
-                                                       y, A.A32, A.g, A.d, m.KC64, nrhs, ntr, wpb));
+                  if (wpb > 4) {
+                    MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M32, MTc, 512>), nb, tb, 0, A.ctx->stream,
+                                                         x, y, A.A32, A.g, A.d, m.KC64, nrhs, ntr, wpb));
+                  } else {
+                    MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M32, MTc>), nb, tb, 0, A.ctx->stream, x,
+                                                         y, A.A32, A.g, A.d, m.KC64, nrhs, ntr, wpb));
+                  }
                   MGM_LAUNCH_CHECK();
                 });
 }
@@ -345,7 +369,10 @@ void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs) 
   const int ntr = (nrhs + 15) / 16;
   ProfScope ps(A.ctx, KC_COARSE_BF16, A.bytes(MGM_PREC_BF16, nrhs));
   // shapes: one tile per wave with 4 / 2 / 1 waves per workgroup, then two
-  // and four tiles per wave (fewer A fragment loads per rhs)
+  // and four tiles per wave (fewer A fragment loads per rhs); with more than
+  // four tiles, also every tile of a site in one workgroup of up to 8 waves
+  // (one or two tiles per wave), so that the site's A fragments are read
+  // from HBM once and shared through the CU's cache
   struct Shape {
     int wpb, nt;
   };
@@ -355,6 +382,9 @@ void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs) 
   if (ntr >= 4) shapes.push_back({2, 2});
   if (ntr >= 4 && m.MT <= 3) shapes.push_back({1, 4});
   if (ntr >= 8 && m.MT <= 3) shapes.push_back({2, 4});
+  const size_t n_small = shapes.size();
+  if (ntr > 4 && ntr <= 8) shapes.push_back({ntr, 1});
+  if (ntr > 4 && ntr <= 16 && m.MT <= 4) shapes.push_back({(ntr + 1) / 2, 2});
   A.ctx->choose("coarsebf16/" + std::to_string(A.g.V) + "/" + std::to_string(A.d) + "/" + std::to_string(nrhs),
                 (int)shapes.size(), [&](int v) {
                   MGM_CHECK(v >= 0 && v < (int)shapes.size(), MGM_ERR_INVALID_ARG,
@@ -362,7 +392,25 @@ void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs) 
                   const int wpb = shapes[v].wpb, tpw = shapes[v].nt;
                   const int groups = (ntr + tpw - 1) / tpw;
                   const dim3 nb((unsigned)A.g.V, (unsigned)((groups + wpb - 1) / wpb)), tb(64 * wpb);
-                  if (tpw == 1) {
+                  if ((size_t)v >= n_small) {
+                    // workgroups of up to 512 threads
+                    if (tpw == 1) {
+                      MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma_bf16<MTc, 1, 512>), nb, tb, 0,
+                                                           A.ctx->stream, x, y, (const uint16_t*)A.Abf, A.g, A.d,
+                                                           nrhs, ntr, wpb));
+                    } else {
+                      switch (m.MT) {
+                        case 1: hipLaunchKernelGGL((k_coarse_mfma_bf16<1, 2, 512>), nb, tb, 0, A.ctx->stream, x, y,
+                                                   (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb); break;
+                        case 2: hipLaunchKernelGGL((k_coarse_mfma_bf16<2, 2, 512>), nb, tb, 0, A.ctx->stream, x, y,
+                                                   (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb); break;
+                        case 3: hipLaunchKernelGGL((k_coarse_mfma_bf16<3, 2, 512>), nb, tb, 0, A.ctx->stream, x, y,
+                                                   (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb); break;
+                        default: hipLaunchKernelGGL((k_coarse_mfma_bf16<4, 2, 512>), nb, tb, 0, A.ctx->stream, x,
+                                                    y, (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb); break;
+                      }
+                    }
+                  } else if (tpw == 1) {
                     MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma_bf16<MTc, 1>), nb, tb, 0, A.ctx->stream, x,
                                                          y, (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb));
                   } else if (tpw == 2) {

@@ -140,6 +140,12 @@ inline int prolong_chunk_rows(const TGeom& t, int rt, int cbytes, int TI) {
 inline size_t prolong_lds(const TGeom& t, int rt, int rc, int cbytes) {
   return sites_bytes(t.bvol) + ((size_t)t.ntv * round4(rt) + (size_t)rc * t.ntv) * cbytes;
 }
+// rhs per prolongation workgroup: kTransferRT, halved when the coarse values
+// of a full tile would take more than half of the 64 KiB LDS (FP64 with more
+// than 32 test vectors)
+inline int prolong_rt(const TGeom& t, int cbytes) {
+  return (size_t)t.ntv * kTransferRT * cbytes > 32768 ? kTransferRT / 2 : kTransferRT;
+}
 
 // fine sites of aggregate a, in local (lexicographic) order, into LDS
 __device__ __forceinline__ void aggregate_sites(const TGeom& t, int64_t a, int64_t* sites) {
@@ -315,14 +321,14 @@ __global__ __launch_bounds__(256) void k_restrict(const typename PX::S* __restri
 template <class P, class PM, int TI, class PX = P>
 __global__ __launch_bounds__(256) void k_prolong(const typename P::S* __restrict__ xc, const typename P::S* __restrict__ x,
                                                  typename P::S* __restrict__ y, const typename PM::S* __restrict__ Pm,
-                                                 TGeom t, int nrhs, int mode, int rc,
+                                                 TGeom t, int nrhs, int mode, int rc, int rtile,
                                                  const typename PX::S* __restrict__ xq, const double* __restrict__ xs) {
   using R = typename P::R;
   extern __shared__ __align__(16) char smem[];
   const int64_t a = blockIdx.x >> 1;
   const int chi = blockIdx.x & 1;
-  const int r0 = blockIdx.y * kTransferRT;
-  const int rt = nrhs - r0 < kTransferRT ? nrhs - r0 : kTransferRT;
+  const int r0 = blockIdx.y * rtile;
+  const int rt = nrhs - r0 < rtile ? nrhs - r0 : rtile;
   const int K = t.ntv, half = t.half, rows = t.rows;
   const int rtp = round4(rt), ntr = rtp >> 2;
   const int Q = rc / TI, NT = Q * ntr;
@@ -415,8 +421,8 @@ void Transfer::restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const {
   ProfScope ps(ctx, KC_TRANSFER, bytes(p, nrhs));
   const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(kTransferTB);
   const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
-  MGM_CHECK(t.ntv <= 32 && t.bvol <= 1024, MGM_ERR_SHAPE,
-            "transfers support at most 32 test vectors and 1024 sites per aggregate");
+  MGM_CHECK(t.ntv <= 64 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 64 test vectors and 1024 sites per aggregate");
   if (p == MGM_PREC_F64) {
     const int rc = restrict_chunk_rows(t, rt, 16);
     hipLaunchKernelGGL((k_restrict<F64, F64>), nb, tb, restrict_lds(t, rt, rc, 16), ctx->stream,
@@ -433,18 +439,22 @@ void Transfer::restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const {
 
 void Transfer::prolong(mgm_prec p, const void* xc, const void* x, void* y, int nrhs, int mode) const {
   ProfScope ps(ctx, KC_TRANSFER, bytes(p, nrhs));
-  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(kTransferTB);
-  const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
-  MGM_CHECK(t.ntv <= 32 && t.bvol <= 1024, MGM_ERR_SHAPE,
-            "transfers support at most 32 test vectors and 1024 sites per aggregate");
+  MGM_CHECK(t.ntv <= 64 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 64 test vectors and 1024 sites per aggregate");
   if (p == MGM_PREC_F64) {
+    const int tile = prolong_rt(t, 16), rt = nrhs < tile ? nrhs : tile;
+    const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + tile - 1) / tile)), tb(kTransferTB);
     const int rc = prolong_chunk_rows(t, rt, 16, 1);
     hipLaunchKernelGGL((k_prolong<F64, F64, 1>), nb, tb, prolong_lds(t, rt, rc, 16), ctx->stream,
-                       (const double2*)xc, (const double2*)x, (double2*)y, P64, t, nrhs, mode, rc, nullptr, nullptr);
+                       (const double2*)xc, (const double2*)x, (double2*)y, P64, t, nrhs, mode, rc, tile, nullptr,
+                       nullptr);
   } else if (p == MGM_PREC_F32) {
+    const int tile = prolong_rt(t, 8), rt = nrhs < tile ? nrhs : tile;
+    const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + tile - 1) / tile)), tb(kTransferTB);
     const int rc = prolong_chunk_rows(t, rt, 8, 2);
     hipLaunchKernelGGL((k_prolong<F32, F16, 2>), nb, tb, prolong_lds(t, rt, rc, 8), ctx->stream,
-                       (const float2*)xc, (const float2*)x, (float2*)y, P16, t, nrhs, mode, rc, nullptr, nullptr);
+                       (const float2*)xc, (const float2*)x, (float2*)y, P16, t, nrhs, mode, rc, tile, nullptr,
+                       nullptr);
   } else {
     throw Error(MGM_ERR_INVALID_ARG, "prolong: precision must be F64 or F32");
   }
@@ -455,8 +465,8 @@ void Transfer::restrict16(const __half2* x16, const double* xs, float2* yc, int 
   ProfScope ps(ctx, KC_TRANSFER, bytes(MGM_PREC_F32, nrhs));
   const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(kTransferTB);
   const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
-  MGM_CHECK(t.ntv <= 32 && t.bvol <= 1024, MGM_ERR_SHAPE,
-            "transfers support at most 32 test vectors and 1024 sites per aggregate");
+  MGM_CHECK(t.ntv <= 64 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 64 test vectors and 1024 sites per aggregate");
   MGM_CHECK(P16 != nullptr && xs != nullptr, MGM_ERR_INVALID_ARG, "FP16 transfer input needs P16 and scales");
   const int rc = restrict_chunk_rows(t, rt, 8);
   hipLaunchKernelGGL((k_restrict<F32, F16, F16>), nb, tb, restrict_lds(t, rt, rc, 8), ctx->stream, x16, yc, P16, t,
@@ -466,14 +476,14 @@ void Transfer::restrict16(const __half2* x16, const double* xs, float2* yc, int 
 
 void Transfer::prolong16(const float2* xc, const __half2* x16, const double* xs, float2* y, int nrhs) const {
   ProfScope ps(ctx, KC_TRANSFER, bytes(MGM_PREC_F32, nrhs));
-  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(kTransferTB);
-  const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
-  MGM_CHECK(t.ntv <= 32 && t.bvol <= 1024, MGM_ERR_SHAPE,
-            "transfers support at most 32 test vectors and 1024 sites per aggregate");
+  const int tile = prolong_rt(t, 8), rt = nrhs < tile ? nrhs : tile;
+  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + tile - 1) / tile)), tb(kTransferTB);
+  MGM_CHECK(t.ntv <= 64 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 64 test vectors and 1024 sites per aggregate");
   MGM_CHECK(P16 != nullptr && xs != nullptr, MGM_ERR_INVALID_ARG, "FP16 transfer input needs P16 and scales");
   const int rc = prolong_chunk_rows(t, rt, 8, 2);
   hipLaunchKernelGGL((k_prolong<F32, F16, 2, F16>), nb, tb, prolong_lds(t, rt, rc, 8), ctx->stream, xc,
-                     (const float2*)nullptr, y, P16, t, nrhs, 3, rc, x16, xs);
+                     (const float2*)nullptr, y, P16, t, nrhs, 3, rc, tile, x16, xs);
   MGM_LAUNCH_CHECK();
 }
 
@@ -620,13 +630,22 @@ __device__ __forceinline__ int64_t hop_neighbour(const LGeom& g, const int c[4],
   return index_of(g, cc);
 }
 
-constexpr int kGalPairs = 16;  // (i, j) pairs per thread: d*d <= 256*16
+constexpr int kGalPairs = 16;  // (i, j) pairs per thread: d * jc <= 256 * kGalPairs
 
-__global__ void k_galerkin_fine(FineOp op, TGeom t, const double2* __restrict__ Pm, double2* __restrict__ Ac) {
-  extern __shared__ double2 T[];  // [12][d]
+// Both Galerkin kernels run one workgroup per (coarse site, stencil
+// direction, chunk of jc coarse columns j).  For every fine site x of the
+// aggregate, the sum over the hops k of x that land in that direction of
+// B[x, k] P(y_k) (the chunk's columns) is staged in LDS, and each thread
+// accumulates up to kGalPairs entries (i, j) of P(x)^H times that sum.
+__global__ void k_galerkin_fine(FineOp op, TGeom t, const double2* __restrict__ Pm, double2* __restrict__ Ac,
+                                int jc) {
+  extern __shared__ double2 T[];  // [12][jc] hop sums, then [2][6][ntv] rows of P(x)
   const int64_t a = blockIdx.x;
   const int tgt = blockIdx.y;
+  const int j0 = blockIdx.z * jc;
   const int d = 2 * t.ntv, ntv = t.ntv, tid = threadIdx.x;
+  const int nj = d - j0 < jc ? d - j0 : jc;
+  double2* PX = T + 12 * jc;
   cx<double> acc[kGalPairs];
   for (int q = 0; q < kGalPairs; q++) acc[q] = {0, 0};
   int ca[4];
@@ -637,13 +656,18 @@ __global__ void k_galerkin_fine(FineOp op, TGeom t, const double2* __restrict__ 
     l[1] = rem % t.b[1]; rem /= t.b[1];
     l[2] = rem % t.b[2]; rem /= t.b[2];
     l[3] = rem;
+    bool any = false;
+    for (int k = 0; k < 9; k++) any |= hop_target(k, l, t.b) == tgt;
+    if (!any) continue;  // uniform over the workgroup
     for (int m = 0; m < 4; m++) fc[m] = ca[m] * t.b[m] + l[m];
     const int64_t s = index_of(t.f, fc);
-    for (int k = 0; k < 9; k++) {
-      if (hop_target(k, l, t.b) != tgt) continue;
-      const int64_t y = hop_neighbour(t.f, fc, k);
-      if (tid < d) {
-        const int j = tid, chij = j / ntv, kk = j % ntv;
+    if (tid < nj) {
+      const int j = j0 + tid, chij = j / ntv, kk = j % ntv;
+      cx<double> sum[12];
+      for (int m = 0; m < 12; m++) sum[m] = {0, 0};
+      for (int k = 0; k < 9; k++) {
+        if (hop_target(k, l, t.b) != tgt) continue;
+        const int64_t y = hop_neighbour(t.f, fc, k);
         int64_t ay;
         int locy;
         agg_of(t, y, ay, locy);
@@ -655,38 +679,46 @@ __global__ void k_galerkin_fine(FineOp op, TGeom t, const double2* __restrict__ 
         }
         cx<double> o[12];
         wilson_block(op, k, s, y, fc, p, o);
-        for (int m = 0; m < 12; m++) T[m * d + j] = make_double2(o[m].re, o[m].im);
+        for (int m = 0; m < 12; m++) sum[m] = sum[m] + o[m];
       }
-      __syncthreads();
-      for (int q = 0; q < kGalPairs; q++) {
-        int pidx = tid + q * blockDim.x;
-        if (pidx >= d * d) break;
-        int i = pidx / d, j = pidx % d;
-        int chii = i / ntv, ki = i % ntv;
-        const double2* pr = Pm + ((a * 2 + chii) * t.rows + loc * 6) * (int64_t)ntv + ki;
-        for (int m = 0; m < 6; m++) {
-          double2 pv = pr[(int64_t)m * ntv];
-          double2 tv = T[(6 * chii + m) * d + j];
-          fmac_(acc[q], cx<double>{pv.x, pv.y}, cx<double>{tv.x, tv.y});
-        }
-      }
-      __syncthreads();
+      for (int m = 0; m < 12; m++) T[m * jc + tid] = make_double2(sum[m].re, sum[m].im);
     }
+    for (int e = tid; e < 12 * ntv; e += blockDim.x) {
+      const int chi = e / (6 * ntv), r = e - chi * 6 * ntv;  // r = m ntv + k
+      PX[e] = Pm[((a * 2 + chi) * t.rows + loc * 6) * (int64_t)ntv + r];
+    }
+    __syncthreads();
+    for (int q = 0; q < kGalPairs; q++) {
+      int pidx = tid + q * blockDim.x;
+      if (pidx >= d * nj) break;
+      int i = pidx / nj, jj = pidx % nj;
+      int chii = i / ntv, ki = i % ntv;
+      const double2* pr = PX + chii * 6 * ntv + ki;
+      for (int m = 0; m < 6; m++) {
+        double2 pv = pr[m * ntv];
+        double2 tv = T[(6 * chii + m) * jc + jj];
+        fmac_(acc[q], cx<double>{pv.x, pv.y}, cx<double>{tv.x, tv.y});
+      }
+    }
+    __syncthreads();
   }
   const int64_t Vc = t.c.V;
   for (int q = 0; q < kGalPairs; q++) {
     int pidx = tid + q * blockDim.x;
-    if (pidx >= d * d) break;
-    int i = pidx / d, j = pidx % d;
+    if (pidx >= d * nj) break;
+    int i = pidx / nj, j = j0 + pidx % nj;
     Ac[((int64_t)(tgt * d + i) * d + j) * Vc + a] = make_double2(acc[q].re, acc[q].im);
   }
 }
 
-__global__ void k_galerkin_coarse(CoarseOp op, TGeom t, const double2* __restrict__ Pm, double2* __restrict__ Ac) {
-  extern __shared__ double2 T[];  // [dl][d]
+__global__ void k_galerkin_coarse(CoarseOp op, TGeom t, const double2* __restrict__ Pm, double2* __restrict__ Ac,
+                                  int jc) {
+  extern __shared__ double2 T[];  // [dl][jc]
   const int64_t a = blockIdx.x;
   const int tgt = blockIdx.y;
+  const int j0 = blockIdx.z * jc;
   const int d = 2 * t.ntv, ntv = t.ntv, tid = threadIdx.x;
+  const int nj = d - j0 < jc ? d - j0 : jc;
   const int dl = t.f.dof, hl = t.half;
   const int64_t Vl = t.f.V;
   cx<double> acc[kGalPairs];
@@ -699,69 +731,84 @@ __global__ void k_galerkin_coarse(CoarseOp op, TGeom t, const double2* __restric
     l[1] = rem % t.b[1]; rem /= t.b[1];
     l[2] = rem % t.b[2]; rem /= t.b[2];
     l[3] = rem;
+    bool any = false;
+    for (int k = 0; k < 9; k++) any |= hop_target(k, l, t.b) == tgt;
+    if (!any) continue;  // uniform over the workgroup
     for (int m = 0; m < 4; m++) fc[m] = ca[m] * t.b[m] + l[m];
     const int64_t s = index_of(t.f, fc);
-    for (int k = 0; k < 9; k++) {
-      if (hop_target(k, l, t.b) != tgt) continue;
-      const int64_t y = hop_neighbour(t.f, fc, k);
-      if (tid < d) {
-        const int j = tid, chij = j / ntv, kk = j % ntv;
+    // entries (i2, jj) of the chunk's hop sum, one per thread at a time
+    for (int e = tid; e < dl * nj; e += blockDim.x) {
+      const int i2 = e / nj, jj = e - i2 * nj;
+      const int j = j0 + jj, chij = j / ntv, kk = j % ntv;
+      cx<double> o = {0, 0};
+      for (int k = 0; k < 9; k++) {
+        if (hop_target(k, l, t.b) != tgt) continue;
+        const int64_t y = hop_neighbour(t.f, fc, k);
         int64_t ay;
         int locy;
         agg_of(t, y, ay, locy);
         const double2* py = Pm + ((ay * 2 + chij) * t.rows + locy * hl) * (int64_t)ntv + kk;
-        for (int i2 = 0; i2 < dl; i2++) {
-          cx<double> o = {0, 0};
-          const double2* Arow = op.A64 + ((int64_t)(k * dl + i2) * dl + chij * hl) * Vl + s;
-          for (int mm = 0; mm < hl; mm++) {
-            double2 av = Arow[(int64_t)mm * Vl];
-            double2 pv = py[(int64_t)mm * ntv];
-            fma_(o, cx<double>{av.x, av.y}, cx<double>{pv.x, pv.y});
-          }
-          T[i2 * d + j] = make_double2(o.re, o.im);
-        }
-      }
-      __syncthreads();
-      for (int q = 0; q < kGalPairs; q++) {
-        int pidx = tid + q * blockDim.x;
-        if (pidx >= d * d) break;
-        int i = pidx / d, j = pidx % d;
-        int chii = i / ntv, ki = i % ntv;
-        const double2* pr = Pm + ((a * 2 + chii) * t.rows + loc * hl) * (int64_t)ntv + ki;
+        const double2* Arow = op.A64 + ((int64_t)(k * dl + i2) * dl + chij * hl) * Vl + s;
         for (int mm = 0; mm < hl; mm++) {
-          double2 pv = pr[(int64_t)mm * ntv];
-          double2 tv = T[(chii * hl + mm) * d + j];
-          fmac_(acc[q], cx<double>{pv.x, pv.y}, cx<double>{tv.x, tv.y});
+          double2 av = Arow[(int64_t)mm * Vl];
+          double2 pv = py[(int64_t)mm * ntv];
+          fma_(o, cx<double>{av.x, av.y}, cx<double>{pv.x, pv.y});
         }
       }
-      __syncthreads();
+      T[i2 * jc + jj] = make_double2(o.re, o.im);
     }
+    __syncthreads();
+    for (int q = 0; q < kGalPairs; q++) {
+      int pidx = tid + q * blockDim.x;
+      if (pidx >= d * nj) break;
+      int i = pidx / nj, jj = pidx % nj;
+      int chii = i / ntv, ki = i % ntv;
+      const double2* pr = Pm + ((a * 2 + chii) * t.rows + loc * hl) * (int64_t)ntv + ki;
+      for (int mm = 0; mm < hl; mm++) {
+        double2 pv = pr[(int64_t)mm * ntv];
+        double2 tv = T[(chii * hl + mm) * jc + jj];
+        fmac_(acc[q], cx<double>{pv.x, pv.y}, cx<double>{tv.x, tv.y});
+      }
+    }
+    __syncthreads();
   }
   const int64_t Vc = t.c.V;
   for (int q = 0; q < kGalPairs; q++) {
     int pidx = tid + q * blockDim.x;
-    if (pidx >= d * d) break;
-    int i = pidx / d, j = pidx % d;
+    if (pidx >= d * nj) break;
+    int i = pidx / nj, j = j0 + pidx % nj;
     Ac[((int64_t)(tgt * d + i) * d + j) * Vc + a] = make_double2(acc[q].re, acc[q].im);
   }
+}
+
+// columns per Galerkin workgroup: all d when the pairs and the staged rows
+// fit, else the largest power of two that does
+static int galerkin_jc(int d, int rows_staged) {
+  int jc = d;
+  while (jc > 1 && ((size_t)d * jc > (size_t)256 * kGalPairs || (size_t)rows_staged * jc * sizeof(double2) > 65536))
+    jc = (jc + 1) / 2;
+  return jc;
 }
 
 void mg_galerkin_fine(Context* c, const FineOp& op, const Transfer& T, CoarseOp& out) {
   const TGeom& t = T.t;
   const int d = 2 * t.ntv;
-  MGM_CHECK(d * d <= 256 * kGalPairs && d <= 64, MGM_ERR_SHAPE, "too many test vectors");
-  size_t sh = (size_t)12 * d * sizeof(double2);
-  hipLaunchKernelGGL(k_galerkin_fine, dim3((unsigned)t.c.V, 9), dim3(256), sh, c->stream, op, t, T.P64, out.A64);
+  MGM_CHECK(d <= 128, MGM_ERR_SHAPE, "too many test vectors");
+  const int jc = galerkin_jc(d, 12);
+  const size_t sh = (size_t)12 * (jc + t.ntv) * sizeof(double2);
+  hipLaunchKernelGGL(k_galerkin_fine, dim3((unsigned)t.c.V, 9, (unsigned)((d + jc - 1) / jc)), dim3(256), sh,
+                     c->stream, op, t, T.P64, out.A64, jc);
   MGM_LAUNCH_CHECK();
 }
 
 void mg_galerkin_coarse(Context* c, const CoarseOp& op, const Transfer& T, CoarseOp& out) {
   const TGeom& t = T.t;
   const int d = 2 * t.ntv;
-  MGM_CHECK(d * d <= 256 * kGalPairs && d <= 64 && t.f.dof <= 64, MGM_ERR_SHAPE, "too many test vectors");
-  size_t sh = (size_t)t.f.dof * d * sizeof(double2);
-  hipLaunchKernelGGL(k_galerkin_coarse, dim3((unsigned)t.c.V, 9), dim3(256), sh, c->stream, op, t, T.P64,
-                     out.A64);
+  MGM_CHECK(d <= 128 && t.f.dof <= 128, MGM_ERR_SHAPE, "too many test vectors");
+  const int jc = galerkin_jc(d, t.f.dof);
+  const size_t sh = (size_t)t.f.dof * jc * sizeof(double2);
+  hipLaunchKernelGGL(k_galerkin_coarse, dim3((unsigned)t.c.V, 9, (unsigned)((d + jc - 1) / jc)), dim3(256), sh,
+                     c->stream, op, t, T.P64, out.A64, jc);
   MGM_LAUNCH_CHECK();
 }
 

@@ -188,6 +188,62 @@ def test_coarse_bf16_backward_blocks(wide, nrhs):
         assert rel(from_gpu(got).astype(np.complex128).reshape(nrhs, -1), want.reshape(nrhs, -1)) < 5e-5
 
 
+def _coarse_want(op, x, prec):
+    """Reference of the level-l stencil in precision prec for input x."""
+    if prec != "bf16":
+        return op.matvec(x.astype(np.complex128).reshape(x.shape[0], -1))
+    B, nbr = op.stencil()
+    d = op.d
+    g = np.where(np.arange(d) < d // 2, 1.0, -1.0)
+    Bf = _bf16c(B[:, :5])
+    blocks = np.concatenate([Bf] + [
+        (g[None, :, None] * np.conj(np.transpose(Bf[nbr[5 + mu], 1 + mu], (0, 2, 1))) * g[None, None, :])[:, None]
+        for mu in range(4)], axis=1)
+    xr = _bf16c(x.astype(np.complex128))
+    want = np.zeros(x.shape, dtype=np.complex128)
+    for k in range(9):
+        want += np.einsum("sij,nsj->nsi", blocks[:, k], xr[:, nbr[k], :])
+    return want.reshape(x.shape[0], -1)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f32", "f64"])
+@pytest.mark.parametrize("nrhs", [37, 100])
+def test_coarse_stencil_every_launch_shape(ctx, wide, prec, nrhs):
+    """Every launch shape the autotuner may pick for the coarse stencils
+    (waves per workgroup, tiles per wave, all of a site's tiles in one
+    workgroup) against the oracle: f64 within 1e-10 (the bar of D_c), f32
+    within 2e-6, bf16 within 5e-5 of the BF16-rounded stencil."""
+    import torch
+    p = wide
+    tag = {"bf16": "coarsebf16", "f32": "coarse32", "f64": "coarse64"}[prec]
+    bar = {"bf16": 5e-5, "f32": 2e-6, "f64": 1e-10}[prec]
+    for l in (1, 2):
+        op = p.oh.ops[l]
+        x = _rand(op.V, op.d, nrhs, 600 + l)
+        if prec != "f64":
+            x = x.astype(np.complex64)
+        xg = to_gpu(x)
+        want = _coarse_want(op, x, prec)
+        key = "%s/%d/%d/%d" % (tag, op.V, op.d, nrhs)
+        ctx.autotune(True)
+        try:
+            p.h.apply_prec(l, xg, prec)
+        finally:
+            ctx.autotune(False)
+        torch.cuda.synchronize()
+        rep = ctx.tune_report()
+        assert key in rep, (key, list(rep))
+        nvar = len(rep[key][1])
+        if nrhs == 100:  # seven tiles: the whole-site shapes are among the candidates
+            assert nvar >= (4 if prec != "bf16" else 7), (key, nvar)
+        for v in range(nvar):
+            ctx.tune_set(key, v)
+            got = p.h.apply_prec(l, xg, prec)
+            torch.cuda.synchronize()
+            assert rel(from_gpu(got).astype(np.complex128).reshape(nrhs, -1), want) < bar, (key, v)
+        ctx.tune_set(key, 0)
+
+
 def _f16_pairs(x):
     """numpy (nrhs, sites, dof) complex -> device float16 pairs (dof, sites, nrhs, 2)
     and the values they hold as complex128 (nrhs, sites, dof)"""
