@@ -600,11 +600,14 @@ __global__ __launch_bounds__(256) void k_dslash_rb(typename P::S* __restrict__ o
 // while it is in registers.  The t-hops read the same tile of the adjacent
 // time slices, which belong to the neighbouring blocks in block order (the
 // time slice is the fastest block index), so they are loaded by blocks
-// resident on the same XCD at about the same step.  Every hop and the clover
-// term use the same arithmetic as k_dslash; the terms are summed in another
-// order (the backward z hop first, as it is formed one step early, and the
-// forward z hop last, after the loads of the next plane are in flight), so
-// the two kernels agree to rounding.
+// resident on the same XCD; they too are formed one step early, in the step
+// in which the owners of those slices load the plane as their next one, so
+// the rows are still in L2 (a step later, the streams of the 32 blocks on an
+// XCD have moved more than its 4 MB of L2 through it).  Every hop and the
+// clover term use the same arithmetic as k_dslash; the terms are summed in
+// another order (the backward z and the t hops first, as they are formed one
+// step early, and the forward z hop last, after the loads of the next plane
+// are in flight), so the two kernels agree to rounding.
 
 // gg = U h (forward) or U^H h (backward) for the half spinor h = u -/+ A_mu l
 // of ps
@@ -980,8 +983,30 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
         buf[lidx(k, hrow ? kRows - 1 : 0, col)] = IO::raw(rin, vo, (uint32_t)((TY / 2) * j) * spb);
     }
   };
+  // t hops of plane zz from the adjacent slices into acc.  In the smoother
+  // step they are formed one step early (at the end of the step before plane
+  // zz), when the owners of the adjacent slices load plane zz as their next
+  // plane: both reads of those rows fall into the same step, and the second
+  // finds them in L2.  The other forms keep them in their own step (their
+  // dot accumulators leave no registers for the early form).
+  constexpr bool kTEarly = MR;
+  auto t_hops = [&](int zz, cx<R>(&a)[12]) {
+    const uint32_t s_own = (uint32_t)zz * sz + (uint32_t)t * st + rowoff;
+#pragma unroll 1
+    for (int hop = 0; hop < 2; hop++) {
+      const bool fwd = hop == 0;
+      const uint32_t sn = (uint32_t)zz * sz + (uint32_t)(fwd ? tp : tm) * st + rowoff;
+      S ps[12];
+      cx<R> gg[2][3];
+#pragma unroll
+      for (int k = 0; k < 12; k++) ps[k] = IO::raw(rin, (sn * nrhs + r) * IO::SB, (uint32_t)k * spb);
+      hop_raw<P, PK>(ps, 3, fwd, ru, upb, (fwd ? s_own : sn) * IO::SB, gg);
+      hop_add<P>(3, fwd, fwd ? ftp : ftm, gg, a);
+    }
+  };
   // The accumulator of a plane starts as the backward z-hop contribution of
-  // the plane before it, formed while that plane is in registers.
+  // the plane before it, formed while that plane is in registers, plus the
+  // plane's t hops.
   cx<R> acc[12];
   {
     const int zm = z0 == 0 ? g.Z - 1 : z0 - 1;
@@ -994,6 +1019,7 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k] = {0, 0};
     hop_add<P>(2, false, (R)-0.5, gg, acc);
+    if (kTEarly) t_hops(z0, acc);
     const uint32_t s0 = (uint32_t)z0 * sz + (uint32_t)t * st + rowoff;
 #pragma unroll
     for (int k = 0; k < 12; k++) {
@@ -1036,18 +1062,7 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
       hop_raw<P, PK>(ps, mu, fwd, ru, upb, ls * IO::SB, gg);
       hop_add<P>(mu, fwd, (R)-0.5, gg, acc);
     }
-    // t hops from the adjacent slices
-#pragma unroll 1
-    for (int hop = 0; hop < 2; hop++) {
-      const bool fwd = hop == 0;
-      const uint32_t sn = (uint32_t)z * sz + (uint32_t)(fwd ? tp : tm) * st + rowoff;
-      S ps[12];
-      cx<R> gg[2][3];
-#pragma unroll
-      for (int k = 0; k < 12; k++) ps[k] = IO::raw(rin, (sn * nrhs + r) * IO::SB, (uint32_t)k * spb);
-      hop_raw<P, PK>(ps, 3, fwd, ru, upb, (fwd ? s : sn) * IO::SB, gg);
-      hop_add<P>(3, fwd, fwd ? ftp : ftm, gg, acc);
-    }
+    if (!kTEarly) t_hops(z, acc);
     // next plane (kept raw for staging); its loads overlap the clover term
     S nx[12];
     {
@@ -1142,6 +1157,7 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
       for (int k = 0; k < 12; k++) acc[k] = {0, 0};
       hop_add<P>(2, false, (R)-0.5, gg, acc);
     }
+    if (kTEarly && i + 1 < zs) t_hops(zp, acc);
   }
   if (DOT) {
     // per-rhs block sums: lane % nbr is the rhs within the group (nbr divides
