@@ -77,13 +77,62 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_11424_amd", "csrc", f)
                   for f in ("dslash.hip", "fine_dev.h", "fine.h", "common.h")]
 
 
-def kernel_sources_hash():
+def kernel_sources_hash(files=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files or KERNEL_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+# MFMA and HBM counters of the level-1 BF16 coarse stencil of the 32^3 x 64
+# workload (8^3 x 16 coarse sites, 48 dof) from rocprofv3 --pmc runs of
+# bench.py --micro coarse, with the sources they were taken with
+COARSE_MFMA_FILE = os.path.join(ROOT, "profiles", "coarse_bf16_8x8x8x16_d48_mfma.txt")
+COARSE_SOURCES = [os.path.join(ROOT, "paper_2509_11424_amd", "csrc", f)
+                  for f in ("coarse_mfma.hip", "mg.h", "common.h")]
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense BF16 matrix-core peak of MI355X
+
+
+def coarse_mfma_evidence():
+    """Matrix-core utilisation and HBM traffic of the level-1 BF16 coarse
+    stencil at the rhs counts of its record: executed MFMA flops
+    (SQ_INSTS_VALU_MFMA_MOPS_BF16, in units of 512 flop) and useful complex
+    block-product flops (8 * 9 * d^2 per site and rhs) per microsecond of the
+    autotuned launch, against the dense BF16 peak; calibrated FETCH_SIZE /
+    WRITE_SIZE bytes against the algorithmic ones.  None without a record."""
+    kv = {}
+    try:
+        with open(COARSE_MFMA_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#") and not line.startswith(" "):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+    except OSError:
+        return None
+    try:
+        sites, d = int(kv["sites"]), int(kv["dof"])
+        out = {"kernel": "k_coarse_mfma_bf16 (level-1 coarse stencil, %d sites, %d dof)" % (sites, d),
+               "record": os.path.relpath(COARSE_MFMA_FILE, ROOT), "peak_tflops": BF16_MFMA_PEAK_TFLOPS,
+               "sources_match": kv.get("kernel_sources_sha256") == kernel_sources_hash(COARSE_SOURCES)}
+        fs, ws = float(kv["fetch_scale"]), float(kv["write_scale"])
+        for n in [int(v) for v in kv["nrhs"].split()]:
+            us = float(kv["avg_us_nrhs%d" % n])
+            executed = float(kv["mfma_mops_bf16_nrhs%d" % n]) * 512.0
+            useful = 8.0 * 9 * d * d * n * sites
+            traffic = (float(kv["fetch_kib_nrhs%d" % n]) * fs + float(kv["write_kib_nrhs%d" % n]) * ws) * 1024.0
+            alg = sites * (9.0 * d * d * 4 + 2.0 * d * n * 8)
+            out["nrhs%d" % n] = {"variant": int(kv["variant_nrhs%d" % n]), "avg_us": us,
+                                 "mfma_tflops_executed": executed / us / 1e6,
+                                 "mfma_util": executed / us / 1e6 / BF16_MFMA_PEAK_TFLOPS,
+                                 "useful_tflops": useful / us / 1e6,
+                                 "hbm_gbps_measured": traffic / us / 1e3,
+                                 "hbm_frac_measured": traffic / us / 1e3 / HBM_PEAK_GBS,
+                                 "algorithmic_gbps": alg / us / 1e3, "traffic_over_algorithmic": traffic / alg}
+        return out
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
 
 
 def dslash_flops(kclass, V, launches, total_bytes):
@@ -293,6 +342,11 @@ def cpu_baseline(cfg, U, out_path):
 
 # ------------------------------------------------------------------- GPU
 
+def progress(msg):
+    """One progress line on stderr (the JSON result stays alone on stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def run(args):
     import numpy as np
     cfg = dict(CONFIGS[args.config])
@@ -302,6 +356,7 @@ def run(args):
     t0 = time.time()
     U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])
     t_gauge = time.time() - t0
+    progress("gauge field %s generated in %.1f s" % ("x".join(map(str, cfg["dims"])), t_gauge))
     cpu_pid = None
     cpu_out = os.path.join("/tmp", "mgm_cpu_baseline_%d.json" % os.getpid())
     if args.cpu:
@@ -352,6 +407,7 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
                     max_nrhs_level=cfg["batch"], restart=cfg["restart"], mixed=mixed)
     torch.cuda.synchronize()
     t_setup = time.time() - t0
+    progress("hierarchy built in %.1f s" % t_setup)
     kind = "mg_mixed" if mixed else "mg"
     # mixed form: FP16-storage fine smoother, BF16 MFMA coarse operators,
     # autotuned launch shapes and graph-captured coarse-grid corrections
@@ -430,8 +486,11 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
         "kernels_note": "HIP-event statistics of eagerly launched kernels; launches replayed from the captured "
                         "coarse-grid-correction graphs are not timed per class",
         "tuned_shapes": len(ctx.tune_report()) if mixed else 0,
+        "coarse_mfma": coarse_mfma_evidence(),
     }
+    progress("timed steps done: %.1f RHS/s" % value)
     line["per_level"] = per_level_rates(m, ctx, h, cfg, sd, batch, torch)
+    progress("per-level rates done")
     weights = None
     if args.learned or args.ttt:
         del h, results
@@ -445,6 +504,7 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
                                max_nrhs_level=cfg["batch"], restart=cfg["restart"], mixed=1)
 
         line["time_to_target"] = time_to_target(m, ctx, op, cfg, make_mixed, sd, args, weights)
+        progress("time to target done")
     if cpu_pid:
         os.waitpid(cpu_pid, 0)
         try:
@@ -525,9 +585,11 @@ def observables(args):
                           coarse_bf16=True, smoother_f16=True, graphs=True)
         ctx.autotune(True)
         T = cfg["dims"][3]
+        nprobe = list(args.obs_probes) if args.obs_probes else list(cfg["nprobe"])
         for obs, decs in (("corr", ("orthogonal", "oblique", "plain")), ("loops", ("orthogonal", "plain"))):
             for dec in decs:
-                npr = list(cfg["nprobe"]) if dec != "plain" else [cfg["nprobe"][0]] + [0] * (L - 1)
+                npr = nprobe if dec != "plain" else [nprobe[0]] + [0] * (L - 1)
+                print(json.dumps({"start": obs, "decomposition": dec, "nprobe": npr}), flush=True)
                 torch.cuda.synchronize()
                 t0 = time.time()
                 # the sources of every probe group of correlators and loops
@@ -584,6 +646,7 @@ def hierarchy_study(args):
         variants = [("default", list(cfg["ntv"]), False), ("ntv64", [64] + list(cfg["ntv"][1:]), False),
                     ("refined", list(cfg["ntv"]), True)]
         for name, ntv, refine in variants:
+            print(json.dumps({"start": name, "ntv": ntv}), flush=True)
             torch.cuda.synchronize()
             t0 = time.time()
             h = m.Hierarchy(op, cfg["blocks"], ntv, seed=cfg["pseed"] + 1000, max_nrhs=batch[0],
@@ -862,6 +925,7 @@ def time_to_target(m, ctx, op, cfg, make_mixed, sd_mixed, args, weights=None):
                       max_nrhs_level=b64, restart=cfg["restart"], mixed=0)
     sd64 = m.solve_desc(tol=1e-10, kind="mg", smooth=6, smooth_coarse=2, coarse_iters=1, maxiter=5000)
     p64 = pilot(h64, sd64, b64)
+    progress("time to target: FP64 pilot %.1f s" % p64["seconds"])
     eps2 = p64["total_var"]
     out = {"eps2": eps2, "f64": final(h64, sd64, p64, eps2, b64)}
     out["f64"]["batch"] = b64
@@ -869,6 +933,7 @@ def time_to_target(m, ctx, op, cfg, make_mixed, sd_mixed, args, weights=None):
     torch.cuda.empty_cache()
     h_mixed = make_mixed()
     pm = pilot(h_mixed, sd_mixed, cfg["batch"])
+    progress("time to target: mixed pilot %.1f s" % pm["seconds"])
     out["mixed"] = final(h_mixed, sd_mixed, pm, eps2, cfg["batch"])
     out["mixed"]["batch"] = cfg["batch"]
     if weights is not None:
@@ -910,6 +975,8 @@ def main():
                     help="per-term variance against setup cost for N_tv 64 and refined test vectors")
     ap.add_argument("--observables", action="store_true",
                     help="estimate C(t) three ways and the loops two ways with the timed form, one line each")
+    ap.add_argument("--obs-probes", type=int, nargs="+", default=None,
+                    help="observables: probes per group (default: the configuration's)")
     ap.add_argument("--micro", choices=["dslash", "dslash_dot", "step", "copy", "coarse"])
     ap.add_argument("--level", type=int, default=1, help="micro coarse: hierarchy level of the stencil")
     ap.add_argument("--tune", action="store_true", help="micro: autotune the launch shape first")
