@@ -2,6 +2,7 @@
 // aggregation-based unitary P_l from N_tv test vectors approximating low
 // modes of D_l, Galerkin D_{l+1} = P_l^H D_l P_l).
 #include "lib.h"
+#include "block.h"
 
 namespace mgm {
 
@@ -153,8 +154,13 @@ void Hier::layout(Arena& a) {
   a.off = base;
   tv.assign(L > 0 ? L - 1 : 0, nullptr);
   for (int l = 0; l + 1 < L; l++) tv[l] = a.take_n<double2>((size_t)n(l) * desc.ntv[l]);
+  // the rough smoothing runs on chunks of kSetupChunk test vectors: its four
+  // temporaries hold that many columns, not N_tv (a quarter of the memory
+  // at N_tv 24 on the fine level, where four full-width copies would not fit
+  // next to the hierarchy on the largest lattices)
   size_t tmp_max = 0;
-  for (int l = 0; l + 1 < L; l++) tmp_max = std::max(tmp_max, (size_t)n(l) * desc.ntv[l]);
+  for (int l = 0; l + 1 < L; l++) tmp_max = std::max(tmp_max, (size_t)n(l) * std::min(desc.ntv[l], kSetupChunk));
+  setup_v = a.take_n<double2>(tmp_max);
   setup_y = a.take_n<double2>(tmp_max);
   setup_rho = a.take_n<double2>(tmp_max);
   setup_q = a.take_n<double2>(tmp_max);
@@ -181,21 +187,24 @@ void Hier::build_level(int l, const double2* tvsrc) {
   finish_level(l, src);
 }
 
-// The rough test vectors of level l into tv[l].
+// The rough test vectors of level l into tv[l], kSetupChunk columns at a
+// time (every column is smoothed on its own, so the chunking changes nothing
+// but the batch width of the launches).
 void Hier::rough_tv(int l) {
   Context* c = ctx;
   const int ntv = desc.ntv[l];
-  {
-    Vec v = vec(l, MGM_PREC_F64, tv[l], ntv);
+  for (int k0 = 0; k0 < ntv; k0 += kSetupChunk) {
+    const int nb = std::min(kSetupChunk, ntv - k0);
+    Vec v = vec(l, MGM_PREC_F64, setup_v, nb);
     Vec y = v.with(setup_y), rho = v.with(setup_rho), q = v.with(setup_q);
-    // Z4 starts (kind 7), then setup_steps rounds of MR_k smoothing and
-    // normalisation: v <- MR(D_l, v) / |MR(D_l, v)|
-    draw_z4(c, desc.seed, (uint32_t)(256 * l + 7), 0, ntv, g[l].V, g[l].dof, MGM_PREC_F64, tv[l]);
+    // Z4 starts (kind 7, probes k0 ..), then setup_steps rounds of MR_k
+    // smoothing and normalisation: v <- MR(D_l, v) / |MR(D_l, v)|
+    draw_z4(c, desc.seed, (uint32_t)(256 * l + 7), (uint64_t)k0, nb, g[l].V, g[l].dof, MGM_PREC_F64, setup_v);
     for (int it = 0; it < desc.setup_steps; it++) {
       b_zero(c, y);
       b_copy(c, rho, v);
       for (int k = 0; k < desc.setup_mr; k++) {
-        apply(l, MGM_PREC_F64, rho.p, q.p, ntv);
+        apply(l, MGM_PREC_F64, rho.p, q.p, nb);
         b_dot_norm(c, scratch, q, rho, setup_qr, setup_qq);
         b_mr_update(c, setup_qr, setup_qq, rho, q, y);
       }
@@ -203,6 +212,7 @@ void Hier::rough_tv(int l) {
       b_copy(c, v, y);
       b_normalize(c, v, setup_n2, nullptr);
     }
+    blk_scatter(c, setup_v, ntv, k0, nb, n(l), tv[l]);
   }
 }
 

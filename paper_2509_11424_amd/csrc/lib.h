@@ -55,6 +55,9 @@ struct EstWS {
   double2* slice_out = nullptr;
 };
 
+// test vectors smoothed together in the rough setup recipe
+constexpr int kSetupChunk = 4;
+
 struct Hier {
   Context* ctx = nullptr;
   FineOp* fine = nullptr;
@@ -72,6 +75,7 @@ struct Hier {
   size_t pinned_n = 0;
   // setup buffers (alias the solver region)
   std::vector<double2*> tv;  // per transfer: ntv test vectors (FP64)
+  double2* setup_v = nullptr;
   double2* setup_y = nullptr;
   double2* setup_rho = nullptr;
   double2* setup_q = nullptr;
