@@ -77,7 +77,10 @@ const char* mgm_version(void);
 /* ------------------------------------------------------------- context */
 
 /* Binds the library to HIP device `device` and to `hip_stream` (a
- * hipStream_t, NULL for the default stream).  Errors: INVALID_ARG, HIP. */
+ * hipStream_t, NULL for the default stream).  Every later call on this
+ * context or on an object built from it makes that device current for its
+ * duration and restores the caller's current device on return, so contexts
+ * on different devices can be used from one thread.  Errors: INVALID_ARG, HIP. */
 mgm_status mgm_context_create(int device, void* hip_stream, mgm_context* out);
 /* Switches the stream used by later calls on this context. */
 mgm_status mgm_context_set_stream(mgm_context ctx, void* hip_stream);

@@ -118,6 +118,15 @@ void Context::prof_flush() {
     return MGM_ERR_INVALID_ARG;                   \
   }
 
+// the context a handle runs on (nullptr for a NULL handle: the call's own
+// argument check reports it)
+static const mgm::Context* ctx_of(mgm_context c) { return c ? &c->c : nullptr; }
+static const mgm::Context* ctx_of(mgm_operator o) { return o ? o->ctx : nullptr; }
+static const mgm::Context* ctx_of(mgm_hierarchy h) { return h ? h->h.ctx : nullptr; }
+static const mgm::Context* ctx_of(mgm_deflation f) { return f && f->owner ? f->owner->h.ctx : nullptr; }
+static const mgm::Context* ctx_of(mgm_net n) { return n && n->op ? n->op->ctx : nullptr; }
+#define API_ON(handle) mgm::DeviceScope device_scope_(ctx_of(handle));
+
 extern "C" {
 
 const char* mgm_status_string(mgm_status s) {
@@ -163,6 +172,7 @@ mgm_status mgm_context_create(int device, void* hip_stream, mgm_context* out) {
 
 mgm_status mgm_context_set_stream(mgm_context ctx, void* hip_stream) {
   API_BEGIN
+  API_ON(ctx)
   MGM_CHECK(ctx != nullptr, MGM_ERR_INVALID_ARG, "ctx is NULL");
   ctx->c.stream = (hipStream_t)hip_stream;
   API_END
@@ -170,6 +180,7 @@ mgm_status mgm_context_set_stream(mgm_context ctx, void* hip_stream) {
 
 mgm_status mgm_context_set_autotune(mgm_context ctx, int32_t enable) {
   API_BEGIN
+  API_ON(ctx)
   MGM_CHECK(ctx != nullptr, MGM_ERR_INVALID_ARG, "ctx is NULL");
   ctx->c.tune.enabled = enable != 0;
   API_END
@@ -177,6 +188,7 @@ mgm_status mgm_context_set_autotune(mgm_context ctx, int32_t enable) {
 
 mgm_status mgm_context_tune_report(mgm_context ctx, char* buf, size_t bytes, size_t* needed) {
   API_BEGIN
+  API_ON(ctx)
   MGM_CHECK(ctx != nullptr, MGM_ERR_INVALID_ARG, "ctx is NULL");
   std::string out;
   for (auto& kv : ctx->c.tune.table) {
@@ -199,6 +211,7 @@ mgm_status mgm_context_tune_report(mgm_context ctx, char* buf, size_t bytes, siz
 
 mgm_status mgm_context_tune_set(mgm_context ctx, const char* key, int32_t variant) {
   API_BEGIN
+  API_ON(ctx)
   MGM_CHECK(ctx != nullptr && key != nullptr, MGM_ERR_INVALID_ARG, "NULL argument");
   MGM_CHECK(variant >= 0, MGM_ERR_INVALID_ARG, "variant must be >= 0");
   Tuner::Entry e;
@@ -248,6 +261,7 @@ mgm_status mgm_operator_workspace_size(const mgm_lattice_desc* desc, size_t* byt
 mgm_status mgm_operator_create(mgm_context ctx, const mgm_lattice_desc* desc, const double* gauge_host,
                                void* ws_dev, size_t ws_bytes, mgm_operator* out) {
   API_BEGIN
+  API_ON(ctx)
   MGM_CHECK(ctx && gauge_host && ws_dev && out, MGM_ERR_INVALID_ARG, "NULL argument");
   MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   Geom g = geom_of(desc);
@@ -273,6 +287,7 @@ mgm_status mgm_operator_create(mgm_context ctx, const mgm_lattice_desc* desc, co
 
 mgm_status mgm_operator_apply(mgm_operator op, mgm_prec prec, const void* x, void* y, int32_t nrhs) {
   API_BEGIN
+  API_ON(op)
   MGM_CHECK(op && x && y && nrhs >= 1, MGM_ERR_INVALID_ARG, "bad arguments");
   MGM_CHECK(x != y, MGM_ERR_INVALID_ARG, "x and y must not overlap");
   op->op.apply(prec, x, y, nrhs);
@@ -286,6 +301,7 @@ static size_t dot_ws_bytes(const FineOp& op, mgm_prec prec, int nrhs) {
 
 mgm_status mgm_operator_dot_workspace_size(mgm_operator op, mgm_prec prec, int32_t nrhs, size_t* bytes) {
   API_BEGIN
+  API_ON(op)
   MGM_CHECK(op && bytes && nrhs >= 1 && nrhs <= 256, MGM_ERR_INVALID_ARG, "bad arguments");
   *bytes = dot_ws_bytes(op->op, prec, nrhs);
   API_END
@@ -294,6 +310,7 @@ mgm_status mgm_operator_dot_workspace_size(mgm_operator op, mgm_prec prec, int32
 mgm_status mgm_operator_apply_dot(mgm_operator op, mgm_prec prec, const void* x, void* y, int32_t nrhs,
                                   void* ws_dev, size_t ws_bytes, void* yx_dev, void* yy_dev) {
   API_BEGIN
+  API_ON(op)
   MGM_CHECK(op && x && y && ws_dev && yx_dev && yy_dev, MGM_ERR_INVALID_ARG, "NULL argument");
   MGM_CHECK(nrhs >= 1 && nrhs <= 256, MGM_ERR_INVALID_ARG, "nrhs must be 1..256");
   MGM_CHECK(x != y, MGM_ERR_INVALID_ARG, "x and y must not overlap");
@@ -313,6 +330,7 @@ mgm_status mgm_operator_smoother_step(mgm_operator op, const void* r_dev, void* 
                                       const void* qr_prev_dev, const void* qq_prev_dev, int32_t nrhs,
                                       void* ws_dev, size_t ws_bytes, void* yx_dev, void* yy_dev) {
   API_BEGIN
+  API_ON(op)
   MGM_CHECK(op && r_dev && r_next_dev && x_dev && qr_prev_dev && qq_prev_dev && ws_dev && yx_dev && yy_dev,
             MGM_ERR_INVALID_ARG, "NULL argument");
   MGM_CHECK(nrhs >= 1 && nrhs <= 256, MGM_ERR_INVALID_ARG, "nrhs must be 1..256");
@@ -347,6 +365,7 @@ void mgm_operator_destroy(mgm_operator op) { delete op; }
 mgm_status mgm_draw_noise(mgm_context ctx, int32_t kind, uint64_t seed, uint32_t stream, uint64_t first_probe,
                           int32_t nprobe, int64_t n_site, int32_t dof, mgm_prec prec, void* out_dev) {
   API_BEGIN
+  API_ON(ctx)
   MGM_CHECK(ctx && out_dev && nprobe >= 1 && n_site >= 1 && dof >= 1, MGM_ERR_INVALID_ARG, "bad arguments");
   MGM_CHECK(first_probe + (uint64_t)nprobe <= (1ull << 32), MGM_ERR_INVALID_ARG,
             "probe indices must be below 2^32 (32-bit counter word)");
@@ -358,6 +377,7 @@ mgm_status mgm_draw_noise(mgm_context ctx, int32_t kind, uint64_t seed, uint32_t
 mgm_status mgm_draw_z4(mgm_context ctx, uint64_t seed, uint32_t stream, uint64_t first_probe, int32_t nprobe,
                        int64_t n_site, int32_t dof, mgm_prec prec, void* out) {
   API_BEGIN
+  API_ON(ctx)
   MGM_CHECK(ctx && out && nprobe >= 1 && n_site >= 1 && dof >= 1, MGM_ERR_INVALID_ARG, "bad arguments");
   MGM_CHECK(first_probe + (uint64_t)nprobe <= (1ull << 32), MGM_ERR_INVALID_ARG,
             "probe indices must be below 2^32 (32-bit counter word)");
@@ -397,6 +417,7 @@ static void check_hdesc(mgm_operator op, const mgm_hierarchy_desc* d) {
 
 mgm_status mgm_hierarchy_workspace_size(mgm_operator op, const mgm_hierarchy_desc* desc, size_t* bytes) {
   API_BEGIN
+  API_ON(op)
   check_hdesc(op, desc);
   MGM_CHECK(bytes, MGM_ERR_INVALID_ARG, "bytes is NULL");
   Hier h;
@@ -412,6 +433,7 @@ mgm_status mgm_hierarchy_workspace_size(mgm_operator op, const mgm_hierarchy_des
 mgm_status mgm_hierarchy_create(mgm_operator op, const mgm_hierarchy_desc* desc, void* ws_dev, size_t ws_bytes,
                                 mgm_hierarchy* out) {
   API_BEGIN
+  API_ON(op)
   check_hdesc(op, desc);
   MGM_CHECK(ws_dev && out, MGM_ERR_INVALID_ARG, "NULL argument");
   MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -439,6 +461,7 @@ mgm_status mgm_hierarchy_create(mgm_operator op, const mgm_hierarchy_desc* desc,
 
 mgm_status mgm_hierarchy_level_info(mgm_hierarchy h, int32_t level, int64_t* sites, int32_t* dof, int64_t* n) {
   API_BEGIN
+  API_ON(h)
   MGM_CHECK(h && level >= 0 && level < h->h.L, MGM_ERR_INVALID_ARG, "bad level");
   if (sites) *sites = h->h.g[level].V;
   if (dof) *dof = h->h.g[level].dof;
@@ -449,6 +472,7 @@ mgm_status mgm_hierarchy_level_info(mgm_hierarchy h, int32_t level, int64_t* sit
 mgm_status mgm_hierarchy_export(mgm_hierarchy hh, int32_t level, mgm_export_kind what, void* host_buf,
                                 size_t bytes) {
   API_BEGIN
+  API_ON(hh)
   MGM_CHECK(hh && host_buf, MGM_ERR_INVALID_ARG, "NULL argument");
   Hier& h = hh->h;
   MGM_CHECK(level >= 0 && level + 1 < h.L, MGM_ERR_INVALID_ARG, "bad transfer level");
@@ -513,6 +537,7 @@ static void check_level(mgm_hierarchy h, int level, int nrhs, bool transfer) {
 
 mgm_status mgm_level_apply(mgm_hierarchy h, int32_t level, const void* x, void* y, int32_t nrhs) {
   API_BEGIN
+  API_ON(h)
   check_level(h, level, nrhs, false);
   MGM_CHECK(x && y && x != y, MGM_ERR_INVALID_ARG, "bad vectors");
   h->h.apply(level, MGM_PREC_F64, x, y, nrhs);
@@ -522,6 +547,7 @@ mgm_status mgm_level_apply(mgm_hierarchy h, int32_t level, const void* x, void* 
 mgm_status mgm_level_apply_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const void* x, void* y,
                                 int32_t nrhs) {
   API_BEGIN
+  API_ON(h)
   check_level(h, level, nrhs, false);
   MGM_CHECK(x && y && x != y, MGM_ERR_INVALID_ARG, "bad vectors");
   MGM_CHECK(!(level == 0 && prec == MGM_PREC_BF16) && !(level > 0 && prec == MGM_PREC_F16), MGM_ERR_INVALID_ARG,
@@ -532,6 +558,7 @@ mgm_status mgm_level_apply_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, c
 
 mgm_status mgm_restrict(mgm_hierarchy h, int32_t level, const void* x, void* y, int32_t nrhs) {
   API_BEGIN
+  API_ON(h)
   check_level(h, level, nrhs, true);
   MGM_CHECK(x && y, MGM_ERR_INVALID_ARG, "bad vectors");
   h->h.T[level].restrict_(MGM_PREC_F64, x, y, nrhs);
@@ -540,6 +567,7 @@ mgm_status mgm_restrict(mgm_hierarchy h, int32_t level, const void* x, void* y, 
 
 mgm_status mgm_prolong(mgm_hierarchy h, int32_t level, const void* x, void* y, int32_t nrhs) {
   API_BEGIN
+  API_ON(h)
   check_level(h, level, nrhs, true);
   MGM_CHECK(x && y, MGM_ERR_INVALID_ARG, "bad vectors");
   h->h.T[level].prolong(MGM_PREC_F64, x, nullptr, y, nrhs, 0);
@@ -556,6 +584,7 @@ static void check_transfer_prec(mgm_hierarchy h, mgm_prec prec) {
 mgm_status mgm_restrict_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const void* x, void* y,
                              int32_t nrhs) {
   API_BEGIN
+  API_ON(h)
   check_level(h, level, nrhs, true);
   MGM_CHECK(x && y, MGM_ERR_INVALID_ARG, "bad vectors");
   check_transfer_prec(h, prec);
@@ -566,6 +595,7 @@ mgm_status mgm_restrict_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, cons
 mgm_status mgm_prolong_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const void* x, void* y,
                             int32_t nrhs) {
   API_BEGIN
+  API_ON(h)
   check_level(h, level, nrhs, true);
   MGM_CHECK(x && y, MGM_ERR_INVALID_ARG, "bad vectors");
   check_transfer_prec(h, prec);
@@ -576,6 +606,7 @@ mgm_status mgm_prolong_prec(mgm_hierarchy h, int32_t level, mgm_prec prec, const
 mgm_status mgm_restrict_f16(mgm_hierarchy h, int32_t level, const void* x16, const double* scale, void* y,
                             int32_t nrhs) {
   API_BEGIN
+  API_ON(h)
   check_level(h, level, nrhs, true);
   MGM_CHECK(x16 && scale && y && x16 != y, MGM_ERR_INVALID_ARG, "bad vectors");
   check_transfer_prec(h, MGM_PREC_F32);
@@ -586,6 +617,7 @@ mgm_status mgm_restrict_f16(mgm_hierarchy h, int32_t level, const void* x16, con
 mgm_status mgm_prolong_add_f16(mgm_hierarchy h, int32_t level, const void* xc, const void* x16,
                                const double* scale, void* y, int32_t nrhs) {
   API_BEGIN
+  API_ON(h)
   check_level(h, level, nrhs, true);
   MGM_CHECK(xc && x16 && scale && y && y != x16 && y != xc, MGM_ERR_INVALID_ARG, "bad vectors");
   check_transfer_prec(h, MGM_PREC_F32);
@@ -595,6 +627,7 @@ mgm_status mgm_prolong_add_f16(mgm_hierarchy h, int32_t level, const void* xc, c
 
 mgm_status mgm_project_out(mgm_hierarchy h, int32_t level, const void* x, void* y, int32_t nrhs) {
   API_BEGIN
+  API_ON(h)
   check_level(h, level, nrhs, true);
   MGM_CHECK(x && y, MGM_ERR_INVALID_ARG, "bad vectors");
   Hier& H = h->h;
@@ -629,6 +662,7 @@ mgm_status mgm_solve(mgm_hierarchy h, int32_t level, const mgm_solve_desc* desc,
                      int32_t nrhs, mgm_solve_stats* stats) {
   mgm_status st = MGM_OK;
   try {
+    API_ON(h)
     check_level(h, level, nrhs, false);
     MGM_CHECK(b && x && b != x, MGM_ERR_INVALID_ARG, "bad vectors");
     SolveCfg cfg = cfg_of(desc);
@@ -659,6 +693,7 @@ mgm_status mgm_solve(mgm_hierarchy h, int32_t level, const mgm_solve_desc* desc,
 
 mgm_status mgm_estimate_sizes_query(mgm_hierarchy h, const mgm_estimate_desc* desc, mgm_estimate_sizes* sizes) {
   API_BEGIN
+  API_ON(h)
   MGM_CHECK(h && desc && sizes, MGM_ERR_INVALID_ARG, "NULL argument");
   *sizes = estimate_sizes(h->h, *desc);
   API_END
@@ -666,6 +701,7 @@ mgm_status mgm_estimate_sizes_query(mgm_hierarchy h, const mgm_estimate_desc* de
 
 mgm_status mgm_estimate(mgm_hierarchy h, const mgm_estimate_desc* desc, mgm_estimate_result* out) {
   API_BEGIN
+  API_ON(h)
   MGM_CHECK(h && desc && out, MGM_ERR_INVALID_ARG, "NULL argument");
   cfg_of(&desc->solve);
   auto t0 = std::chrono::steady_clock::now();
@@ -678,6 +714,7 @@ mgm_status mgm_estimate(mgm_hierarchy h, const mgm_estimate_desc* desc, mgm_esti
 
 mgm_status mgm_hierarchy_refine_workspace_size(mgm_hierarchy h, size_t* bytes) {
   API_BEGIN
+  API_ON(h)
   MGM_CHECK(h && bytes, MGM_ERR_INVALID_ARG, "NULL argument");
   *bytes = refine_workspace_bytes(h->h);
   API_END
@@ -686,6 +723,7 @@ mgm_status mgm_hierarchy_refine_workspace_size(mgm_hierarchy h, size_t* bytes) {
 mgm_status mgm_hierarchy_refine(mgm_hierarchy h, const mgm_refine_desc* desc, void* ws_dev, size_t ws_bytes,
                                 mgm_refine_stats* stats, double* rho_host, double* theta_host) {
   API_BEGIN
+  API_ON(h)
   MGM_CHECK(h && desc && ws_dev, MGM_ERR_INVALID_ARG, "NULL argument");
   MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   MGM_CHECK(ws_bytes >= refine_workspace_bytes(h->h), MGM_ERR_WORKSPACE, "refinement workspace too small");
@@ -713,6 +751,7 @@ static void check_defl_desc(mgm_hierarchy h, const mgm_deflation_desc* d) {
 
 mgm_status mgm_deflation_workspace_size(mgm_hierarchy h, const mgm_deflation_desc* desc, size_t* bytes) {
   API_BEGIN
+  API_ON(h)
   check_defl_desc(h, desc);
   MGM_CHECK(bytes != nullptr, MGM_ERR_INVALID_ARG, "bytes is NULL");
   Defl f;
@@ -728,6 +767,7 @@ mgm_status mgm_deflation_create(mgm_hierarchy h, const mgm_deflation_desc* desc,
                                 mgm_deflation* out) {
   mgm_status st = MGM_OK;
   try {
+    API_ON(h)
     check_defl_desc(h, desc);
     MGM_CHECK(ws_dev && out, MGM_ERR_INVALID_ARG, "NULL argument");
     MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -766,6 +806,7 @@ mgm_status mgm_deflation_create(mgm_hierarchy h, const mgm_deflation_desc* desc,
 
 mgm_status mgm_deflation_export(mgm_deflation f, double* host_buf, size_t bytes) {
   API_BEGIN
+  API_ON(f)
   MGM_CHECK(f && host_buf, MGM_ERR_INVALID_ARG, "NULL argument");
   const size_t need = (size_t)f->f.H->n(0) * f->f.k * sizeof(double2);
   MGM_CHECK(bytes >= need, MGM_ERR_INVALID_ARG, "host buffer too small");
@@ -777,6 +818,7 @@ mgm_status mgm_deflation_export(mgm_deflation f, double* host_buf, size_t bytes)
 
 mgm_status mgm_deflation_info(mgm_deflation f, double* exact_trace, double* setup_s, double* exact_s) {
   API_BEGIN
+  API_ON(f)
   MGM_CHECK(f != nullptr, MGM_ERR_INVALID_ARG, "NULL argument");
   if (exact_trace) {
     exact_trace[0] = f->f.exact.real();
@@ -807,6 +849,7 @@ mgm_status mgm_mlmc_allocate(int32_t nterms, const double* var, const double* co
 
 mgm_status mgm_profile_enable(mgm_context ctx, int32_t on) {
   API_BEGIN
+  API_ON(ctx)
   MGM_CHECK(ctx, MGM_ERR_INVALID_ARG, "ctx is NULL");
   ctx->c.prof.on = on != 0;
   API_END
@@ -814,6 +857,7 @@ mgm_status mgm_profile_enable(mgm_context ctx, int32_t on) {
 
 mgm_status mgm_profile_reset(mgm_context ctx) {
   API_BEGIN
+  API_ON(ctx)
   MGM_CHECK(ctx, MGM_ERR_INVALID_ARG, "ctx is NULL");
   ctx->c.prof_flush();
   for (int k = 0; k < KC_COUNT; k++) {
@@ -826,6 +870,7 @@ mgm_status mgm_profile_reset(mgm_context ctx) {
 
 mgm_status mgm_profile_query(mgm_context ctx, int32_t kclass, int64_t* launches, double* ms, double* bytes) {
   API_BEGIN
+  API_ON(ctx)
   MGM_CHECK(ctx && kclass >= 0 && kclass < KC_COUNT, MGM_ERR_INVALID_ARG, "bad arguments");
   ctx->c.prof_flush();
   if (launches) *launches = ctx->c.prof.launches[kclass];
@@ -853,6 +898,7 @@ static void check_net_desc(mgm_operator op, const mgm_net_desc* d) {
 
 mgm_status mgm_net_workspace_size(mgm_operator op, const mgm_net_desc* desc, size_t* bytes) {
   API_BEGIN
+  API_ON(op)
   check_net_desc(op, desc);
   MGM_CHECK(bytes != nullptr, MGM_ERR_INVALID_ARG, "bytes is NULL");
   Net n;
@@ -867,6 +913,7 @@ mgm_status mgm_net_workspace_size(mgm_operator op, const mgm_net_desc* desc, siz
 mgm_status mgm_net_create(mgm_operator op, const mgm_net_desc* desc, void* ws_dev, size_t ws_bytes,
                           mgm_net* out) {
   API_BEGIN
+  API_ON(op)
   check_net_desc(op, desc);
   MGM_CHECK(ws_dev && out, MGM_ERR_INVALID_ARG, "NULL argument");
   MGM_CHECK(((uintptr_t)ws_dev & 255) == 0, MGM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -894,6 +941,7 @@ mgm_status mgm_net_create(mgm_operator op, const mgm_net_desc* desc, void* ws_de
 
 mgm_status mgm_net_bind(mgm_net net, mgm_operator op) {
   API_BEGIN
+  API_ON(net)
   MGM_CHECK(net && op, MGM_ERR_INVALID_ARG, "NULL argument");
   const Geom& a = net->n.op->g;
   const Geom& b = op->op.g;
@@ -907,6 +955,7 @@ mgm_status mgm_net_bind(mgm_net net, mgm_operator op) {
 
 mgm_status mgm_net_num_weights(mgm_net net, int64_t* count) {
   API_BEGIN
+  API_ON(net)
   MGM_CHECK(net && count, MGM_ERR_INVALID_ARG, "NULL argument");
   *count = net->n.nw;
   API_END
@@ -914,6 +963,7 @@ mgm_status mgm_net_num_weights(mgm_net net, int64_t* count) {
 
 mgm_status mgm_net_set_weights(mgm_net net, const double* w_host) {
   API_BEGIN
+  API_ON(net)
   MGM_CHECK(net && w_host, MGM_ERR_INVALID_ARG, "NULL argument");
   std::vector<double> w(w_host, w_host + 2 * net->n.nw);
   net->n.upload_weights(w);
@@ -922,6 +972,7 @@ mgm_status mgm_net_set_weights(mgm_net net, const double* w_host) {
 
 mgm_status mgm_net_get_weights(mgm_net net, double* w_host) {
   API_BEGIN
+  API_ON(net)
   MGM_CHECK(net && w_host, MGM_ERR_INVALID_ARG, "NULL argument");
   MGM_HIP(hipMemcpyAsync(w_host, net->n.w64, sizeof(double2) * net->n.nw, hipMemcpyDeviceToHost,
                          net->n.ctx->stream));
@@ -933,6 +984,7 @@ static const char kNetMagic[8] = {'M', 'G', 'M', 'N', 'E', 'T', '0', '1'};
 
 mgm_status mgm_net_save(mgm_net net, const char* path) {
   API_BEGIN
+  API_ON(net)
   MGM_CHECK(net && path, MGM_ERR_INVALID_ARG, "NULL argument");
   std::vector<double> w(2 * (size_t)net->n.nw);
   MGM_HIP(hipMemcpyAsync(w.data(), net->n.w64, sizeof(double2) * net->n.nw, hipMemcpyDeviceToHost,
@@ -954,6 +1006,7 @@ mgm_status mgm_net_save(mgm_net net, const char* path) {
 
 mgm_status mgm_net_load(mgm_net net, const char* path) {
   API_BEGIN
+  API_ON(net)
   MGM_CHECK(net && path, MGM_ERR_INVALID_ARG, "NULL argument");
   std::FILE* f = std::fopen(path, "rb");
   MGM_CHECK(f != nullptr, MGM_ERR_INVALID_ARG, std::string("cannot open ") + path);
@@ -984,6 +1037,7 @@ mgm_status mgm_net_load(mgm_net net, const char* path) {
 
 mgm_status mgm_net_apply(mgm_net net, const void* r_dev, void* y_dev, int32_t nrhs) {
   API_BEGIN
+  API_ON(net)
   MGM_CHECK(net && r_dev && y_dev, MGM_ERR_INVALID_ARG, "NULL argument");
   net->n.apply((const float2*)r_dev, (float2*)y_dev, nrhs);
   API_END
@@ -992,6 +1046,7 @@ mgm_status mgm_net_apply(mgm_net net, const void* r_dev, void* y_dev, int32_t nr
 mgm_status mgm_net_loss_grad(mgm_net net, const void* r_dev, const void* e_dev, int32_t nrhs, double* loss,
                              double* grad_host) {
   API_BEGIN
+  API_ON(net)
   MGM_CHECK(net && r_dev && e_dev, MGM_ERR_INVALID_ARG, "NULL argument");
   const double l = net->n.loss_grad((const float2*)r_dev, (const float2*)e_dev, nrhs);
   if (loss) *loss = l;
@@ -1006,6 +1061,7 @@ mgm_status mgm_net_loss_grad(mgm_net net, const void* r_dev, const void* e_dev, 
 mgm_status mgm_net_train(mgm_net net, mgm_hierarchy h, const mgm_train_desc* desc, mgm_train_stats* stats,
                          double* loss_history) {
   API_BEGIN
+  API_ON(net)
   MGM_CHECK(net && h && desc, MGM_ERR_INVALID_ARG, "NULL argument");
   net_train(h->h, net->n, *desc, stats, loss_history);
   API_END

@@ -14,6 +14,7 @@
 // fastest so lanes of one site share (broadcast) its links and clover.
 #include "fine.h"
 #include "fine_dev.h"
+#include "devonce.h"
 
 namespace mgm {
 
@@ -1206,13 +1207,11 @@ void FineOp::layout(Arena& a, const Geom& g, FineOp* op) {
 }
 
 void FineOp::build(const double* gauge_host) {
-  static bool sigma_ready = false;
-  if (!sigma_ready) {
+  once_per_device([] {
     double sig[6][2][2][2][2];
     host_sigma(sig);
     MGM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_sigma), sig, sizeof(sig)));
-    sigma_ready = true;
-  }
+  });
   const int64_t V = g.V;
   // host [V][4][3][3] complex -> device [mu][9][V]
   std::vector<double2> tmp((size_t)36 * V);

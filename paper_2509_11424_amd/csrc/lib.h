@@ -58,6 +58,27 @@ struct EstWS {
 // test vectors smoothed together in the rough setup recipe
 constexpr int kSetupChunk = 4;
 
+// Makes the device of a context current for the duration of one library call
+// (and restores the caller's device), so that contexts on different devices
+// can be driven from one thread.
+struct DeviceScope {
+  int prev = -1;
+  explicit DeviceScope(const Context* c) {
+    if (!c) return;
+    int cur = 0;
+    MGM_HIP(hipGetDevice(&cur));
+    if (cur != c->device) {
+      MGM_HIP(hipSetDevice(c->device));
+      prev = cur;
+    }
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+  DeviceScope(const DeviceScope&) = delete;
+  DeviceScope& operator=(const DeviceScope&) = delete;
+};
+
 struct Hier {
   Context* ctx = nullptr;
   FineOp* fine = nullptr;

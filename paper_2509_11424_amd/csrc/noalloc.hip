@@ -63,6 +63,7 @@ extern "C" mgm_status mgm_operator_apply_dot_noalloc(mgm_operator op, mgm_prec p
               "mgm_operator_apply_dot_noalloc needs " + std::to_string(need_bytes) +
                   " bytes of reduction scratch for this lattice and nrhs; the fixed array holds " +
                   std::to_string(kNoAllocScratchBytes) + " (use mgm_operator_apply_dot with a workspace)");
+    DeviceScope on(op->ctx);
     double2* part = (double2*)noalloc_scratch(op->ctx->device);
     Scratch sc;
     sc.partial = part + part_entries;

@@ -5,6 +5,7 @@
 // independent function of (seed, stream, probe, index), so any probe range can
 // be drawn in any batch and reproduced bit for bit.
 #include "probe.h"
+#include "devonce.h"
 
 namespace mgm {
 
@@ -254,13 +255,11 @@ static void host_gammas(double out[6][4][4][2]) {
 }
 
 void loop_gamma(Context* c, const LoopArgs& A, int64_t Vs, int T, int nrhs, double2* partial, double2* out) {
-  static bool ready = false;
-  if (!ready) {
+  once_per_device([] {
     double g[6][4][4][2];
     host_gammas(g);
     MGM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gamma), g, sizeof(g)));
-    ready = true;
-  }
+  });
   MGM_CHECK(A.nvec <= kMaxLoopVecs && nrhs <= 256, MGM_ERR_INVALID_ARG, "loop_gamma: bad arguments");
   hipLaunchKernelGGL(k_loop_gamma, dim3(kSliceChunks, T), dim3(256), 0, c->stream, A, Vs, T, nrhs, partial);
   int n = A.nvec * 6 * nrhs * T;
