@@ -8,6 +8,8 @@ its rhs into tiles of 32) and the fine Galerkin product runs in four column
 chunks; the second Galerkin product stages 128-dof rows.
 wide: 8^4, aggregates 2^4 twice, N_tv 8 then 40: the second coarse level has
 80 dof (five MFMA tiles) and its Galerkin product runs in two column chunks.
+The refinement of 64 test vectors (block products and CholeskyQR of 64
+columns) runs on 4^4.
 
 Bars as for the smaller hierarchies: aggregation maps bit-exact; P and D_c
 within 1e-10; transfers within 1e-10 (FP64) and 1e-5 (FP32 with FP16 P,
@@ -180,3 +182,36 @@ def test_orthogonal_trace_per_probe(deep, wide, which):
         got = res["samples"][q][:, 0, 0]
         assert np.all(np.abs(got - w) <= 1e-8 * (np.abs(w) + sc)), (which, q, got, w)
     assert res["stats"]["max_rel_residual"] <= 1e-12
+
+
+def test_refined_64_test_vectors():
+    """Refinement of 64 test vectors (three inverse block-power steps with
+    Rayleigh-Ritz on Gamma5 D, as in tests/test_gpu_refine.py for 8) on a 4^4
+    clover lattice with 2^4 aggregates (96 rows per block): eigen-residuals
+    within 1e-8 relative, the rebuilt P and D_c within 1e-9, and per-probe
+    orthogonal tr(D^-1) terms within 1e-8 of |a| + |b|."""
+    import paper_2509_11424_amd as m
+    from oracle.dirac import WilsonClover
+    from oracle.multigrid import Hierarchy
+    from oracle.solve import level_solver
+    from oracle import estimators as E
+    ctx = m.Context(0)
+    U = gauge_field((4, 4, 4, 4), 0.5, 12)
+    op = m.Operator(ctx, U, 0.05, 1.0)
+    h = m.Hierarchy(op, [(2, 2, 2, 2)], [64], seed=104, max_nrhs=16, restart=20, mixed=2)
+    st = h.refine(max_iters=3, eig_tol=0.0, power_tol=1e-12, batch=16, solve=m.solve_desc(tol=1e-12))
+    assert st["steps"] == 3 and st["converged"]
+    D = WilsonClover(U, 0.05, 1.0)
+    Dinv = np.linalg.inv(D.dense())
+    oh = Hierarchy(D, [(2, 2, 2, 2)], [64], seed=104, refine=(lambda b: Dinv @ b, 3, 0.0))
+    np.testing.assert_allclose(st["rho"], oh.refine_rho, rtol=1e-8)
+    assert rel(h.export(0, "P"), oh.transfers[0].P) < 1e-9
+    assert rel(h.export(0, "coarse"), oh.ops[1].blocks) < 1e-9
+    solvers = [level_solver(o) for o in oh.ops]
+    res = h.estimate("trace", "orthogonal", [3, 3], seed=31, batch=3, solve=m.solve_desc(tol=1e-12))
+    want = [E.O_samples(oh, solvers, 0, 31, 3), E.F_samples(oh, solvers, 0, 31, 3),
+            E.coarsest_samples(oh, solvers, 31, 3)]
+    sc = np.abs(E.plain_samples(oh, solvers, 31, 1)[0])
+    for q in range(3):
+        got = res["samples"][q][:, 0, 0]
+        assert np.all(np.abs(got - want[q]) <= 1e-8 * (np.abs(want[q]) + sc)), q
