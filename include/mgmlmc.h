@@ -237,7 +237,7 @@ mgm_status mgm_draw_noise(mgm_context ctx, int32_t kind, uint64_t seed, uint32_t
 typedef struct {
   int32_t nlevels;                    /* 2..MGM_MAX_LEVELS */
   int32_t block[MGM_MAX_LEVELS - 1][4];
-  int32_t ntv[MGM_MAX_LEVELS - 1];    /* test vectors per transfer, 1..64 (coarse dof 2 ntv) */
+  int32_t ntv[MGM_MAX_LEVELS - 1];    /* test vectors per transfer, 1..128 (coarse dof 2 ntv) */
   int32_t setup_steps;                /* default 20 */
   int32_t setup_mr;                   /* default 4 */
   uint64_t seed;                      /* test-vector probes (kind 7) */

@@ -399,8 +399,8 @@ static void check_hdesc(mgm_operator op, const mgm_hierarchy_desc* d) {
   int dims[4] = {op->op.g.X, op->op.g.Y, op->op.g.Z, op->op.g.T};
   int dof = 12;
   for (int l = 0; l + 1 < d->nlevels; l++) {
-    MGM_CHECK(d->ntv[l] >= 1 && d->ntv[l] <= 64, MGM_ERR_INVALID_ARG, "ntv must be 1..64");
-    MGM_CHECK(2 * d->ntv[l] <= 128 && dof <= 128, MGM_ERR_SHAPE, "coarse dof must be <= 128");
+    MGM_CHECK(d->ntv[l] >= 1 && d->ntv[l] <= 128, MGM_ERR_INVALID_ARG, "ntv must be 1..128");
+    MGM_CHECK(2 * d->ntv[l] <= 256 && dof <= 256, MGM_ERR_SHAPE, "coarse dof must be <= 256");
     for (int m = 0; m < 4; m++) {
       int b = d->block[l][m];
       MGM_CHECK(b >= 1 && dims[m] % b == 0 && dims[m] / b >= 2, MGM_ERR_SHAPE,

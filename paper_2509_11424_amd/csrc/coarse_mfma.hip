@@ -285,7 +285,30 @@ __global__ __launch_bounds__(MAXT) void k_coarse_mfma_bf16(const float2* __restr
     case 6: { constexpr int MTc = 6; __VA_ARGS__; } break; \
     case 7: { constexpr int MTc = 7; __VA_ARGS__; } break; \
     case 8: { constexpr int MTc = 8; __VA_ARGS__; } break; \
-    default: throw Error(MGM_ERR_SHAPE, "coarse dof must be <= 128"); \
+    case 9: { constexpr int MTc = 9; __VA_ARGS__; } break; \
+    case 10: { constexpr int MTc = 10; __VA_ARGS__; } break; \
+    case 11: { constexpr int MTc = 11; __VA_ARGS__; } break; \
+    case 12: { constexpr int MTc = 12; __VA_ARGS__; } break; \
+    case 13: { constexpr int MTc = 13; __VA_ARGS__; } break; \
+    case 14: { constexpr int MTc = 14; __VA_ARGS__; } break; \
+    case 15: { constexpr int MTc = 15; __VA_ARGS__; } break; \
+    case 16: { constexpr int MTc = 16; __VA_ARGS__; } break; \
+    default: throw Error(MGM_ERR_SHAPE, "coarse dof must be <= 256"); \
+  }
+
+// the 512-thread shapes and two tiles per wave exist up to eight row tiles
+// (their registers)
+#define MT_DISPATCH8(MTV, ...)                      \
+  switch (MTV) {                                    \
+    case 1: { constexpr int MTc = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int MTc = 2; __VA_ARGS__; } break; \
+    case 3: { constexpr int MTc = 3; __VA_ARGS__; } break; \
+    case 4: { constexpr int MTc = 4; __VA_ARGS__; } break; \
+    case 5: { constexpr int MTc = 5; __VA_ARGS__; } break; \
+    case 6: { constexpr int MTc = 6; __VA_ARGS__; } break; \
+    case 7: { constexpr int MTc = 7; __VA_ARGS__; } break; \
+    case 8: { constexpr int MTc = 8; __VA_ARGS__; } break; \
+    default: throw Error(MGM_ERR_INVALID_ARG, "coarse shape not built for more than eight row tiles"); \
   }
 
 // Waves (16-rhs tiles) per workgroup of at most 256 threads: 4 by default
@@ -304,7 +327,7 @@ static int wpb_count(int ntr) { return ntr >= 4 ? 3 : ntr >= 2 ? 2 : 1; }
 // FP64 / FP32 shapes: the wpb_of candidates, then (5 to 8 tiles) every tile
 // of a site in one workgroup of up to 512 threads, so that the site's A
 // fragments are read from HBM once and shared through the CU's cache
-static int shapes4_count(int ntr) { return wpb_count(ntr) + (ntr > 4 && ntr <= 8 ? 1 : 0); }
+static int shapes4_count(int ntr, int mt) { return wpb_count(ntr) + (ntr > 4 && ntr <= 8 && mt <= 8 ? 1 : 0); }
 static int wpb4_of(int ntr, int v) { return v < wpb_count(ntr) ? wpb_of(ntr, v) : ntr; }
 
 void coarse_apply_mfma64(const CoarseOp& A, const double2* x, double2* y, int nrhs) {
@@ -312,13 +335,13 @@ void coarse_apply_mfma64(const CoarseOp& A, const double2* x, double2* y, int nr
   const int ntr = (nrhs + 15) / 16;
   ProfScope ps(A.ctx, KC_COARSE_F64, A.bytes(MGM_PREC_F64, nrhs));
   A.ctx->choose("coarse64/" + std::to_string(A.g.V) + "/" + std::to_string(A.d) + "/" + std::to_string(nrhs),
-                shapes4_count(ntr), [&](int v) {
-                  MGM_CHECK(v >= 0 && v < shapes4_count(ntr), MGM_ERR_INVALID_ARG,
+                shapes4_count(ntr, m.MT), [&](int v) {
+                  MGM_CHECK(v >= 0 && v < shapes4_count(ntr, m.MT), MGM_ERR_INVALID_ARG,
                             "coarse launch variant out of range");
                   const int wpb = wpb4_of(ntr, v);
                   const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + wpb - 1) / wpb)), tb(64 * wpb);
                   if (wpb > 4) {
-                    MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M64, MTc, 512>), nb, tb, 0, A.ctx->stream,
+                    MT_DISPATCH8(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M64, MTc, 512>), nb, tb, 0, A.ctx->stream,
                                                          x, y, A.Ap64, A.g, A.d, m.KC64, nrhs, ntr, wpb));
                   } else {
                     MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M64, MTc>), nb, tb, 0, A.ctx->stream, x,
@@ -333,13 +356,13 @@ void coarse_apply_mfma32(const CoarseOp& A, const float2* x, float2* y, int nrhs
   const int ntr = (nrhs + 15) / 16;
   ProfScope ps(A.ctx, KC_COARSE_F32, A.bytes(MGM_PREC_F32, nrhs));
   A.ctx->choose("coarse32/" + std::to_string(A.g.V) + "/" + std::to_string(A.d) + "/" + std::to_string(nrhs),
-                shapes4_count(ntr), [&](int v) {
-                  MGM_CHECK(v >= 0 && v < shapes4_count(ntr), MGM_ERR_INVALID_ARG,
+                shapes4_count(ntr, m.MT), [&](int v) {
+                  MGM_CHECK(v >= 0 && v < shapes4_count(ntr, m.MT), MGM_ERR_INVALID_ARG,
                             "coarse launch variant out of range");
                   const int wpb = wpb4_of(ntr, v);
                   const dim3 nb((unsigned)A.g.V, (unsigned)((ntr + wpb - 1) / wpb)), tb(64 * wpb);
                   if (wpb > 4) {
-                    MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M32, MTc, 512>), nb, tb, 0, A.ctx->stream,
+                    MT_DISPATCH8(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M32, MTc, 512>), nb, tb, 0, A.ctx->stream,
                                                          x, y, A.A32, A.g, A.d, m.KC64, nrhs, ntr, wpb));
                   } else {
                     MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma4<M32, MTc>), nb, tb, 0, A.ctx->stream, x,
@@ -378,12 +401,12 @@ void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs) 
   };
   std::vector<Shape> shapes;
   for (int v = 0; v < wpb_count(ntr); v++) shapes.push_back({wpb_of(ntr, v), 1});
-  if (ntr >= 2) shapes.push_back({1, 2});
-  if (ntr >= 4) shapes.push_back({2, 2});
+  if (ntr >= 2 && m.MT <= 8) shapes.push_back({1, 2});
+  if (ntr >= 4 && m.MT <= 8) shapes.push_back({2, 2});
   if (ntr >= 4 && m.MT <= 3) shapes.push_back({1, 4});
   if (ntr >= 8 && m.MT <= 3) shapes.push_back({2, 4});
   const size_t n_small = shapes.size();
-  if (ntr > 4 && ntr <= 8) shapes.push_back({ntr, 1});
+  if (ntr > 4 && ntr <= 8 && m.MT <= 8) shapes.push_back({ntr, 1});
   if (ntr > 4 && ntr <= 16 && m.MT <= 4) shapes.push_back({(ntr + 1) / 2, 2});
   A.ctx->choose("coarsebf16/" + std::to_string(A.g.V) + "/" + std::to_string(A.d) + "/" + std::to_string(nrhs),
                 (int)shapes.size(), [&](int v) {
@@ -395,7 +418,7 @@ void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs) 
                   if ((size_t)v >= n_small) {
                     // workgroups of up to 512 threads
                     if (tpw == 1) {
-                      MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma_bf16<MTc, 1, 512>), nb, tb, 0,
+                      MT_DISPATCH8(m.MT, hipLaunchKernelGGL((k_coarse_mfma_bf16<MTc, 1, 512>), nb, tb, 0,
                                                            A.ctx->stream, x, y, (const uint16_t*)A.Abf, A.g, A.d,
                                                            nrhs, ntr, wpb));
                     } else {
@@ -414,7 +437,7 @@ void coarse_apply_mfma(const CoarseOp& A, const float2* x, float2* y, int nrhs) 
                     MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma_bf16<MTc, 1>), nb, tb, 0, A.ctx->stream, x,
                                                          y, (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb));
                   } else if (tpw == 2) {
-                    MT_DISPATCH(m.MT, hipLaunchKernelGGL((k_coarse_mfma_bf16<MTc, 2>), nb, tb, 0, A.ctx->stream, x,
+                    MT_DISPATCH8(m.MT, hipLaunchKernelGGL((k_coarse_mfma_bf16<MTc, 2>), nb, tb, 0, A.ctx->stream, x,
                                                          y, (const uint16_t*)A.Abf, A.g, A.d, nrhs, ntr, wpb));
                   } else {
                     switch (m.MT) {

@@ -140,11 +140,21 @@ inline int prolong_chunk_rows(const TGeom& t, int rt, int cbytes, int TI) {
 inline size_t prolong_lds(const TGeom& t, int rt, int rc, int cbytes) {
   return sites_bytes(t.bvol) + ((size_t)t.ntv * round4(rt) + (size_t)rc * t.ntv) * cbytes;
 }
-// rhs per prolongation workgroup: kTransferRT, halved when the coarse values
-// of a full tile would take more than half of the 64 KiB LDS (FP64 with more
-// than 32 test vectors)
+// rhs per prolongation workgroup: kTransferRT, halved while the coarse
+// values of a full tile would take more than half of the 64 KiB LDS (FP64
+// with more than 32 test vectors, FP32 with more than 64)
 inline int prolong_rt(const TGeom& t, int cbytes) {
-  return (size_t)t.ntv * kTransferRT * cbytes > 32768 ? kTransferRT / 2 : kTransferRT;
+  int rt = kTransferRT;
+  while (rt > 4 && (size_t)t.ntv * rt * cbytes > 32768) rt /= 2;
+  return rt;
+}
+// rhs per restriction workgroup: kTransferRT, halved while the 4 x 4 output
+// tiles of (test vectors) x (rhs) outnumber the workgroup's threads (more
+// than 64 test vectors)
+inline int restrict_rt(const TGeom& t) {
+  int rt = kTransferRT;
+  while (rt > 4 && (round4(t.ntv) / 4) * (rt / 4) > kTransferTB) rt /= 2;
+  return rt;
 }
 
 // fine sites of aggregate a, in local (lexicographic) order, into LDS
@@ -237,13 +247,13 @@ __device__ __forceinline__ void lds_ld4(const cx<R>* p, cx<R> (&v)[4]) {
 template <class P, class PM, class PX = P>
 __global__ __launch_bounds__(256) void k_restrict(const typename PX::S* __restrict__ x, typename P::S* __restrict__ yc,
                                                   const typename PM::S* __restrict__ Pm, TGeom t, int nrhs, int rc,
-                                                  const double* __restrict__ xs) {
+                                                  int rtile, const double* __restrict__ xs) {
   using R = typename P::R;
   extern __shared__ __align__(16) char smem[];
   const int64_t a = blockIdx.x >> 1;
   const int chi = blockIdx.x & 1;
-  const int r0 = blockIdx.y * kTransferRT;
-  const int rt = nrhs - r0 < kTransferRT ? nrhs - r0 : kTransferRT;
+  const int r0 = blockIdx.y * rtile;
+  const int rt = nrhs - r0 < rtile ? nrhs - r0 : rtile;
   const int K = t.ntv, half = t.half, rows = t.rows;
   const int Kp = round4(K), rtp = round4(rt), ntr = rtp >> 2;
   const int T = (Kp >> 2) * ntr, G = kTransferTB / T;
@@ -419,18 +429,18 @@ double Transfer::bytes(mgm_prec p, int nrhs) const {
 
 void Transfer::restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const {
   ProfScope ps(ctx, KC_TRANSFER, bytes(p, nrhs));
-  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(kTransferTB);
-  const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
-  MGM_CHECK(t.ntv <= 64 && t.bvol <= 1024, MGM_ERR_SHAPE,
-            "transfers support at most 64 test vectors and 1024 sites per aggregate");
+  MGM_CHECK(t.ntv <= 128 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 128 test vectors and 1024 sites per aggregate");
+  const int tile = restrict_rt(t), rt = nrhs < tile ? nrhs : tile;
+  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + tile - 1) / tile)), tb(kTransferTB);
   if (p == MGM_PREC_F64) {
     const int rc = restrict_chunk_rows(t, rt, 16);
     hipLaunchKernelGGL((k_restrict<F64, F64>), nb, tb, restrict_lds(t, rt, rc, 16), ctx->stream,
-                       (const double2*)x, (double2*)yc, P64, t, nrhs, rc, nullptr);
+                       (const double2*)x, (double2*)yc, P64, t, nrhs, rc, tile, nullptr);
   } else if (p == MGM_PREC_F32) {
     const int rc = restrict_chunk_rows(t, rt, 8);
     hipLaunchKernelGGL((k_restrict<F32, F16>), nb, tb, restrict_lds(t, rt, rc, 8), ctx->stream,
-                       (const float2*)x, (float2*)yc, P16, t, nrhs, rc, nullptr);
+                       (const float2*)x, (float2*)yc, P16, t, nrhs, rc, tile, nullptr);
   } else {
     throw Error(MGM_ERR_INVALID_ARG, "restrict: precision must be F64 or F32");
   }
@@ -439,8 +449,8 @@ void Transfer::restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const {
 
 void Transfer::prolong(mgm_prec p, const void* xc, const void* x, void* y, int nrhs, int mode) const {
   ProfScope ps(ctx, KC_TRANSFER, bytes(p, nrhs));
-  MGM_CHECK(t.ntv <= 64 && t.bvol <= 1024, MGM_ERR_SHAPE,
-            "transfers support at most 64 test vectors and 1024 sites per aggregate");
+  MGM_CHECK(t.ntv <= 128 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 128 test vectors and 1024 sites per aggregate");
   if (p == MGM_PREC_F64) {
     const int tile = prolong_rt(t, 16), rt = nrhs < tile ? nrhs : tile;
     const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + tile - 1) / tile)), tb(kTransferTB);
@@ -463,14 +473,14 @@ void Transfer::prolong(mgm_prec p, const void* xc, const void* x, void* y, int n
 
 void Transfer::restrict16(const __half2* x16, const double* xs, float2* yc, int nrhs) const {
   ProfScope ps(ctx, KC_TRANSFER, bytes(MGM_PREC_F32, nrhs));
-  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + kTransferRT - 1) / kTransferRT)), tb(kTransferTB);
-  const int rt = nrhs < kTransferRT ? nrhs : kTransferRT;
-  MGM_CHECK(t.ntv <= 64 && t.bvol <= 1024, MGM_ERR_SHAPE,
-            "transfers support at most 64 test vectors and 1024 sites per aggregate");
+  MGM_CHECK(t.ntv <= 128 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 128 test vectors and 1024 sites per aggregate");
   MGM_CHECK(P16 != nullptr && xs != nullptr, MGM_ERR_INVALID_ARG, "FP16 transfer input needs P16 and scales");
+  const int tile = restrict_rt(t), rt = nrhs < tile ? nrhs : tile;
+  const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + tile - 1) / tile)), tb(kTransferTB);
   const int rc = restrict_chunk_rows(t, rt, 8);
   hipLaunchKernelGGL((k_restrict<F32, F16, F16>), nb, tb, restrict_lds(t, rt, rc, 8), ctx->stream, x16, yc, P16, t,
-                     nrhs, rc, xs);
+                     nrhs, rc, tile, xs);
   MGM_LAUNCH_CHECK();
 }
 
@@ -478,8 +488,8 @@ void Transfer::prolong16(const float2* xc, const __half2* x16, const double* xs,
   ProfScope ps(ctx, KC_TRANSFER, bytes(MGM_PREC_F32, nrhs));
   const int tile = prolong_rt(t, 8), rt = nrhs < tile ? nrhs : tile;
   const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + tile - 1) / tile)), tb(kTransferTB);
-  MGM_CHECK(t.ntv <= 64 && t.bvol <= 1024, MGM_ERR_SHAPE,
-            "transfers support at most 64 test vectors and 1024 sites per aggregate");
+  MGM_CHECK(t.ntv <= 128 && t.bvol <= 1024, MGM_ERR_SHAPE,
+            "transfers support at most 128 test vectors and 1024 sites per aggregate");
   MGM_CHECK(P16 != nullptr && xs != nullptr, MGM_ERR_INVALID_ARG, "FP16 transfer input needs P16 and scales");
   const int rc = prolong_chunk_rows(t, rt, 8, 2);
   hipLaunchKernelGGL((k_prolong<F32, F16, 2, F16>), nb, tb, prolong_lds(t, rt, rc, 8), ctx->stream, xc,
@@ -793,7 +803,7 @@ static int galerkin_jc(int d, int rows_staged) {
 void mg_galerkin_fine(Context* c, const FineOp& op, const Transfer& T, CoarseOp& out) {
   const TGeom& t = T.t;
   const int d = 2 * t.ntv;
-  MGM_CHECK(d <= 128, MGM_ERR_SHAPE, "too many test vectors");
+  MGM_CHECK(d <= 256, MGM_ERR_SHAPE, "too many test vectors");
   const int jc = galerkin_jc(d, 12);
   const size_t sh = (size_t)12 * (jc + t.ntv) * sizeof(double2);
   hipLaunchKernelGGL(k_galerkin_fine, dim3((unsigned)t.c.V, 9, (unsigned)((d + jc - 1) / jc)), dim3(256), sh,
@@ -804,7 +814,7 @@ void mg_galerkin_fine(Context* c, const FineOp& op, const Transfer& T, CoarseOp&
 void mg_galerkin_coarse(Context* c, const CoarseOp& op, const Transfer& T, CoarseOp& out) {
   const TGeom& t = T.t;
   const int d = 2 * t.ntv;
-  MGM_CHECK(d <= 128 && t.f.dof <= 128, MGM_ERR_SHAPE, "too many test vectors");
+  MGM_CHECK(d <= 256 && t.f.dof <= 256, MGM_ERR_SHAPE, "too many test vectors");
   const int jc = galerkin_jc(d, t.f.dof);
   const size_t sh = (size_t)t.f.dof * jc * sizeof(double2);
   hipLaunchKernelGGL(k_galerkin_coarse, dim3((unsigned)t.c.V, 9, (unsigned)((d + jc - 1) / jc)), dim3(256), sh,

@@ -1,5 +1,5 @@
 """Hierarchies with more test vectors (Sec. 5: N_tv beyond the 24-32 of the
-production settings), against the FP64 oracle.
+production settings, up to 64 and 128), against the FP64 oracle.
 
 deep: 4 x 4 x 4 x 8 clover lattice, aggregates 2^4 then (1, 1, 1, 2),
 N_tv 64 then 8: the first coarse level has 128 dof per site (eight 16-row
@@ -9,7 +9,7 @@ chunks; the second Galerkin product stages 128-dof rows.
 wide: 8^4, aggregates 2^4 twice, N_tv 8 then 40: the second coarse level has
 80 dof (five MFMA tiles) and its Galerkin product runs in two column chunks.
 The refinement of 64 test vectors (block products and CholeskyQR of 64
-columns) runs on 4^4.
+columns) runs on 4^4.  widest: 128 test vectors, a 256-dof coarse level.
 
 Bars as for the smaller hierarchies: aggregation maps bit-exact; P and D_c
 within 1e-10; transfers within 1e-10 (FP64) and 1e-5 (FP32 with FP16 P,
@@ -215,3 +215,94 @@ def test_refined_64_test_vectors():
     for q in range(3):
         got = res["samples"][q][:, 0, 0]
         assert np.all(np.abs(got - want[q]) <= 1e-8 * (np.abs(want[q]) + sc)), q
+
+
+@pytest.fixture(scope="module")
+def widest():
+    """128 test vectors on 4 x 4 x 4 x 8 with aggregates of 2 x 2 x 2 x 4 sites
+    (192 rows per block): a 16-site coarse level of 256 dof (sixteen MFMA row
+    tiles), restrictions in rhs tiles of 32, FP64 prolongations in tiles of 16,
+    Galerkin products in sixteen column chunks."""
+    return _Pair((4, 4, 4, 8), 0.5, 68, 0.1, [(2, 2, 2, 4)], [128], 69, max_nrhs=40)
+
+
+def test_128_vectors_P_coarse_and_transfers(widest):
+    import torch
+    from oracle.multigrid import Transfer
+    p = widest
+    assert p.h.level_info(1)[1] == 256
+    assert np.array_equal(p.h.export(0, "agg_map"), p.oh.transfers[0].agg.block_index())
+    assert rel(p.h.export(0, "P"), p.oh.transfers[0].P) < 1e-10
+    assert rel(p.h.export(0, "coarse"), p.oh.ops[1].blocks) < 1e-10
+    tr = p.oh.transfers[0]
+    s, d, _ = p.h.level_info(0)
+    cs, cd, _ = p.h.level_info(1)
+    for nrhs in (1, 37):
+        x = _rand(s, d, nrhs, 800 + nrhs)
+        xc = _rand(cs, cd, nrhs, 900 + nrhs)
+        xf, xcf = x.reshape(nrhs, -1), xc.reshape(nrhs, -1)
+        assert rel(from_gpu(p.h.restrict(0, to_gpu(x))).reshape(nrhs, -1), tr.restrict(xf)) < 1e-10, nrhs
+        assert rel(from_gpu(p.h.prolong(0, to_gpu(xc))).reshape(nrhs, -1), tr.prolong(xcf)) < 1e-10, nrhs
+        assert rel(from_gpu(p.h.project_out(0, to_gpu(x))).reshape(nrhs, -1), tr.project_out(xf)) < 1e-10, nrhs
+        re = tr.P.real.astype(np.float32).astype(np.float16).astype(np.float64)
+        im = tr.P.imag.astype(np.float32).astype(np.float16).astype(np.float64)
+        t16 = Transfer(tr.agg, re + 1j * im)
+        x32, xc32 = x.astype(np.complex64), xc.astype(np.complex64)
+        yc = p.h.restrict(0, to_gpu(x32).to(torch.complex64), prec="f32")
+        y = p.h.prolong(0, to_gpu(xc32).to(torch.complex64), prec="f32")
+        assert rel(from_gpu(yc).reshape(nrhs, -1), t16.restrict(x32.astype(np.complex128).reshape(nrhs, -1))) < 1e-5
+        assert rel(from_gpu(y).reshape(nrhs, -1), t16.prolong(xc32.astype(np.complex128).reshape(nrhs, -1))) < 1e-5
+
+
+def test_128_vectors_coarse_stencil(widest):
+    """256-dof blocks: FP64 within 1e-10 of the oracle stencil, FP32 within
+    2e-6, BF16 within 5e-5 of the BF16-rounded stencil, at 21 and 37 rhs."""
+    import torch
+    p = widest
+    op = p.oh.ops[1]
+    B, nbr = op.stencil()
+    d, V = op.d, op.V
+    g = np.where(np.arange(d) < d // 2, 1.0, -1.0)
+    Bf = _bf16(B[:, :5].real) + 1j * _bf16(B[:, :5].imag)
+    blocks = np.concatenate([Bf] + [
+        (g[None, :, None] * np.conj(np.transpose(Bf[nbr[5 + mu], 1 + mu], (0, 2, 1))) * g[None, None, :])[:, None]
+        for mu in range(4)], axis=1)
+    for nrhs in (21, 37):
+        x = _rand(V, d, nrhs, 700 + nrhs)
+        got = p.h.apply_prec(1, to_gpu(x), "f64")
+        assert rel(from_gpu(got).reshape(nrhs, -1), op.matvec(x.reshape(nrhs, -1))) < 1e-10
+        x32 = x.astype(np.complex64)
+        got = p.h.apply_prec(1, to_gpu(x32), "f32")
+        want = op.matvec(x32.astype(np.complex128).reshape(nrhs, -1))
+        assert rel(from_gpu(got).astype(np.complex128).reshape(nrhs, -1), want) < 2e-6
+        xr = _bf16(x32.real) + 1j * _bf16(x32.imag)
+        want = np.zeros((nrhs, V, d), dtype=np.complex128)
+        for k in range(9):
+            want += np.einsum("sij,nsj->nsi", blocks[:, k], xr[:, nbr[k], :])
+        got = p.h.apply_prec(1, to_gpu(x32), "bf16")
+        assert got.dtype == torch.complex64
+        assert rel(from_gpu(got).astype(np.complex128).reshape(nrhs, -1), want.reshape(nrhs, -1)) < 5e-5
+
+
+def test_128_vectors_solves_and_trace(widest):
+    import torch
+    import paper_2509_11424_amd as m
+    from oracle import estimators as E
+    p = widest
+    for l in range(2):
+        s, d, _ = p.h.level_info(l)
+        b = _rand(s, d, 3, 90 + l)
+        torch.cuda.synchronize()
+        x, st = p.h.solve(l, to_gpu(b), m.solve_desc(tol=1e-12, kind="mg_mixed", maxiter=4000))
+        torch.cuda.synchronize()
+        assert st["max_rel_residual"] <= 1e-12, l
+        want = np.stack([p.solvers[l](bb) for bb in b.reshape(3, -1)])
+        assert rel(from_gpu(x).reshape(3, -1), want) < 1e-9, l
+    seed, N = 77, 2
+    res = p.h.estimate("trace", "orthogonal", [N, N], seed=seed, batch=2, solve=m.solve_desc(tol=1e-12))
+    want = [E.O_samples(p.oh, p.solvers, 0, seed, N), E.F_samples(p.oh, p.solvers, 0, seed, N),
+            E.coarsest_samples(p.oh, p.solvers, seed, N)]
+    sc = np.abs(E.plain_samples(p.oh, p.solvers, seed, 1)[0])
+    for q, w in enumerate(want):
+        got = res["samples"][q][:, 0, 0]
+        assert np.all(np.abs(got - w) <= 1e-8 * (np.abs(w) + sc)), (q, got, w)
