@@ -306,3 +306,51 @@ def test_128_vectors_solves_and_trace(widest):
     for q, w in enumerate(want):
         got = res["samples"][q][:, 0, 0]
         assert np.all(np.abs(got - w) <= 1e-8 * (np.abs(w) + sc)), (q, got, w)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f32", "f64"])
+def test_128_vectors_every_coarse_launch_shape(widest, prec):
+    """Every launch shape the autotuner may pick for the 256-dof stencil at
+    100 rhs (seven 16-rhs tiles): one, two or four waves per workgroup, one
+    tile per wave (the wider shapes stop at eight row tiles)."""
+    import torch
+    p = widest
+    op = p.oh.ops[1]
+    B, nbr = op.stencil()
+    d, V, nrhs = op.d, op.V, 100
+    x = _rand(V, d, nrhs, 950)
+    if prec != "f64":
+        x = x.astype(np.complex64)
+    if prec == "bf16":
+        g = np.where(np.arange(d) < d // 2, 1.0, -1.0)
+        Bf = _bf16(B[:, :5].real) + 1j * _bf16(B[:, :5].imag)
+        blocks = np.concatenate([Bf] + [
+            (g[None, :, None] * np.conj(np.transpose(Bf[nbr[5 + mu], 1 + mu], (0, 2, 1))) * g[None, None, :])[:, None]
+            for mu in range(4)], axis=1)
+        xr = _bf16(x.real) + 1j * _bf16(x.imag)
+        want = np.zeros((nrhs, V, d), dtype=np.complex128)
+        for k in range(9):
+            want += np.einsum("sij,nsj->nsi", blocks[:, k], xr[:, nbr[k], :])
+        want = want.reshape(nrhs, -1)
+    else:
+        want = op.matvec(x.astype(np.complex128).reshape(nrhs, -1))
+    bar = {"bf16": 5e-5, "f32": 2e-6, "f64": 1e-10}[prec]
+    tag = {"bf16": "coarsebf16", "f32": "coarse32", "f64": "coarse64"}[prec]
+    key = "%s/%d/%d/%d" % (tag, V, d, nrhs)
+    xg = to_gpu(x)
+    p.ctx.autotune(True)
+    try:
+        p.h.apply_prec(1, xg, prec)
+    finally:
+        p.ctx.autotune(False)
+    torch.cuda.synchronize()
+    rep = p.ctx.tune_report()
+    assert key in rep, (key, list(rep))
+    nvar = len(rep[key][1])
+    assert nvar == 3, (key, nvar)
+    for v in range(nvar):
+        p.ctx.tune_set(key, v)
+        got = p.h.apply_prec(1, xg, prec)
+        torch.cuda.synchronize()
+        assert rel(from_gpu(got).astype(np.complex128).reshape(nrhs, -1), want) < bar, (key, v)
+    p.ctx.tune_set(key, 0)
