@@ -678,6 +678,116 @@ def hierarchy_study(args):
             torch.cuda.empty_cache()
 
 
+def _cpu_mlmc_worker(args_conn):
+    """One forked worker of the host MG-MLMC run: its share of the probes of
+    every orthogonal term, solved by the oracle (single-threaded BLAS)."""
+    (oh, seed, ranges, conn) = args_conn
+    from threadpoolctl import threadpool_limits
+    from oracle import estimators as E
+    from oracle.solve import level_solver
+    with threadpool_limits(1):
+        t0 = time.time()
+        solvers = [level_solver(o, tol=1e-10) for o in oh.ops]
+        out = {"O": E.O_samples(oh, solvers, 0, seed, ranges[0][1], first=ranges[0][0]).tolist(),
+               "F": E.F_samples(oh, solvers, 0, seed, ranges[1][1], first=ranges[1][0]).tolist(),
+               "C": E.coarsest_samples(oh, solvers, seed, ranges[2][1], first=ranges[2][0]).tolist()}
+        out["seconds"] = time.time() - t0
+    conn.send(json.dumps({k: ([[v.real, v.imag] for v in val] if isinstance(val, list) else val)
+                          for k, val in out.items()}))
+    conn.close()
+
+
+def cpu_study(args):
+    """The FP64 oracle on the host cores at the small workloads (no GPU): per
+    workload one Wilson(-clover) application and one GMRES(50) solve of a Z4
+    right-hand side to a true relative residual of 1e-10, single-threaded;
+    and the whole two-level orthogonal MG-MLMC tr(D^-1) estimate on 8^4 at
+    50 / 200 probes (hierarchy single-threaded, the probes split over forked
+    single-threaded workers).  One JSON line per measurement."""
+    import numpy as np
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from lattice_inputs import gauge_field
+    from oracle.dirac import WilsonClover
+    from oracle.solve import gmres
+    from oracle.philox import z4_vector
+    from oracle.multigrid import Hierarchy
+    ncpu = os.cpu_count() or 1
+    workers = max(1, min(CPU_WORKERS_MAX, ncpu))
+    cases = [("4^4 Wilson (m0 0.2)", (4, 4, 4, 4), 0.3, 11, 0.2, 0.0),
+             ("8^4 Wilson-clover (m0 0.05, roughness 0.5)", (8, 8, 8, 8), 0.5, 12, 0.05, 1.0),
+             ("16^4 Wilson-clover (m0 0.01, roughness 0.6)", (16, 16, 16, 16), 0.6, 13, 0.01, 1.0)]
+    for name, dims, eps, gseed, m0, csw in cases:
+        with threadpool_limits(1):
+            U = gauge_field(dims, eps, gseed)
+            t0 = time.time()
+            D = WilsonClover(U, m0, csw)
+            t_build = time.time() - t0
+            x = np.random.default_rng(0).standard_normal(D.n) + 0j
+            t0 = time.time()
+            D.matvec(x)
+            t_apply = time.time() - t0
+            cnt = [0]
+
+            def mv(v):
+                cnt[0] += 1
+                return D.matvec(v)
+
+            b = z4_vector(D.n, 7, 0, 0)
+            t0 = time.time()
+            xs = gmres(mv, b, tol=1e-10, restart=50)
+            t_solve = time.time() - t0
+            res = float(np.linalg.norm(b - D.matvec(xs)) / np.linalg.norm(b))
+        print(json.dumps({"cpu_study": "apply_and_solve", "workload": name, "sites": int(np.prod(dims)),
+                          "cores": 1, "build_s": t_build, "apply_s": t_apply,
+                          "apply_GBps": 1536.0 * np.prod(dims) / t_apply / 1e9,
+                          "solve_s": t_solve, "applications": cnt[0], "rel_residual": res}), flush=True)
+    # whole 8^4 two-level orthogonal estimate (50 / 200 probes)
+    cfg = CONFIGS["c2"]
+    with threadpool_limits(1):
+        U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])
+        t_all = time.time()
+        D = WilsonClover(U, cfg["m0"], cfg["csw"])
+        t0 = time.time()
+        oh = Hierarchy(D, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000)
+        t_setup = time.time() - t0
+    n0, n1 = cfg["nprobe"]
+
+    def split(n, w):
+        base, extra = divmod(n, w)
+        out, first = [], 0
+        for i in range(w):
+            k = base + (1 if i < extra else 0)
+            out.append((first, k))
+            first += k
+        return out
+
+    so, sf, sc = split(n0, workers), split(n0, workers), split(n1, workers)
+    ctxm = mp.get_context("fork")
+    pipes, procs = [], []
+    t0 = time.time()
+    for w in range(workers):
+        a, bconn = ctxm.Pipe(duplex=False)
+        pr = ctxm.Process(target=_cpu_mlmc_worker, args=((oh, cfg["pseed"], (so[w], sf[w], sc[w]), bconn),))
+        pr.start()
+        pipes.append(a)
+        procs.append(pr)
+    parts = [json.loads(pp.recv()) for pp in pipes]
+    for pr in procs:
+        pr.join()
+    t_probes = time.time() - t0
+    samples = {k: np.array([complex(*v) for p_ in parts for v in p_[k]]) for k in ("O", "F", "C")}
+    var = {k: float(np.sum(np.abs(v - v.mean()) ** 2) / (len(v) - 1)) for k, v in samples.items()}
+    total = sum(complex(v.mean()) for v in samples.values())
+    total_var = sum(var[k] / len(samples[k]) for k in samples)
+    print(json.dumps({"cpu_study": "mlmc_8x8x8x8", "workload": cfg["name"], "cores": workers,
+                      "setup_s_single_thread": t_setup, "probes_s_wall": t_probes,
+                      "worker_seconds_sum": sum(p_["seconds"] for p_ in parts),
+                      "total_s": time.time() - t_all, "rhs_solved": n0 + 2 * n0 + n1,
+                      "tr_Dinv": [total.real, total.imag], "var_of_mean": total_var, "term_var": var}),
+          flush=True)
+
+
 def per_level_rates(m, ctx, h, cfg, sd, batch, torch):
     """RHS solved per second on each level alone: one batch of the level's
     size of Z4 right-hand sides solved to 1e-10 with the timed form's
@@ -971,6 +1081,8 @@ def main():
     ap.add_argument("--cpu", type=int, default=1)
     ap.add_argument("--ttt", type=int, default=1, help="time to target variance, FP64 against the mixed form")
     ap.add_argument("--learned", action="store_true", help="also measure the learned-preconditioner form")
+    ap.add_argument("--cpu-study", action="store_true",
+                    help="the FP64 oracle on the host cores at the small workloads (no GPU)")
     ap.add_argument("--hierarchy-study", action="store_true",
                     help="per-term variance against setup cost for N_tv 64 and refined test vectors")
     ap.add_argument("--observables", action="store_true",
@@ -996,6 +1108,8 @@ def main():
         observables(args)
     elif args.hierarchy_study:
         hierarchy_study(args)
+    elif args.cpu_study:
+        cpu_study(args)
     else:
         run(args)
 
