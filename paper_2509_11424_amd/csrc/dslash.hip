@@ -1300,7 +1300,8 @@ struct MarchShape {
 };
 static const MarchShape kMarchShapes[] = {
     {4, 16, 8}, {4, 8, 8},  {8, 16, 4},  {8, 8, 4}, {16, 16, 2}, {16, 8, 2}, {8, 8, 2},
-    {4, 8, 4},  {4, 8, 2},  {16, 16, 1}, {16, 8, 1}, {8, 8, 1},  {4, 8, 1},  {2, 8, 8}};
+    {4, 8, 4},  {4, 8, 2},  {16, 16, 1}, {16, 8, 1}, {8, 8, 1},  {4, 8, 1},  {2, 8, 8},
+    {4, 32, 8}, {8, 32, 4}, {4, 32, 4}, {16, 32, 2}};
 
 static size_t march_lds(const Geom& g, mgm_prec p, const MarchShape& m, bool dot) {
   size_t b = (size_t)2 * 12 * (m.ty + 2) * g.X * m.nbr * prec_bytes(p);  // two plane buffers
