@@ -966,12 +966,6 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
     const double d = wqq[r];
     if (d > 0.0) om = {(R)(wqr[r].x / d), (R)(wqr[r].y / d)};
   }
-  // x += omega r at one element of this block's own planes (r as loaded)
-  auto x_update = [&](uint32_t vo, uint32_t so, S rv) {
-    cx<R> xv = IO::cvt(IO::raw(rx, vo, so));
-    fma_(xv, om, IO::cvt(rv));
-    IO::st(rx, vo, so, xv);
-  };
   auto stage_halo = [&](int zz, S* buf) {
     // the per-thread dof offset goes into the lane offset, the per-j one
     // into the uniform offset
@@ -1026,7 +1020,6 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
     for (int k = 0; k < 12; k++) {
       const S rv = IO::raw(rin, (s0 * nrhs + r) * IO::SB, (uint32_t)k * spb);
       pl[lidx(k, yl + 1, col)] = rv;
-      if (MR) x_update((s0 * nrhs + r) * IO::SB, (uint32_t)k * spb, rv);
     }
     stage_halo(z0, pl);
   }
@@ -1102,15 +1095,21 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
     if (i + 1 < zs) {
       const uint32_t vn = (((uint32_t)zp * sz + (uint32_t)t * st + rowoff) * nrhs + r) * IO::SB;
 #pragma unroll
-      for (int k = 0; k < 12; k++) {
-        nxt[lidx(k, yl + 1, col)] = nx[k];
-        if (MR) x_update(vn, (uint32_t)k * spb, nx[k]);
-      }
+      for (int k = 0; k < 12; k++) nxt[lidx(k, yl + 1, col)] = nx[k];
       stage_halo(zp, nxt);
     }
     // backward z hop of this plane (into the next one's accumulator), then
     // the store; the fused dots take the values of q rounded to the storage
-    // type
+    // type.  In the smoother step x += omega r for this plane goes with the
+    // store: its x loads are issued before the hop, so the hop's arithmetic
+    // covers their latency (updating x when the plane is staged exposes the
+    // whole load latency before the barrier).
+    S xr[12];
+    if (MR) {
+      const uint32_t vx = (s * nrhs + r) * IO::SB;
+#pragma unroll
+      for (int k = 0; k < 12; k++) xr[k] = IO::raw(rx, vx, (uint32_t)k * spb);
+    }
     {
       cx<R> gg[2][3];
       {
@@ -1126,13 +1125,16 @@ __global__ __launch_bounds__(MAXT) void k_dslash_march(typename P::S* __restrict
       for (int k = 0; k < 12; k++) {
         const cx<R> pvk = IO::cvt(cur[lidx(k, yl + 1, col)]);  // centre, re-read from LDS
         if (MR) {
-          // r - omega q (x + omega r was done when the plane was loaded)
+          // r - omega q, and x + omega r
           cx<R> rn = pvk;
           rn.re = fmar(-om.re, acc[k].re, rn.re);
           rn.re = fmar(om.im, acc[k].im, rn.re);
           rn.im = fmar(-om.re, acc[k].im, rn.im);
           rn.im = fmar(-om.im, acc[k].re, rn.im);
           IO::st(rout, vo, (uint32_t)k * spb, rn);
+          cx<R> xv = IO::cvt(xr[k]);
+          fma_(xv, om, pvk);
+          IO::st(rx, vo, (uint32_t)k * spb, xv);
         } else {
           IO::st(rout, vo, (uint32_t)k * spb, acc[k]);
         }
