@@ -422,9 +422,10 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     pin_keys = {kc: {n: "%s/%d/%d/%d" % (TUNE_PREFIX[kc], m.api.PREC["f16"], op.V, n)
                      for n in rhs_counts(traffic_record(kc))} for kc in TUNE_PREFIX}
     if mixed:
-        # the smoother kernels keep the launch shapes their HBM counters were
-        # recorded with (the fastest measured); everything else is tuned
-        for kc, keys in pin_keys.items():
+        # on the workload the HBM counters were recorded on, the smoother
+        # kernels keep the launch shapes of the record (the fastest measured);
+        # everything else is tuned
+        for kc, keys in (pin_keys.items() if args.config == "c4" else ()):
             rec = traffic_record(kc)
             for n, key in keys.items():
                 if "variant_nrhs%d" % n in rec:
@@ -457,7 +458,9 @@ def _run_gpu(args, cfg, U, t_gauge, cpu_pid, cpu_out, m, torch):
     ds = max(("dslash_f64", "dslash_f32", "dslash_f16", "dslash_step"), key=lambda k: prof[k]["ms"])
     q = prof[ds]
     rep = ctx.tune_report()
-    variants = {n: rep[k][0] for n, k in pin_keys.get(ds, {}).items() if k in rep}
+    # launch variants the dominant class ran with, per rhs count (pinned or tuned)
+    pref = "%s/%d/%d/" % (TUNE_PREFIX.get(ds, ""), m.api.PREC["f16"], op.V)
+    variants = {int(k[len(pref):]): v[0] for k, v in rep.items() if ds in TUNE_PREFIX and k.startswith(pref)}
     avg_ms = q["ms"] / max(q["launches"], 1)
     bytes_launch = q["bytes"] / max(q["launches"], 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if q["launches"] else 0.0
