@@ -13,9 +13,12 @@ mgm_context_tune_set and checked
   FP64: 1e-6 of ||y|| ||x||).
 
 Lattices: 8x16x8x4 (one z-run covering the whole z extent, so the first plane's
-backward neighbour wraps) and 16x4x16x6 (two z-runs, T not a multiple of four).
-The last test runs the bench's launch configuration, 32^3 x 64 at eight FP16
-right-hand sides, against the FP64 dslash.
+backward neighbour wraps), 16x4x16x6 (two z-runs, T not a multiple of four)
+and 8x8x32x4 (the 32-plane runs, one per time slice and tile).  The last
+tests run the bench's launch configuration, 32^3 x 64: the reducing dslash at
+eight FP16 right-hand sides against the FP64 dslash, and every launch variant
+of the fused smoother step at 16 and 4 right-hand sides against its
+definition and the oracle's stencil at sampled sites.
 """
 import numpy as np
 import pytest
@@ -47,7 +50,8 @@ class Lat:
 
 @pytest.fixture(scope="module")
 def lats(ctx):
-    return {"8x16x8x4": Lat(ctx, (8, 16, 8, 4), 41), "16x4x16x6": Lat(ctx, (16, 4, 16, 6), 42)}
+    return {"8x16x8x4": Lat(ctx, (8, 16, 8, 4), 41), "16x4x16x6": Lat(ctx, (16, 4, 16, 6), 42),
+            "8x8x32x4": Lat(ctx, (8, 8, 32, 4), 44)}
 
 
 def _inputs(lat, prec, nrhs, seed):
@@ -90,7 +94,7 @@ def _close_to_site_parallel(y, y0, prec):
         assert np.all(np.abs(a - b) <= 2.0 ** -10 * np.abs(b) + 2.0 ** -24 + 1e-7 * np.abs(b).max())
 
 
-@pytest.mark.parametrize("lname", ["8x16x8x4", "16x4x16x6"])
+@pytest.mark.parametrize("lname", ["8x16x8x4", "16x4x16x6", "8x8x32x4"])
 @pytest.mark.parametrize("prec", ["f32", "f16"])
 @pytest.mark.parametrize("nrhs", [1, 4, 8])
 def test_march_shapes_apply(ctx, lats, lname, prec, nrhs):
@@ -117,7 +121,7 @@ def test_march_shapes_apply(ctx, lats, lname, prec, nrhs):
     assert n_march >= 1  # every case here has at least one plane-marching shape
 
 
-@pytest.mark.parametrize("lname", ["8x16x8x4", "16x4x16x6"])
+@pytest.mark.parametrize("lname", ["8x16x8x4", "16x4x16x6", "8x8x32x4"])
 @pytest.mark.parametrize("prec,nrhs", [("f16", 8), ("f16", 4), ("f32", 4), ("f16", 1)])
 def test_march_shapes_fused_reductions(ctx, lats, lname, prec, nrhs):
     import torch
@@ -148,15 +152,21 @@ def test_march_shapes_fused_reductions(ctx, lats, lname, prec, nrhs):
     ctx.tune_set(key, 0)
 
 
-def test_march_full_size_f16_eight_rhs(ctx):
-    """32^3 x 64 at eight FP16 right-hand sides (the fused smoother's launch in
-    the bench): every shape against the FP64 dslash of the same rounded input
-    and against variant 0, and its dots against torch's sums."""
+@pytest.fixture(scope="module")
+def full(ctx):
+    """The bench's fine lattice, 32^3 x 64 (roughness 0.6, m0 0.02, c_sw 1)."""
+    import paper_2509_11424_amd as m
+    U = gauge_field((32, 32, 32, 64), 0.6, 14)
+    return U, m.Operator(ctx, U, 0.02, 1.0)
+
+
+def test_march_full_size_f16_eight_rhs(ctx, full):
+    """32^3 x 64 at eight FP16 right-hand sides: every shape of the reducing
+    dslash against the FP64 dslash of the same rounded input and against
+    variant 0, and its dots against torch's sums."""
     import torch
     import paper_2509_11424_amd as m
-    dims = (32, 32, 32, 64)
-    U = gauge_field(dims, 0.6, 14)
-    op = m.Operator(ctx, U, 0.02, 1.0)
+    U, op = full
     V, nrhs = op.V, 8
     g = torch.Generator(device="cuda:0").manual_seed(3)
     x = torch.randn((12, V, nrhs, 2), generator=g, device="cuda:0").to(torch.float16)
@@ -198,12 +208,12 @@ def test_march_full_size_f16_eight_rhs(ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("lname", ["8x16x8x4", "16x4x16x6"])
+@pytest.mark.parametrize("lname", ["8x16x8x4", "16x4x16x6", "8x8x32x4"])
 @pytest.mark.parametrize("nrhs", [16, 4])
 def test_fused_smoother_step(ctx, lats, lname, nrhs):
-    """mgm_operator_smoother_step in both arithmetic forms (the launch
-    variants are the marching shapes with FP32 arithmetic on converted
-    values, then the same shapes with packed FP16 arithmetic).
+    """mgm_operator_smoother_step in every launch variant: the marching
+    shapes with FP32 arithmetic on converted values, then the same shapes
+    with packed FP16 arithmetic.
 
     FP32 form against its definition built from the reducing dslash: q = D r,
     r' = r - omega q, x' = x + omega r with omega = qr / qq of the previous
@@ -247,37 +257,39 @@ def test_fused_smoother_step(ctx, lats, lname, nrhs):
     qo = lat.D.matvec(rr)
     omn = om.cpu().numpy()
     out = {}
-    for v, packed in ((0, False), (ns, True)):
+    for v in range(nvar):
+        packed = v >= ns
         ctx.tune_set(key, v)
         x = x0.clone()
         rn, yx, yy = op.smoother_step(r, x, qr, qq)
         torch.cuda.synchronize()
-        out[packed] = (rn, yx, yy)
-        assert torch.all((c(x) - want_x).abs() <= 2.0 ** -10 * want_x.abs() + 2.0 ** -14 + 1e-6), packed
-        assert torch.equal(rn[:, :, 0], r[:, :, 0]) and torch.equal(x[:, :, 0], x0[:, :, 0])
+        out[v] = (rn, yx, yy)
+        assert torch.all((c(x) - want_x).abs() <= 2.0 ** -10 * want_x.abs() + 2.0 ** -14 + 1e-6), v
+        assert torch.equal(rn[:, :, 0], r[:, :, 0]) and torch.equal(x[:, :, 0], x0[:, :, 0]), v
         if not packed:
             want_r = c(r) - om * c(q)
             slack = om.abs() * c(q).abs() * 2.0 ** -10
-            assert torch.all((c(rn) - want_r).abs() <= 2.0 ** -10 * want_r.abs() + slack + 2.0 ** -14 + 1e-6)
-            assert torch.all((yx - yx_ref).abs() <= 1e-4 * yy_ref.sqrt() * nr)
-            assert torch.all((yy - yy_ref).abs() <= 1e-4 * yy_ref)
+            assert torch.all((c(rn) - want_r).abs() <= 2.0 ** -10 * want_r.abs() + slack + 2.0 ** -14 + 1e-6), v
+            assert torch.all((yx - yx_ref).abs() <= 1e-4 * yy_ref.sqrt() * nr), v
+            assert torch.all((yy - yy_ref).abs() <= 1e-4 * yy_ref), v
         else:
-            rn32, yx32, yy32 = out[False]
+            rn32, yx32, yy32 = out[v - ns]
             d = (c(rn) - c(rn32)).abs().pow(2).sum(dim=(0, 1)).sqrt()
             nq = c(q).abs().pow(2).sum(dim=(0, 1)).sqrt()
             nrn = c(rn32).abs().pow(2).sum(dim=(0, 1)).sqrt()
-            assert torch.all(d <= 2.0 ** -10 * nrn + 2e-3 * om.abs() * nq + 1e-6)
-            assert torch.all((yx - yx32).abs() <= 2e-3 * yy32.sqrt() * nr)
-            assert torch.all((yy - yy32).abs() <= 4e-3 * yy32)
+            assert torch.all(d <= 2.0 ** -10 * nrn + 2e-3 * om.abs() * nq + 1e-6), v
+            assert torch.all((yx - yx32).abs() <= 2e-3 * yy32.sqrt() * nr), v
+            assert torch.all((yy - yy32).abs() <= 4e-3 * yy32), v
         rn_np = from_gpu(c(rn)).reshape(nrhs, -1)
         yxn, yyn = yx.cpu().numpy(), yy.cpu().numpy()
         for j in range(nrhs):
             want_rj = rr[j] - omn[j] * qo[j]
             nqj = np.linalg.norm(qo[j])
             assert np.linalg.norm(rn_np[j] - want_rj) <= 2.0 ** -10 * np.linalg.norm(want_rj) + \
-                abs(omn[j]) * 4e-3 * nqj, (packed, j)
-            assert abs(yxn[j] - np.vdot(qo[j], rr[j])) <= 4e-3 * nqj * np.linalg.norm(rr[j]), (packed, j)
-            assert abs(yyn[j] - nqj ** 2) <= 8e-3 * nqj ** 2, (packed, j)
+                abs(omn[j]) * 4e-3 * nqj, (v, j)
+            assert abs(yxn[j] - np.vdot(qo[j], rr[j])) <= 4e-3 * nqj * np.linalg.norm(rr[j]), (v, j)
+            assert abs(yyn[j] - nqj ** 2) <= 8e-3 * nqj ** 2, (v, j)
+    del out
     ctx.tune_set(key, 0)
 
 
@@ -291,3 +303,84 @@ def test_fused_smoother_step_refuses_lattice_without_tile(ctx):
     z = torch.zeros(4, dtype=torch.complex128, device="cuda:0")
     with pytest.raises(RuntimeError, match="SHAPE"):
         op.smoother_step(t, t.clone(), z, torch.ones(4, dtype=torch.float64, device="cuda:0"))
+
+
+@pytest.mark.parametrize("nrhs", [16, 4])
+def test_fused_smoother_step_full_size(ctx, full, nrhs):
+    """32^3 x 64 at the bench's fine-level batches (16, and 4 for the rest of
+    20 probes): every launch variant of the fused smoother step, among them
+    the 32-plane shapes the bench runs.
+
+    x' = x + omega r within one FP16 ulp of the update; FP32 forms: r' = r -
+    omega q per element against q from the reducing FP16 dslash (slack for
+    its rounding, as on the small lattices) and the dots within 1e-4; packed
+    forms: r' norm-wise and the dots within 2e-3 of the FP32 form of the same
+    shape; every variant: r' at 12 sampled sites and two rhs against r - omega
+    q with q from the oracle's stencil on the stored FP16 r (FP64), within the
+    FP16 operator's bound (4e-3 of |q|) plus one FP16 ulp of r'."""
+    import torch
+    import paper_2509_11424_amd as m
+    U, op = full
+    V = op.V
+    g = torch.Generator(device="cuda:0").manual_seed(190 + nrhs)
+    shape = (12, V, nrhs, 2)
+    r, x0 = (torch.randn(shape, generator=g, device="cuda:0").to(torch.float16) for _ in range(2))
+    qr = torch.complex(torch.randn(nrhs, generator=g, device="cuda:0", dtype=torch.float64),
+                       torch.randn(nrhs, generator=g, device="cuda:0", dtype=torch.float64)) * 0.05
+    qq = torch.rand(nrhs, generator=g, device="cuda:0", dtype=torch.float64) + 0.5
+    key = "dslash_step/%d/%d/%d" % (m.api.PREC["f16"], V, nrhs)
+    nvar = _variants(ctx, key, lambda: op.smoother_step(r, x0.clone(), qr, qq))
+    assert nvar % 2 == 0 and nvar >= 2
+    ns = nvar // 2
+    q, yx_ref, yy_ref = op.apply_dot(r, prec="f16")
+    torch.cuda.synchronize()
+
+    def c(t):
+        return torch.view_as_complex(t.float().contiguous())
+
+    def n2(t):  # per-rhs squared norms, summed in FP64
+        return t.abs().double().pow(2).sum(dim=(0, 1))
+
+    om = torch.where(qq > 0, qr / qq, torch.zeros_like(qr))
+    om32 = om.to(torch.complex64)
+    want_x = c(x0) + om32 * c(r)
+    nr, nq = n2(c(r)).sqrt(), n2(c(q)).sqrt()
+    # oracle q at sampled sites for the first two rhs
+    st = LocalStencil(U, 0.02, 1.0)
+    sites = np.random.default_rng(11).integers(0, V, 12)
+    rs = [c(r)[:, :, j].to(torch.complex128).cpu().numpy().T for j in range(2)]  # (V, 12)
+    qs = [[st.at(s_, rs[j]) for s_ in sites] for j in range(2)]
+    omn = om.cpu().numpy()
+    out = {}
+    for v in range(nvar):
+        packed = v >= ns
+        ctx.tune_set(key, v)
+        x = x0.clone()
+        rn, yx, yy = op.smoother_step(r, x, qr, qq)
+        torch.cuda.synchronize()
+        assert torch.all((c(x) - want_x).abs() <= 2.0 ** -10 * want_x.abs() + 2.0 ** -14 + 1e-6), v
+        del x
+        if not packed:
+            want_r = c(r) - om32 * c(q)
+            slack = om32.abs() * c(q).abs() * 2.0 ** -10
+            assert torch.all((c(rn) - want_r).abs() <= 2.0 ** -10 * want_r.abs() + slack + 2.0 ** -14 + 1e-6), v
+            del want_r, slack
+            assert torch.all((yx - yx_ref).abs() <= 1e-4 * yy_ref.sqrt() * nr), v
+            assert torch.all((yy - yy_ref).abs() <= 1e-4 * yy_ref), v
+            out[v] = (rn, yx, yy)
+        else:
+            rn32, yx32, yy32 = out.pop(v - ns)
+            d = n2(c(rn) - c(rn32)).sqrt()
+            assert torch.all(d <= 2.0 ** -10 * n2(c(rn32)).sqrt() + 2e-3 * om.abs() * nq + 1e-6), v
+            assert torch.all((yx - yx32).abs() <= 2e-3 * yy32.sqrt() * nr), v
+            assert torch.all((yy - yy32).abs() <= 4e-3 * yy32), v
+        for j in range(2):
+            rnj = c(rn)[:, :, j].to(torch.complex128).cpu().numpy().T
+            for k, s_ in enumerate(sites):
+                want = rs[j][s_] - omn[j] * qs[j][k]
+                assert np.linalg.norm(rnj[s_] - want) <= 2.0 ** -10 * np.linalg.norm(want) + \
+                    abs(omn[j]) * 4e-3 * np.linalg.norm(qs[j][k]) + 1e-6, (v, j, s_)
+    out.clear()
+    ctx.tune_set(key, 0)
+    del r, x0, q, want_x
+    torch.cuda.empty_cache()
