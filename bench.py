@@ -20,6 +20,7 @@ iteration count of a measured 16^4 solve).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4|c3|c2]
                   [--form mixed|f64] [--cpu 0|1] [--ttt 0|1] [--learned [--net-widths 4 8 8 4]]
+  python bench.py --solve-study --config c3 [--nrhs 12,32,64]   # fine-level RHS/s per form and batch
 
 Kernel micro-benchmarks (used for the profiler runs of single kernels):
 
@@ -791,6 +792,66 @@ def cpu_study(args):
           flush=True)
 
 
+def solve_study(args):
+    """RHS solved per second to 1e-10 on the fine level over batch size and
+    form: plain FP64 multigrid, the mixed form without captured coarse-grid
+    corrections and the mixed form with them (each with the settings the
+    time-to-target comparison uses for it; autotuned launch shapes in the
+    mixed forms), hierarchy setup timed apart.  One JSON line per (form,
+    batch) of Z4 right-hand sides: seconds of one solve after an untimed solve
+    of the same batch, iterations, and each right-hand side's true residual
+    |b - D x| / |b| recomputed with the FP64 operator; only the right-hand
+    sides at or below 1e-10 are counted in the rate."""
+    cfg = dict(CONFIGS[args.config])
+    from lattice_inputs import gauge_field
+    U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])
+    import torch
+    import paper_2509_11424_amd as m
+    sizes = [int(v) for v in args.nrhs.split(",")] if args.nrhs != "8" else [12, 32, 64]
+    stream = torch.cuda.Stream(device=0)
+    with torch.cuda.stream(stream):
+        ctx = m.Context(0)
+        op = m.Operator(ctx, U, cfg["m0"], cfg["csw"])
+        for mixed in (0, 1):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            h = m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=max(sizes),
+                            restart=cfg["restart"], mixed=mixed)
+            torch.cuda.synchronize()
+            setup = time.time() - t0
+            print(json.dumps({"study": "solve", "workload": cfg["name"], "form": "mixed" if mixed else "f64",
+                              "setup_s": setup, "hierarchy_workspace_gb": h.ws.numel() / 1e9}), flush=True)
+            forms = [("mixed", False), ("mixed+graphs", True)] if mixed else [("f64", False)]
+            for name, graphs in forms:
+                if mixed:
+                    sd = m.solve_desc(tol=1e-10, kind="mg_mixed", smooth=args.smooth, smooth_coarse=args.smooth_coarse,
+                                      coarse_iters=args.coarse_iters, inner_tol=args.inner_tol, maxiter=5000,
+                                      coarse_bf16=True, smoother_f16=True, graphs=graphs)
+                else:
+                    sd = m.solve_desc(tol=1e-10, kind="mg", smooth=6, smooth_coarse=2, coarse_iters=1, maxiter=5000)
+                ctx.autotune(bool(mixed))
+                for n in sizes:
+                    s_, d_, _ = h.level_info(0)
+                    b = m.draw_z4(ctx, cfg["pseed"] + 950, 0, 0, n, s_, d_, "f64")
+                    h.solve(0, b, sd)
+                    torch.cuda.synchronize()
+                    t0 = time.time()
+                    x, st = h.solve(0, b, sd)
+                    torch.cuda.synchronize()
+                    dt = time.time() - t0
+                    r = b - op.apply(x, prec="f64")
+                    rel_res = (r.abs().pow(2).sum(dim=(0, 1)) / b.abs().pow(2).sum(dim=(0, 1))).sqrt()
+                    ok = int((rel_res <= 1e-10).sum().item())
+                    print(json.dumps({"study": "solve", "form": name, "nrhs": n, "seconds": dt,
+                                      "rhs_per_s": ok / dt, "rhs_counted": ok, "iterations": st["iterations"],
+                                      "iterations_per_rhs": st["iterations"] / n,
+                                      "max_true_rel_residual": rel_res.max().item()}), flush=True)
+                    del b, x, r
+                ctx.autotune(False)
+            del h
+            torch.cuda.empty_cache()
+
+
 def per_level_rates(m, ctx, h, cfg, sd, batch, torch):
     """RHS solved per second on each level alone: one batch of the level's
     size of Z4 right-hand sides solved to 1e-10 with the timed form's
@@ -1092,6 +1153,8 @@ def main():
                     help="estimate C(t) three ways and the loops two ways with the timed form, one line each")
     ap.add_argument("--obs-probes", type=int, nargs="+", default=None,
                     help="observables: probes per group (default: the configuration's)")
+    ap.add_argument("--solve-study", action="store_true",
+                    help="RHS/s to 1e-10 on the fine level over batch size (--nrhs, default 12,32,64) and form")
     ap.add_argument("--micro", choices=["dslash", "dslash_dot", "step", "copy", "coarse"])
     ap.add_argument("--level", type=int, default=1, help="micro coarse: hierarchy level of the stencil")
     ap.add_argument("--tune", action="store_true", help="micro: autotune the launch shape first")
@@ -1113,6 +1176,8 @@ def main():
         hierarchy_study(args)
     elif args.cpu_study:
         cpu_study(args)
+    elif args.solve_study:
+        solve_study(args)
     else:
         run(args)
 
