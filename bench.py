@@ -807,7 +807,7 @@ def solve_study(args):
     U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])
     import torch
     import paper_2509_11424_amd as m
-    sizes = [int(v) for v in args.nrhs.split(",")] if args.nrhs != "8" else [12, 32, 64]
+    sizes = [int(v) for v in (args.nrhs or "12,32,64").split(",")]
     stream = torch.cuda.Stream(device=0)
     with torch.cuda.stream(stream):
         ctx = m.Context(0)
@@ -1160,7 +1160,7 @@ def main():
     ap.add_argument("--tune", action="store_true", help="micro: autotune the launch shape first")
     ap.add_argument("--variant", type=int, default=None, help="micro: pin this launch variant")
     ap.add_argument("--prec", default="f32", help="comma list of f64, f32, f16")
-    ap.add_argument("--nrhs", default="8", help="comma list of rhs counts")
+    ap.add_argument("--nrhs", default=None, help="comma list of rhs counts (micro: default 8)")
     ap.add_argument("--iters", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -1169,6 +1169,7 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.micro:
+        args.nrhs = args.nrhs or "8"
         micro(args)
     elif args.observables:
         observables(args)
