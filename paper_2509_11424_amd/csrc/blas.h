@@ -10,6 +10,11 @@ struct Vec {
   int dof = 0;
   int nrhs = 0;
   mgm_prec prec = MGM_PREC_F64;
+  // columns stored in groups of `group` right-hand sides, group-major
+  // ([nrhs / group][dof][site][group]); 0: the plain (dof, site, rhs) layout.
+  // Only the scaled conversions below read or write grouped vectors.
+  int group = 0;
+  int gs() const { return group > 0 ? group : nrhs; }
   int64_t n() const { return nsite * dof * nrhs; }
   size_t bytes() const { return (size_t)n() * prec_bytes(prec); }
   Vec with(void* q) const {
@@ -40,11 +45,14 @@ void b_copy(Context* c, Vec dst, Vec src);  // converting copy, same shape
 void b_axpy(Context* c, const double2* a, double sgn, Vec x, Vec y);
 // y = x + sgn * a[r] * y
 void b_xpay(Context* c, Vec x, const double2* a, double sgn, Vec y);
-// dst[e] = s[r] * src[e] (converting copy with a per-rhs real scale)
+// dst[e] = s[r] * src[e] (converting copy with a per-rhs real scale; either
+// side may be grouped)
 void b_copy_scaled(Context* c, Vec dst, Vec src, const double* s);
-// dst[e] = s[r] * (a[e] - b[e]) (converting, per-rhs real scale)
+// dst[e] = s[r] * (a[e] - b[e]) (converting, per-rhs real scale; dst may be
+// grouped)
 void b_sub_scaled(Context* c, Vec dst, Vec a, Vec b, const double* s);
-// dst[e] += s[r] * src[e] (converting, per-rhs real scale)
+// dst[e] += s[r] * src[e] (converting, per-rhs real scale; src may be
+// grouped)
 void b_add_scaled(Context* c, Vec dst, Vec src, const double* s);
 // s[r] = sqrt(target2 / n2[r]) and inv[r] = 1 / s[r] (both 0 where n2[r] = 0;
 // n2 == nullptr stands for n2[r] = 1)

@@ -3,6 +3,7 @@
 // deterministic: fixed per-thread element sets, a fixed-order LDS tree per
 // block and a fixed-order sum over block partials in a second kernel.
 #include "blas.h"
+#include "group.h"
 
 namespace mgm {
 
@@ -32,6 +33,23 @@ struct RhsIter {
   __device__ void next() {
     r += step;
     if (r >= nrhs) r -= nrhs;
+  }
+};
+
+// (row, rhs) of element i of a plain (row, rhs) block, advanced by a
+// fixed stride
+struct RowRhsIter {
+  int64_t row, step_row;
+  int r, step_r, nrhs;
+  __device__ RowRhsIter(int64_t i0, int64_t stride, int nr)
+      : row(i0 / nr), step_row(stride / nr), r((int)(i0 % nr)), step_r((int)(stride % nr)), nrhs(nr) {}
+  __device__ void next() {
+    row += step_row;
+    r += step_r;
+    if (r >= nrhs) {
+      r -= nrhs;
+      row++;
+    }
   }
 };
 
@@ -71,54 +89,85 @@ void b_copy(Context* c, Vec dst, Vec src) {
   MGM_LAUNCH_CHECK();
 }
 
+// The scaled conversions take the column-group size of each operand (gd for
+// the destination, gs for the source; nrhs for a plain operand).
 template <class PD, class PS>
-__global__ void k_copy_scaled(void* dst, const void* src, int64_t n, int nrhs, const double* s) {
+__global__ void k_copy_scaled(void* dst, const void* src, int64_t n, int nrhs, const double* s, int gd, int gs) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next()) std_<PD>(dst, i, s[it.r] * ldd<PS>(src, i));
+  if (gd == nrhs && gs == nrhs) {
+    for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next()) std_<PD>(dst, i, s[it.r] * ldd<PS>(src, i));
+    return;
+  }
+  const int64_t rows = n / nrhs;
+  for (RowRhsIter it(i, stride, nrhs); i < n; i += stride, it.next())
+    std_<PD>(dst, grouped_index(it.row, it.r, nrhs, gd, rows),
+             s[it.r] * ldd<PS>(src, grouped_index(it.row, it.r, nrhs, gs, rows)));
+}
+static void check_groups(const Vec& v) {
+  MGM_CHECK(v.group == 0 || (v.group > 0 && v.nrhs % v.group == 0), MGM_ERR_INVALID_ARG,
+            "column groups must divide the rhs count");
 }
 void b_copy_scaled(Context* c, Vec dst, Vec src, const double* s) {
   int64_t n = src.n();
   MGM_CHECK(dst.n() == n && dst.nrhs == src.nrhs, MGM_ERR_INVALID_ARG, "copy: shape mismatch");
+  check_groups(dst);
+  check_groups(src);
   if (n == 0) return;
   DISPATCH_PREC(dst.prec, PD, DISPATCH_PREC(src.prec, PS,
       hipLaunchKernelGGL((k_copy_scaled<PD, PS>), dim3(ew_blocks(n)), dim3(256), 0, c->stream, dst.p, src.p, n,
-                         src.nrhs, s)));
+                         src.nrhs, s, dst.gs(), src.gs())));
   MGM_LAUNCH_CHECK();
 }
 
 template <class PD, class PS>
-__global__ void k_sub_scaled(void* dst, const void* a, const void* b, int64_t n, int nrhs, const double* s) {
+__global__ void k_sub_scaled(void* dst, const void* a, const void* b, int64_t n, int nrhs, const double* s, int gd) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next())
-    std_<PD>(dst, i, s[it.r] * (ldd<PS>(a, i) - ldd<PS>(b, i)));
+  if (gd == nrhs) {
+    for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next())
+      std_<PD>(dst, i, s[it.r] * (ldd<PS>(a, i) - ldd<PS>(b, i)));
+    return;
+  }
+  const int64_t rows = n / nrhs;
+  for (RowRhsIter it(i, stride, nrhs); i < n; i += stride, it.next())
+    std_<PD>(dst, grouped_index(it.row, it.r, nrhs, gd, rows), s[it.r] * (ldd<PS>(a, i) - ldd<PS>(b, i)));
 }
 void b_sub_scaled(Context* c, Vec dst, Vec a, Vec b, const double* s) {
   int64_t n = a.n();
   MGM_CHECK(dst.n() == n && b.n() == n && dst.nrhs == a.nrhs && b.prec == a.prec, MGM_ERR_INVALID_ARG,
             "sub: shape mismatch");
+  MGM_CHECK(a.group == 0 && b.group == 0, MGM_ERR_INVALID_ARG, "sub: grouped operands");
+  check_groups(dst);
   if (n == 0) return;
   DISPATCH_PREC(dst.prec, PD, DISPATCH_PREC(a.prec, PS,
       hipLaunchKernelGGL((k_sub_scaled<PD, PS>), dim3(ew_blocks(n)), dim3(256), 0, c->stream, dst.p, a.p, b.p,
-                         n, a.nrhs, s)));
+                         n, a.nrhs, s, dst.gs())));
   MGM_LAUNCH_CHECK();
 }
 
 template <class PD, class PS>
-__global__ void k_add_scaled(void* dst, const void* src, int64_t n, int nrhs, const double* s) {
+__global__ void k_add_scaled(void* dst, const void* src, int64_t n, int nrhs, const double* s, int gs) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next())
-    std_<PD>(dst, i, ldd<PD>(dst, i) + s[it.r] * ldd<PS>(src, i));
+  if (gs == nrhs) {
+    for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next())
+      std_<PD>(dst, i, ldd<PD>(dst, i) + s[it.r] * ldd<PS>(src, i));
+    return;
+  }
+  const int64_t rows = n / nrhs;
+  for (RowRhsIter it(i, stride, nrhs); i < n; i += stride, it.next())
+    std_<PD>(dst, i, ldd<PD>(dst, i) + s[it.r] * ldd<PS>(src, grouped_index(it.row, it.r, nrhs, gs, rows)));
 }
 void b_add_scaled(Context* c, Vec dst, Vec src, const double* s) {
   int64_t n = src.n();
   MGM_CHECK(dst.n() == n && dst.nrhs == src.nrhs, MGM_ERR_INVALID_ARG, "add: shape mismatch");
+  MGM_CHECK(dst.group == 0, MGM_ERR_INVALID_ARG, "add: grouped destination");
+  check_groups(src);
   if (n == 0) return;
   DISPATCH_PREC(dst.prec, PD, DISPATCH_PREC(src.prec, PS,
       hipLaunchKernelGGL((k_add_scaled<PD, PS>), dim3(ew_blocks(n)), dim3(256), 0, c->stream, dst.p, src.p, n,
-                         src.nrhs, s)));
+                         src.nrhs, s, src.gs())));
   MGM_LAUNCH_CHECK();
 }
 

@@ -32,8 +32,9 @@ struct Transfer {
   void prolong(mgm_prec p, const void* xc, const void* x, void* y, int nrhs, int mode) const;
   // FP32 transfers whose fine input is FP16 scaled per rhs by xs:
   // y_c = P^H (xs x16) and y = xs x16 + P x_c
-  void restrict16(const __half2* x16, const double* xs, float2* yc, int nrhs) const;
-  void prolong16(const float2* xc, const __half2* x16, const double* xs, float2* y, int nrhs) const;
+  // x16 in column groups of xgs right-hand sides (0: plain layout)
+  void restrict16(const __half2* x16, const double* xs, float2* yc, int nrhs, int xgs = 0) const;
+  void prolong16(const float2* xc, const __half2* x16, const double* xs, float2* y, int nrhs, int xgs = 0) const;
   double bytes(mgm_prec p, int nrhs) const;
 };
 

@@ -5,6 +5,7 @@
 
 #include <type_traits>
 #include "fine_dev.h"
+#include "group.h"
 
 namespace mgm {
 
@@ -243,11 +244,12 @@ __device__ __forceinline__ void lds_ld4(const cx<R>* p, cx<R> (&v)[4]) {
 // Thread (g, u) accumulates the output tile u = (k/4, r/4) over the rows
 // g, g + G, ... of every chunk; the G partial tiles are then summed in group
 // order through LDS.
-// The input x may be stored in another format PX, scaled per rhs by xs.
+// The input x may be stored in another format PX, scaled per rhs by xs, and
+// in column groups of xgs right-hand sides (xgs = nrhs: plain layout).
 template <class P, class PM, class PX = P>
 __global__ __launch_bounds__(256) void k_restrict(const typename PX::S* __restrict__ x, typename P::S* __restrict__ yc,
                                                   const typename PM::S* __restrict__ Pm, TGeom t, int nrhs, int rc,
-                                                  int rtile, const double* __restrict__ xs) {
+                                                  int rtile, const double* __restrict__ xs, int xgs) {
   using R = typename P::R;
   extern __shared__ __align__(16) char smem[];
   const int64_t a = blockIdx.x >> 1;
@@ -281,7 +283,8 @@ __global__ __launch_bounds__(256) void k_restrict(const typename PX::S* __restri
       cx<R> v = {0, 0};
       if (r < rt) {
         const int row = row0 + ii, loc = row / half, j = row - loc * half;
-        const cx<typename PX::R> u = PX::ld(x, ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + r);
+        const cx<typename PX::R> u =
+            PX::ld(x, grouped_index((int64_t)(chi * half + j) * Vf + sS[loc], r0 + r, nrhs, xgs, 2 * half * Vf));
         v = {(R)u.re, (R)u.im};
         if (xs) v = (R)xs[r0 + r] * v;
       }
@@ -324,7 +327,8 @@ __global__ __launch_bounds__(256) void k_restrict(const typename PX::S* __restri
 }
 
 // y = P x_c (mode 0), x - P x_c (mode 1), y + P x_c (mode 2), or
-// xs * x + P x_c (mode 3, x stored as PX and scaled per rhs by xs)
+// xs * x + P x_c (mode 3, x stored as PX, scaled per rhs by xs and in column
+// groups of xgs right-hand sides)
 // P rows of a chunk sit transposed in LDS; thread u = (q, r/4) owns rows
 // q, q + Q, ..., q + (TI-1) Q of the chunk (Q = rc / TI) by four right-hand
 // sides, and loads the destination entries it updates before its products.
@@ -332,7 +336,8 @@ template <class P, class PM, int TI, class PX = P>
 __global__ __launch_bounds__(256) void k_prolong(const typename P::S* __restrict__ xc, const typename P::S* __restrict__ x,
                                                  typename P::S* __restrict__ y, const typename PM::S* __restrict__ Pm,
                                                  TGeom t, int nrhs, int mode, int rc, int rtile,
-                                                 const typename PX::S* __restrict__ xq, const double* __restrict__ xs) {
+                                                 const typename PX::S* __restrict__ xq, const double* __restrict__ xs,
+                                                 int xgs) {
   using R = typename P::R;
   extern __shared__ __align__(16) char smem[];
   const int64_t a = blockIdx.x >> 1;
@@ -364,22 +369,25 @@ __global__ __launch_bounds__(256) void k_prolong(const typename P::S* __restrict
     for (int uo = tid; uo < NT; uo += kTransferTB) {
       const int q = uo / ntr, rtt = uo - q * ntr;
       if (q >= nr) continue;
-      int64_t base[TI];
+      int64_t base[TI], frow[TI];
       cx<R> acc[TI][4];
 #pragma unroll
       for (int i = 0; i < TI; i++) {
         const int ii = q + Q * i;
         base[i] = -1;
+        frow[i] = 0;
         if (ii < nr) {
           const int row = row0 + ii, loc = row / half, j = row - loc * half;
-          base[i] = ((int64_t)(chi * half + j) * Vf + sS[loc]) * nrhs + r0 + 4 * rtt;
+          frow[i] = (int64_t)(chi * half + j) * Vf + sS[loc];
+          base[i] = frow[i] * nrhs + r0 + 4 * rtt;
         }
 #pragma unroll
         for (int rr = 0; rr < 4; rr++) {
           acc[i][rr] = {0, 0};
           if (mode != 0 && base[i] >= 0 && 4 * rtt + rr < rt) {
             if (mode == 3) {
-              const cx<typename PX::R> u = PX::ld(xq, base[i] + rr);
+              const cx<typename PX::R> u =
+                  PX::ld(xq, grouped_index(frow[i], r0 + 4 * rtt + rr, nrhs, xgs, 2 * half * Vf));
               acc[i][rr] = (R)xs[r0 + 4 * rtt + rr] * cx<R>{(R)u.re, (R)u.im};
             } else {
               acc[i][rr] = P::ld(src, base[i] + rr);
@@ -436,11 +444,11 @@ void Transfer::restrict_(mgm_prec p, const void* x, void* yc, int nrhs) const {
   if (p == MGM_PREC_F64) {
     const int rc = restrict_chunk_rows(t, rt, 16);
     hipLaunchKernelGGL((k_restrict<F64, F64>), nb, tb, restrict_lds(t, rt, rc, 16), ctx->stream,
-                       (const double2*)x, (double2*)yc, P64, t, nrhs, rc, tile, nullptr);
+                       (const double2*)x, (double2*)yc, P64, t, nrhs, rc, tile, nullptr, nrhs);
   } else if (p == MGM_PREC_F32) {
     const int rc = restrict_chunk_rows(t, rt, 8);
     hipLaunchKernelGGL((k_restrict<F32, F16>), nb, tb, restrict_lds(t, rt, rc, 8), ctx->stream,
-                       (const float2*)x, (float2*)yc, P16, t, nrhs, rc, tile, nullptr);
+                       (const float2*)x, (float2*)yc, P16, t, nrhs, rc, tile, nullptr, nrhs);
   } else {
     throw Error(MGM_ERR_INVALID_ARG, "restrict: precision must be F64 or F32");
   }
@@ -457,43 +465,48 @@ void Transfer::prolong(mgm_prec p, const void* xc, const void* x, void* y, int n
     const int rc = prolong_chunk_rows(t, rt, 16, 1);
     hipLaunchKernelGGL((k_prolong<F64, F64, 1>), nb, tb, prolong_lds(t, rt, rc, 16), ctx->stream,
                        (const double2*)xc, (const double2*)x, (double2*)y, P64, t, nrhs, mode, rc, tile, nullptr,
-                       nullptr);
+                       nullptr, nrhs);
   } else if (p == MGM_PREC_F32) {
     const int tile = prolong_rt(t, 8), rt = nrhs < tile ? nrhs : tile;
     const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + tile - 1) / tile)), tb(kTransferTB);
     const int rc = prolong_chunk_rows(t, rt, 8, 2);
     hipLaunchKernelGGL((k_prolong<F32, F16, 2>), nb, tb, prolong_lds(t, rt, rc, 8), ctx->stream,
                        (const float2*)xc, (const float2*)x, (float2*)y, P16, t, nrhs, mode, rc, tile, nullptr,
-                       nullptr);
+                       nullptr, nrhs);
   } else {
     throw Error(MGM_ERR_INVALID_ARG, "prolong: precision must be F64 or F32");
   }
   MGM_LAUNCH_CHECK();
 }
 
-void Transfer::restrict16(const __half2* x16, const double* xs, float2* yc, int nrhs) const {
+void Transfer::restrict16(const __half2* x16, const double* xs, float2* yc, int nrhs, int xgs) const {
   ProfScope ps(ctx, KC_TRANSFER, bytes(MGM_PREC_F32, nrhs));
   MGM_CHECK(t.ntv <= 128 && t.bvol <= 1024, MGM_ERR_SHAPE,
             "transfers support at most 128 test vectors and 1024 sites per aggregate");
   MGM_CHECK(P16 != nullptr && xs != nullptr, MGM_ERR_INVALID_ARG, "FP16 transfer input needs P16 and scales");
+  if (xgs <= 0) xgs = nrhs;
+  MGM_CHECK(nrhs % xgs == 0, MGM_ERR_INVALID_ARG, "column groups must divide the rhs count");
   const int tile = restrict_rt(t), rt = nrhs < tile ? nrhs : tile;
   const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + tile - 1) / tile)), tb(kTransferTB);
   const int rc = restrict_chunk_rows(t, rt, 8);
   hipLaunchKernelGGL((k_restrict<F32, F16, F16>), nb, tb, restrict_lds(t, rt, rc, 8), ctx->stream, x16, yc, P16, t,
-                     nrhs, rc, tile, xs);
+                     nrhs, rc, tile, xs, xgs);
   MGM_LAUNCH_CHECK();
 }
 
-void Transfer::prolong16(const float2* xc, const __half2* x16, const double* xs, float2* y, int nrhs) const {
+void Transfer::prolong16(const float2* xc, const __half2* x16, const double* xs, float2* y, int nrhs,
+                         int xgs) const {
   ProfScope ps(ctx, KC_TRANSFER, bytes(MGM_PREC_F32, nrhs));
   const int tile = prolong_rt(t, 8), rt = nrhs < tile ? nrhs : tile;
   const dim3 nb((unsigned)(2 * t.c.V), (unsigned)((nrhs + tile - 1) / tile)), tb(kTransferTB);
   MGM_CHECK(t.ntv <= 128 && t.bvol <= 1024, MGM_ERR_SHAPE,
             "transfers support at most 128 test vectors and 1024 sites per aggregate");
   MGM_CHECK(P16 != nullptr && xs != nullptr, MGM_ERR_INVALID_ARG, "FP16 transfer input needs P16 and scales");
+  if (xgs <= 0) xgs = nrhs;
+  MGM_CHECK(nrhs % xgs == 0, MGM_ERR_INVALID_ARG, "column groups must divide the rhs count");
   const int rc = prolong_chunk_rows(t, rt, 8, 2);
   hipLaunchKernelGGL((k_prolong<F32, F16, 2, F16>), nb, tb, prolong_lds(t, rt, rc, 8), ctx->stream, xc,
-                     (const float2*)nullptr, y, P16, t, nrhs, 3, rc, tile, x16, xs);
+                     (const float2*)nullptr, y, P16, t, nrhs, 3, rc, tile, x16, xs, xgs);
   MGM_LAUNCH_CHECK();
 }
 

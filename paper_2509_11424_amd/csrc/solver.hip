@@ -37,21 +37,28 @@ static void op_apply(Hier& H, int l, mgm_prec p, bool inner, const SolveCfg& cfg
 // that applies D, moves r and x by the previous step's MR length and forms
 // the dots that give the next length (FineOp::apply_step).  r ping-pongs
 // between b (the caller's scratch input, overwritten) and w.rho; the return
-// value is the buffer that holds the final residual b - D y.
-static void* mr_smooth_fused(Hier& H, Vec b, Vec y, int nu) {
+// value is the buffer that holds the final residual b - D y.  g: the column
+// group b and y hold (b.nrhs right-hand sides from rhs g * b.nrhs on), whose
+// q, rho and per-rhs dots sit at the same offsets of the workspace.
+static void* mr_smooth_fused(Hier& H, Vec b, Vec y, int nu, int g = 0) {
   LevelWS& w = H.ws16[0];
   Context* c = H.ctx;
-  int64_t nb = H.fine->apply_dot(MGM_PREC_F16, b.p, w.q, b.nrhs, H.dpart);
-  b_finalize_dot_norm(c, H.scratch, H.dpart, nb, b.nrhs, w.qr, w.qq);
-  b_mr_update(c, w.qr, w.qq, b, b.with(w.q), y, nullptr, true);  // y = alpha b
+  const int64_t ge = H.n(0) * b.nrhs;  // entries of one group
+  const int r0 = g * b.nrhs;
+  __half2* q = (__half2*)w.q + g * ge;
+  double2 *qr = w.qr + r0, *qr2 = w.qr2 + r0;
+  double *qq = w.qq + r0, *qq2 = w.qq2 + r0;
+  int64_t nb = H.fine->apply_dot(MGM_PREC_F16, b.p, q, b.nrhs, H.dpart);
+  b_finalize_dot_norm(c, H.scratch, H.dpart, nb, b.nrhs, qr, qq);
+  b_mr_update(c, qr, qq, b, b.with(q), y, nullptr, true);  // y = alpha b
   void* r = b.p;
-  void* r_next = w.rho;
+  void* r_next = (__half2*)w.rho + g * ge;
   for (int i = 1; i < nu; i++) {
-    double2* qr_prev = (i & 1) ? w.qr : w.qr2;
-    double* qq_prev = (i & 1) ? w.qq : w.qq2;
+    double2* qr_prev = (i & 1) ? qr : qr2;
+    double* qq_prev = (i & 1) ? qq : qq2;
     nb = H.fine->apply_step(MGM_PREC_F16, r, r_next, y.p, qr_prev, qq_prev, b.nrhs, H.dpart);
     if (i + 1 < nu)
-      b_finalize_dot_norm(c, H.scratch, H.dpart, nb, b.nrhs, (i & 1) ? w.qr2 : w.qr, (i & 1) ? w.qq2 : w.qq);
+      b_finalize_dot_norm(c, H.scratch, H.dpart, nb, b.nrhs, (i & 1) ? qr2 : qr, (i & 1) ? qq2 : qq);
     std::swap(r, r_next);
   }
   return r;
@@ -91,6 +98,22 @@ static bool smooth_f16(Hier& H, int l, mgm_prec p, const SolveCfg& cfg) {
          H.ws16[0].rho != nullptr;
 }
 
+// Column groups of the FP16 smoother: with more than kSmoothGroup rhs (a
+// multiple of it) and the fused step, its vectors are stored group-major
+// ([nrhs / 8][dof][site][8]) and smoothed one group at a time, so that a
+// block of the step kernel holds all rhs of a site's run and reads whole
+// 128-byte lines (8 FP16 rhs of a dof are 32 bytes; with 16 rhs stored
+// together each block read half of every line).  Returns the group size
+// (nrhs: no groups).
+constexpr int kSmoothGroup = 8;
+static bool smooth_fusable(Hier& H, int nrhs, const SolveCfg& cfg) {
+  return cfg.smooth >= 2 && H.ws16[0].qr2 != nullptr && H.fine->step_fusable(MGM_PREC_F16, nrhs);
+}
+static int smooth_group(Hier& H, int nrhs, const SolveCfg& cfg) {
+  if (nrhs > kSmoothGroup && nrhs % kSmoothGroup == 0 && smooth_fusable(H, kSmoothGroup, cfg)) return kSmoothGroup;
+  return nrhs;
+}
+
 // Smoothing e = S r on level l.  On the fine level of the mixed V-cycle the
 // smoother runs in FP16 storage: the input is scaled per rhs to unit RMS
 // entries (MR is homogeneous of degree one, and FP16 keeps its full
@@ -109,6 +132,7 @@ struct Smooth16 {
   const __half2* y = nullptr;
   const __half2* r = nullptr;
   const double* inv = nullptr;
+  int gs = 0;  // column group size of y and r
 };
 static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, Vec* res = nullptr,
                    bool unit = false, bool add = false, const Vec* sub = nullptr, Smooth16* o16 = nullptr) {
@@ -117,7 +141,9 @@ static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg
   if (smooth_f16(H, l, p, cfg)) {
     LevelWS& w = H.ws16[0];
     Context* c = H.ctx;
+    const int gs = smooth_group(H, r.nrhs, cfg);
     Vec r16 = r.as(MGM_PREC_F16, w.r), y16 = r.as(MGM_PREC_F16, w.t);
+    r16.group = y16.group = gs < r.nrhs ? gs : 0;
     if (!unit) b_norm2(c, H.scratch, r, w.n2a);
     b_unit_scales(c, unit ? nullptr : w.n2a, (double)r.nsite * r.dof, r.nrhs, w.mask, w.n2b);
     if (sub)
@@ -125,14 +151,25 @@ static void smooth(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg
     else
       b_copy_scaled(c, r16, r, w.mask);
     void* rf = w.rho;
-    if (cfg.smooth >= 2 && w.qr2 != nullptr && H.fine->step_fusable(MGM_PREC_F16, r.nrhs))
-      rf = mr_smooth_fused(H, r16, y16, cfg.smooth);
-    else
+    if (smooth_fusable(H, gs, cfg)) {
+      // each group is a plain (dof, site, gs) block
+      const int64_t ge = H.n(0) * gs;
+      for (int g = 0; g < r.nrhs / gs; g++) {
+        Vec rg = r16, yg = y16;
+        rg.group = yg.group = 0;
+        rg.nrhs = yg.nrhs = gs;
+        rg.p = (__half2*)w.r + g * ge;
+        yg.p = (__half2*)w.t + g * ge;
+        rf = mr_smooth_fused(H, rg, yg, cfg.smooth, g) == rg.p ? w.r : w.rho;
+      }
+    } else {
       mr_smooth(H, 0, MGM_PREC_F16, r16, y16, cfg.smooth, cfg);
+    }
     if (o16) {
       o16->y = (const __half2*)y16.p;
       o16->r = (const __half2*)rf;
       o16->inv = w.n2b;
+      o16->gs = gs;
       return;
     }
     if (add)
@@ -222,12 +259,12 @@ void vcycle(Hier& H, int l, mgm_prec p, Vec r, Vec e, const SolveCfg& cfg, bool 
   LevelWS& wc = H.ws(l + 1, p);
   Vec rc = H.vec(l + 1, p, wc.bc, nrhs), ec = H.vec(l + 1, p, wc.xc, nrhs);
   if (o16.y)
-    H.T[l].restrict16(o16.r, o16.inv, (float2*)rc.p, nrhs);
+    H.T[l].restrict16(o16.r, o16.inv, (float2*)rc.p, nrhs, o16.gs);
   else
     H.T[l].restrict_(p, t.p, rc.p, nrhs);
   coarse_correction(H, l + 1, p, rc, ec, cfg);
   if (o16.y)
-    H.T[l].prolong16((const float2*)ec.p, o16.y, o16.inv, (float2*)e.p, nrhs);
+    H.T[l].prolong16((const float2*)ec.p, o16.y, o16.inv, (float2*)e.p, nrhs, o16.gs);
   else
     H.T[l].prolong(p, ec.p, nullptr, e.p, nrhs, 2);  // e += P e_c
   op_apply(H, l, p, true, cfg, e.p, t.p, nrhs);

@@ -63,27 +63,27 @@ def test_fused_step_applies_to_every_fine_batch(bp):
         assert bp.op.step_fusable(nrhs), nrhs
 
 
-def _orthogonal_parts(p, seed):
+def _orthogonal_parts(p, seed, nprobe=NPROBE):
     """Oracle per-probe values of O_0, O_1, F_0, F_1, coarsest, with the
     magnitude |a| + |b| of each difference term X = a - b."""
     from oracle import estimators as E
     from oracle.philox import z4_vector, stream_id, KIND_F
     vals, scales = [], []
     for l in range(2):
-        X = E.O_samples(p.oh, p.solvers, l, seed, NPROBE[l])
+        X = E.O_samples(p.oh, p.solvers, l, seed, nprobe[l])
         vals.append(X)
         scales.append(np.abs(X))
     for l in range(2):
-        X = E.F_samples(p.oh, p.solvers, l, seed, NPROBE[l])
+        X = E.F_samples(p.oh, p.solvers, l, seed, nprobe[l])
         tr = p.oh.transfers[l]
-        sc = np.zeros(NPROBE[l])
-        for k in range(NPROBE[l]):
+        sc = np.zeros(nprobe[l])
+        for k in range(nprobe[l]):
             x = z4_vector(p.oh.ops[l + 1].n, seed, stream_id(l, KIND_F), k)
             px = tr.prolong(x)
             sc[k] = abs(np.vdot(px, p.solvers[l](px))) + abs(np.vdot(x, p.solvers[l + 1](x)))
         vals.append(X)
         scales.append(sc)
-    X = E.coarsest_samples(p.oh, p.solvers, seed, NPROBE[2])
+    X = E.coarsest_samples(p.oh, p.solvers, seed, nprobe[2])
     vals.append(X)
     scales.append(np.abs(X))
     return vals, scales
@@ -140,3 +140,71 @@ def test_bench_settings_solves_match_oracle(bp, level):
     assert st["max_rel_residual"] <= 1e-12
     want = np.stack([p.solvers[level](bb) for bb in b.reshape(nrhs, -1)])
     assert rel(from_gpu(x).reshape(nrhs, -1), want) < 1e-9
+
+
+# Sixteen fine right-hand sides: the FP16 smoother stores its vectors in two
+# column groups of eight and smooths them one group at a time (the step
+# kernel runs at 8 rhs); conversions and FP16-input transfers read and write
+# the grouped layout.
+NPROBE16 = [16, 6, 12]
+BATCH16 = [16, 4, 8]
+
+
+@pytest.fixture(scope="module")
+def bp16(bp):
+    import paper_2509_11424_amd as m
+    h = m.Hierarchy(bp.op, BLOCKS, NTV, seed=82, max_nrhs=BATCH16[0], max_nrhs_level=BATCH16, restart=12,
+                    mixed=1)
+    bp.stream.synchronize()
+    return h
+
+
+def _step_keys(p, m):
+    rep = p.ctx.tune_report()
+    return {n for n in (8, 16) if "dslash_step/%d/%d/%d" % (m.api.PREC["f16"], p.op.V, n) in rep}
+
+
+def test_grouped_smoother_solve_matches_oracle(bp, bp16):
+    """Sixteen fine right-hand sides with the benchmark's settings: solutions
+    at tol 1e-12 within 1e-9 of the oracle's; the step kernel ran on 8-rhs
+    groups, never on all 16 together."""
+    import paper_2509_11424_amd as m
+    p = bp
+    s, d, n = bp16.level_info(0)
+    nrhs = 16
+    rng = np.random.default_rng(86)
+    b = rng.standard_normal((nrhs, s, d)) + 1j * rng.standard_normal((nrhs, s, d))
+    before = _step_keys(p, m)
+    p.ctx.autotune(True)
+    try:
+        x, st = bp16.solve(0, to_gpu(b), bench_solve_desc(m))
+    finally:
+        p.ctx.autotune(False)
+    p.stream.synchronize()
+    assert st["max_rel_residual"] <= 1e-12
+    want = np.stack([p.solvers[0](bb) for bb in b.reshape(nrhs, -1)])
+    assert rel(from_gpu(x).reshape(nrhs, -1), want) < 1e-9
+    keys = _step_keys(p, m) - before
+    assert 8 in _step_keys(p, m) and 16 not in keys
+
+
+def test_grouped_smoother_estimate_matches_oracle(bp, bp16):
+    """An estimate with 16 fine probes per batch (grouped FP16 smoother,
+    captured coarse-grid corrections, autotuning) against the oracle probe by
+    probe (1e-8 relative, differences against |a| + |b|)."""
+    import paper_2509_11424_amd as m
+    p = bp
+    seed = 87
+    want, scale = _orthogonal_parts(p, seed, NPROBE16)
+    p.ctx.autotune(True)
+    try:
+        res = bp16.estimate("trace", "orthogonal", NPROBE16, seed=seed, batch=BATCH16, solve=bench_solve_desc(m))
+    finally:
+        p.ctx.autotune(False)
+    p.stream.synchronize()
+    assert res["stats"]["max_rel_residual"] <= 1e-12
+    for q in range(5):
+        got = res["samples"][q][:, 0, 0]
+        assert got.shape == want[q].shape, q
+        err = np.abs(got - want[q]) / scale[q]
+        assert np.all(err <= 1e-8), (q, err.max())
