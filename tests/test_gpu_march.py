@@ -17,7 +17,7 @@ backward neighbour wraps), 16x4x16x6 (two z-runs, T not a multiple of four)
 and 8x8x32x4 (the 32-plane runs, one per time slice and tile).  The last
 tests run the bench's launch configuration, 32^3 x 64: the reducing dslash at
 eight FP16 right-hand sides against the FP64 dslash, and every launch variant
-of the fused smoother step at 16 and 4 right-hand sides against its
+of the fused smoother step at 16, 8 and 4 right-hand sides against its
 definition and the oracle's stencil at sampled sites.
 """
 import numpy as np
@@ -307,11 +307,12 @@ def test_fused_smoother_step_refuses_lattice_without_tile(ctx):
         op.smoother_step(t, t.clone(), z, torch.ones(4, dtype=torch.float64, device="cuda:0"))
 
 
-@pytest.mark.parametrize("nrhs", [16, 4])
+@pytest.mark.parametrize("nrhs", [16, 8, 4])
 def test_fused_smoother_step_full_size(ctx, full, nrhs):
-    """32^3 x 64 at the bench's fine-level batches (16, and 4 for the rest of
-    20 probes): every launch variant of the fused smoother step, among them
-    the 32-plane shapes the bench runs.
+    """32^3 x 64 at the rhs counts of the bench's fine level (a batch of 16,
+    smoothed in column groups of 8, and 4 for the rest of 20 probes): every
+    launch variant of the fused smoother step, among them the 32-plane
+    shapes the bench runs.
 
     x' = x + omega r within one FP16 ulp of the update; FP32 forms: r' = r -
     omega q per element against q from the reducing FP16 dslash (slack for
