@@ -166,8 +166,8 @@ def traffic_record(kclass):
 
 
 def rhs_counts(kv):
-    """The two rhs counts of the timed region's launches that a counter file
-    covers (larger first; 8 and 4 when it does not say)."""
+    """The rhs counts of the timed region's launches that a counter file
+    covers, larger first (one or two; 8 and 4 when it does not say)."""
     c = [int(v) for v in kv.get("rhs_counts", "8 4").split()]
     return max(c), min(c)
 
@@ -175,11 +175,11 @@ def rhs_counts(kv):
 def measured_traffic(kclass, V, launches, total_bytes, variants=None):
     """Calibrated HBM bytes per launch of the kernel class in the timed region,
     or None.  The counter file holds FETCH_SIZE / WRITE_SIZE per launch at the
-    two rhs counts the timed region uses on the fine level, taken with
-    the launch variants it names; the split of the region's launches between
-    the counts follows from its launch count and algorithmic bytes.  None when
-    the counters were taken with other kernel sources or launch variants, or
-    the launches do not split into those counts."""
+    one or two rhs counts the timed region uses on the fine level, taken with
+    the launch variants it names; with two, the split of the region's
+    launches between them follows from its launch count and algorithmic
+    bytes.  None when the counters were taken with other kernel sources or
+    launch variants, or the launches do not split into those counts."""
     try:
         kv = traffic_record(kclass)
         if kv.get("kernel_sources_sha256") != kernel_sources_hash():
@@ -192,6 +192,8 @@ def measured_traffic(kclass, V, launches, total_bytes, variants=None):
         t = {n: (float(kv["fetch_kib_nrhs%d" % n]) * fs + float(kv["write_kib_nrhs%d" % n]) * ws) * 1024.0
              for n in (hi, lo)}
         bh, bl = dslash_bytes(kclass, V, hi), dslash_bytes(kclass, V, lo)
+        if hi == lo:  # one rhs count: every launch must be of it
+            return t[lo] if abs(total_bytes - launches * bl) <= 1e-6 * total_bytes else None
         nh = (total_bytes - launches * bl) / (bh - bl)
         if abs(nh - round(nh)) > 1e-3 * launches or nh < -0.5 or nh > launches + 0.5:
             return None
@@ -204,13 +206,14 @@ def measured_traffic(kclass, V, launches, total_bytes, variants=None):
 CONFIGS = {
     # 32^3 x 64, csw 1, roughness 0.6, m0 0.02; 4^4 (24 tv) then 2^4 (32 tv);
     # probes 20 / 100 / 400 on the fine / middle / coarsest difference levels
-    # batch: rhs per solve batch on each level in the mixed form (16 on the
-    # fine level: the largest tried that fits, 198 GB of workspace; all 100
-    # middle-level probes of a term at once; 80 on the coarsest); the FP64
-    # form of the time-to-target comparison keeps 8 on the fine level (its
-    # FP64 Krylov workspace would need about 245 GB at 16)
+    # batch: rhs per solve batch on each level in the mixed form (all 20
+    # fine-level probes of a term at once, 238 GB of workspace, its FP16
+    # smoother in five column groups of 4; all 100 middle-level probes of a
+    # term at once; 80 on the coarsest); the FP64 form of the time-to-target
+    # comparison keeps 8 on the fine level (its FP64 Krylov workspace would
+    # need about 245 GB at 16)
     "c4": dict(dims=(32, 32, 32, 64), eps=0.6, m0=0.02, csw=1.0, gseed=14, blocks=[(4, 4, 4, 4), (2, 2, 2, 2)],
-               ntv=[24, 32], nprobe=[20, 100, 400], pseed=104, batch=[16, 100, 80], batch_f64=[8, 100, 80],
+               ntv=[24, 32], nprobe=[20, 100, 400], pseed=104, batch=[20, 100, 80], batch_f64=[8, 100, 80],
                restart=12,
                name="32^3x64 Wilson-clover (csw 1, roughness 0.6, m0 0.02), 3-level orthogonal MG-MLMC "
                     "tr(D^-1), aggregates 4^4/2^4, N_tv 24/32, probes 20/100/400"),

@@ -98,19 +98,21 @@ static bool smooth_f16(Hier& H, int l, mgm_prec p, const SolveCfg& cfg) {
          H.ws16[0].rho != nullptr;
 }
 
-// Column groups of the FP16 smoother: with more than kSmoothGroup rhs (a
-// multiple of it) and the fused step, its vectors are stored group-major
-// ([nrhs / 8][dof][site][8]) and smoothed one group at a time, so that a
-// block of the step kernel holds all rhs of a site's run and reads whole
-// 128-byte lines (8 FP16 rhs of a dof are 32 bytes; with 16 rhs stored
-// together each block read half of every line).  Returns the group size
+// Column groups of the FP16 smoother: with more than 8 rhs and the fused
+// step, its vectors are stored group-major ([nrhs / gs][dof][site][gs], gs
+// = 8 when 8 divides nrhs, else 4 when 4 does) and smoothed one group at a
+// time, so that a block of the step kernel holds all rhs of a site's run and
+// reads whole 128-byte lines (8 FP16 rhs of a dof are 32 bytes; with 16 rhs
+// stored together each block read half of every line, and 20 rhs have no
+// marching shape with more than 4 rhs per block).  Returns the group size
 // (nrhs: no groups).
-constexpr int kSmoothGroup = 8;
 static bool smooth_fusable(Hier& H, int nrhs, const SolveCfg& cfg) {
   return cfg.smooth >= 2 && H.ws16[0].qr2 != nullptr && H.fine->step_fusable(MGM_PREC_F16, nrhs);
 }
 static int smooth_group(Hier& H, int nrhs, const SolveCfg& cfg) {
-  if (nrhs > kSmoothGroup && nrhs % kSmoothGroup == 0 && smooth_fusable(H, kSmoothGroup, cfg)) return kSmoothGroup;
+  if (nrhs <= 8) return nrhs;
+  for (int gs : {8, 4})
+    if (nrhs % gs == 0 && smooth_fusable(H, gs, cfg)) return gs;
   return nrhs;
 }
 

@@ -142,37 +142,36 @@ def test_bench_settings_solves_match_oracle(bp, level):
     assert rel(from_gpu(x).reshape(nrhs, -1), want) < 1e-9
 
 
-# Sixteen fine right-hand sides: the FP16 smoother stores its vectors in two
-# column groups of eight and smooths them one group at a time (the step
-# kernel runs at 8 rhs); conversions and FP16-input transfers read and write
-# the grouped layout.
-NPROBE16 = [16, 6, 12]
-BATCH16 = [16, 4, 8]
+# More than eight fine right-hand sides: the FP16 smoother stores its vectors
+# in column groups (of 8 for 16 rhs, of 4 for 20) and smooths them one group
+# at a time (the step kernel runs at the group's rhs count); conversions and
+# FP16-input transfers read and write the grouped layout.
+CAP16 = [20, 4, 8]
+GROUP = {16: 8, 20: 4}
 
 
 @pytest.fixture(scope="module")
 def bp16(bp):
     import paper_2509_11424_amd as m
-    h = m.Hierarchy(bp.op, BLOCKS, NTV, seed=82, max_nrhs=BATCH16[0], max_nrhs_level=BATCH16, restart=12,
-                    mixed=1)
+    h = m.Hierarchy(bp.op, BLOCKS, NTV, seed=82, max_nrhs=CAP16[0], max_nrhs_level=CAP16, restart=12, mixed=1)
     bp.stream.synchronize()
     return h
 
 
 def _step_keys(p, m):
     rep = p.ctx.tune_report()
-    return {n for n in (8, 16) if "dslash_step/%d/%d/%d" % (m.api.PREC["f16"], p.op.V, n) in rep}
+    return {n for n in (4, 8, 16, 20) if "dslash_step/%d/%d/%d" % (m.api.PREC["f16"], p.op.V, n) in rep}
 
 
-def test_grouped_smoother_solve_matches_oracle(bp, bp16):
-    """Sixteen fine right-hand sides with the benchmark's settings: solutions
-    at tol 1e-12 within 1e-9 of the oracle's; the step kernel ran on 8-rhs
-    groups, never on all 16 together."""
+@pytest.mark.parametrize("nrhs", [16, 20])
+def test_grouped_smoother_solve_matches_oracle(bp, bp16, nrhs):
+    """16 and 20 fine right-hand sides with the benchmark's settings:
+    solutions at tol 1e-12 within 1e-9 of the oracle's; the step kernel ran
+    on the column groups (8 and 4 rhs), never on the whole batch."""
     import paper_2509_11424_amd as m
     p = bp
     s, d, n = bp16.level_info(0)
-    nrhs = 16
-    rng = np.random.default_rng(86)
+    rng = np.random.default_rng(86 + nrhs)
     b = rng.standard_normal((nrhs, s, d)) + 1j * rng.standard_normal((nrhs, s, d))
     before = _step_keys(p, m)
     p.ctx.autotune(True)
@@ -185,20 +184,22 @@ def test_grouped_smoother_solve_matches_oracle(bp, bp16):
     want = np.stack([p.solvers[0](bb) for bb in b.reshape(nrhs, -1)])
     assert rel(from_gpu(x).reshape(nrhs, -1), want) < 1e-9
     keys = _step_keys(p, m) - before
-    assert 8 in _step_keys(p, m) and 16 not in keys
+    assert GROUP[nrhs] in _step_keys(p, m) and nrhs not in keys
 
 
-def test_grouped_smoother_estimate_matches_oracle(bp, bp16):
-    """An estimate with 16 fine probes per batch (grouped FP16 smoother,
-    captured coarse-grid corrections, autotuning) against the oracle probe by
-    probe (1e-8 relative, differences against |a| + |b|)."""
+@pytest.mark.parametrize("nfine", [16, 20])
+def test_grouped_smoother_estimate_matches_oracle(bp, bp16, nfine):
+    """Estimates with 16 and 20 fine probes in one batch (grouped FP16
+    smoother, captured coarse-grid corrections, autotuning) against the oracle
+    probe by probe (1e-8 relative, differences against |a| + |b|)."""
     import paper_2509_11424_amd as m
     p = bp
-    seed = 87
-    want, scale = _orthogonal_parts(p, seed, NPROBE16)
+    seed = 87 + nfine
+    nprobe = [nfine, 6, 12]
+    want, scale = _orthogonal_parts(p, seed, nprobe)
     p.ctx.autotune(True)
     try:
-        res = bp16.estimate("trace", "orthogonal", NPROBE16, seed=seed, batch=BATCH16, solve=bench_solve_desc(m))
+        res = bp16.estimate("trace", "orthogonal", nprobe, seed=seed, batch=[nfine, 4, 8], solve=bench_solve_desc(m))
     finally:
         p.ctx.autotune(False)
     p.stream.synchronize()
