@@ -214,6 +214,7 @@ CONFIGS = {
     # need about 245 GB at 16)
     "c4": dict(dims=(32, 32, 32, 64), eps=0.6, m0=0.02, csw=1.0, gseed=14, blocks=[(4, 4, 4, 4), (2, 2, 2, 2)],
                ntv=[24, 32], nprobe=[20, 100, 400], pseed=104, batch=[20, 100, 80], batch_f64=[8, 100, 80],
+               aux_fine_batch=8,
                restart=12,
                name="32^3x64 Wilson-clover (csw 1, roughness 0.6, m0 0.02), 3-level orthogonal MG-MLMC "
                     "tr(D^-1), aggregates 4^4/2^4, N_tv 24/32, probes 20/100/400"),
@@ -236,6 +237,14 @@ CONFIGS = {
                name="8^4 Wilson-clover (csw 1, roughness 0.5, m0 0.05), 2-level orthogonal MG-MLMC tr(D^-1), "
                     "2^4 aggregates, N_tv 8, probes 50/200"),
 }
+
+
+def aux_fine_batch(cfg):
+    """Fine-level batch of the observables and hierarchy-study legs, whose
+    hierarchies hold more fine vectors per rhs than the trace bench's: half
+    the trace bench's fine batch (8 on the 32^3 x 64 workload, a multiple of
+    the FP16 smoother's column groups)."""
+    return cfg.get("aux_fine_batch", max(1, cfg["batch"][0] // 2))
 
 
 def rhs_per_step(nprobe):
@@ -582,9 +591,9 @@ def observables(args):
         ctx = m.Context(0)
         op = m.Operator(ctx, U, cfg["m0"], cfg["csw"])
         L = len(cfg["blocks"]) + 1
-        # the fine batch is halved against the trace bench: the fine-level
-        # term vectors of correlators and loops take (4L - 3) fine vectors per rhs
-        batch = [max(1, cfg["batch"][0] // 2)] + list(cfg["batch"][1:])
+        # a smaller fine batch than the trace bench's: the fine-level term
+        # vectors of correlators and loops take (4L - 3) fine vectors per rhs
+        batch = [aux_fine_batch(cfg)] + list(cfg["batch"][1:])
         h = m.Hierarchy(op, cfg["blocks"], cfg["ntv"], seed=cfg["pseed"] + 1000, max_nrhs=batch[0],
                         max_nrhs_level=batch, restart=cfg["restart"], mixed=1, with_corr=True)
         sd = m.solve_desc(tol=1e-10, kind="mg_mixed", smooth=args.smooth, smooth_coarse=args.smooth_coarse,
@@ -643,9 +652,9 @@ def hierarchy_study(args):
     with torch.cuda.stream(stream):
         ctx = m.Context(0)
         op = m.Operator(ctx, U, cfg["m0"], cfg["csw"])
-        # half the fine batch of the trace bench: room for 64 test vectors
-        # and for the refinement's block vectors
-        batch = [max(1, cfg["batch"][0] // 2)] + list(cfg["batch"][1:])
+        # a smaller fine batch than the trace bench's: room for 64 test
+        # vectors and for the refinement's block vectors
+        batch = [aux_fine_batch(cfg)] + list(cfg["batch"][1:])
         sd = m.solve_desc(tol=1e-10, kind="mg_mixed", smooth=args.smooth, smooth_coarse=args.smooth_coarse,
                           coarse_iters=args.coarse_iters, inner_tol=args.inner_tol, maxiter=5000,
                           coarse_bf16=True, smoother_f16=True, graphs=True)
