@@ -241,9 +241,9 @@ CONFIGS = {
 
 def aux_fine_batch(cfg):
     """Fine-level batch of the observables and hierarchy-study legs, whose
-    hierarchies hold more fine vectors per rhs than the trace bench's: half
-    the trace bench's fine batch (8 on the 32^3 x 64 workload, a multiple of
-    the FP16 smoother's column groups)."""
+    hierarchies hold more fine vectors per rhs than the trace bench's: the
+    configuration's own value (8 on the 32^3 x 64 workload), else half the
+    trace bench's fine batch."""
     return cfg.get("aux_fine_batch", max(1, cfg["batch"][0] // 2))
 
 
