@@ -61,6 +61,29 @@ def test_traffic_gate_rejects_other_launch_variants(tmp_path, monkeypatch):
     assert bench.kernel_name("dslash_f16", {8: 0, 4: 2}).startswith("k_dslash<")
 
 
+def test_traffic_gate_with_one_rhs_count(tmp_path, monkeypatch):
+    """A record of one rhs count (the bench's 20-rhs batches run the step in
+    4-rhs groups only): every launch must be of that count."""
+    import bench
+    f = tmp_path / "t.txt"
+    f.write_text("kernel_sources_sha256: %s\nrhs_counts: 4\nfetch_scale: 2\nwrite_scale: 1\nvariant_nrhs4: 25\n"
+                 "fetch_kib_nrhs4: 3\nwrite_kib_nrhs4: 5\n" % bench.kernel_sources_hash())
+    monkeypatch.setitem(bench.TRAFFIC_FILES, "dslash_f16", str(f))
+    V = 1024
+    b4 = bench.dslash_bytes("dslash_f16", V, 4)
+    assert bench.rhs_counts(bench.traffic_record("dslash_f16")) == (4, 4)
+    assert bench.measured_traffic("dslash_f16", V, 5, 5 * b4, {4: 25}) == (3 * 2 + 5) * 1024.0
+    assert bench.measured_traffic("dslash_f16", V, 5, 4 * b4 + bench.dslash_bytes("dslash_f16", V, 8),
+                                  {4: 25}) is None
+    assert bench.measured_traffic("dslash_f16", V, 5, 5 * b4, {4: 24}) is None
+
+
+def test_auxiliary_fine_batch():
+    import bench
+    assert bench.aux_fine_batch(bench.CONFIGS["c4"]) == 8
+    assert bench.aux_fine_batch(bench.CONFIGS["c2"]) == bench.CONFIGS["c2"]["batch"][0] // 2
+
+
 def test_roofline_takes_the_tighter_roof():
     import bench
     V = 32 * 32 * 32 * 64
