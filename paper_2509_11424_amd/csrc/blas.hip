@@ -53,6 +53,13 @@ struct RowRhsIter {
   }
 };
 
+// Routines that apply per-rhs factors or reduce per rhs read the plain
+// (dof, site, rhs) layout only; a vector with column groups reaching them is
+// a caller's mistake.
+static void plain_layout(const Vec& v) {
+  MGM_CHECK(v.group == 0, MGM_ERR_INVALID_ARG, "vector with column groups passed to a plain-layout routine");
+}
+
 static inline unsigned ew_blocks(int64_t n) {
   int64_t b = (n + 255) / 256;
   return (unsigned)(b < 65536 * 4 ? b : 65536 * 4);
@@ -198,6 +205,8 @@ __global__ void k_axpy(const double2* a, double sgn, const void* x, void* y, int
   }
 }
 void b_axpy(Context* c, const double2* a, double sgn, Vec x, Vec y) {
+  plain_layout(x);
+  plain_layout(y);
   int64_t n = x.n();
   MGM_CHECK(y.n() == n && x.prec == y.prec, MGM_ERR_INVALID_ARG, "axpy: mismatch");
   if (n == 0) return;
@@ -220,6 +229,8 @@ __global__ void k_xpay(const void* x, const double2* a, double sgn, void* y, int
   }
 }
 void b_xpay(Context* c, Vec x, const double2* a, double sgn, Vec y) {
+  plain_layout(x);
+  plain_layout(y);
   int64_t n = x.n();
   MGM_CHECK(y.n() == n && x.prec == y.prec, MGM_ERR_INVALID_ARG, "xpay: mismatch");
   if (n == 0) return;
@@ -253,6 +264,7 @@ __global__ void k_normalize(void* x, const double* n2, double* beta, int64_t n, 
   }
 }
 void b_normalize(Context* c, Vec x, const double* n2, double* beta) {
+  plain_layout(x);
   int64_t n = x.n();
   if (n == 0) return;
   DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_normalize<P>, dim3(ew_blocks(n)), dim3(256), 0, c->stream,
@@ -267,6 +279,7 @@ __global__ void k_scale_rhs(void* x, const double* m, int64_t n, int nrhs) {
   for (RhsIter it(i, stride, nrhs); i < n; i += stride, it.next()) std_<P>(x, i, m[it.r] * ldd<P>(x, i));
 }
 void b_scale_rhs(Context* c, Vec x, const double* m) {
+  plain_layout(x);
   int64_t n = x.n();
   if (n == 0) return;
   DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_scale_rhs<P>, dim3(ew_blocks(n)), dim3(256), 0, c->stream,
@@ -299,6 +312,10 @@ __global__ __launch_bounds__(256) void k_mr_update(const double2* qr, const doub
 }
 void b_mr_update(Context* c, const double2* qr, const double* qq, Vec rho, Vec q, Vec y, const Vec* rho_in,
                  bool y_zero) {
+  plain_layout(rho);
+  plain_layout(q);
+  plain_layout(y);
+  if (rho_in) plain_layout(*rho_in);
   int64_t n = rho.n();
   if (n == 0) return;
   MGM_CHECK(rho.nrhs >= 1 && rho.nrhs <= 256, MGM_ERR_INVALID_ARG, "at most 256 right-hand sides");
@@ -416,6 +433,8 @@ __global__ void k_dot(const void* x, const void* y, int nrhs, RedPlan pl, double
   block_store<1>(v, partial, nrhs);
 }
 void b_dot(Context* c, Scratch& s, Vec x, Vec y, double2* out) {
+  plain_layout(x);
+  plain_layout(y);
   RedPlan pl = red_plan(x.n(), x.nrhs);
   need(s, (size_t)pl.blocks * x.nrhs);
   DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_dot<P>, dim3(pl.blocks), dim3(256), 0, c->stream, x.p, y.p,
@@ -439,6 +458,7 @@ __global__ void k_norm2(const void* x, int nrhs, RedPlan pl, double2* partial) {
   block_store<1>(v, partial, nrhs);
 }
 void b_norm2(Context* c, Scratch& s, Vec x, double* out) {
+  plain_layout(x);
   RedPlan pl = red_plan(x.n(), x.nrhs);
   need(s, (size_t)pl.blocks * x.nrhs);
   DISPATCH_PREC(x.prec, P, hipLaunchKernelGGL(k_norm2<P>, dim3(pl.blocks), dim3(256), 0, c->stream, x.p,
@@ -467,6 +487,8 @@ __global__ void k_rsub_norm2(const void* b, void* r, int nrhs, RedPlan pl, doubl
   block_store<1>(v, partial, nrhs);
 }
 void b_rsub_norm2(Context* c, Scratch& s, Vec b, Vec r, double* out) {
+  plain_layout(b);
+  plain_layout(r);
   MGM_CHECK(b.n() == r.n() && b.nrhs == r.nrhs && b.prec == r.prec, MGM_ERR_INVALID_ARG, "rsub: shape mismatch");
   RedPlan pl = red_plan(r.n(), r.nrhs);
   need(s, (size_t)pl.blocks * r.nrhs);
@@ -498,6 +520,8 @@ __global__ void k_dot_norm(const void* q, const void* rho, int nrhs, RedPlan pl,
   block_store<2>(v, partial, nrhs);
 }
 void b_dot_norm(Context* c, Scratch& s, Vec q, Vec rho, double2* qr, double* qq) {
+  plain_layout(q);
+  plain_layout(rho);
   RedPlan pl = red_plan(q.n(), q.nrhs);
   need(s, (size_t)pl.blocks * 2 * q.nrhs);
   DISPATCH_PREC(q.prec, P, hipLaunchKernelGGL(k_dot_norm<P>, dim3(pl.blocks), dim3(256), 0, c->stream, q.p,
@@ -550,6 +574,8 @@ static void launch_multidot(Context* c, const typename P::S* b0, int64_t stride,
 }
 
 void b_multidot(Context* c, Scratch& s, Vec base, int64_t stride, int k, Vec w, double2* out) {
+  plain_layout(base);
+  plain_layout(w);
   RedPlan pl = red_plan(w.n(), w.nrhs);
   const int KB = 8;
   need(s, (size_t)pl.blocks * KB * w.nrhs);
@@ -595,6 +621,8 @@ __global__ void k_multiaxpy(const void* base, int64_t stride, int k, const doubl
 }
 void b_multiaxpy(Context* c, Scratch& s, Vec base, int64_t stride, int k, const double2* h, double sgn, Vec w,
                  double* n2, bool overwrite) {
+  plain_layout(base);
+  plain_layout(w);
   RedPlan pl = red_plan(w.n(), w.nrhs);
   need(s, (size_t)pl.blocks * w.nrhs);
   DISPATCH_PREC(w.prec, P, hipLaunchKernelGGL(k_multiaxpy<P>, dim3(pl.blocks), dim3(256), 0, c->stream,
@@ -690,6 +718,8 @@ __global__ __launch_bounds__(256) void k_multiaxpy_dot(const void* base, int64_t
 
 void b_multiaxpy_dot(Context* c, Scratch& s, Vec base, int64_t stride, int k, const double2* h, Vec w,
                      double2* out) {
+  plain_layout(base);
+  plain_layout(w);
   MGM_CHECK(k >= 1 && k <= kFusedGS, MGM_ERR_INVALID_ARG, "fused Gram-Schmidt sweep takes 1..16 vectors");
   RedPlan pl = red_plan(w.n(), w.nrhs);
   need(s, (size_t)pl.blocks * k * w.nrhs);
