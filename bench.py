@@ -215,6 +215,9 @@ CONFIGS = {
     "c4": dict(dims=(32, 32, 32, 64), eps=0.6, m0=0.02, csw=1.0, gseed=14, blocks=[(4, 4, 4, 4), (2, 2, 2, 2)],
                ntv=[24, 32], nprobe=[20, 100, 400], pseed=104, batch=[20, 100, 80], batch_f64=[8, 100, 80],
                aux_fine_batch=8,
+               # with --learned: the network's activations at the time-to-target
+               # run need the room a fine batch of 16 leaves (198 GB hierarchy)
+               batch_learned=[16, 100, 80],
                restart=12,
                name="32^3x64 Wilson-clover (csw 1, roughness 0.6, m0 0.02), 3-level orthogonal MG-MLMC "
                     "tr(D^-1), aggregates 4^4/2^4, N_tv 24/32, probes 20/100/400"),
@@ -363,6 +366,8 @@ def progress(msg):
 def run(args):
     import numpy as np
     cfg = dict(CONFIGS[args.config])
+    if args.learned and "batch_learned" in cfg:
+        cfg["batch"] = list(cfg["batch_learned"])
     if args.batch:
         cfg["batch"] = list(args.batch)
     from lattice_inputs import gauge_field
