@@ -366,7 +366,9 @@ def progress(msg):
 def run(args):
     import numpy as np
     cfg = dict(CONFIGS[args.config])
-    if args.learned and "batch_learned" in cfg:
+    if args.form == "f64" and "batch_f64" in cfg:
+        cfg["batch"] = list(cfg["batch_f64"])  # the FP64 form's own batches (its Krylov workspace)
+    elif args.learned and "batch_learned" in cfg:
         cfg["batch"] = list(cfg["batch_learned"])
     if args.batch:
         cfg["batch"] = list(args.batch)
