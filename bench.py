@@ -363,15 +363,23 @@ def progress(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def run_batches(cfg, form, learned, batch=None):
+    """Per-level batches of the timed run: the FP64 form's own (its Krylov
+    workspace), with --learned the ones its measurement used, else the
+    configuration's; an explicit --batch wins."""
+    if batch:
+        return list(batch)
+    if form == "f64" and "batch_f64" in cfg:
+        return list(cfg["batch_f64"])
+    if learned and "batch_learned" in cfg:
+        return list(cfg["batch_learned"])
+    return list(cfg["batch"])
+
+
 def run(args):
     import numpy as np
     cfg = dict(CONFIGS[args.config])
-    if args.form == "f64" and "batch_f64" in cfg:
-        cfg["batch"] = list(cfg["batch_f64"])  # the FP64 form's own batches (its Krylov workspace)
-    elif args.learned and "batch_learned" in cfg:
-        cfg["batch"] = list(cfg["batch_learned"])
-    if args.batch:
-        cfg["batch"] = list(args.batch)
+    cfg["batch"] = run_batches(cfg, args.form, args.learned, args.batch)
     from lattice_inputs import gauge_field
     t0 = time.time()
     U = gauge_field(cfg["dims"], cfg["eps"], cfg["gseed"])

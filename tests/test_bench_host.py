@@ -113,3 +113,14 @@ def test_traffic_split_follows_the_recorded_rhs_counts(tmp_path, monkeypatch):
     total = 2 * bench.dslash_bytes("dslash_f16", V, 16) + bench.dslash_bytes("dslash_f16", V, 4)
     assert abs(bench.measured_traffic("dslash_f16", V, 3, total) - 14 * 1024.0 / 3) < 1e-9
     assert bench.rhs_counts(bench.traffic_record("dslash_f16")) == (16, 4)
+
+
+def test_run_batches():
+    import bench
+    c4 = bench.CONFIGS["c4"]
+    assert bench.run_batches(c4, "mixed", False) == c4["batch"] == [20, 100, 80]
+    assert bench.run_batches(c4, "f64", False) == c4["batch_f64"]
+    assert bench.run_batches(c4, "mixed", True) == [16, 100, 80]
+    assert bench.run_batches(c4, "f64", True, [4, 8, 8]) == [4, 8, 8]
+    c3 = bench.CONFIGS["c3"]
+    assert bench.run_batches(c3, "f64", True) == c3["batch"]
